@@ -1,0 +1,755 @@
+/*
+ * ZipNN oracle: a plain, slow, obviously-correct CPU implementation of the
+ * byte-grouping + chunked canonical Huffman codec, used ONLY as test
+ * infrastructure.  Only the test suite, the smoke check and the benchmark's
+ * cpu_baseline leg may load this library; the product path never does.
+ *
+ * What it computes (ZipNN, arXiv 2411.05239):
+ *   - a tensor is a long array of numbers (paper §II-B), cut into fixed-size
+ *     chunks that are compressed independently (paper §V-A, "Chunking");
+ *   - inside a chunk the words are split into one stream per byte position,
+ *     the most significant byte (sign + high exponent bits) first
+ *     (paper §III-A "Exponent Extraction", §III-B "Byte Grouping");
+ *   - each stream is coded with Huffman only, no LZ stage (paper §III-A
+ *     "Huffman only Compression"); a stream holding one value collapses to a
+ *     header (paper §III-B), and a stream that does not compress is stored
+ *     as is (paper §III-B, §V-B); the decision is per byte-group (§V-A);
+ *   - a map with one entry per (chunk, byte-group) lets every chunk decode on
+ *     its own (paper §V-A, "Metadata and parallelism");
+ *   - optionally the input is first XORed with a base tensor (paper §IV-B).
+ * The paper does not fix the Huffman variant or the container bytes.  This
+ * file uses: an optimal length-limited code found by package-merge
+ * (Larmore & Hirschberg, JACM 1990) with ties broken by (frequency, symbol)
+ * and leaves before packages; canonical codes in RFC 1951 §3.2.2 order; code
+ * bits most-significant first into an LSB-first bit stream; W interleaved
+ * sub-streams of round-robin groups of g symbols; and the 64-byte header /
+ * 16-byte map-entry container described in zipnn_oracle.h.
+ *
+ * Everything here is deliberately simple: bit-by-bit writing and reading,
+ * plain loops, no tables beyond the canonical decode counts.
+ */
+#include "zipnn_oracle.h"
+
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- helpers */
+
+static int dtype_width(int dtype)
+{
+    switch (dtype) {
+    case ORC_BF16: return 2;
+    case ORC_FP16: return 2;
+    case ORC_FP32: return 4;
+    case ORC_FP8_E4M3: return 1;
+    case ORC_U8: return 1;
+    default: return 0;
+    }
+}
+
+static int is_pow2(uint64_t v) { return v != 0 && (v & (v - 1)) == 0; }
+
+static uint64_t align16(uint64_t v) { return (v + 15u) & ~(uint64_t)15u; }
+
+static void put_u16(uint8_t* p, uint16_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
+static void put_u32(uint8_t* p, uint32_t v) { for (int i = 0; i < 4; i++) p[i] = (uint8_t)(v >> (8 * i)); }
+static void put_u64(uint8_t* p, uint64_t v) { for (int i = 0; i < 8; i++) p[i] = (uint8_t)(v >> (8 * i)); }
+static uint16_t get_u16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
+static uint32_t get_u32(const uint8_t* p)
+{
+    uint32_t v = 0;
+    for (int i = 3; i >= 0; i--) v = (v << 8) | p[i];
+    return v;
+}
+static uint64_t get_u64(const uint8_t* p)
+{
+    uint64_t v = 0;
+    for (int i = 7; i >= 0; i--) v = (v << 8) | p[i];
+    return v;
+}
+
+int orc_check_params(int B, uint32_t chunk_bytes, uint32_t S, uint32_t g, uint32_t L)
+{
+    if (B == 0) return ORC_E_INVAL;
+    if (!is_pow2(chunk_bytes) || chunk_bytes < ORC_MIN_CHUNK || chunk_bytes > ORC_MAX_CHUNK) return ORC_E_INVAL;
+    if (!is_pow2(g) || g > ORC_MAX_G) return ORC_E_INVAL;
+    if (!is_pow2(S) || S < g || S > ORC_MAX_S) return ORC_E_INVAL;
+    if (L < ORC_MIN_L || L > ORC_MAX_L) return ORC_E_INVAL;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------- byte grouping */
+
+/* Stream k of element j is byte (B-1-k) of the little-endian word, so
+ * stream 0 is the most significant byte: sign + exponent bits for BF16,
+ * FP16 and FP32 (paper §III-A exponent extraction, §III-B byte grouping). */
+void orc_split_stream(const uint8_t* words, uint64_t m, int B, int k, uint8_t* out)
+{
+    for (uint64_t j = 0; j < m; j++) out[j] = words[j * (uint64_t)B + (uint64_t)(B - 1 - k)];
+}
+
+/* Inverse of orc_split_stream for one stream. */
+static void merge_stream(const uint8_t* in, uint64_t m, int B, int k, uint8_t* words)
+{
+    for (uint64_t j = 0; j < m; j++) words[j * (uint64_t)B + (uint64_t)(B - 1 - k)] = in[j];
+}
+
+/* ------------------------------------------------------- package-merge */
+
+typedef struct {
+    uint64_t w;   /* weight */
+    int leaf;     /* rank of the leaf in the sorted leaf list, or -1 for a package */
+} pm_item;
+
+/* Optimal prefix-code lengths with every length <= L (Larmore & Hirschberg
+ * package-merge).  Leaves are the symbols with f > 0 in ascending
+ * (f, symbol) order.  Starting from the leaf list, L-1 times: pair the
+ * current list's items (0+1, 2+3, ...; an odd last item is dropped) into
+ * packages whose weight is the sum, then merge the leaves and the packages
+ * into the next list by weight, a leaf before a package of equal weight.
+ * The first 2n'-2 items of the last list are selected; a selected leaf adds
+ * one to its symbol's length and a selected package selects its two
+ * children in the list it was made from.  Since the packages of a list are
+ * made from consecutive pairs, selecting the first p packages selects the
+ * first 2p items of the list below, which is how the expansion is done.
+ * Returns the number of coded symbols n', or a negative error. */
+int orc_package_merge(const uint64_t f[256], int L, uint8_t len_out[256])
+{
+    int sym[256];
+    int n = 0;
+    memset(len_out, 0, 256);
+    for (int s = 0; s < 256; s++)
+        if (f[s] > 0) sym[n++] = s;
+    if (n < 2) return n;               /* zero or one symbol: no code needed */
+    if (L < 1 || L > 30 || n > (1 << L)) return ORC_E_INVAL;
+    /* insertion sort of the leaves by (f, symbol) -- plain and stable */
+    for (int i = 1; i < n; i++) {
+        int s = sym[i];
+        int j = i - 1;
+        while (j >= 0 && (f[sym[j]] > f[s] || (f[sym[j]] == f[s] && sym[j] > s))) {
+            sym[j + 1] = sym[j];
+            j--;
+        }
+        sym[j + 1] = s;
+    }
+    pm_item* lists[32];
+    int lens[32];
+    int cap = 2 * n;
+    for (int d = 0; d < L; d++) {
+        lists[d] = (pm_item*)malloc(sizeof(pm_item) * (size_t)cap);
+        if (!lists[d]) {
+            for (int e = 0; e < d; e++) free(lists[e]);
+            return ORC_E_NOMEM;
+        }
+    }
+    /* list 0: the leaves */
+    for (int i = 0; i < n; i++) {
+        lists[0][i].w = f[sym[i]];
+        lists[0][i].leaf = i;
+    }
+    lens[0] = n;
+    for (int d = 1; d < L; d++) {
+        const pm_item* prev = lists[d - 1];
+        int npk = lens[d - 1] / 2;
+        /* merge leaves (i) and packages (p); leaf first on equal weight */
+        int i = 0, p = 0, o = 0;
+        while (i < n || p < npk) {
+            uint64_t pw = 0;
+            if (p < npk) pw = prev[2 * p].w + prev[2 * p + 1].w;
+            if (i < n && (p >= npk || f[sym[i]] <= pw)) {
+                lists[d][o].w = f[sym[i]];
+                lists[d][o].leaf = i;
+                i++;
+            } else {
+                lists[d][o].w = pw;
+                lists[d][o].leaf = -1;
+                p++;
+            }
+            o++;
+        }
+        lens[d] = o;
+    }
+    /* selection, top list first */
+    int sel = 2 * n - 2;
+    int count[256];
+    memset(count, 0, sizeof(count));
+    for (int d = L - 1; d >= 0; d--) {
+        int npk_sel = 0;
+        if (sel > lens[d]) {           /* cannot happen for n <= 2^L */
+            for (int e = 0; e < L; e++) free(lists[e]);
+            return ORC_E_INVAL;
+        }
+        for (int t = 0; t < sel; t++) {
+            if (lists[d][t].leaf >= 0)
+                count[lists[d][t].leaf]++;
+            else
+                npk_sel++;
+        }
+        sel = 2 * npk_sel;
+    }
+    for (int i = 0; i < n; i++) len_out[sym[i]] = (uint8_t)count[i];
+    for (int d = 0; d < L; d++) free(lists[d]);
+    return n;
+}
+
+/* ------------------------------------------------------- canonical codes */
+
+/* RFC 1951 §3.2.2: count the codes of each length, find the first code of
+ * each length, then hand out consecutive codes to the symbols of each length
+ * in increasing symbol order. */
+void orc_canonical_codes(const uint8_t len[256], int L, uint32_t code[256])
+{
+    uint32_t bl_count[32] = {0};
+    uint32_t next_code[32] = {0};
+    for (int s = 0; s < 256; s++)
+        if (len[s]) bl_count[len[s]]++;
+    uint32_t c = 0;
+    for (int bits = 1; bits <= L; bits++) {
+        c = (c + bl_count[bits - 1]) << 1;
+        next_code[bits] = c;
+    }
+    for (int s = 0; s < 256; s++) {
+        code[s] = 0;
+        if (len[s]) code[s] = next_code[len[s]]++;
+    }
+}
+
+/* ------------------------------------------------------- bit I/O */
+
+/* Stream bit i is bit (i mod 8) of byte i/8 (LSB-first); a code goes in most
+ * significant code bit first. */
+static void put_code(uint8_t* buf, uint64_t* pos, uint32_t code, int len)
+{
+    for (int b = len - 1; b >= 0; b--) {
+        uint32_t bit = (code >> b) & 1u;
+        buf[*pos >> 3] |= (uint8_t)(bit << (*pos & 7));
+        (*pos)++;
+    }
+}
+
+static int get_bit(const uint8_t* buf, uint64_t nbits, uint64_t* pos)
+{
+    if (*pos >= nbits) return -1;
+    int bit = (buf[*pos >> 3] >> (*pos & 7)) & 1;
+    (*pos)++;
+    return bit;
+}
+
+/* ------------------------------------------------------- per-stream coding */
+
+typedef struct {
+    int mode;           /* ORC_MODE_* */
+    uint8_t rle;        /* value of an RLE stream */
+    uint64_t bytes;     /* payload bytes */
+    uint8_t* payload;   /* malloc'd (NULL for RLE) */
+} stream_out;
+
+static uint32_t huf_header_bytes(uint64_t W) { return (uint32_t)align16(128 + 2 * W); }
+
+/* Encode one byte-group (stream) of one chunk: m symbols.  The method
+ * decision is made per byte-group (paper §V-A): RAW when the policy says so;
+ * RLE when the stream holds a single value (paper §III-B: a zero stream is
+ * replaced by a header -- generalised to any single value); otherwise the
+ * Huffman payload, kept under AUTO only if it is strictly smaller than the
+ * raw bytes (paper §III-B, §V-B: incompressible groups are stored). */
+static int encode_stream(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g, int L, int policy,
+                         stream_out* out)
+{
+    memset(out, 0, sizeof(*out));
+    if (policy == ORC_POLICY_RAW) goto raw;
+    uint64_t f[256];
+    memset(f, 0, sizeof(f));
+    for (uint64_t j = 0; j < m; j++) f[sym[j]]++;
+    int distinct = 0;
+    int only = 0;
+    for (int s = 0; s < 256; s++)
+        if (f[s]) {
+            distinct++;
+            only = s;
+        }
+    if (distinct == 1) {
+        out->mode = ORC_MODE_RLE;
+        out->rle = (uint8_t)only;
+        out->bytes = 0;
+        return ORC_OK;
+    }
+    uint8_t len[256];
+    int rc = orc_package_merge(f, L, len);
+    if (rc < 0) return rc;
+    uint64_t T = 0;
+    for (int s = 0; s < 256; s++) T += f[s] * len[s];
+    uint64_t W = (m + S - 1) / S;
+    uint64_t H = huf_header_bytes(W);
+    uint64_t size_huf = H + (T + 7) / 8;
+    if (policy == ORC_POLICY_AUTO && size_huf >= m) goto raw;
+
+    uint32_t code[256];
+    orc_canonical_codes(len, L, code);
+    uint8_t* p = (uint8_t*)calloc(size_huf, 1);
+    if (!p) return ORC_E_NOMEM;
+    for (int i = 0; i < 128; i++) p[i] = (uint8_t)(len[2 * i] | (len[2 * i + 1] << 4));
+    uint8_t* bits = p + H;
+    uint64_t G = (m + g - 1) / g;
+    uint64_t pos = 0;
+    for (uint64_t w = 0; w < W; w++) {
+        uint64_t start = pos;
+        for (uint64_t q = w; q < G; q += W) {
+            uint64_t j_end = (q + 1) * g < m ? (q + 1) * g : m;
+            for (uint64_t j = q * g; j < j_end; j++) put_code(bits, &pos, code[sym[j]], len[sym[j]]);
+        }
+        uint64_t lw = pos - start;
+        if (lw > 0xFFFF) {
+            free(p);
+            return ORC_E_INVAL;
+        }
+        put_u16(p + 128 + 2 * w, (uint16_t)lw);
+    }
+    if (pos != T) {
+        free(p);
+        return ORC_E_INVAL;
+    }
+    out->mode = ORC_MODE_HUF;
+    out->bytes = size_huf;
+    out->payload = p;
+    return ORC_OK;
+
+raw:
+    out->mode = ORC_MODE_RAW;
+    out->bytes = m;
+    out->payload = (uint8_t*)malloc(m ? m : 1);
+    if (!out->payload) return ORC_E_NOMEM;
+    memcpy(out->payload, sym, m);
+    return ORC_OK;
+}
+
+/* Decode a Huffman payload of m symbols.  Returns ORC_OK or ORC_E_CORRUPT. */
+static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, uint32_t g, int L,
+                      uint8_t* sym)
+{
+    uint64_t W = (m + S - 1) / S;
+    uint64_t H = huf_header_bytes(W);
+    if (bytes < H) return ORC_E_CORRUPT;
+    uint8_t len[256];
+    for (int i = 0; i < 128; i++) {
+        len[2 * i] = p[i] & 15;
+        len[2 * i + 1] = p[i] >> 4;
+    }
+    /* the table must be a complete prefix code: at least two symbols, no
+     * length above L, Kraft sum exactly one */
+    int n_coded = 0;
+    uint64_t kraft = 0;
+    for (int s = 0; s < 256; s++) {
+        if (!len[s]) continue;
+        if (len[s] > L) return ORC_E_CORRUPT;
+        n_coded++;
+        kraft += (uint64_t)1 << (L - len[s]);
+    }
+    if (n_coded < 2 || kraft != ((uint64_t)1 << L)) return ORC_E_CORRUPT;
+    for (uint64_t i = 128 + 2 * W; i < H; i++)
+        if (p[i] != 0) return ORC_E_CORRUPT;
+    uint64_t T = 0;
+    for (uint64_t w = 0; w < W; w++) T += get_u16(p + 128 + 2 * w);
+    if (bytes != H + (T + 7) / 8) return ORC_E_CORRUPT;
+    const uint8_t* bits = p + H;
+    /* padding bits after T must be zero */
+    for (uint64_t b = T; b < 8 * ((T + 7) / 8); b++)
+        if ((bits[b >> 3] >> (b & 7)) & 1) return ORC_E_CORRUPT;
+
+    /* canonical decoding tables: symbols sorted by (length, symbol) and the
+     * count of codes of each length */
+    int count[32] = {0};
+    int sorted[256];
+    int ns = 0;
+    for (int l = 1; l <= L; l++)
+        for (int s = 0; s < 256; s++)
+            if (len[s] == l) {
+                sorted[ns++] = s;
+                count[l]++;
+            }
+    uint64_t G = (m + g - 1) / g;
+    uint64_t pos = 0;
+    for (uint64_t w = 0; w < W; w++) {
+        uint64_t start = pos;
+        uint64_t lw = get_u16(p + 128 + 2 * w);
+        uint64_t end = start + lw;
+        for (uint64_t q = w; q < G; q += W) {
+            uint64_t j_end = (q + 1) * g < m ? (q + 1) * g : m;
+            for (uint64_t j = q * g; j < j_end; j++) {
+                /* read code bits one at a time; after l bits, the code value
+                 * minus the first code of length l is the index among the
+                 * symbols of length l if it is below their count */
+                int code = 0, first = 0, index = 0, found = -1;
+                for (int l = 1; l <= L; l++) {
+                    int bit = get_bit(bits, end, &pos);
+                    if (bit < 0) return ORC_E_CORRUPT;
+                    code |= bit;
+                    if (code - first < count[l]) {
+                        found = sorted[index + code - first];
+                        break;
+                    }
+                    index += count[l];
+                    first += count[l];
+                    first <<= 1;
+                    code <<= 1;
+                }
+                if (found < 0) return ORC_E_CORRUPT;
+                sym[j] = (uint8_t)found;
+            }
+        }
+        if (pos != end) return ORC_E_CORRUPT;   /* a sub-stream must be used up exactly */
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------- chunk workers */
+
+typedef struct {
+    const uint8_t* src;
+    const uint8_t* base;
+    uint64_t n;
+    int B;
+    uint32_t E;           /* elements per chunk */
+    uint32_t S, g;
+    int L;
+    const uint8_t* policy;
+    stream_out* outs;     /* n_chunks * B */
+    uint32_t n_chunks;
+    uint32_t next;        /* next chunk to take */
+    pthread_mutex_t mu;
+    int rc;
+} enc_job;
+
+static int encode_chunk(enc_job* J, uint32_t c)
+{
+    uint64_t e0 = (uint64_t)c * J->E;
+    uint64_t m = J->n - e0 < J->E ? J->n - e0 : J->E;
+    uint8_t* words = (uint8_t*)malloc(m * (uint64_t)J->B);
+    uint8_t* s = (uint8_t*)malloc(m);
+    if (!words || !s) {
+        free(words);
+        free(s);
+        return ORC_E_NOMEM;
+    }
+    /* XOR delta against the base (paper §IV-B), bytewise */
+    for (uint64_t i = 0; i < m * (uint64_t)J->B; i++) {
+        uint8_t x = J->src[e0 * J->B + i];
+        words[i] = J->base ? (uint8_t)(x ^ J->base[e0 * J->B + i]) : x;
+    }
+    int rc = ORC_OK;
+    for (int k = 0; k < J->B && rc == ORC_OK; k++) {
+        orc_split_stream(words, m, J->B, k, s);
+        rc = encode_stream(s, m, J->S, J->g, J->L, J->policy[k], &J->outs[(uint64_t)c * J->B + k]);
+    }
+    free(words);
+    free(s);
+    return rc;
+}
+
+static void* enc_worker(void* arg)
+{
+    enc_job* J = (enc_job*)arg;
+    for (;;) {
+        pthread_mutex_lock(&J->mu);
+        uint32_t c = J->next++;
+        int stop = J->rc != ORC_OK;
+        pthread_mutex_unlock(&J->mu);
+        if (stop || c >= J->n_chunks) break;
+        int rc = encode_chunk(J, c);
+        if (rc != ORC_OK) {
+            pthread_mutex_lock(&J->mu);
+            if (J->rc == ORC_OK) J->rc = rc;
+            pthread_mutex_unlock(&J->mu);
+        }
+    }
+    return NULL;
+}
+
+static void run_threads(void* (*fn)(void*), void* job, int nthreads)
+{
+    if (nthreads <= 1) {
+        fn(job);
+        return;
+    }
+    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    int started = 0;
+    for (int t = 0; t < nthreads; t++)
+        if (pthread_create(&th[t], NULL, fn, job) == 0) started++;
+        else break;
+    if (started == 0) fn(job);
+    for (int t = 0; t < started; t++) pthread_join(th[t], NULL);
+    free(th);
+}
+
+/* ------------------------------------------------------- public API */
+
+uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes)
+{
+    int B = dtype_width(dtype);
+    if (!B || !is_pow2(chunk_bytes)) return 0;
+    uint64_t E = chunk_bytes / (uint64_t)B;
+    uint64_t nc = (n + E - 1) / E;
+    /* header + map + every payload raw (AUTO never exceeds raw) + alignment;
+     * a HUF-forced stream can exceed raw by its table and sub-stream lengths,
+     * plus up to L bits per symbol beyond 8 */
+    uint64_t per_chunk_extra = (uint64_t)B * (15 + 16 + 128 + 16 + 2 * (uint64_t)E + (uint64_t)E / 2 + 1);
+    return 64 + n * (uint64_t)B + nc * per_chunk_extra;
+}
+
+int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, uint32_t chunk_bytes,
+                 uint32_t S, uint32_t g, uint32_t L, const uint8_t* policy_in, void* dst_v, uint64_t dst_cap,
+                 uint64_t* dst_len, int nthreads)
+{
+    const uint8_t* src = (const uint8_t*)src_v;
+    const uint8_t* base = (const uint8_t*)base_v;
+    uint8_t* dst = (uint8_t*)dst_v;
+    int B = dtype_width(dtype);
+    if (!B || (!src && n) || !dst || !dst_len) return ORC_E_INVAL;
+    int rc = orc_check_params(B, chunk_bytes, S, g, L);
+    if (rc) return rc;
+    uint8_t policy[4] = {0, 0, 0, 0};
+    for (int k = 0; k < B; k++) {
+        policy[k] = policy_in ? policy_in[k] : ORC_POLICY_AUTO;
+        if (policy[k] > ORC_POLICY_RAW) return ORC_E_INVAL;
+    }
+    uint32_t E = chunk_bytes / (uint32_t)B;
+    uint64_t nc64 = (n + E - 1) / E;
+    if (nc64 > 0xFFFFFFFFu) return ORC_E_INVAL;
+    uint32_t n_chunks = (uint32_t)nc64;
+
+    enc_job J;
+    memset(&J, 0, sizeof(J));
+    J.src = src;
+    J.base = base;
+    J.n = n;
+    J.B = B;
+    J.E = E;
+    J.S = S;
+    J.g = g;
+    J.L = (int)L;
+    J.policy = policy;
+    J.n_chunks = n_chunks;
+    J.outs = (stream_out*)calloc((size_t)n_chunks * B + 1, sizeof(stream_out));
+    if (!J.outs) return ORC_E_NOMEM;
+    pthread_mutex_init(&J.mu, NULL);
+    run_threads(enc_worker, &J, nthreads);
+    pthread_mutex_destroy(&J.mu);
+    rc = J.rc;
+
+    /* placement: chunk-major order, every payload 16-byte aligned */
+    uint64_t payload_base = 64 + 16 * (uint64_t)n_chunks * B;
+    uint64_t cur = 0;
+    if (rc == ORC_OK) {
+        for (uint64_t e = 0; e < (uint64_t)n_chunks * B; e++)
+            if (J.outs[e].bytes) cur = align16(cur + J.outs[e].bytes);
+        if (payload_base + cur > dst_cap) rc = ORC_E_NOSPACE;
+    }
+    if (rc == ORC_OK) {
+        uint64_t total = payload_base + cur;
+        memset(dst, 0, total);
+        memcpy(dst, "ZNN1", 4);
+        put_u16(dst + 4, 1);
+        dst[6] = (uint8_t)dtype;
+        dst[7] = (uint8_t)B;
+        put_u64(dst + 8, n);
+        put_u32(dst + 16, chunk_bytes);
+        put_u16(dst + 20, (uint16_t)S);
+        dst[22] = (uint8_t)g;
+        dst[23] = (uint8_t)L;
+        put_u32(dst + 24, base ? ORC_FLAG_DELTA : 0);
+        put_u32(dst + 28, n_chunks);
+        put_u64(dst + 32, total);
+        for (int k = 0; k < 4; k++) dst[40 + k] = policy[k];
+        cur = 0;
+        for (uint64_t e = 0; e < (uint64_t)n_chunks * B; e++) {
+            uint8_t* ent = dst + 64 + 16 * e;
+            stream_out* o = &J.outs[e];
+            put_u64(ent, cur);
+            put_u32(ent + 8, (uint32_t)o->bytes);
+            ent[12] = (uint8_t)o->mode;
+            ent[13] = o->mode == ORC_MODE_RLE ? o->rle : 0;
+            if (o->bytes) {
+                memcpy(dst + payload_base + cur, o->payload, o->bytes);
+                cur = align16(cur + o->bytes);
+            }
+        }
+        *dst_len = total;
+    }
+    for (uint64_t e = 0; e < (uint64_t)n_chunks * B; e++) free(J.outs[e].payload);
+    free(J.outs);
+    return rc;
+}
+
+int orc_parse_header(const void* src_v, uint64_t src_len, orc_header* h)
+{
+    const uint8_t* src = (const uint8_t*)src_v;
+    if (!src || src_len < 64) return ORC_E_FORMAT;
+    if (memcmp(src, "ZNN1", 4) != 0 || get_u16(src + 4) != 1) return ORC_E_FORMAT;
+    h->dtype = src[6];
+    h->B = src[7];
+    h->n = get_u64(src + 8);
+    h->chunk_bytes = get_u32(src + 16);
+    h->S = get_u16(src + 20);
+    h->g = src[22];
+    h->L = src[23];
+    h->flags = get_u32(src + 24);
+    h->n_chunks = get_u32(src + 28);
+    h->total = get_u64(src + 32);
+    for (int k = 0; k < 4; k++) h->policy[k] = src[40 + k];
+    if (dtype_width(h->dtype) == 0 || dtype_width(h->dtype) != h->B) return ORC_E_FORMAT;
+    if (orc_check_params(h->B, h->chunk_bytes, h->S, h->g, h->L) != ORC_OK) return ORC_E_FORMAT;
+    if (h->flags & ~(uint32_t)ORC_FLAG_DELTA) return ORC_E_FORMAT;
+    for (int i = 44; i < 64; i++)
+        if (src[i]) return ORC_E_FORMAT;
+    uint64_t E = h->chunk_bytes / h->B;
+    if ((h->n + E - 1) / E != h->n_chunks) return ORC_E_FORMAT;
+    uint64_t payload_base = 64 + 16 * (uint64_t)h->n_chunks * h->B;
+    if (h->total < payload_base || h->total > src_len) return ORC_E_FORMAT;
+    return ORC_OK;
+}
+
+typedef struct {
+    const uint8_t* src;
+    const uint8_t* base;
+    uint8_t* dst;
+    orc_header h;
+    uint32_t next;
+    pthread_mutex_t mu;
+    int rc;
+} dec_job;
+
+static int decode_chunk(dec_job* J, uint32_t c)
+{
+    const orc_header* h = &J->h;
+    uint64_t E = h->chunk_bytes / h->B;
+    uint64_t e0 = (uint64_t)c * E;
+    uint64_t m = h->n - e0 < E ? h->n - e0 : E;
+    uint64_t payload_base = 64 + 16 * (uint64_t)h->n_chunks * h->B;
+    uint8_t* s = (uint8_t*)malloc(m);
+    uint8_t* words = (uint8_t*)malloc(m * h->B);
+    if (!s || !words) {
+        free(s);
+        free(words);
+        return ORC_E_NOMEM;
+    }
+    int rc = ORC_OK;
+    for (int k = 0; k < h->B && rc == ORC_OK; k++) {
+        const uint8_t* ent = J->src + 64 + 16 * ((uint64_t)c * h->B + k);
+        uint64_t off = get_u64(ent);
+        uint64_t bytes = get_u32(ent + 8);
+        int mode = ent[12];
+        const uint8_t* p = J->src + payload_base + off;
+        if (mode == ORC_MODE_RAW) {
+            memcpy(s, p, m);
+        } else if (mode == ORC_MODE_RLE) {
+            memset(s, ent[13], m);
+        } else {
+            rc = decode_huf(p, bytes, m, h->S, h->g, h->L, s);
+        }
+        if (rc == ORC_OK) merge_stream(s, m, h->B, k, words);
+    }
+    if (rc == ORC_OK) {
+        for (uint64_t i = 0; i < m * h->B; i++) {
+            uint8_t y = words[i];
+            J->dst[e0 * h->B + i] = J->base ? (uint8_t)(y ^ J->base[e0 * h->B + i]) : y;
+        }
+    }
+    free(s);
+    free(words);
+    return rc;
+}
+
+static void* dec_worker(void* arg)
+{
+    dec_job* J = (dec_job*)arg;
+    for (;;) {
+        pthread_mutex_lock(&J->mu);
+        uint32_t c = J->next++;
+        int stop = J->rc != ORC_OK;
+        pthread_mutex_unlock(&J->mu);
+        if (stop || c >= J->h.n_chunks) break;
+        int rc = decode_chunk(J, c);
+        if (rc != ORC_OK) {
+            pthread_mutex_lock(&J->mu);
+            if (J->rc == ORC_OK) J->rc = rc;
+            pthread_mutex_unlock(&J->mu);
+        }
+    }
+    return NULL;
+}
+
+/* Check every map entry before touching a payload: modes, sizes and the
+ * exact chunk-major, 16-byte-aligned placement. */
+static int check_map(const uint8_t* src, const orc_header* h)
+{
+    uint64_t E = h->chunk_bytes / h->B;
+    uint64_t payload_base = 64 + 16 * (uint64_t)h->n_chunks * h->B;
+    uint64_t cur = 0;
+    for (uint64_t c = 0; c < h->n_chunks; c++) {
+        uint64_t m = h->n - c * E < E ? h->n - c * E : E;
+        uint64_t W = (m + h->S - 1) / h->S;
+        for (int k = 0; k < h->B; k++) {
+            const uint8_t* ent = src + 64 + 16 * (c * h->B + k);
+            uint64_t off = get_u64(ent);
+            uint64_t bytes = get_u32(ent + 8);
+            int mode = ent[12];
+            if (ent[14] || ent[15]) return ORC_E_CORRUPT;
+            if (off != cur) return ORC_E_CORRUPT;
+            if (mode == ORC_MODE_RAW) {
+                if (bytes != m || ent[13]) return ORC_E_CORRUPT;
+            } else if (mode == ORC_MODE_RLE) {
+                if (bytes != 0) return ORC_E_CORRUPT;
+            } else if (mode == ORC_MODE_HUF) {
+                if (bytes < huf_header_bytes(W) || ent[13]) return ORC_E_CORRUPT;
+            } else {
+                return ORC_E_CORRUPT;
+            }
+            if (payload_base + off + bytes > h->total) return ORC_E_CORRUPT;
+            if (bytes) cur = align16(cur + bytes);
+        }
+    }
+    if (payload_base + cur != h->total) return ORC_E_CORRUPT;
+    return ORC_OK;
+}
+
+int orc_decompress(const void* src_v, uint64_t src_len, const void* base_v, void* dst_v, uint64_t dst_cap,
+                   int nthreads)
+{
+    const uint8_t* src = (const uint8_t*)src_v;
+    orc_header h;
+    int rc = orc_parse_header(src, src_len, &h);
+    if (rc) return rc;
+    if ((h.flags & ORC_FLAG_DELTA) && !base_v) return ORC_E_INVAL;
+    if (!(h.flags & ORC_FLAG_DELTA) && base_v) return ORC_E_INVAL;
+    if (h.n * h.B > dst_cap) return ORC_E_NOSPACE;
+    if (h.n && !dst_v) return ORC_E_INVAL;
+    rc = check_map(src, &h);
+    if (rc) return rc;
+    dec_job J;
+    memset(&J, 0, sizeof(J));
+    J.src = src;
+    J.base = (const uint8_t*)base_v;
+    J.dst = (uint8_t*)dst_v;
+    J.h = h;
+    pthread_mutex_init(&J.mu, NULL);
+    run_threads(dec_worker, &J, nthreads);
+    pthread_mutex_destroy(&J.mu);
+    return J.rc;
+}
+
+/* Payload of one (chunk, stream) entry, for per-chunk parity sampling. */
+int orc_entry(const void* src_v, uint64_t src_len, uint32_t chunk, int k, uint64_t* off_abs, uint64_t* bytes,
+              int* mode, int* rle)
+{
+    const uint8_t* src = (const uint8_t*)src_v;
+    orc_header h;
+    int rc = orc_parse_header(src, src_len, &h);
+    if (rc) return rc;
+    if (chunk >= h.n_chunks || k < 0 || k >= h.B) return ORC_E_INVAL;
+    const uint8_t* ent = src + 64 + 16 * ((uint64_t)chunk * h.B + k);
+    *off_abs = 64 + 16 * (uint64_t)h.n_chunks * h.B + get_u64(ent);
+    *bytes = get_u32(ent + 8);
+    *mode = ent[12];
+    *rle = ent[13];
+    return ORC_OK;
+}

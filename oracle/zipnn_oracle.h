@@ -1,0 +1,77 @@
+/*
+ * ZipNN oracle (test infrastructure only -- never linked by the product).
+ *
+ * Container format produced and accepted here (all integers little-endian):
+ *
+ *   header, 64 bytes:
+ *     0  "ZNN1"            4  u16 version = 1     6  u8 dtype     7  u8 B
+ *     8  u64 n_elems       16 u32 chunk_bytes     20 u16 S        22 u8 g
+ *     23 u8 L              24 u32 flags (bit0: XOR delta)         28 u32 n_chunks
+ *     32 u64 total_bytes   40 u8 policy[4]        44..63 zero
+ *   map at 64: n_chunks*B entries of 16 bytes, chunk-major (entry c*B+k):
+ *     u64 offset from payload_base | u32 bytes | u8 mode | u8 rle value | u16 0
+ *   payload_base = 64 + 16*n_chunks*B; payloads in map order, each starting
+ *   at a 16-byte aligned offset; padding is zero; RLE entries have no bytes
+ *   and carry the running offset; total_bytes = payload_base + aligned end.
+ *   RAW payload: the m stream bytes.
+ *   HUF payload: 128 bytes of 4-bit code lengths (byte i = l[2i] | l[2i+1]<<4)
+ *     | u16 bit length of each of the W = ceil(m/S) sub-streams | zero pad to
+ *     align16(128 + 2W) | the W sub-streams, bit-contiguous, LSB-first, last
+ *     byte zero padded.  Group q of g consecutive symbols belongs to
+ *     sub-stream q mod W.
+ */
+#ifndef ZIPNN_ORACLE_H
+#define ZIPNN_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORC_OK = 0,
+    ORC_E_INVAL = -1,
+    ORC_E_FORMAT = -2,
+    ORC_E_CORRUPT = -3,
+    ORC_E_NOSPACE = -4,
+    ORC_E_NOMEM = -5
+};
+enum { ORC_BF16 = 1, ORC_FP16 = 2, ORC_FP32 = 3, ORC_FP8_E4M3 = 4, ORC_U8 = 5 };
+enum { ORC_POLICY_AUTO = 0, ORC_POLICY_HUF = 1, ORC_POLICY_RAW = 2 };
+enum { ORC_MODE_RAW = 0, ORC_MODE_HUF = 1, ORC_MODE_RLE = 2 };
+enum { ORC_FLAG_DELTA = 1 };
+
+#define ORC_MIN_CHUNK 256u
+#define ORC_MAX_CHUNK (4u << 20)
+#define ORC_MAX_S 4096u
+#define ORC_MAX_G 16u
+#define ORC_MIN_L 8u
+#define ORC_MAX_L 12u
+
+typedef struct {
+    int dtype, B;
+    uint64_t n;
+    uint32_t chunk_bytes, S, g, L, flags, n_chunks;
+    uint64_t total;
+    uint8_t policy[4];
+} orc_header;
+
+int orc_check_params(int B, uint32_t chunk_bytes, uint32_t S, uint32_t g, uint32_t L);
+void orc_split_stream(const uint8_t* words, uint64_t m, int B, int k, uint8_t* out);
+int orc_package_merge(const uint64_t f[256], int L, uint8_t len_out[256]);
+void orc_canonical_codes(const uint8_t len[256], int L, uint32_t code[256]);
+uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes);
+int orc_compress(const void* src, int dtype, uint64_t n, const void* base, uint32_t chunk_bytes, uint32_t S,
+                 uint32_t g, uint32_t L, const uint8_t* policy, void* dst, uint64_t dst_cap, uint64_t* dst_len,
+                 int nthreads);
+int orc_parse_header(const void* src, uint64_t src_len, orc_header* h);
+int orc_decompress(const void* src, uint64_t src_len, const void* base, void* dst, uint64_t dst_cap,
+                   int nthreads);
+int orc_entry(const void* src, uint64_t src_len, uint32_t chunk, int k, uint64_t* off_abs, uint64_t* bytes,
+              int* mode, int* rle);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
