@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 ZipNN codec (byte grouping + chunked Huffman).
+
+Default workload: one FP32 tensor of 8192 x 8192 elements (256 MiB), row r
+drawn from N(0, sigma_r) with log10(sigma_r) ~ U(-3, -1), 256 KiB chunks,
+every byte group Huffman-coded only where that beats raw (AUTO).
+
+One step = the whole hot path on that tensor, input resident in HBM:
+compress (split + histogram + code build + placement + bit packing) and
+decompress (table build + Huffman decode + merge + store).  The headline
+`value` is decode throughput in GB/s of uncompressed bytes (the paper's
+convention), from HIP events around every decode launch of the timed steps
+(on the stream the kernel runs on); `encode_GBps` is the same for compress.
+
+Prints ONE JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def _src_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(workload: str, alg_bytes: int):
+    """HBM bytes per decode launch from the committed rocprofv3 counter
+    summary, or None if it is missing or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"k_decode_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        if rec.get("decode_src_sha") != _src_hash(os.path.join(ROOT, "paper_2411_05239_amd", "csrc", "decode.hip")):
+            return None
+        return rec.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def make_workload(name: str):
+    import torch
+
+    from paper_2411_05239_amd import workloads
+    from paper_2411_05239_amd import zipnn as Z
+
+    if name == "c1":
+        x = workloads.fp32_rows(8192, 8192, seed=1)
+        p = Z.zipnn_default_params(Z.ZIPNN_FP32)
+        desc = {"workload": "fp32_8192x8192_rowsigma_loguniform_1e-3_1e-1", "dtype": "fp32", "elements": x.numel(),
+                "bytes": x.numel() * 4, "chunk_bytes": p.chunk_bytes, "S": p.substream_syms, "g": p.group,
+                "L": p.max_code_len, "policy": "auto"}
+    elif name == "c0":
+        x = workloads.bf16_normal(4_194_304, seed=0)
+        p = Z.make_params(Z.ZIPNN_BF16, policy=[Z.ZIPNN_HUF, Z.ZIPNN_RAW])
+        desc = {"workload": "bf16_4194304_normal_0.02", "dtype": "bf16", "elements": x.numel(),
+                "bytes": x.numel() * 2, "chunk_bytes": p.chunk_bytes, "S": p.substream_syms, "g": p.group,
+                "L": p.max_code_len, "policy": "huf,raw"}
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return x, p, desc
+
+
+def cpu_baseline(x_cpu, p, gpu_container, budget_s: float):
+    """The oracle (plain C, test infrastructure) on the host cores: one full
+    compress and repeated full decompressions of the same tensor."""
+    import numpy as np
+
+    import oracle
+
+    from paper_2411_05239_amd import zipnn as Z
+
+    code = Z.torch_dtype_code(x_cpu.dtype)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    kw = dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy))
+    t0 = time.perf_counter()
+    c = oracle.compress(x_cpu, code, nthreads=threads, **kw)
+    t_enc = time.perf_counter() - t0
+    matches = bool(np.array_equal(c, gpu_container))
+    reps, t_dec = 0, 0.0
+    while reps == 0 or t_dec < budget_s:
+        t0 = time.perf_counter()
+        out = oracle.decompress(c, nthreads=threads)
+        t_dec += time.perf_counter() - t0
+        reps += 1
+    ok = bool(np.array_equal(out, oracle.as_bytes(x_cpu)))
+    U = x_cpu.numel() * x_cpu.element_size()
+    return {
+        "value": round(U * reps / t_dec / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+        "sample": f"full tensor ({U} bytes): 1 compress + {reps} decompress passes, {threads} threads",
+        "encode_GBps": round(U / t_enc / 1e9, 4), "roundtrip_ok": ok, "container_matches_gpu": matches,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=4.0)
+    ap.add_argument("--decode-only", action="store_true", help="time decode launches only (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this codec build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2411_05239_amd import zipnn as Z
+
+    x_cpu, p, desc = make_workload(args.workload)
+    dev = torch.device("cuda", 0)
+    x = x_cpu.to(dev)
+    U = x.numel() * x.element_size()
+    codec = Z.Codec(0)
+    stream = torch.cuda.current_stream()
+
+    # correctness gate before any number: GPU round trip bit-exact
+    c = codec.compress(x, p)
+    out = torch.empty_like(x)
+    codec.decompress(c, out)
+    if not torch.equal(out.view(torch.uint8), x.view(torch.uint8)):
+        print(json.dumps({"error": "round trip mismatch"}))
+        sys.exit(1)
+    C = c.numel()
+    cbuf = torch.empty(Z.zipnn_compress_bound(Z.torch_dtype_code(x.dtype), x.numel(), p), dtype=torch.uint8,
+                       device=dev)
+    scrub = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+
+    def step(i, timed, ev):
+        scrub.fill_(i & 0xFF)   # evict the 256 MB last-level cache between steps
+        if not args.decode_only:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            cc = codec.compress(x, p, out=cbuf)
+            e1.record(stream)
+            assert cc.numel() == C
+            ev["enc"].append((e0, e1))
+            scrub.fill_((i + 1) & 0xFF)
+        d0 = torch.cuda.Event(enable_timing=True)
+        d1 = torch.cuda.Event(enable_timing=True)
+        d0.record(stream)
+        Z.zipnn_decompress(codec.ctx, c.data_ptr(), C, None, out.data_ptr(), U, stream.cuda_stream)
+        d1.record(stream)
+        ev["dec"].append((d0, d1))
+
+    ev = {"enc": [], "dec": []}
+    for i in range(args.warmup):
+        step(i, False, ev)
+    torch.cuda.synchronize()
+    ev = {"enc": [], "dec": []}
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i, True, ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = codec.status()
+    if st != Z.ZIPNN_OK or not torch.equal(out.view(torch.uint8), x.view(torch.uint8)):
+        print(json.dumps({"error": f"decode status {st} or mismatch after timing"}))
+        sys.exit(1)
+    dec_ms = [a.elapsed_time(b) for a, b in ev["dec"]]
+    enc_ms = [a.elapsed_time(b) for a, b in ev["enc"]]
+    dec_avg = statistics.mean(dec_ms)
+    alg = C + U  # decode: read the container, write the tensor
+    achieved = alg / (dec_avg * 1e-3) / 1e9
+    traffic = _traffic(args.workload, alg)
+    rec = {
+        "metric": "decode GB/s at bit-exact roundtrip (uncompressed bytes / decode time); encode GB/s beside it",
+        "value": round(U / (dec_avg * 1e-3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": desc,
+        "decode_ms": {"mean": round(dec_avg, 4), "median": round(statistics.median(dec_ms), 4),
+                      "p10": round(sorted(dec_ms)[len(dec_ms) // 10], 4),
+                      "p90": round(sorted(dec_ms)[(len(dec_ms) * 9) // 10], 4)},
+        "encode_GBps": round(U / (statistics.mean(enc_ms) * 1e-3) / 1e9, 2) if enc_ms else None,
+        "encode_ms": {"mean": round(statistics.mean(enc_ms), 4), "median": round(statistics.median(enc_ms), 4)}
+        if enc_ms else None,
+        "compressed_bytes": C,
+        "ratio": round(C / U, 5),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "kernel": "k_decode", "algorithmic_bytes_per_launch": alg},
+        "paper_context": "ZipNN CPU: up to 80 GB/s decompression, 13 GB/s compression (Xeon 8480+, 16 workers)",
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(x_cpu, p, c.cpu().numpy(), args.cpu_budget)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

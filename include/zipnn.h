@@ -1,0 +1,164 @@
+/*
+ * zipnn.h -- C ABI of the MI355X (gfx950) ZipNN codec: lossless compression
+ * of model weights by byte grouping + chunked canonical Huffman coding
+ * (ZipNN, arXiv 2411.05239).
+ *
+ * Method, as the paper states it:
+ *   - a tensor is a long array of numbers (§II-B); it is cut into fixed-size
+ *     chunks (256 KB by default) that compress and decompress independently
+ *     (§V-A "Chunking");
+ *   - the words of a chunk are regrouped into one byte stream per byte
+ *     position, the exponent byte first (§III-A "Exponent Extraction",
+ *     §III-B "Byte Grouping");
+ *   - each stream is entropy coded with Huffman only (§III-A "Huffman only
+ *     Compression"); a single-valued stream shrinks to a header and an
+ *     incompressible stream is stored as is (§III-B); the choice is made per
+ *     byte-group (§V-A);
+ *   - a map holding metadata per chunk and per byte-group allows parallel
+ *     decompression of the variable-size chunks (§V-A "Metadata and
+ *     parallelism");
+ *   - a tensor may be stored as the XOR delta against a base (§IV-B).
+ *
+ * Container bytes (little-endian; identical to what the CPU reference codec
+ * of this project writes):
+ *   header (64 B): "ZNN1" | u16 version=1 | u8 dtype | u8 B | u64 n_elems |
+ *     u32 chunk_bytes | u16 S | u8 g | u8 L | u32 flags (bit0 = XOR delta) |
+ *     u32 n_chunks | u64 total_bytes | u8 policy[4] | 20 zero bytes
+ *   map: n_chunks*B entries of 16 B, chunk-major: u64 payload offset (from
+ *     payload_base = 64 + 16*n_chunks*B) | u32 bytes | u8 mode (0 RAW, 1 HUF,
+ *     2 RLE) | u8 RLE value | u16 0
+ *   payloads: in map order, each at a 16-byte aligned offset, zero padded.
+ *     RAW = the m stream bytes.  RLE = nothing.  HUF = 128 B of 4-bit code
+ *     lengths | u16 bit length of each of the W = ceil(m/S) sub-streams |
+ *     zero pad to align16(128+2W) | the sub-streams, bit-contiguous, LSB-first,
+ *     canonical codes written most significant bit first; group q of g
+ *     consecutive symbols belongs to sub-stream q mod W.
+ *   Stream k of element j is byte B-1-k of the little-endian word.  Codes are
+ *   optimal among prefix codes with lengths <= L (package-merge, ties by
+ *   (frequency, symbol)) and assigned in canonical (length, symbol) order.
+ *
+ * Conventions for every call below:
+ *   - "device" pointers point to memory of the context's HIP device; every
+ *     device buffer (src, dst, base) must be 16-byte aligned;
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream);
+ *   - the caller owns every buffer it passes; the library never frees them;
+ *   - a negative return is a zipnn_status; argument errors are reported
+ *     before any work is queued.
+ */
+#ifndef ZIPNN_H
+#define ZIPNN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ZIPNN_OK = 0,
+    ZIPNN_E_INVAL = -1,    /* bad argument or parameter */
+    ZIPNN_E_FORMAT = -2,   /* not a valid container header */
+    ZIPNN_E_CORRUPT = -3,  /* map, table or bitstream inconsistent */
+    ZIPNN_E_NOSPACE = -4,  /* output capacity too small */
+    ZIPNN_E_NOMEM = -5,    /* device or host allocation failed */
+    ZIPNN_E_HIP = -6,      /* a HIP runtime call failed */
+    ZIPNN_E_BUSY = -7      /* result not ready yet (serving API) */
+} zipnn_status;
+
+typedef enum {
+    ZIPNN_BF16 = 1,        /* B = 2 */
+    ZIPNN_FP16 = 2,        /* B = 2 */
+    ZIPNN_FP32 = 3,        /* B = 4 */
+    ZIPNN_FP8_E4M3 = 4,    /* B = 1 */
+    ZIPNN_U8 = 5           /* B = 1 */
+} zipnn_dtype;
+
+typedef enum {
+    ZIPNN_AUTO = 0,        /* HUF if strictly smaller than raw, RLE if single-valued, else RAW */
+    ZIPNN_HUF = 1,         /* always Huffman (RLE if single-valued) */
+    ZIPNN_RAW = 2          /* always stored */
+} zipnn_policy;
+
+/* Format parameters (they change the container bytes and are stored in it).
+ *   chunk_bytes     power of two, 256 .. 4 MiB (paper §V-A default: 256 KiB)
+ *   substream_syms  S, power of two, g .. 4096, with chunk_bytes/B/S <= 4096
+ *   group           g, 1, 2, 4 or 8
+ *   max_code_len    L, 8 .. 11
+ *   policy[k]       zipnn_policy of stream k (k < B) */
+typedef struct {
+    uint32_t chunk_bytes;
+    uint16_t substream_syms;
+    uint8_t group;
+    uint8_t max_code_len;
+    uint8_t policy[4];
+} zipnn_params;
+
+/* Summary of a container, filled by zipnn_inspect from host bytes. */
+typedef struct {
+    int dtype;
+    int B;
+    uint64_t n_elems;
+    uint64_t total_bytes;
+    uint32_t n_chunks;
+    uint32_t chunk_bytes;
+    uint32_t S, g, L;
+    int is_delta;
+    uint64_t bytes_by_mode[3];    /* payload bytes in RAW, HUF, RLE entries */
+    uint64_t entries_by_mode[3];  /* entry counts per mode */
+} zipnn_info;
+
+typedef struct zipnn_ctx_s* zipnn_ctx;
+
+/* Create a context on HIP device `hip_device`.  The context owns device
+ * scratch (grown on demand by compress), a sticky device-side status word and
+ * pinned host staging.  Returns ZIPNN_OK and *out, or a negative status. */
+int zipnn_ctx_create(int hip_device, zipnn_ctx* out);
+
+/* Release everything the context owns.  NULL is ignored. */
+void zipnn_ctx_destroy(zipnn_ctx ctx);
+
+/* Wait for `stream`, then return the sticky status set by device-side checks
+ * since the last clear (ZIPNN_OK, ZIPNN_E_FORMAT, ZIPNN_E_CORRUPT or
+ * ZIPNN_E_NOSPACE); the first error recorded wins.  clear != 0 resets it. */
+int zipnn_ctx_status(zipnn_ctx ctx, void* stream, int clear);
+
+/* Fill *out with the defaults for `dtype`: 256 KiB chunks (paper §V-A),
+ * S = 512, g = 4, L = 11, AUTO on every stream. */
+void zipnn_default_params(int dtype, zipnn_params* out);
+
+/* Check params for `dtype`; ZIPNN_OK or ZIPNN_E_INVAL. */
+int zipnn_check_params(int dtype, const zipnn_params* p);
+
+/* Upper bound of the container size for n_elems of dtype under p (0 on bad
+ * arguments). */
+uint64_t zipnn_compress_bound(int dtype, uint64_t n_elems, const zipnn_params* p);
+
+/* Compress n_elems elements of `dtype` at device pointer src (XORed first
+ * with device `base` of the same size when base != NULL, paper §IV-B) into
+ * device buffer dst of dst_cap bytes.  Blocking: returns after the container
+ * is complete on `stream`, with its size in *dst_len (host pointer).
+ * ZIPNN_E_NOSPACE if dst_cap is too small (dst contents then undefined). */
+int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n_elems, const void* base,
+                   const zipnn_params* p, void* dst, uint64_t dst_cap, uint64_t* dst_len, void* stream);
+
+/* Decompress the container at device pointer src (src_len bytes) into device
+ * buffer dst (dst_cap bytes; needs n_elems*B), XORing with device `base`
+ * (n_elems*B bytes) for a delta container.  Asynchronous on `stream`: the
+ * header, map, tables and bitstreams are validated on the device, and any
+ * inconsistency is recorded in the context's sticky status (read it with
+ * zipnn_ctx_status); nothing outside dst[0, n_elems*B) is ever written, but
+ * after an error dst holds unspecified bytes. */
+int zipnn_decompress(zipnn_ctx ctx, const void* src, uint64_t src_len, const void* base, void* dst,
+                     uint64_t dst_cap, void* stream);
+
+/* Validate a container's header and map from HOST memory (len bytes: at
+ * least the header and the map) and summarise it in *out. */
+int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out);
+
+/* Static English text for a status code. */
+const char* zipnn_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZIPNN_H */

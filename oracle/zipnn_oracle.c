@@ -76,6 +76,8 @@ int orc_check_params(int B, uint32_t chunk_bytes, uint32_t S, uint32_t g, uint32
     if (!is_pow2(g) || g > ORC_MAX_G) return ORC_E_INVAL;
     if (!is_pow2(S) || S < g || S > ORC_MAX_S) return ORC_E_INVAL;
     if (L < ORC_MIN_L || L > ORC_MAX_L) return ORC_E_INVAL;
+    /* sub-streams per chunk: per stream, and over all B streams */
+    if (chunk_bytes / (uint32_t)B / S > ORC_MAX_W || chunk_bytes / S > ORC_MAX_BW) return ORC_E_INVAL;
     return ORC_OK;
 }
 

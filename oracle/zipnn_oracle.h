@@ -45,9 +45,11 @@ enum { ORC_FLAG_DELTA = 1 };
 #define ORC_MIN_CHUNK 256u
 #define ORC_MAX_CHUNK (4u << 20)
 #define ORC_MAX_S 4096u
-#define ORC_MAX_G 16u
+#define ORC_MAX_G 8u
+#define ORC_MAX_W 4096u
+#define ORC_MAX_BW 8192u
 #define ORC_MIN_L 8u
-#define ORC_MAX_L 12u
+#define ORC_MAX_L 11u
 
 typedef struct {
     int dtype, B;

@@ -1,0 +1,132 @@
+// Internal declarations shared by the HIP kernels and the host runtime of the
+// gfx950 ZipNN codec.  The container layout is documented in include/zipnn.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "zipnn.h"
+
+namespace zipnn {
+
+constexpr uint32_t kMinChunk = 256;
+constexpr uint32_t kMaxChunk = 4u << 20;
+constexpr uint32_t kMaxS = 4096;
+constexpr uint32_t kMaxG = 8;
+constexpr uint32_t kMinL = 8;
+constexpr uint32_t kMaxL = 11;
+constexpr uint32_t kMaxW = 4096;           // sub-streams per chunk and stream
+constexpr uint32_t kMaxBW = 8192;          // sub-streams per chunk over all B streams
+constexpr uint32_t kLutSize = 1u << kMaxL;  // decode table entries per stream
+constexpr uint32_t kFlagDelta = 1;
+constexpr int kModeRaw = 0, kModeHuf = 1, kModeRle = 2;
+constexpr int kBlock = 256;                 // threads per workgroup (4 waves)
+
+__host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15u) & ~uint64_t(15); }
+__host__ __device__ inline bool pow2(uint64_t v) { return v && !(v & (v - 1)); }
+
+__host__ __device__ inline int dtype_bytes(int dt)
+{
+    return dt == ZIPNN_BF16 || dt == ZIPNN_FP16 ? 2 : dt == ZIPNN_FP32 ? 4 : dt == ZIPNN_FP8_E4M3 || dt == ZIPNN_U8 ? 1 : 0;
+}
+
+__host__ __device__ inline int check_params(int B, uint32_t chunk, uint32_t S, uint32_t g, uint32_t L)
+{
+    if (!B || !pow2(chunk) || chunk < kMinChunk || chunk > kMaxChunk) return ZIPNN_E_INVAL;
+    if (!pow2(g) || g > kMaxG || !pow2(S) || S < g || S > kMaxS) return ZIPNN_E_INVAL;
+    if (L < kMinL || L > kMaxL) return ZIPNN_E_INVAL;
+    if (chunk / uint32_t(B) / S > kMaxW || chunk / S > kMaxBW) return ZIPNN_E_INVAL;
+    return ZIPNN_OK;
+}
+
+// Size of the part of a HUF payload that precedes the bitstream.
+__host__ __device__ inline uint32_t huf_head(uint32_t W) { return uint32_t(align16(128u + 2u * W)); }
+
+struct Header {
+    uint64_t n, total, payload_base;
+    uint32_t dtype, B, chunk, S, g, L, flags, n_chunks, E;
+};
+
+// Parse and validate a 64-byte header (16-byte aligned words).  Usable on the
+// host and on the device.
+__host__ __device__ inline int parse_header(const uint32_t* w, uint64_t src_len, Header& h)
+{
+    if (w[0] != 0x314E4E5Au) return ZIPNN_E_FORMAT;            // "ZNN1"
+    if ((w[1] & 0xFFFFu) != 1u) return ZIPNN_E_FORMAT;
+    h.dtype = (w[1] >> 16) & 0xFF;
+    h.B = w[1] >> 24;
+    h.n = uint64_t(w[2]) | (uint64_t(w[3]) << 32);
+    h.chunk = w[4];
+    h.S = w[5] & 0xFFFF;
+    h.g = (w[5] >> 16) & 0xFF;
+    h.L = w[5] >> 24;
+    h.flags = w[6];
+    h.n_chunks = w[7];
+    h.total = uint64_t(w[8]) | (uint64_t(w[9]) << 32);
+    if (dtype_bytes(int(h.dtype)) != int(h.B) || h.B == 0) return ZIPNN_E_FORMAT;
+    if (check_params(int(h.B), h.chunk, h.S, h.g, h.L) != ZIPNN_OK) return ZIPNN_E_FORMAT;
+    if (h.flags & ~kFlagDelta) return ZIPNN_E_FORMAT;
+    for (int i = 11; i < 16; i++)
+        if (w[i]) return ZIPNN_E_FORMAT;
+    h.E = h.chunk / h.B;
+    if ((h.n + h.E - 1) / h.E != h.n_chunks) return ZIPNN_E_FORMAT;
+    h.payload_base = 64 + 16ull * h.n_chunks * h.B;
+    if (h.total < h.payload_base || h.total > src_len) return ZIPNN_E_FORMAT;
+    return ZIPNN_OK;
+}
+
+// One tensor of a (possibly batched) decode.
+struct DecDesc {
+    const uint8_t* src;
+    uint64_t src_len;
+    const uint8_t* base;   // XOR base or nullptr
+    uint8_t* dst;
+    uint64_t dst_cap;
+};
+
+// One tensor of a (possibly batched) encode.
+struct EncDesc {
+    const uint8_t* src;
+    const uint8_t* base;
+    uint8_t* dst;          // container
+    uint64_t dst_cap;
+    uint64_t n;
+    uint32_t chunk0;       // index of this tensor's first chunk in the scratch arrays
+    uint32_t n_chunks;
+};
+
+// Per-(chunk, stream) result of the analysis kernel.
+struct EncEntry {
+    uint32_t bytes;        // payload bytes
+    uint8_t mode;
+    uint8_t rle;
+    uint16_t pad;
+};
+
+// Encode-side code table entry: canonical code | length << 16.
+using CodeWord = uint32_t;
+
+struct EncParams {
+    uint32_t dtype, B, chunk, S, g, L, flags;
+    uint8_t policy[4];
+};
+
+// Launchers (decode.hip / encode.hip).  A null descriptor array means "the
+// single tensor passed by value".
+hipError_t launch_decode_one(const DecDesc& one, int* d_status, int grid, hipStream_t s);
+hipError_t launch_decode_batch(const DecDesc* d_descs, int n_desc, uint64_t* d_item_prefix, int* d_status, int grid,
+                               hipStream_t s);
+hipError_t launch_clear_status(int* d_status, hipStream_t s);
+int decode_grid_size(int device);
+
+hipError_t launch_analyze(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
+                          uint32_t total_chunks, const EncParams& p, EncEntry* entries, CodeWord* codes,
+                          hipStream_t s);
+hipError_t launch_place(const EncDesc& one, const EncDesc* d_descs, int n_desc, const EncParams& p,
+                        const EncEntry* entries, uint64_t* d_offsets /* per entry */,
+                        uint64_t* d_totals /* per desc */, hipStream_t s);
+hipError_t launch_pack(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
+                       uint32_t total_chunks, const EncParams& p, const EncEntry* entries, const CodeWord* codes,
+                       const uint64_t* offsets, const uint64_t* d_totals, hipStream_t s);
+
+}  // namespace zipnn

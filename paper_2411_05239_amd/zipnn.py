@@ -1,0 +1,232 @@
+"""ctypes binding of ``include/zipnn.h`` (libzipnn_hip.so).
+
+The ``zipnn_*`` functions mirror the C ABI one to one and only marshal
+arguments; every step of compression and decompression runs in the HIP
+kernels of the library.  ``Codec`` adds tensor-level conveniences on top (it
+allocates device buffers with PyTorch and passes their pointers and the
+current HIP stream).  There is no fallback: if the library is missing or no
+GPU is visible, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzipnn_hip.so")
+
+ZIPNN_OK, ZIPNN_E_INVAL, ZIPNN_E_FORMAT, ZIPNN_E_CORRUPT = 0, -1, -2, -3
+ZIPNN_E_NOSPACE, ZIPNN_E_NOMEM, ZIPNN_E_HIP, ZIPNN_E_BUSY = -4, -5, -6, -7
+ZIPNN_BF16, ZIPNN_FP16, ZIPNN_FP32, ZIPNN_FP8_E4M3, ZIPNN_U8 = 1, 2, 3, 4, 5
+ZIPNN_AUTO, ZIPNN_HUF, ZIPNN_RAW = 0, 1, 2
+WIDTH = {ZIPNN_BF16: 2, ZIPNN_FP16: 2, ZIPNN_FP32: 4, ZIPNN_FP8_E4M3: 1, ZIPNN_U8: 1}
+
+# every symbol declared in include/zipnn.h
+EXPORTS = [
+    "zipnn_strerror", "zipnn_ctx_create", "zipnn_ctx_destroy", "zipnn_ctx_status", "zipnn_default_params",
+    "zipnn_check_params", "zipnn_compress_bound", "zipnn_compress", "zipnn_decompress", "zipnn_inspect",
+]
+
+
+class ZipnnError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        self.code = code
+        msg = lib().zipnn_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} ({code})" if where else f"{msg} ({code})")
+
+
+class zipnn_params(ctypes.Structure):
+    _fields_ = [("chunk_bytes", ctypes.c_uint32), ("substream_syms", ctypes.c_uint16),
+                ("group", ctypes.c_uint8), ("max_code_len", ctypes.c_uint8), ("policy", ctypes.c_uint8 * 4)]
+
+    def __repr__(self):
+        return (f"zipnn_params(chunk_bytes={self.chunk_bytes}, S={self.substream_syms}, g={self.group}, "
+                f"L={self.max_code_len}, policy={list(self.policy)})")
+
+
+class zipnn_info(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("B", ctypes.c_int), ("n_elems", ctypes.c_uint64),
+                ("total_bytes", ctypes.c_uint64), ("n_chunks", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32),
+                ("S", ctypes.c_uint32), ("g", ctypes.c_uint32), ("L", ctypes.c_uint32), ("is_delta", ctypes.c_int),
+                ("bytes_by_mode", ctypes.c_uint64 * 3), ("entries_by_mode", ctypes.c_uint64 * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libzipnn_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2411_05239_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+        P = ctypes.POINTER
+        L.zipnn_strerror.argtypes, L.zipnn_strerror.restype = [i32], ctypes.c_char_p
+        L.zipnn_ctx_create.argtypes, L.zipnn_ctx_create.restype = [i32, P(vp)], i32
+        L.zipnn_ctx_destroy.argtypes, L.zipnn_ctx_destroy.restype = [vp], None
+        L.zipnn_ctx_status.argtypes, L.zipnn_ctx_status.restype = [vp, vp, i32], i32
+        L.zipnn_default_params.argtypes, L.zipnn_default_params.restype = [i32, P(zipnn_params)], None
+        L.zipnn_check_params.argtypes, L.zipnn_check_params.restype = [i32, P(zipnn_params)], i32
+        L.zipnn_compress_bound.argtypes, L.zipnn_compress_bound.restype = [i32, u64, P(zipnn_params)], u64
+        L.zipnn_compress.argtypes = [vp, vp, i32, u64, vp, P(zipnn_params), vp, u64, P(u64), vp]
+        L.zipnn_compress.restype = i32
+        L.zipnn_decompress.argtypes, L.zipnn_decompress.restype = [vp, vp, u64, vp, vp, u64, vp], i32
+        L.zipnn_inspect.argtypes, L.zipnn_inspect.restype = [vp, u64, P(zipnn_info)], i32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise ZipnnError(rc, where)
+    return rc
+
+
+# ---------------------------------------------------------------- C ABI mirror
+
+def zipnn_strerror(code: int) -> str:
+    return lib().zipnn_strerror(code).decode()
+
+
+def zipnn_ctx_create(device: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().zipnn_ctx_create(device, ctypes.byref(h)), "zipnn_ctx_create")
+    return h.value
+
+
+def zipnn_ctx_destroy(ctx: int) -> None:
+    lib().zipnn_ctx_destroy(ctx)
+
+
+def zipnn_ctx_status(ctx: int, stream: int, clear: bool = False) -> int:
+    return lib().zipnn_ctx_status(ctx, stream, 1 if clear else 0)
+
+
+def zipnn_default_params(dtype: int) -> zipnn_params:
+    p = zipnn_params()
+    lib().zipnn_default_params(dtype, ctypes.byref(p))
+    return p
+
+
+def zipnn_check_params(dtype: int, p: zipnn_params) -> int:
+    return lib().zipnn_check_params(dtype, ctypes.byref(p))
+
+
+def zipnn_compress_bound(dtype: int, n: int, p: zipnn_params) -> int:
+    return lib().zipnn_compress_bound(dtype, n, ctypes.byref(p))
+
+
+def zipnn_compress(ctx, src, dtype, n, base, p, dst, dst_cap, stream) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().zipnn_compress(ctx, src, dtype, n, base, ctypes.byref(p), dst, dst_cap, ctypes.byref(out), stream),
+           "zipnn_compress")
+    return out.value
+
+
+def zipnn_decompress(ctx, src, src_len, base, dst, dst_cap, stream) -> None:
+    _check(lib().zipnn_decompress(ctx, src, src_len, base, dst, dst_cap, stream), "zipnn_decompress")
+
+
+def zipnn_inspect(host_bytes: bytes) -> zipnn_info:
+    info = zipnn_info()
+    buf = ctypes.create_string_buffer(bytes(host_bytes), len(host_bytes))
+    _check(lib().zipnn_inspect(buf, len(host_bytes), ctypes.byref(info)), "zipnn_inspect")
+    return info
+
+
+# ---------------------------------------------------------------- tensor helpers
+
+def torch_dtype_code(dt) -> int:
+    import torch
+
+    table = {torch.bfloat16: ZIPNN_BF16, torch.float16: ZIPNN_FP16, torch.float32: ZIPNN_FP32,
+             torch.float8_e4m3fn: ZIPNN_FP8_E4M3, torch.uint8: ZIPNN_U8, torch.int8: ZIPNN_U8}
+    if dt not in table:
+        raise ValueError(f"unsupported dtype {dt}")
+    return table[dt]
+
+
+def make_params(dtype: int, chunk_bytes: int | None = None, S: int | None = None, g: int | None = None,
+                L: int | None = None, policy=None) -> zipnn_params:
+    p = zipnn_default_params(dtype)
+    if chunk_bytes is not None:
+        p.chunk_bytes = chunk_bytes
+        if S is None:  # keep 256 sub-streams per full chunk
+            p.substream_syms = max(1, min(4096, chunk_bytes // WIDTH[dtype] // 256))
+    if S is not None:
+        p.substream_syms = S
+    if g is not None:
+        p.group = g
+    if L is not None:
+        p.max_code_len = L
+    if policy is not None:
+        for k, v in enumerate(policy):
+            p.policy[k] = v
+    p.substream_syms = max(p.substream_syms, p.group)
+    return p
+
+
+class Codec:
+    """Tensor-level front end of one zipnn context on a HIP device."""
+
+    def __init__(self, device: int = 0):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the zipnn codec runs only on the GPU")
+        self.device = device
+        self.ctx = zipnn_ctx_create(device)
+
+    def close(self):
+        if self.ctx:
+            zipnn_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stream():
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+
+    def compress(self, x, params: zipnn_params | None = None, base=None, out=None):
+        """Compress device tensor x -> uint8 device tensor holding the container."""
+        import torch
+
+        dt = torch_dtype_code(x.dtype)
+        x = x.contiguous()
+        if base is not None:
+            base = base.contiguous()
+            assert base.dtype == x.dtype and base.numel() == x.numel() and base.device == x.device
+        p = params or zipnn_default_params(dt)
+        n = x.numel()
+        cap = zipnn_compress_bound(dt, n, p)
+        if cap == 0:
+            raise ZipnnError(ZIPNN_E_INVAL, "params")
+        if out is None or out.numel() < cap:
+            out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        ln = zipnn_compress(self.ctx, x.data_ptr(), dt, n, base.data_ptr() if base is not None else None, p,
+                            out.data_ptr(), out.numel(), self._stream())
+        return out[:ln]
+
+    def decompress(self, c, out, base=None, check: bool = True):
+        """Decompress container c (uint8 device tensor) into `out` (any dtype,
+        n*B bytes).  With check=True, synchronises and raises on a device-side
+        error."""
+        zipnn_decompress(self.ctx, c.data_ptr(), c.numel(), base.data_ptr() if base is not None else None,
+                         out.data_ptr(), out.numel() * out.element_size(), self._stream())
+        if check:
+            st = zipnn_ctx_status(self.ctx, self._stream(), clear=True)
+            if st != ZIPNN_OK:
+                raise ZipnnError(st, "zipnn_decompress (device)")
+        return out
+
+    def status(self, clear: bool = True) -> int:
+        return zipnn_ctx_status(self.ctx, self._stream(), clear)

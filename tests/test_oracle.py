@@ -235,7 +235,7 @@ def test_roundtrip_and_spec_agreement(oracle_lib, dtype, n_extra):
         w = raw.view(np.uint32)
         w[: len(SPECIAL_FP32)] = SPECIAL_FP32
     for policy in [(oracle.AUTO,) * 4, (oracle.HUF,) * 4, (oracle.RAW, oracle.HUF, oracle.AUTO, oracle.HUF)]:
-        for S, gg in [(64, 4), (16, 1), (128, 16)]:
+        for S, gg in [(64, 4), (16, 1), (128, 8)]:
             c = oracle.compress(raw, dtype, chunk_bytes=chunk, S=S, g=gg, policy=policy[:B])
             assert np.array_equal(oracle.decompress(c), raw)
             assert spec.compress(raw, dtype, chunk_bytes=chunk, S=S, g=gg, policy=policy[:B]) == c.tobytes()
@@ -413,7 +413,8 @@ def test_truncated_and_small_output_rejected(oracle_lib):
 def test_invalid_params_rejected(oracle_lib):
     x = np.zeros(100, np.uint16)
     for kw in [dict(chunk_bytes=1000), dict(chunk_bytes=128), dict(S=3), dict(g=3), dict(S=2, g=4),
-               dict(L=7), dict(L=13), dict(S=8192), dict(g=32, S=64)]:
+               dict(L=7), dict(L=12), dict(S=8192), dict(g=16, S=64),
+               dict(chunk_bytes=1 << 20, S=64)]:
         with pytest.raises(oracle.OracleError) as ei:
             oracle.compress(x, oracle.BF16, **kw)
         assert ei.value.code == oracle.E_INVAL
