@@ -29,10 +29,15 @@
  *     2 RLE) | u8 RLE value | u16 0
  *   payloads: in map order, each at a 16-byte aligned offset, zero padded.
  *     RAW = the m stream bytes.  RLE = nothing.  HUF = 128 B of 4-bit code
- *     lengths | u16 bit length of each of the W = ceil(m/S) sub-streams |
- *     zero pad to align16(128+2W) | the sub-streams, bit-contiguous, LSB-first,
- *     canonical codes written most significant bit first; group q of g
- *     consecutive symbols belongs to sub-stream q mod W.
+ *     lengths | u32 word count of each of the NG = ceil(W/64) lane groups |
+ *     zero pad to align16(128+4*NG) | the lane groups' word streams.
+ *   Huffman layout: W = ceil(m/S) sub-streams; group q of g consecutive
+ *   symbols belongs to sub-stream q mod W; sub-stream 64j+l is lane l of lane
+ *   group j.  A sub-stream's canonical codes (most significant bit first,
+ *   packed LSB-first) are cut into 32-bit words, and a lane group's words are
+ *   stored in the order its 64 lanes take them when decoding in lock-step:
+ *   in round r every lane with symbols left takes its next word if it holds
+ *   fewer than 2L bits (lanes in order), then decodes its symbols 2r, 2r+1.
  *   Stream k of element j is byte B-1-k of the little-endian word.  Codes are
  *   optimal among prefix codes with lengths <= L (package-merge, ties by
  *   (frequency, symbol)) and assigned in canonical (length, symbol) order.
@@ -82,7 +87,8 @@ typedef enum {
 /* Format parameters (they change the container bytes and are stored in it).
  *   chunk_bytes     power of two, 256 .. 4 MiB (paper §V-A default: 256 KiB)
  *   substream_syms  S, power of two, g .. 4096, with chunk_bytes/B/S <= 4096
- *   group           g, 1, 2, 4 or 8
+ *                   and chunk_bytes/S <= 8192
+ *   group           g, 2, 4 or 8
  *   max_code_len    L, 8 .. 11
  *   policy[k]       zipnn_policy of stream k (k < B) */
 typedef struct {
@@ -123,7 +129,8 @@ void zipnn_ctx_destroy(zipnn_ctx ctx);
 int zipnn_ctx_status(zipnn_ctx ctx, void* stream, int clear);
 
 /* Fill *out with the defaults for `dtype`: 256 KiB chunks (paper §V-A),
- * S = 512, g = 4, L = 11, AUTO on every stream. */
+ * S = chunk elements / 256 (so a chunk has 256 sub-streams: 512 for 2-byte,
+ * 256 for 4-byte, 1024 for 1-byte types), g = 4, L = 11, AUTO everywhere. */
 void zipnn_default_params(int dtype, zipnn_params* out);
 
 /* Check params for `dtype`; ZIPNN_OK or ZIPNN_E_INVAL. */
@@ -143,13 +150,23 @@ int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n_elems, 
 
 /* Decompress the container at device pointer src (src_len bytes) into device
  * buffer dst (dst_cap bytes; needs n_elems*B), XORing with device `base`
- * (n_elems*B bytes) for a delta container.  Asynchronous on `stream`: the
- * header, map, tables and bitstreams are validated on the device, and any
- * inconsistency is recorded in the context's sticky status (read it with
- * zipnn_ctx_status); nothing outside dst[0, n_elems*B) is ever written, but
- * after an error dst holds unspecified bytes. */
+ * (n_elems*B bytes) for a delta container (paper §IV-B).  The 64-byte header
+ * is copied to the host first (ordered on `stream`, the call waits for it) to
+ * pick the kernel; header errors, a missing or unexpected base and a small
+ * dst_cap are returned directly.  The decode itself is then queued on
+ * `stream`: the map, tables and word streams are validated on the device and
+ * any inconsistency is recorded in the context's sticky status (read it with
+ * zipnn_ctx_status).  Nothing outside dst[0, n_elems*B) is written; after an
+ * error dst holds unspecified bytes. */
 int zipnn_decompress(zipnn_ctx ctx, const void* src, uint64_t src_len, const void* base, void* dst,
                      uint64_t dst_cap, void* stream);
+
+/* As zipnn_decompress, for a caller that already holds a host copy of the
+ * container's 64-byte header (`header_host`): nothing waits, the call only
+ * queues the decode on `stream`.  The device checks its own header against
+ * the one given and reports a mismatch as ZIPNN_E_FORMAT in the status. */
+int zipnn_decompress_async(zipnn_ctx ctx, const void* header_host, const void* src, uint64_t src_len,
+                           const void* base, void* dst, uint64_t dst_cap, void* stream);
 
 /* Validate a container's header and map from HOST memory (len bytes: at
  * least the header and the map) and summarise it in *out. */

@@ -70,7 +70,7 @@ def lib():
         L.orc_compress.restype = i32
         L.orc_decompress.argtypes = [u8p, u64, u8p, u8p, u64, i32]
         L.orc_decompress.restype = i32
-        L.orc_compress_bound.argtypes = [i32, u64, u32]
+        L.orc_compress_bound.argtypes = [i32, u64, u32, u32]
         L.orc_compress_bound.restype = u64
         L.orc_package_merge.argtypes = [u8p, i32, u8p]
         L.orc_package_merge.restype = i32
@@ -109,7 +109,7 @@ def compress(x, dtype: int, *, base=None, chunk_bytes: int = 262144, S: int = 51
     if base is not None:
         bb = as_bytes(base)
         assert bb.size == xb.size
-    cap = lib().orc_compress_bound(dtype, n, chunk_bytes)
+    cap = lib().orc_compress_bound(dtype, n, chunk_bytes, S)
     out = np.zeros(max(cap, 64), dtype=np.uint8)
     pol = np.array(list(policy) + [0] * (4 - len(policy)), dtype=np.uint8)
     dlen = ctypes.c_uint64(0)

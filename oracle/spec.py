@@ -99,6 +99,37 @@ def _a16(x: int) -> int:
     return (x + 15) // 16 * 16
 
 
+LANES = 64
+
+
+def _substreams(m: int, S: int, g: int) -> list[list[int]]:
+    """Element indices of each sub-stream: group q of g symbols -> q mod W."""
+    W = -(-m // S)
+    subs = [[] for _ in range(W)]
+    for q in range(-(-m // g)):
+        subs[q % W].extend(range(q * g, min(q * g + g, m)))
+    return subs
+
+
+def _request_schedule(n_syms: list[int], lens_of, L: int) -> list[list[int]]:
+    """For one lane group: per round, the lanes (ascending) that take a word.
+    A lane with symbols left in round r takes a word when it buffers < 2L bits,
+    then consumes the code lengths of its symbols 2r and 2r+1."""
+    buffered = [0] * len(n_syms)
+    schedule = []
+    for r in range(max((n + 1) // 2 for n in n_syms)):
+        takers = []
+        for lane, n in enumerate(n_syms):
+            if 2 * r >= n:
+                continue
+            if buffered[lane] < 2 * L:
+                takers.append(lane)
+                buffered[lane] += 32
+            buffered[lane] -= sum(lens_of(lane, t) for t in (2 * r, 2 * r + 1) if t < n)
+        schedule.append(takers)
+    return schedule
+
+
 def encode_stream(sym: np.ndarray, S: int, g: int, L: int, policy: int) -> tuple[int, int, bytes]:
     """-> (mode, rle value, payload bytes)"""
     m = len(sym)
@@ -109,28 +140,38 @@ def encode_stream(sym: np.ndarray, S: int, g: int, L: int, policy: int) -> tuple
     if len(present) == 1:
         return MODE_RLE, present[0], b""
     lengths = pm_lengths({s: int(counts[s]) for s in present}, L)
-    T = sum(int(counts[s]) * lengths[s] for s in present)
-    W = -(-m // S)
-    H = _a16(128 + 2 * W)
-    if policy == AUTO and H + (T + 7) // 8 >= m:
-        return MODE_RAW, 0, sym.tobytes()
     codes = canonical(lengths)
-    bits: list[int] = []
-    sub_len = []
-    G = -(-m // g)
-    for w in range(W):
-        before = len(bits)
-        for q in range(w, G, W):
-            for j in range(q * g, min(q * g + g, m)):
-                c, l = codes[int(sym[j])]
-                bits.extend((c >> (l - 1 - b)) & 1 for b in range(l))
-        sub_len.append(len(bits) - before)
+    subs = _substreams(m, S, g)
+    W = len(subs)
+    NG = -(-W // LANES)
+    H = _a16(128 + 4 * NG)
+    counts_out, words_out = [], []
+    for j in range(NG):
+        group = subs[LANES * j: LANES * j + LANES]
+        # each lane's bit string (as a Python int, bit i = i-th stream bit)
+        lane_words = []
+        for idx in group:
+            acc, nbits = 0, 0
+            for e in idx:
+                c, l = codes[int(sym[e])]
+                for b in range(l):
+                    acc |= ((c >> (l - 1 - b)) & 1) << nbits
+                    nbits += 1
+            lane_words.append([(acc >> (32 * k)) & 0xFFFFFFFF for k in range(nbits // 32 + 3)])
+        sched = _request_schedule([len(x) for x in group], lambda lane, t: lengths[int(sym[group[lane][t]])], L)
+        nxt = [0] * len(group)
+        stream = []
+        for takers in sched:
+            for lane in takers:
+                stream.append(lane_words[lane][nxt[lane]])
+                nxt[lane] += 1
+        counts_out.append(len(stream))
+        words_out.extend(stream)
     table = bytes(lengths.get(2 * i, 0) | (lengths.get(2 * i + 1, 0) << 4) for i in range(128))
-    lens = b"".join(struct.pack("<H", x) for x in sub_len)
-    stream = bytearray((len(bits) + 7) // 8)
-    for i, b in enumerate(bits):
-        stream[i // 8] |= b << (i % 8)
-    payload = table + lens + bytes(H - 128 - 2 * W) + bytes(stream)
+    head = table + struct.pack(f"<{NG}I", *counts_out)
+    payload = head + bytes(H - len(head)) + struct.pack(f"<{len(words_out)}I", *words_out)
+    if policy == AUTO and len(payload) >= m:
+        return MODE_RAW, 0, sym.tobytes()
     return MODE_HUF, 0, payload
 
 
@@ -196,24 +237,38 @@ def _decode_huf(p: bytes, m: int, S: int, g: int, L: int) -> np.ndarray:
             if l:
                 lengths[s] = l
     book = {(l, c): s for s, (c, l) in canonical(lengths).items()}
-    W = -(-m // S)
-    sub_len = [struct.unpack("<H", p[128 + 2 * w: 130 + 2 * w])[0] for w in range(W)]
-    stream = p[_a16(128 + 2 * W):]
-    pos = 0
+    subs = _substreams(m, S, g)
+    W = len(subs)
+    NG = -(-W // LANES)
+    H = _a16(128 + 4 * NG)
+    nwords = struct.unpack(f"<{NG}I", p[128:128 + 4 * NG])
+    words = struct.unpack(f"<{(len(p) - H) // 4}I", p[H:])
     out = np.zeros(m, dtype=np.uint8)
-    G = -(-m // g)
-    for w in range(W):
-        end = pos + sub_len[w]
-        for q in range(w, G, W):
-            for j in range(q * g, min(q * g + g, m)):
-                c, l = 0, 0
-                while (l, c) not in book:
-                    if pos >= end or l >= L:
-                        raise SpecError("bad code")
-                    c = (c << 1) | ((stream[pos // 8] >> (pos % 8)) & 1)
-                    l += 1
+    pos = 0
+    for j in range(NG):
+        group = subs[LANES * j: LANES * j + LANES]
+        bits = [0] * len(group)       # received bits, as an int per lane
+        have = [0] * len(group)       # received bit count
+        used = [0] * len(group)       # consumed bit count
+        for r in range(max((len(x) + 1) // 2 for x in group)):
+            for lane, idx in enumerate(group):
+                if 2 * r >= len(idx):
+                    continue
+                if have[lane] - used[lane] < 2 * L:
+                    bits[lane] |= words[pos] << have[lane]
+                    have[lane] += 32
                     pos += 1
-                out[j] = book[(l, c)]
-        if pos != end:
-            raise SpecError("sub-stream length")
+                for t in (2 * r, 2 * r + 1):
+                    if t >= len(idx):
+                        break
+                    c, l = 0, 0
+                    while (l, c) not in book:
+                        if l >= L:
+                            raise SpecError("bad code")
+                        c = (c << 1) | ((bits[lane] >> used[lane]) & 1)
+                        used[lane] += 1
+                        l += 1
+                    out[idx[t]] = book[(l, c)]
+        if pos != sum(nwords[: j + 1]):
+            raise SpecError("word count")
     return out

@@ -73,7 +73,7 @@ int orc_check_params(int B, uint32_t chunk_bytes, uint32_t S, uint32_t g, uint32
 {
     if (B == 0) return ORC_E_INVAL;
     if (!is_pow2(chunk_bytes) || chunk_bytes < ORC_MIN_CHUNK || chunk_bytes > ORC_MAX_CHUNK) return ORC_E_INVAL;
-    if (!is_pow2(g) || g > ORC_MAX_G) return ORC_E_INVAL;
+    if (!is_pow2(g) || g < ORC_MIN_G || g > ORC_MAX_G) return ORC_E_INVAL;
     if (!is_pow2(S) || S < g || S > ORC_MAX_S) return ORC_E_INVAL;
     if (L < ORC_MIN_L || L > ORC_MAX_L) return ORC_E_INVAL;
     /* sub-streams per chunk: per stream, and over all B streams */
@@ -230,14 +230,6 @@ static void put_code(uint8_t* buf, uint64_t* pos, uint32_t code, int len)
     }
 }
 
-static int get_bit(const uint8_t* buf, uint64_t nbits, uint64_t* pos)
-{
-    if (*pos >= nbits) return -1;
-    int bit = (buf[*pos >> 3] >> (*pos & 7)) & 1;
-    (*pos)++;
-    return bit;
-}
-
 /* ------------------------------------------------------- per-stream coding */
 
 typedef struct {
@@ -247,7 +239,99 @@ typedef struct {
     uint8_t* payload;   /* malloc'd (NULL for RLE) */
 } stream_out;
 
-static uint32_t huf_header_bytes(uint64_t W) { return (uint32_t)align16(128 + 2 * W); }
+/* Bytes of a HUF payload before its word streams: the nibble table, one u32
+ * word count per lane group, zero padding to 16. */
+static uint64_t huf_head_bytes(uint64_t W)
+{
+    return align16(128 + 4 * ((W + ORC_LANES - 1) / ORC_LANES));
+}
+
+/* Element indices (within the chunk) of the symbols of sub-stream w, in
+ * order: the groups q = w, w+W, w+2W, ... of g consecutive symbols, the last
+ * group of the chunk possibly shorter.  Returns how many. */
+static uint64_t substream_symbols(uint64_t m, uint64_t W, uint64_t g, uint64_t w, uint64_t* idx)
+{
+    uint64_t G = (m + g - 1) / g, n = 0;
+    for (uint64_t q = w; q < G; q += W) {
+        uint64_t j_end = (q + 1) * g < m ? (q + 1) * g : m;
+        for (uint64_t j = q * g; j < j_end; j++) idx[n++] = j;
+    }
+    return n;
+}
+
+/* Build the HUF payload of m symbols with the given code lengths.
+ *
+ * Sub-stream w holds the codes of its symbols back to back; its bit sequence
+ * is cut into 32-bit words (word k = bits 32k..32k+31, zero past the end).
+ * The sub-streams are taken 64 at a time (a lane group: sub-stream 64j+l is
+ * lane l of group j) and the words of one lane group are stored in the order
+ * in which a decoder that runs its 64 lanes in lock-step asks for them:
+ * in round r every lane that still has symbols decodes its symbols 2r and
+ * 2r+1; right before that, a lane whose bit buffer holds fewer than 2L bits
+ * takes its next word.  Within a round the lanes take words in lane order.
+ * A lane may take one word past its last code bit (all zero). */
+static int huf_payload(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g, int L, const uint8_t len[256],
+                       stream_out* out)
+{
+    uint32_t code[256];
+    orc_canonical_codes(len, L, code);
+    uint64_t W = (m + S - 1) / S;
+    uint64_t NG = (W + ORC_LANES - 1) / ORC_LANES;
+    uint64_t H = huf_head_bytes(W);
+    uint64_t G = (m + g - 1) / g;
+    uint64_t nmax = ((G + W - 1) / W) * g;                    /* symbols of the longest sub-stream */
+    uint64_t lane_bytes = (nmax * (uint64_t)L + 7) / 8 + 8;   /* room for one extra zero word */
+    uint64_t max_words = W * ((nmax * (uint64_t)L + 31) / 32 + 2);
+    uint8_t* p = (uint8_t*)calloc(H + 4 * max_words, 1);
+    uint64_t* idx = (uint64_t*)malloc(sizeof(uint64_t) * ORC_LANES * (nmax ? nmax : 1));
+    uint8_t* bits = (uint8_t*)malloc(ORC_LANES * lane_bytes);
+    if (!p || !idx || !bits) {
+        free(p);
+        free(idx);
+        free(bits);
+        return ORC_E_NOMEM;
+    }
+    for (int i = 0; i < 128; i++) p[i] = (uint8_t)(len[2 * i] | (len[2 * i + 1] << 4));
+    uint64_t wpos = 0;
+    for (uint64_t j = 0; j < NG; j++) {
+        uint64_t lanes = W - ORC_LANES * j < ORC_LANES ? W - ORC_LANES * j : ORC_LANES;
+        uint64_t n[ORC_LANES], taken[ORC_LANES], rounds = 0;
+        int cnt[ORC_LANES];
+        memset(bits, 0, ORC_LANES * lane_bytes);
+        for (uint64_t l = 0; l < lanes; l++) {
+            uint64_t* ix = idx + l * nmax;
+            n[l] = substream_symbols(m, W, g, ORC_LANES * j + l, ix);
+            uint64_t pos = 0;
+            for (uint64_t t = 0; t < n[l]; t++) put_code(bits + l * lane_bytes, &pos, code[sym[ix[t]]], len[sym[ix[t]]]);
+            taken[l] = 0;
+            cnt[l] = 0;
+            if ((n[l] + 1) / 2 > rounds) rounds = (n[l] + 1) / 2;
+        }
+        uint64_t start = wpos;
+        for (uint64_t r = 0; r < rounds; r++) {
+            for (uint64_t l = 0; l < lanes; l++) {
+                if (2 * r >= n[l]) continue;
+                if (cnt[l] < 2 * L) {
+                    uint32_t word = get_u32(bits + l * lane_bytes + 4 * taken[l]);
+                    put_u32(p + H + 4 * wpos, word);
+                    wpos++;
+                    taken[l]++;
+                    cnt[l] += 32;
+                }
+                const uint64_t* ix = idx + l * nmax;
+                cnt[l] -= len[sym[ix[2 * r]]];
+                if (2 * r + 1 < n[l]) cnt[l] -= len[sym[ix[2 * r + 1]]];
+            }
+        }
+        put_u32(p + 128 + 4 * j, (uint32_t)(wpos - start));
+    }
+    free(idx);
+    free(bits);
+    out->mode = ORC_MODE_HUF;
+    out->bytes = H + 4 * wpos;
+    out->payload = p;
+    return ORC_OK;
+}
 
 /* Encode one byte-group (stream) of one chunk: m symbols.  The method
  * decision is made per byte-group (paper §V-A): RAW when the policy says so;
@@ -279,41 +363,13 @@ static int encode_stream(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g,
     uint8_t len[256];
     int rc = orc_package_merge(f, L, len);
     if (rc < 0) return rc;
-    uint64_t T = 0;
-    for (int s = 0; s < 256; s++) T += f[s] * len[s];
-    uint64_t W = (m + S - 1) / S;
-    uint64_t H = huf_header_bytes(W);
-    uint64_t size_huf = H + (T + 7) / 8;
-    if (policy == ORC_POLICY_AUTO && size_huf >= m) goto raw;
-
-    uint32_t code[256];
-    orc_canonical_codes(len, L, code);
-    uint8_t* p = (uint8_t*)calloc(size_huf, 1);
-    if (!p) return ORC_E_NOMEM;
-    for (int i = 0; i < 128; i++) p[i] = (uint8_t)(len[2 * i] | (len[2 * i + 1] << 4));
-    uint8_t* bits = p + H;
-    uint64_t G = (m + g - 1) / g;
-    uint64_t pos = 0;
-    for (uint64_t w = 0; w < W; w++) {
-        uint64_t start = pos;
-        for (uint64_t q = w; q < G; q += W) {
-            uint64_t j_end = (q + 1) * g < m ? (q + 1) * g : m;
-            for (uint64_t j = q * g; j < j_end; j++) put_code(bits, &pos, code[sym[j]], len[sym[j]]);
-        }
-        uint64_t lw = pos - start;
-        if (lw > 0xFFFF) {
-            free(p);
-            return ORC_E_INVAL;
-        }
-        put_u16(p + 128 + 2 * w, (uint16_t)lw);
+    rc = huf_payload(sym, m, S, g, L, len, out);
+    if (rc != ORC_OK) return rc;
+    if (policy == ORC_POLICY_AUTO && out->bytes >= m) {
+        free(out->payload);
+        out->payload = NULL;
+        goto raw;
     }
-    if (pos != T) {
-        free(p);
-        return ORC_E_INVAL;
-    }
-    out->mode = ORC_MODE_HUF;
-    out->bytes = size_huf;
-    out->payload = p;
     return ORC_OK;
 
 raw:
@@ -325,12 +381,15 @@ raw:
     return ORC_OK;
 }
 
-/* Decode a Huffman payload of m symbols.  Returns ORC_OK or ORC_E_CORRUPT. */
+/* Decode a Huffman payload of m symbols by replaying the lock-step rounds
+ * described at huf_payload: each lane collects the words it takes, and reads
+ * its codes one bit at a time from them.  Returns ORC_OK or ORC_E_CORRUPT. */
 static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, uint32_t g, int L,
                       uint8_t* sym)
 {
     uint64_t W = (m + S - 1) / S;
-    uint64_t H = huf_header_bytes(W);
+    uint64_t NG = (W + ORC_LANES - 1) / ORC_LANES;
+    uint64_t H = huf_head_bytes(W);
     if (bytes < H) return ORC_E_CORRUPT;
     uint8_t len[256];
     for (int i = 0; i < 128; i++) {
@@ -348,15 +407,11 @@ static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, 
         kraft += (uint64_t)1 << (L - len[s]);
     }
     if (n_coded < 2 || kraft != ((uint64_t)1 << L)) return ORC_E_CORRUPT;
-    for (uint64_t i = 128 + 2 * W; i < H; i++)
+    for (uint64_t i = 128 + 4 * NG; i < H; i++)
         if (p[i] != 0) return ORC_E_CORRUPT;
-    uint64_t T = 0;
-    for (uint64_t w = 0; w < W; w++) T += get_u16(p + 128 + 2 * w);
-    if (bytes != H + (T + 7) / 8) return ORC_E_CORRUPT;
-    const uint8_t* bits = p + H;
-    /* padding bits after T must be zero */
-    for (uint64_t b = T; b < 8 * ((T + 7) / 8); b++)
-        if ((bits[b >> 3] >> (b & 7)) & 1) return ORC_E_CORRUPT;
+    uint64_t total = 0;
+    for (uint64_t j = 0; j < NG; j++) total += get_u32(p + 128 + 4 * j);
+    if (bytes != H + 4 * total) return ORC_E_CORRUPT;
 
     /* canonical decoding tables: symbols sorted by (length, symbol) and the
      * count of codes of each length */
@@ -370,38 +425,72 @@ static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, 
                 count[l]++;
             }
     uint64_t G = (m + g - 1) / g;
-    uint64_t pos = 0;
-    for (uint64_t w = 0; w < W; w++) {
-        uint64_t start = pos;
-        uint64_t lw = get_u16(p + 128 + 2 * w);
-        uint64_t end = start + lw;
-        for (uint64_t q = w; q < G; q += W) {
-            uint64_t j_end = (q + 1) * g < m ? (q + 1) * g : m;
-            for (uint64_t j = q * g; j < j_end; j++) {
-                /* read code bits one at a time; after l bits, the code value
-                 * minus the first code of length l is the index among the
-                 * symbols of length l if it is below their count */
-                int code = 0, first = 0, index = 0, found = -1;
-                for (int l = 1; l <= L; l++) {
-                    int bit = get_bit(bits, end, &pos);
-                    if (bit < 0) return ORC_E_CORRUPT;
-                    code |= bit;
-                    if (code - first < count[l]) {
-                        found = sorted[index + code - first];
+    uint64_t nmax = ((G + W - 1) / W) * g;
+    uint64_t max_take = (nmax * (uint64_t)L + 2 * L) / 32 + 2;   /* words a lane can take */
+    uint64_t* idx = (uint64_t*)malloc(sizeof(uint64_t) * ORC_LANES * (nmax ? nmax : 1));
+    uint32_t* got = (uint32_t*)malloc(sizeof(uint32_t) * ORC_LANES * max_take);
+    if (!idx || !got) {
+        free(idx);
+        free(got);
+        return ORC_E_NOMEM;
+    }
+    int rc = ORC_OK;
+    uint64_t wpos = 0;
+    for (uint64_t j = 0; j < NG && rc == ORC_OK; j++) {
+        uint64_t lanes = W - ORC_LANES * j < ORC_LANES ? W - ORC_LANES * j : ORC_LANES;
+        uint64_t n[ORC_LANES], taken[ORC_LANES], bitpos[ORC_LANES], rounds = 0;
+        int cnt[ORC_LANES];
+        for (uint64_t l = 0; l < lanes; l++) {
+            n[l] = substream_symbols(m, W, g, ORC_LANES * j + l, idx + l * nmax);
+            taken[l] = bitpos[l] = 0;
+            cnt[l] = 0;
+            if ((n[l] + 1) / 2 > rounds) rounds = (n[l] + 1) / 2;
+        }
+        uint64_t end = wpos + get_u32(p + 128 + 4 * j);
+        for (uint64_t r = 0; r < rounds && rc == ORC_OK; r++) {
+            for (uint64_t l = 0; l < lanes && rc == ORC_OK; l++) {
+                if (2 * r >= n[l]) continue;
+                if (cnt[l] < 2 * L) {
+                    if (wpos >= end || taken[l] >= max_take) {
+                        rc = ORC_E_CORRUPT;
                         break;
                     }
-                    index += count[l];
-                    first += count[l];
-                    first <<= 1;
-                    code <<= 1;
+                    got[l * max_take + taken[l]++] = get_u32(p + H + 4 * wpos++);
+                    cnt[l] += 32;
                 }
-                if (found < 0) return ORC_E_CORRUPT;
-                sym[j] = (uint8_t)found;
+                for (uint64_t t = 2 * r; t < 2 * r + 2 && t < n[l]; t++) {
+                    /* read code bits one at a time; after l bits, the code
+                     * value minus the first code of length l is the index
+                     * among the symbols of length l if below their count */
+                    int codev = 0, first = 0, index = 0, found = -1;
+                    for (int b = 1; b <= L; b++) {
+                        if (bitpos[l] >= 32 * taken[l]) break;
+                        uint32_t wd = got[l * max_take + bitpos[l] / 32];
+                        codev |= (int)((wd >> (bitpos[l] % 32)) & 1u);
+                        bitpos[l]++;
+                        cnt[l]--;
+                        if (codev - first < count[b]) {
+                            found = sorted[index + codev - first];
+                            break;
+                        }
+                        index += count[b];
+                        first += count[b];
+                        first <<= 1;
+                        codev <<= 1;
+                    }
+                    if (found < 0) {
+                        rc = ORC_E_CORRUPT;
+                        break;
+                    }
+                    sym[idx[l * nmax + t]] = (uint8_t)found;
+                }
             }
         }
-        if (pos != end) return ORC_E_CORRUPT;   /* a sub-stream must be used up exactly */
+        if (rc == ORC_OK && wpos != end) rc = ORC_E_CORRUPT;   /* every word taken exactly */
     }
-    return ORC_OK;
+    free(idx);
+    free(got);
+    return rc;
 }
 
 /* ------------------------------------------------------- chunk workers */
@@ -485,17 +574,18 @@ static void run_threads(void* (*fn)(void*), void* job, int nthreads)
 
 /* ------------------------------------------------------- public API */
 
-uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes)
+uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes, uint32_t S)
 {
     int B = dtype_width(dtype);
-    if (!B || !is_pow2(chunk_bytes)) return 0;
+    if (!B || !is_pow2(chunk_bytes) || S == 0) return 0;
     uint64_t E = chunk_bytes / (uint64_t)B;
     uint64_t nc = (n + E - 1) / E;
-    /* header + map + every payload raw (AUTO never exceeds raw) + alignment;
-     * a HUF-forced stream can exceed raw by its table and sub-stream lengths,
-     * plus up to L bits per symbol beyond 8 */
-    uint64_t per_chunk_extra = (uint64_t)B * (15 + 16 + 128 + 16 + 2 * (uint64_t)E + (uint64_t)E / 2 + 1);
-    return 64 + n * (uint64_t)B + nc * per_chunk_extra;
+    uint64_t W = (E + S - 1) / S;
+    /* per stream: a raw copy, or (HUF forced) the head plus at most L <= 11
+     * bits per symbol and two extra words per sub-stream; plus alignment */
+    uint64_t huf = 128 + 4 * (W / ORC_LANES + 1) + 16 + (E * 11 + 7) / 8 + 8 * W + 8;
+    uint64_t per_stream = (huf > E ? huf : E) + 16;
+    return 64 + nc * (uint64_t)B * (16 + per_stream);
 }
 
 int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, uint32_t chunk_bytes,
@@ -702,7 +792,7 @@ static int check_map(const uint8_t* src, const orc_header* h)
             } else if (mode == ORC_MODE_RLE) {
                 if (bytes != 0) return ORC_E_CORRUPT;
             } else if (mode == ORC_MODE_HUF) {
-                if (bytes < huf_header_bytes(W) || ent[13]) return ORC_E_CORRUPT;
+                if (bytes < huf_head_bytes(W) || ent[13]) return ORC_E_CORRUPT;
             } else {
                 return ORC_E_CORRUPT;
             }

@@ -15,10 +15,15 @@
  *   and carry the running offset; total_bytes = payload_base + aligned end.
  *   RAW payload: the m stream bytes.
  *   HUF payload: 128 bytes of 4-bit code lengths (byte i = l[2i] | l[2i+1]<<4)
- *     | u16 bit length of each of the W = ceil(m/S) sub-streams | zero pad to
- *     align16(128 + 2W) | the W sub-streams, bit-contiguous, LSB-first, last
- *     byte zero padded.  Group q of g consecutive symbols belongs to
- *     sub-stream q mod W.
+ *     | u32 word count of each of the NG = ceil(W/64) lane groups | zero pad
+ *     to align16(128 + 4*NG) | the word streams of lane groups 0..NG-1.
+ *     W = ceil(m/S) sub-streams; group q of g consecutive symbols belongs to
+ *     sub-stream q mod W; sub-stream 64j+l is lane l of lane group j.  A
+ *     sub-stream's codes (most significant bit first, LSB-first packing) are
+ *     cut into 32-bit words; a lane group's words are stored in the order a
+ *     lock-step decoder of its 64 lanes takes them: in round r each lane with
+ *     symbols left takes its next word if it holds fewer than 2L bits (lanes
+ *     in order), then decodes its symbols 2r and 2r+1.
  */
 #ifndef ZIPNN_ORACLE_H
 #define ZIPNN_ORACLE_H
@@ -45,7 +50,9 @@ enum { ORC_FLAG_DELTA = 1 };
 #define ORC_MIN_CHUNK 256u
 #define ORC_MAX_CHUNK (4u << 20)
 #define ORC_MAX_S 4096u
+#define ORC_MIN_G 2u
 #define ORC_MAX_G 8u
+#define ORC_LANES 64u
 #define ORC_MAX_W 4096u
 #define ORC_MAX_BW 8192u
 #define ORC_MIN_L 8u
@@ -63,7 +70,7 @@ int orc_check_params(int B, uint32_t chunk_bytes, uint32_t S, uint32_t g, uint32
 void orc_split_stream(const uint8_t* words, uint64_t m, int B, int k, uint8_t* out);
 int orc_package_merge(const uint64_t f[256], int L, uint8_t len_out[256]);
 void orc_canonical_codes(const uint8_t len[256], int L, uint32_t code[256]);
-uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes);
+uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes, uint32_t S);
 int orc_compress(const void* src, int dtype, uint64_t n, const void* base, uint32_t chunk_bytes, uint32_t S,
                  uint32_t g, uint32_t L, const uint8_t* policy, void* dst, uint64_t dst_cap, uint64_t* dst_len,
                  int nthreads);

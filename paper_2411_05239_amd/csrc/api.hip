@@ -182,7 +182,8 @@ uint64_t zipnn_compress_bound(int dtype, uint64_t n, const zipnn_params* p)
     const uint64_t nc = (n + E - 1) / E;
     const uint64_t W = (E + p->substream_syms - 1) / p->substream_syms;
     // AUTO never exceeds raw; HUF-forced may reach head + L bits per symbol
-    const uint64_t per_stream = huf_head(uint32_t(W)) + (E * p->max_code_len + 7) / 8 + 16;
+    // plus two words of padding per sub-stream
+    const uint64_t per_stream = huf_head(uint32_t(W)) + (E * p->max_code_len + 7) / 8 + 8 * W + 16;
     return 64 + 16 * nc * B + nc * B * (per_stream > E + 16 ? per_stream : E + 16);
 }
 
@@ -204,7 +205,8 @@ int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n, const 
     const size_t off_entries = 0;
     const size_t off_codes = align256(off_entries + ne * sizeof(EncEntry));
     const size_t off_offsets = align256(off_codes + ne * 256 * sizeof(CodeWord));
-    const size_t off_totals = align256(off_offsets + ne * sizeof(uint64_t));
+    const size_t off_nwords = align256(off_offsets + ne * sizeof(uint64_t));
+    const size_t off_totals = align256(off_nwords + ne * 64 * sizeof(uint32_t));
     const size_t need = off_totals + 256;
     int rc = grow_scratch(ctx, need);
     if (rc) return rc;
@@ -212,6 +214,7 @@ int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n, const 
     EncEntry* entries = (EncEntry*)(sc + off_entries);
     CodeWord* codes = (CodeWord*)(sc + off_codes);
     uint64_t* offsets = (uint64_t*)(sc + off_offsets);
+    uint32_t* nwords = (uint32_t*)(sc + off_nwords);
     uint64_t* totals = (uint64_t*)(sc + off_totals);
     EncParams ep = make_params(dtype, *p);
     ep.flags = base ? kFlagDelta : 0;
@@ -223,9 +226,10 @@ int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n, const 
     one.n = n;
     one.chunk0 = 0;
     one.n_chunks = uint32_t(nc);
-    if (launch_analyze(one, nullptr, 1, nullptr, uint32_t(nc), ep, entries, codes, s) != hipSuccess ||
+    if (launch_analyze(one, nullptr, 1, nullptr, uint32_t(nc), ep, entries, codes, nwords, s) != hipSuccess ||
         launch_place(one, nullptr, 1, ep, entries, offsets, totals, s) != hipSuccess ||
-        launch_pack(one, nullptr, 1, nullptr, uint32_t(nc), ep, entries, codes, offsets, totals, s) != hipSuccess ||
+        launch_pack(one, nullptr, 1, nullptr, uint32_t(nc), ep, entries, codes, offsets, totals, nwords, s) !=
+            hipSuccess ||
         hipMemcpyAsync(ctx->h_total, totals, sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return ZIPNN_E_HIP;
@@ -235,22 +239,55 @@ int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n, const 
     return ZIPNN_OK;
 }
 
+static int decompress_common(zipnn_ctx ctx, const uint32_t* hdr_words, const void* src, uint64_t src_len,
+                             const void* base, void* dst, uint64_t dst_cap, hipStream_t s)
+{
+    Header h;
+    int rc = parse_header(hdr_words, src_len, h);
+    if (rc) return rc;
+    const bool delta = (h.flags & kFlagDelta) != 0;
+    if (delta != (base != nullptr)) return ZIPNN_E_INVAL;
+    if (h.n * h.B > dst_cap) return ZIPNN_E_NOSPACE;
+    if (h.n_chunks == 0) return ZIPNN_OK;
+    if (!dst) return ZIPNN_E_INVAL;
+    DecDesc one;
+    one.src = (const uint8_t*)src;
+    one.src_len = src_len;
+    one.base = (const uint8_t*)base;
+    one.dst = (uint8_t*)dst;
+    one.dst_cap = dst_cap;
+    if (launch_decode_one(h, one, ctx->d_status, ctx->dec_grid, s) != hipSuccess) return ZIPNN_E_HIP;
+    return ZIPNN_OK;
+}
+
 int zipnn_decompress(zipnn_ctx ctx, const void* src, uint64_t src_len, const void* base, void* dst, uint64_t dst_cap,
                      void* stream)
 {
     if (!ctx || !src) return ZIPNN_E_INVAL;
     if (src_len < 64) return ZIPNN_E_FORMAT;
     if (!aligned16(src) || !aligned16(dst) || !aligned16(base)) return ZIPNN_E_INVAL;
-    if (!dst && dst_cap) return ZIPNN_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
-    DecDesc one;
-    one.src = (const uint8_t*)src;
-    one.src_len = src_len;
-    one.base = (const uint8_t*)base;
-    one.dst = (uint8_t*)dst;
-    one.dst_cap = dst ? dst_cap : 0;
-    if (launch_decode_one(one, ctx->d_status, ctx->dec_grid, (hipStream_t)stream) != hipSuccess) return ZIPNN_E_HIP;
-    return ZIPNN_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // the kernel is chosen from the header: read its 64 bytes (stream-ordered)
+    if (hipMemcpyAsync(ctx->h_total, src, 64, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return ZIPNN_E_HIP;
+    uint32_t w[16];
+    memcpy(w, ctx->h_total, 64);
+    return decompress_common(ctx, w, src, src_len, base, dst, dst_cap, s);
+}
+
+int zipnn_decompress_async(zipnn_ctx ctx, const void* header_host, const void* src, uint64_t src_len,
+                           const void* base, void* dst, uint64_t dst_cap, void* stream)
+{
+    if (!ctx || !src || !header_host) return ZIPNN_E_INVAL;
+    if (src_len < 64) return ZIPNN_E_FORMAT;
+    if (!aligned16(src) || !aligned16(dst) || !aligned16(base)) return ZIPNN_E_INVAL;
+    DeviceGuard g(ctx->device);
+    uint32_t w[16];
+    memcpy(w, header_host, 64);
+    return decompress_common(ctx, w, src, src_len, base, dst, dst_cap, (hipStream_t)stream);
 }
 
 int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out)

@@ -1,29 +1,28 @@
 // Decode kernels of the gfx950 ZipNN codec.
 //
-// Work item = (tensor, chunk, slice of up to 256 sub-streams).  Chunks are
-// independent given the map (paper §V-A "Metadata and parallelism"), and
-// inside a chunk the W interleaved sub-streams of every Huffman-coded byte
-// group are independent too, so one workgroup of 256 threads decodes one
-// slice: thread t owns sub-stream w = 256*slice + t of EVERY stream of the
-// chunk.  Because all streams of a chunk share the same (m, S, g), sub-stream
-// w of every stream covers the same element positions (groups q = w, w+W,
-// ...), so a thread merges the B byte groups back into words in registers
-// (the inverse of byte grouping, paper §III-A/§III-B), applies the XOR delta
-// (paper §IV-B) and writes g whole words with one vector store; a wave writes
-// 64*g*B contiguous bytes per step.
+// Work item = (tensor, chunk, slice of up to 256 sub-streams = 4 lane groups).
+// Chunks are independent given the map (paper §V-A "Metadata and
+// parallelism"); inside a chunk the W sub-streams of every Huffman-coded byte
+// group are independent too.  One workgroup (4 waves) takes one item: it
+// checks the item's map entries and expands each Huffman table into an LDS
+// lookup table shared by its waves; then wave v decodes lane group 4*slice+v
+// on its own: lane l owns sub-stream 64*(4*slice+v)+l of EVERY stream of the
+// chunk.  All streams of a chunk share (m, S, g), so sub-stream w of every
+// stream covers the same elements (groups q = w, w+W, ...): the lane merges
+// the B byte groups back into words in registers (the inverse of byte
+// grouping, paper §III-A/§III-B), applies the XOR delta (paper §IV-B) and
+// writes g whole words with one vector store; a wave writes 64*g*B
+// contiguous bytes per group.
 //
-// Per item:
-//   1. the B map entries are read and checked (mode, sizes, the exact
-//      chunk-major 16-byte aligned placement) into LDS;
-//   2. each Huffman table (128 B of 4-bit lengths) is checked (Kraft sum
-//      exactly 2^L, >= 2 codes, lengths <= L) and expanded into a 2^L-entry
-//      LDS lookup table {symbol, length} indexed by the next L stream bits;
-//   3. the u16 sub-stream lengths are scanned to find each thread's start bit
-//      and checked against the payload size;
-//   4. the hot loop: per group, every HUF stream peeks L bits, looks up
-//      (symbol, length) in LDS and consumes; RAW streams load g bytes; RLE
-//      streams splat their value; words are assembled and stored;
-//   5. every sub-stream must consume exactly its stored bit length.
+// A lane group's Huffman words are stored in the order its 64 lanes take them
+// when they run in lock-step (round r: a lane holding fewer than 2L bits takes
+// a word, then decodes its symbols 2r and 2r+1), so in every round the lanes
+// that need a word read CONSECUTIVE words: the wave ballots the request, each
+// lane's word index is the popcount of the requesting lanes below it, and the
+// wave's read cursor advances by the ballot's popcount.  The words come from
+// three 64-word windows held one per lane in registers (ds_bpermute picks a
+// lane's word), refilled two windows ahead with coalesced 256-byte loads.
+//
 // Any failed check records ZIPNN_E_CORRUPT / ZIPNN_E_FORMAT in the sticky
 // status word; the decoder never reads outside [src, src+total_bytes) and
 // never writes outside dst[0, n*B).
@@ -37,7 +36,6 @@ struct ItemState {
     uint32_t bytes[4];
     uint32_t mode[4];
     uint32_t rle[4];
-    uint32_t bitbase[4];   // first bit of this slice's first sub-stream
     int err;
 };
 
@@ -71,32 +69,6 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v)
         if (lane >= d) v += o;
     }
     return v;
-}
-
-// Exclusive scan over the 256 threads of the block; *total gets the sum.
-__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* red, uint32_t* total)
-{
-    uint32_t inc = wave_incl_scan(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 63) red[wv] = inc;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        uint32_t s = red[i];
-        pre += i < wv ? s : 0;
-        tot += s;
-    }
-    __syncthreads();
-    *total = tot;
-    return pre + inc - v;
-}
-
-__device__ inline uint32_t block_sum(uint32_t v, uint32_t* red)
-{
-    uint32_t t;
-    block_excl_scan(v, red, &t);
-    return t;
 }
 
 // Expand a 128-byte nibble table into the LSB-first lookup table `lut`
@@ -168,234 +140,256 @@ __device__ bool build_lut(const uint8_t* table, uint32_t L, uint16_t* lut, LutTm
     return true;
 }
 
-// Bit reader over one sub-stream: 64-bit window, refilled one dword at a
-// time; loads past the payload are clamped to its last dword (those bits are
-// never consumed by a well-formed sub-stream).
-struct BitReader {
-    const uint32_t* bs;
-    uint32_t last;
-    uint32_t idx;
-    uint32_t cnt;
-    uint64_t buf;
-    uint32_t start;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-    __device__ inline void init(const uint32_t* base, uint32_t last_dw, uint32_t bit)
-    {
-        bs = base;
-        last = last_dw;
-        start = bit;
-        idx = bit >> 5;
-        uint32_t sh = bit & 31;
-        buf = uint64_t(bs[min(idx, last)] >> sh);
-        cnt = 32 - sh;
-        idx++;
-        refill();
-    }
-    __device__ inline void refill()
-    {
-        if (cnt <= 32) {
-            buf |= uint64_t(bs[min(idx, last)]) << cnt;
-            cnt += 32;
-            idx++;
-        }
-    }
-    __device__ inline uint32_t get(const uint16_t* lut, uint32_t mask)
-    {
-        uint32_t e = lut[uint32_t(buf) & mask];
-        uint32_t l = e >> 8;
-        buf >>= l;
-        cnt -= l;
-        return e & 0xFF;
-    }
-    __device__ inline uint32_t consumed() const { return idx * 32u - cnt - start; }
-};
+constexpr int kDepth = 4;   // groups of raw bytes prefetched ahead per lane
 
 template <int G>
-struct RawLoad;
-template <>
-struct RawLoad<1> {
-    static __device__ inline void run(const uint8_t* p, uint32_t* o) { o[0] = p[0]; }
+struct SlotSize {
+    static constexpr int PW = G >= 4 ? G / 4 : 1;                 // packed words per group
+    static constexpr int N = kDepth * PW > 6 ? kDepth * PW : 6;   // registers per stream slot
 };
-template <>
-struct RawLoad<2> {
-    static __device__ inline void run(const uint8_t* p, uint32_t* o) { o[0] = *(const uint16_t*)p; }
+
+// Uniform (scalar) part of a lane group's Huffman word stream.
+struct WordCursor {
+    const uint32_t* p;   // first word of this lane group's stream
+    uint32_t last;       // index of its last word
+    uint32_t ptr;        // words taken so far
+    uint32_t wb;         // stream index held by lane 0 of window 0 (multiple of 64)
 };
-template <>
-struct RawLoad<4> {
-    static __device__ inline void run(const uint8_t* p, uint32_t* o) { o[0] = *(const uint32_t*)p; }
-};
-template <>
-struct RawLoad<8> {
-    static __device__ inline void run(const uint8_t* p, uint32_t* o)
-    {
-        uint2 v = *(const uint2*)p;
+
+// A stream's register slot holds, for a Huffman stream: three 64-word
+// windows (one word per lane: r[0..2]), the buffered bit count r[3] and the
+// 64-bit bit buffer r[4] | r[5] << 32; for a raw stream: the ring of
+// prefetched groups (r[u*PW + x]).  The mode of a stream is fixed for a chunk,
+// so one set of registers serves both.
+
+__device__ inline void huf_init(uint32_t* r, WordCursor& c, const uint32_t* words, uint32_t nwords, uint32_t lane)
+{
+    c.p = words;
+    c.last = nwords - 1;
+    c.ptr = 0;
+    c.wb = 0;
+    r[0] = words[min(lane, c.last)];
+    r[1] = words[min(64 + lane, c.last)];
+    r[2] = words[min(128 + lane, c.last)];
+    r[3] = 0;
+    r[4] = 0;
+    r[5] = 0;
+}
+
+// One round's word requests: lanes taking part with fewer than 2L buffered
+// bits take the next words of the stream, in lane order.
+__device__ inline void huf_take(uint32_t* r, WordCursor& c, bool part, uint32_t twoL, uint32_t lane)
+{
+    const bool need = part && r[3] < twoL;
+    const uint64_t m = __ballot(need);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    const uint32_t rel = c.ptr - c.wb + below;   // < 128
+    const uint32_t a = __shfl(r[0], int(rel & 63), 64);
+    const uint32_t b = __shfl(r[1], int(rel & 63), 64);
+    const uint32_t word = rel < 64 ? a : b;
+    if (need) {
+        const uint64_t x = uint64_t(word) << r[3];
+        r[4] |= uint32_t(x);
+        r[5] |= uint32_t(x >> 32);
+        r[3] += 32;
+    }
+    c.ptr += uint32_t(__popcll(m));
+    if (c.ptr - c.wb >= 64) {
+        r[0] = r[1];
+        r[1] = r[2];
+        c.wb += 64;
+        r[2] = c.p[min(c.wb + 128 + lane, c.last)];
+    }
+}
+
+__device__ inline uint32_t huf_get(uint32_t* r, const uint16_t* lut, uint32_t mask)
+{
+    const uint32_t e = lut[r[4] & mask];
+    const uint32_t l = e >> 8;
+    r[4] = __builtin_amdgcn_alignbit(r[5], r[4], l);
+    r[5] >>= l;
+    r[3] -= l;
+    return e & 0xFFu;
+}
+
+template <int G>
+__device__ inline void raw_load(const uint8_t* p, uint32_t* o)
+{
+    if constexpr (G == 2) o[0] = *(const uint16_t*)p;
+    else if constexpr (G == 4) o[0] = __builtin_nontemporal_load((const uint32_t*)p);
+    else {
+        u32x2 v = __builtin_nontemporal_load((const u32x2*)p);
         o[0] = v.x;
         o[1] = v.y;
     }
-};
-
-template <int NB>
-struct Store;
-template <>
-struct Store<1> {
-    static __device__ inline void run(uint8_t* d, const uint32_t* w) { d[0] = uint8_t(w[0]); }
-    static __device__ inline void xor_base(const uint8_t* b, uint32_t* w) { w[0] ^= b[0]; }
-};
-template <>
-struct Store<2> {
-    static __device__ inline void run(uint8_t* d, const uint32_t* w) { *(uint16_t*)d = uint16_t(w[0]); }
-    static __device__ inline void xor_base(const uint8_t* b, uint32_t* w) { w[0] ^= *(const uint16_t*)b; }
-};
-template <>
-struct Store<4> {
-    static __device__ inline void run(uint8_t* d, const uint32_t* w) { *(uint32_t*)d = w[0]; }
-    static __device__ inline void xor_base(const uint8_t* b, uint32_t* w) { w[0] ^= *(const uint32_t*)b; }
-};
-template <>
-struct Store<8> {
-    static __device__ inline void run(uint8_t* d, const uint32_t* w) { *(uint2*)d = make_uint2(w[0], w[1]); }
-    static __device__ inline void xor_base(const uint8_t* b, uint32_t* w)
-    {
-        uint2 v = *(const uint2*)b;
-        w[0] ^= v.x;
-        w[1] ^= v.y;
-    }
-};
-template <>
-struct Store<16> {
-    static __device__ inline void run(uint8_t* d, const uint32_t* w) { *(uint4*)d = make_uint4(w[0], w[1], w[2], w[3]); }
-    static __device__ inline void xor_base(const uint8_t* b, uint32_t* w)
-    {
-        uint4 v = *(const uint4*)b;
-        w[0] ^= v.x;
-        w[1] ^= v.y;
-        w[2] ^= v.z;
-        w[3] ^= v.w;
-    }
-};
-template <>
-struct Store<32> {
-    static __device__ inline void run(uint8_t* d, const uint32_t* w)
-    {
-        *(uint4*)d = make_uint4(w[0], w[1], w[2], w[3]);
-        *(uint4*)(d + 16) = make_uint4(w[4], w[5], w[6], w[7]);
-    }
-    static __device__ inline void xor_base(const uint8_t* b, uint32_t* w)
-    {
-        Store<16>::xor_base(b, w);
-        Store<16>::xor_base(b + 16, w + 4);
-    }
-};
-
-template <int B>
-__device__ inline uint32_t stream_byte(const uint32_t (*pk)[2], int k, int i)
-{
-    return (pk[k][i >> 2] >> (8 * (i & 3))) & 0xFFu;
 }
 
-// Decode the groups of sub-stream w of one chunk and store merged words.
-template <int B, int G>
-__device__ void decode_substream(const uint8_t* __restrict__ src, const ItemState& st,
-                                 const uint16_t (*lut)[kLutSize], uint32_t L, uint32_t w, uint32_t W, uint32_t m,
-                                 const uint32_t* bitstart, uint8_t* __restrict__ out,
-                                 const uint8_t* __restrict__ base, int* status)
+template <int NB>
+__device__ inline void store_words(uint8_t* d, const uint32_t* w)
 {
-    constexpr int NBYTES = B * G;
-    constexpr int NW = NBYTES >= 4 ? NBYTES / 4 : 1;
-    const uint32_t mask = (1u << L) - 1;
+    if constexpr (NB == 2) *(uint16_t*)d = uint16_t(w[0]);
+    else if constexpr (NB == 4) __builtin_nontemporal_store(w[0], (uint32_t*)d);
+    else if constexpr (NB == 8) __builtin_nontemporal_store(u32x2{w[0], w[1]}, (u32x2*)d);
+    else if constexpr (NB == 16) __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, (u32x4*)d);
+    else {
+        __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, (u32x4*)d);
+        __builtin_nontemporal_store(u32x4{w[4], w[5], w[6], w[7]}, (u32x4*)(d + 16));
+    }
+}
+
+template <int NB>
+__device__ inline void load_words(const uint8_t* b, uint32_t* w)
+{
+    if constexpr (NB == 2) w[0] = *(const uint16_t*)b;
+    else if constexpr (NB == 4) w[0] = __builtin_nontemporal_load((const uint32_t*)b);
+    else {
+#pragma unroll
+        for (int i = 0; i < NB / 8; i++) {
+            u32x2 v = __builtin_nontemporal_load((const u32x2*)(b + 8 * i));
+            w[2 * i] = v.x;
+            w[2 * i + 1] = v.y;
+        }
+    }
+}
+
+// Decode lane group j of one chunk: every stream's symbols of the lane's
+// sub-stream, merged into words and stored.  Raw bytes (and the XOR base) of
+// a lane's groups are fetched kDepth groups ahead through a register ring.
+template <int B, int G, bool DELTA>
+__device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemState& st,
+                                  const uint16_t (*lut)[kLutSize], const uint32_t (*wprefix)[65], uint32_t L,
+                                  uint32_t j, uint32_t W, uint32_t m, uint8_t* __restrict__ out,
+                                  const uint8_t* __restrict__ base, int* status)
+{
+    constexpr int NB = B * G;
+    constexpr int NW = NB >= 4 ? NB / 4 : 1;
+    constexpr int PW = SlotSize<G>::PW;
+    constexpr int NS = SlotSize<G>::N;
+    constexpr int BD = DELTA ? kDepth : 1;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t w = 64 * j + lane;
+    const uint32_t mask = (1u << L) - 1, twoL = 2 * L;
+    const uint32_t Gtot = (m + G - 1) / G, Gfull = m / G, rem = m - Gfull * G;
+    const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;     // groups of this lane
+    const uint32_t nfull = (w < W && w < Gfull) ? (Gfull - 1 - w) / W + 1 : 0; // full ones
+    const uint32_t ng_max = __builtin_amdgcn_readfirstlane(ng);            // lane 0 has the most
     int mode[B];
     uint32_t rlev[B];
     const uint8_t* pay[B];
-    BitReader br[B];
+    WordCursor cur[B];
+    uint32_t slot[B][NS];
+    uint32_t bring[BD][NW];
 #pragma unroll
     for (int k = 0; k < B; k++) {
         mode[k] = __builtin_amdgcn_readfirstlane(st.mode[k]);
         rlev[k] = st.rle[k] * 0x01010101u;
         pay[k] = src + st.pay[k];
+#pragma unroll
+        for (int x = 0; x < NS; x++) slot[k][x] = 0;
         if (mode[k] == kModeHuf) {
-            const uint32_t W_ = W;
-            const uint32_t head = huf_head(W_);
-            const uint32_t* bs = (const uint32_t*)(pay[k] + head);
-            const uint32_t ext = uint32_t(align16(st.bytes[k])) - head;   // bytes of bitstream area
-            br[k].init(bs, ext / 4 - 1, bitstart[k]);
+            const uint32_t* words = (const uint32_t*)(pay[k] + huf_head(W));
+            const uint32_t s0 = __builtin_amdgcn_readfirstlane(wprefix[k][j]);
+            const uint32_t s1 = __builtin_amdgcn_readfirstlane(wprefix[k][j + 1]);
+            huf_init(slot[k], cur[k], words + s0, s1 - s0, lane);
+        } else if (mode[k] == kModeRaw) {
+#pragma unroll
+            for (int u = 0; u < kDepth; u++)
+                if (uint32_t(u) < nfull) raw_load<G>(pay[k] + (w + u * W) * G, &slot[k][u * PW]);
         }
     }
-    const uint32_t Gfull = m / G;
-    for (uint32_t q = w; q < Gfull; q += W) {
-        const uint32_t e = q * G;
-        uint32_t pk[B][2];
+    if constexpr (DELTA) {
 #pragma unroll
-        for (int k = 0; k < B; k++) {
-            pk[k][0] = pk[k][1] = 0;
-            if (mode[k] == kModeRaw) {
-                RawLoad<G>::run(pay[k] + e, pk[k]);
-            } else if (mode[k] == kModeRle) {
-                pk[k][0] = pk[k][1] = rlev[k];
-            } else {
+        for (int u = 0; u < kDepth; u++) {
 #pragma unroll
-                for (int i = 0; i < G; i++) {
-                    if ((i & 1) == 0) br[k].refill();
-                    pk[k][i >> 2] |= br[k].get(lut[k], mask) << (8 * (i & 3));
+            for (int x = 0; x < NW; x++) bring[u][x] = 0;
+            if (uint32_t(u) < nfull) load_words<NB>(base + uint64_t(w + u * W) * G * B, bring[u]);
+        }
+    }
+    for (uint32_t j0 = 0; j0 < ng_max; j0 += kDepth) {
+#pragma unroll
+        for (int u = 0; u < kDepth; u++) {
+            const uint32_t jj = j0 + u;
+            const uint32_t q = w + jj * W;
+            const bool has = jj < ng;
+            const bool full = jj < nfull;
+            const uint32_t gcnt = full ? G : (has ? rem : 0);
+            const uint32_t qn = q + kDepth * W;
+            const bool okn = jj + kDepth < nfull;
+            uint32_t pk[B][PW];
+#pragma unroll
+            for (int k = 0; k < B; k++) {
+#pragma unroll
+                for (int x = 0; x < PW; x++) pk[k][x] = 0;
+                if (mode[k] == kModeRaw) {
+                    // take this group from the ring, refill the slot kDepth ahead
+#pragma unroll
+                    for (int x = 0; x < PW; x++) pk[k][x] = slot[k][u * PW + x];
+                    if (okn) raw_load<G>(pay[k] + qn * G, &slot[k][u * PW]);
+                } else if (mode[k] == kModeRle) {
+#pragma unroll
+                    for (int x = 0; x < PW; x++) pk[k][x] = rlev[k];
+                } else {
+#pragma unroll
+                    for (int pr = 0; pr < G / 2; pr++) {
+                        const bool part = 2u * pr < gcnt;
+                        huf_take(slot[k], cur[k], part, twoL, lane);
+                        if (part) {
+                            pk[k][(2 * pr) >> 2] |= huf_get(slot[k], lut[k], mask) << (8 * ((2 * pr) & 3));
+                            if (2u * pr + 1 < gcnt)
+                                pk[k][(2 * pr + 1) >> 2] |= huf_get(slot[k], lut[k], mask) << (8 * ((2 * pr + 1) & 3));
+                        }
+                    }
                 }
             }
-        }
-        uint32_t ow[NW];
+            uint32_t ow[NW];
 #pragma unroll
-        for (int x = 0; x < NW; x++) ow[x] = 0;
+            for (int x = 0; x < NW; x++) ow[x] = 0;
+            if constexpr (DELTA) {
 #pragma unroll
-        for (int j = 0; j < NBYTES; j++) {
-            const int i = j / B, b = j % B;
-            ow[j >> 2] |= stream_byte<B>(pk, B - 1 - b, i) << (8 * (j & 3));
-        }
-        uint8_t* d = out + uint64_t(e) * B;
-        if (base) Store<NBYTES>::xor_base(base + uint64_t(e) * B, ow);
-        Store<NBYTES>::run(d, ow);
-    }
-    // a partial last group (only in the last chunk of a tensor)
-    const uint32_t rem = m - Gfull * G;
-    if (rem && (Gfull % W) == w) {
-        const uint32_t e = Gfull * G;
-        uint32_t sy[B][G];
+                for (int x = 0; x < NW; x++) ow[x] = bring[u][x];
+                if (okn) load_words<NB>(base + uint64_t(qn) * G * B, bring[u]);
+            }
+            if (full) {
 #pragma unroll
-        for (int k = 0; k < B; k++) {
+                for (int jb = 0; jb < NB; jb++) {
+                    const int i = jb / B, b = jb % B, k = B - 1 - b;
+                    ow[jb >> 2] ^= ((pk[k][i >> 2] >> (8 * (i & 3))) & 0xFFu) << (8 * (jb & 3));
+                }
+                store_words<NB>(out + uint64_t(q) * G * B, ow);
+            } else if (has) {
+                // the partial last group of a tensor: one byte at a time
+                const uint32_t e = q * G;
+                for (uint32_t i = 0; i < gcnt; i++) {
 #pragma unroll
-            for (int i = 0; i < G; i++) {
-                sy[k][i] = 0;
-                if (uint32_t(i) < rem) {
-                    if (mode[k] == kModeRaw) sy[k][i] = pay[k][e + i];
-                    else if (mode[k] == kModeRle) sy[k][i] = rlev[k] & 0xFF;
-                    else {
-                        br[k].refill();
-                        sy[k][i] = br[k].get(lut[k], mask);
+                    for (int b = 0; b < B; b++) {
+                        const int k = B - 1 - b;
+                        uint32_t v;
+                        if (mode[k] == kModeRaw) v = pay[k][e + i];
+                        else {
+                            v = pk[k][0];
+#pragma unroll
+                            for (int x = 1; x < PW; x++)
+                                if (i >= 4u * x) v = pk[k][x];
+                            v = (v >> (8 * (i & 3))) & 0xFFu;
+                        }
+                        const uint64_t o = uint64_t(e + i) * B + b;
+                        out[o] = DELTA ? uint8_t(v ^ base[o]) : uint8_t(v);
                     }
                 }
             }
         }
-        for (uint32_t i = 0; i < rem; i++) {
-#pragma unroll
-            for (int b = 0; b < B; b++) {
-                uint8_t v = uint8_t(sy[B - 1 - b][0]);
-#pragma unroll
-                for (int ii = 0; ii < G; ii++)
-                    if (uint32_t(ii) == i) v = uint8_t(sy[B - 1 - b][ii]);
-                uint64_t o = uint64_t(e + i) * B + b;
-                out[o] = base ? uint8_t(v ^ base[o]) : v;
-            }
-        }
     }
 #pragma unroll
-    for (int k = 0; k < B; k++) {
-        if (mode[k] == kModeHuf) {
-            // the stored length of this sub-stream
-            const uint16_t* lens = (const uint16_t*)(pay[k] + 128);
-            if (br[k].consumed() != lens[w]) set_status(status, ZIPNN_E_CORRUPT);
-        }
-    }
+    for (int k = 0; k < B; k++)
+        if (mode[k] == kModeHuf && cur[k].ptr != cur[k].last + 1 && lane == 0) set_status(status, ZIPNN_E_CORRUPT);
 }
 
+// Parse one tensor's header on the device and size its work.
 __device__ bool load_tensor(const DecDesc& d, int di, TensorState& ts, int* status, bool report)
 {
-    // every thread reads the header (64 B, served from cache after the first)
     const uint4* hp = (const uint4*)d.src;
     uint32_t w[16];
     int rc = ZIPNN_OK;
@@ -420,7 +414,7 @@ __device__ bool load_tensor(const DecDesc& d, int di, TensorState& ts, int* stat
     ts.valid = rc == ZIPNN_OK;
     ts.items = 0;
     if (rc != ZIPNN_OK) {
-        if (report && threadIdx.x == 0) set_status(status, rc);
+        if (report) set_status(status, rc);
         return false;
     }
     const uint32_t Wf = (ts.h.E + ts.h.S - 1) / ts.h.S;
@@ -433,17 +427,22 @@ __device__ bool load_tensor(const DecDesc& d, int di, TensorState& ts, int* stat
     return true;
 }
 
+// One item: the B map entries are checked, each Huffman table becomes an LDS
+// lookup table, the lane groups' word counts are checked and prefixed, then
+// every wave decodes its lane group.
+template <int B, int G, bool DELTA>
 __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c, uint32_t slice,
-                            uint16_t (*lut)[kLutSize], LutTmp& T, ItemState& st, int* status)
+                            uint16_t (*lut)[kLutSize], uint32_t (*wprefix)[65], LutTmp& T, ItemState& st,
+                            int* status)
 {
     const Header& h = ts.h;
     const int t = threadIdx.x;
-    const uint32_t B = h.B;
     const uint32_t m = uint32_t(min(uint64_t(h.E), h.n - uint64_t(c) * h.E));
     const uint32_t W = (m + h.S - 1) / h.S;
+    const uint32_t NG = (W + 63) / 64;
     if (t == 0) st.err = 0;
     __syncthreads();
-    if (t < int(B)) {
+    if (t < B) {
         const uint64_t e = uint64_t(c) * B + t;
         const uint4 ent = *(const uint4*)(d.src + 64 + 16 * e);
         const uint64_t off = uint64_t(ent.x) | (uint64_t(ent.y) << 32);
@@ -453,7 +452,7 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
         if ((ent.w >> 16) != 0 || mode > 2) err = 1;
         if (mode == kModeRaw && (bytes != m || rle)) err = 1;
         if (mode == kModeRle && bytes != 0) err = 1;
-        if (mode == kModeHuf && (bytes < huf_head(W) || rle)) err = 1;
+        if (mode == kModeHuf && (bytes < huf_head(W) + 4 || ((bytes - huf_head(W)) & 3) || rle)) err = 1;
         if (off & 15) err = 1;
         // the exact placement: this entry starts where its predecessor ends
         uint64_t expect = 0;
@@ -476,9 +475,7 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
     }
     __syncthreads();
     if (st.err) return;
-    uint32_t bitstart[4] = {0, 0, 0, 0};
-    const uint32_t w = slice * kBlock + t;
-    for (uint32_t k = 0; k < B; k++) {
+    for (int k = 0; k < B; k++) {
         if (st.mode[k] != kModeHuf) continue;
         const uint8_t* p = d.src + st.pay[k];
         if (!build_lut(p, h.L, lut[k], T)) {
@@ -489,79 +486,66 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
             __syncthreads();
             return;
         }
-        const uint16_t* lens = (const uint16_t*)(p + 128);
-        uint32_t pre = 0, tot = 0, mine = 0;
-        for (uint32_t v = t; v < W; v += kBlock) {
-            uint32_t l = lens[v];
-            tot += l;
-            if (v < slice * kBlock) pre += l;
-            if (v == w) mine = l;
-        }
-        tot = block_sum(tot, T.red);
-        pre = block_sum(pre, T.red);
-        uint32_t dummy;
-        const uint32_t off = block_excl_scan(mine, T.red, &dummy);
-        bitstart[k] = pre + off;
-        // every symbol takes at least one bit, and the payload must end
-        // exactly where the bitstream does
-        if (tot < m || st.bytes[k] != huf_head(W) + (tot + 7) / 8) {
-            if (t == 0) {
-                st.err = 1;
-                set_status(status, ZIPNN_E_CORRUPT);
+        // word counts of the lane groups -> start of each lane group's words;
+        // every lane takes at least one word, and together they use the
+        // payload exactly
+        if (t < 64) {
+            const uint32_t lanes_here = (uint32_t(t) < NG) ? min(64u, W - 64u * t) : 0u;
+            const uint32_t nw = (uint32_t(t) < NG) ? ((const uint32_t*)(p + 128))[t] : 0u;
+            const uint32_t inc = wave_incl_scan(nw);
+            wprefix[k][t + 1] = inc;
+            if (t == 0) wprefix[k][0] = 0;
+            const bool bad = nw < lanes_here;
+            const uint32_t total = __shfl(inc, 63, 64);
+            if (__ballot(bad) != 0ull || uint64_t(total) * 4 + huf_head(W) != st.bytes[k]) {
+                if (t == 0) {
+                    st.err = 1;
+                    set_status(status, ZIPNN_E_CORRUPT);
+                }
             }
         }
         __syncthreads();
         if (st.err) return;
     }
-    if (w < W) {
+    const uint32_t j = slice * 4 + (t >> 6);
+    if (j < NG) {
         uint8_t* out = d.dst + uint64_t(c) * h.E * B;
-        const uint8_t* base = d.base ? d.base + uint64_t(c) * h.E * B : nullptr;
-        const uint16_t(*cl)[kLutSize] = lut;
-        switch (B * 16 + h.g) {
-#define ZIPNN_CASE(BB, GG)                                                                          \
-    case BB * 16 + GG:                                                                             \
-        decode_substream<BB, GG>(d.src, st, cl, h.L, w, W, m, bitstart, out, base, status);        \
-        break;
-            ZIPNN_CASE(1, 1)
-            ZIPNN_CASE(1, 2)
-            ZIPNN_CASE(1, 4)
-            ZIPNN_CASE(1, 8)
-            ZIPNN_CASE(2, 1)
-            ZIPNN_CASE(2, 2)
-            ZIPNN_CASE(2, 4)
-            ZIPNN_CASE(2, 8)
-            ZIPNN_CASE(4, 1)
-            ZIPNN_CASE(4, 2)
-            ZIPNN_CASE(4, 4)
-            ZIPNN_CASE(4, 8)
-#undef ZIPNN_CASE
-        default:
-            set_status(status, ZIPNN_E_FORMAT);
-        }
+        const uint8_t* base = DELTA ? d.base + uint64_t(c) * h.E * B : nullptr;
+        decode_lane_group<B, G, DELTA>(d.src, st, lut, wprefix, h.L, j, W, m, out, base, status);
     }
     __syncthreads();
 }
 
-// `descs` == nullptr: decode the single tensor `one` (its header parsed on
-// the device, no host round trip); otherwise the batch descs[0..n_desc) whose
-// per-tensor item counts were prefixed by k_plan.
+// `descs` == nullptr: decode the single tensor `one`; otherwise the batch
+// descs[0..n_desc) whose per-tensor item counts k_plan prefixed.  Every tensor
+// of a launch has B-byte words, groups of G and (for DELTA) an XOR base; a
+// header that disagrees is reported as ZIPNN_E_FORMAT.
+template <int B, int G, bool DELTA>
 __global__ __launch_bounds__(kBlock) void k_decode(DecDesc one, const DecDesc* __restrict__ descs, int n_desc,
                                                    const uint64_t* __restrict__ item_prefix, int* status)
 {
+    __shared__ uint16_t lut[B][kLutSize];
+    __shared__ uint32_t wprefix[B][65];
+    __shared__ LutTmp T;
+    __shared__ ItemState st;
+    __shared__ TensorState ts;
+    __shared__ uint64_t n_items_sh;
     if (descs == nullptr) {
         descs = &one;
         n_desc = 1;
         item_prefix = nullptr;
     }
-    __shared__ uint16_t lut[4][kLutSize];
-    __shared__ LutTmp T;
-    __shared__ ItemState st;
-    __shared__ TensorState ts;
-    __shared__ uint64_t n_items_sh;
+    auto matches = [&](const TensorState& x) {
+        return x.h.B == uint32_t(B) && x.h.g == uint32_t(G) && ((x.h.flags & kFlagDelta) != 0) == DELTA;
+    };
     if (threadIdx.x == 0) {
         ts.desc = -1;
         if (item_prefix == nullptr) {
-            load_tensor(descs[0], 0, ts, status, blockIdx.x == 0);
+            const bool ok = load_tensor(descs[0], 0, ts, status, blockIdx.x == 0);
+            if (ok && !matches(ts)) {
+                ts.valid = 0;
+                if (blockIdx.x == 0) set_status(status, ZIPNN_E_FORMAT);
+            }
             n_items_sh = ts.valid ? ts.items : 0;
         } else {
             n_items_sh = item_prefix[n_desc];
@@ -593,34 +577,66 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecDesc one, const DecDesc* _
             c = ts.h.n_chunks - 1;
             slice = uint32_t(local - full_items);
         }
-        decode_item(descs[ts.desc], ts, c, slice, lut, T, st, status);
+        decode_item<B, G, DELTA>(descs[ts.desc], ts, c, slice, lut, wprefix, T, st, status);
     }
 }
 
-// Batched plan: items per tensor -> exclusive prefix (one workgroup).
-__global__ __launch_bounds__(kBlock) void k_plan(const DecDesc* __restrict__ descs, int n_desc,
-                                                 uint64_t* __restrict__ prefix, int* status)
+// Batched plan: items per tensor -> exclusive prefix (one workgroup).  A
+// tensor whose header is invalid or does not match (B, G, DELTA) gets no
+// items and is reported.
+__global__ __launch_bounds__(kBlock) void k_plan(const DecDesc* __restrict__ descs, int n_desc, uint32_t B,
+                                                 uint32_t G, uint32_t delta, uint64_t* __restrict__ prefix,
+                                                 int* status)
 {
     __shared__ TensorState tsv[kBlock];
     __shared__ uint64_t carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int base = 0; base < n_desc; base += kBlock) {
-        const int i = base + threadIdx.x;
-        uint64_t items = 0;
-        if (i < n_desc && load_tensor(descs[i], i, tsv[threadIdx.x], status, true)) items = tsv[threadIdx.x].items;
+    for (int b0 = 0; b0 < n_desc; b0 += kBlock) {
+        const int i = b0 + threadIdx.x;
+        if (i < n_desc && load_tensor(descs[i], i, tsv[threadIdx.x], status, true)) {
+            const Header& h = tsv[threadIdx.x].h;
+            if (h.B != B || h.g != G || ((h.flags & kFlagDelta) != 0) != (delta != 0)) {
+                tsv[threadIdx.x].valid = 0;
+                set_status(status, ZIPNN_E_FORMAT);
+            }
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             uint64_t run = carry;
-            for (int j = 0; j < kBlock && base + j < n_desc; j++) {
-                prefix[base + j] = run;
+            for (int j = 0; j < kBlock && b0 + j < n_desc; j++) {
+                prefix[b0 + j] = run;
                 run += tsv[j].valid ? tsv[j].items : 0;
             }
             carry = run;
-            if (base + kBlock >= n_desc) prefix[n_desc] = run;
+            if (b0 + kBlock >= n_desc) prefix[n_desc] = run;
         }
         __syncthreads();
     }
+}
+
+__global__ void k_clear(int* p) { *p = 0; }
+
+template <int B, int G, bool D>
+hipError_t launch_k(const DecDesc& one, const DecDesc* descs, int n, const uint64_t* prefix, int* st, int grid,
+                    hipStream_t s)
+{
+    k_decode<B, G, D><<<grid, kBlock, 0, s>>>(one, descs, n, prefix, st);
+    return hipGetLastError();
+}
+
+hipError_t dispatch(uint32_t B, uint32_t G, bool delta, const DecDesc& one, const DecDesc* descs, int n,
+                    const uint64_t* prefix, int* st, int grid, hipStream_t s)
+{
+#define ZIPNN_K(BB, GG)                                                                              \
+    if (B == BB && G == GG)                                                                         \
+        return delta ? launch_k<BB, GG, true>(one, descs, n, prefix, st, grid, s)                   \
+                     : launch_k<BB, GG, false>(one, descs, n, prefix, st, grid, s);
+    ZIPNN_K(1, 2) ZIPNN_K(1, 4) ZIPNN_K(1, 8)
+    ZIPNN_K(2, 2) ZIPNN_K(2, 4) ZIPNN_K(2, 8)
+    ZIPNN_K(4, 2) ZIPNN_K(4, 4) ZIPNN_K(4, 8)
+#undef ZIPNN_K
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -630,29 +646,26 @@ int decode_grid_size(int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 1024;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode, kBlock, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode<2, 4, false>, kBlock, 0) != hipSuccess ||
+        per_cu < 1)
         per_cu = 4;
     return prop.multiProcessorCount * per_cu;
 }
 
-hipError_t launch_decode_one(const DecDesc& one, int* d_status, int grid, hipStream_t s)
+hipError_t launch_decode_one(const Header& h, const DecDesc& one, int* d_status, int grid, hipStream_t s)
 {
-    k_decode<<<grid, kBlock, 0, s>>>(one, nullptr, 1, nullptr, d_status);
-    return hipGetLastError();
+    return dispatch(h.B, h.g, (h.flags & kFlagDelta) != 0, one, nullptr, 1, nullptr, d_status, grid, s);
 }
 
-hipError_t launch_decode_batch(const DecDesc* d_descs, int n_desc, uint64_t* d_item_prefix, int* d_status, int grid,
-                               hipStream_t s)
+hipError_t launch_decode_batch(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
+                               uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s)
 {
-    k_plan<<<1, kBlock, 0, s>>>(d_descs, n_desc, d_item_prefix, d_status);
+    k_plan<<<1, kBlock, 0, s>>>(d_descs, n_desc, B, G, delta ? 1u : 0u, d_item_prefix, d_status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     DecDesc none = {};
-    k_decode<<<grid, kBlock, 0, s>>>(none, d_descs, n_desc, d_item_prefix, d_status);
-    return hipGetLastError();
+    return dispatch(B, G, delta, none, d_descs, n_desc, d_item_prefix, d_status, grid, s);
 }
-
-__global__ void k_clear(int* p) { *p = 0; }
 
 hipError_t launch_clear_status(int* d_status, hipStream_t s)
 {

@@ -1,23 +1,26 @@
 // Encode kernels of the gfx950 ZipNN codec.
 //
-//   k_analyze  one workgroup per chunk: reads the chunk once (16-byte loads,
-//              XOR with the base for a delta, paper §IV-B), splits every word
-//              into its B byte groups (paper §III-A/§III-B) and histograms
-//              each group in LDS; then wave k builds the code of group k:
-//              optimal lengths <= L by package-merge (Larmore & Hirschberg,
-//              computed with parallel ranks, see build_code), canonical codes
-//              (RFC 1951 §3.2.2), the coded size and the per-byte-group method
-//              (paper §V-A): RAW / RLE for a single value (paper §III-B) /
-//              HUF only if smaller than raw under AUTO.
+//   k_analyze  one workgroup per chunk: reads the chunk (16-byte loads, XOR
+//              with the base for a delta, paper §IV-B), splits every word into
+//              its B byte groups (paper §III-A/§III-B) and histograms each
+//              group in LDS; wave k then builds the code of group k: optimal
+//              lengths <= L by package-merge (Larmore & Hirschberg, computed
+//              with parallel ranks, see build_code) and canonical codes (RFC
+//              1951 §3.2.2).  A group with one value becomes RLE (paper §III-B);
+//              for a Huffman candidate the four waves replay the decoder's
+//              lock-step word requests lane group by lane group, which gives
+//              the exact payload size, so AUTO keeps Huffman only when it is
+//              strictly smaller than raw (paper §III-B, §V-A).
 //   k_place    one workgroup per tensor: exclusive scan of the 16-byte aligned
 //              payload sizes in chunk-major order -> map entries and header
 //              (the map that enables parallel decode, paper §V-A).
-//   k_pack     one workgroup per chunk: thread t owns sub-streams t, t+256, ...
-//              pass A sums code lengths per sub-stream, a block scan gives bit
-//              offsets, pass B writes the codes (bits shared with a neighbour
-//              sub-stream go through atomicOr on pre-zeroed dwords) and the
-//              RAW groups; every byte of the payload extent, padding included,
-//              is written.
+//   k_pack     one workgroup per chunk: raw groups are copied with 16-byte
+//              stores; for a Huffman group, wave v writes lane groups v, v+4,
+//              ...: its lanes replay the same rounds, and in every round the
+//              lanes that the decoder will serve write their next word to
+//              consecutive slots (ballot + prefix popcount), encoding codes
+//              ahead just far enough to fill that word.  Every byte of the
+//              payload extent, padding included, is written; no atomics.
 #include "zipnn_internal.h"
 
 namespace zipnn {
@@ -34,11 +37,12 @@ struct PmWave {                 // package-merge workspace of one wave
     uint32_t key[256];
     uint8_t len[256];           // code length per symbol
     uint32_t cnt[16];
+    uint32_t cand;              // 1: Huffman candidate (size decided by the replay)
 };
 
 union AnalyzeLds {
     uint32_t hist[kWaves][4][256];   // per-wave sub-histograms (phase 1)
-    PmWave pm[kWaves];               // per-wave code construction (phase 2)
+    PmWave pm[kWaves];               // per-wave code construction (phases 2, 3)
 };
 
 __device__ inline uint32_t wave_sum(uint32_t v)
@@ -94,6 +98,7 @@ __device__ void build_code(const uint32_t* f, uint32_t m, uint32_t W, uint32_t L
         d += __popcll(__ballot(fv[r] > 0));
     }
     for (int r = 0; r < 4; r++) codes[lane + 64 * r] = 0;
+    if (lane == 0) P.cand = 0;
     if (policy == ZIPNN_RAW || d <= 1) {
         if (lane == 0) {
             EncEntry e;
@@ -181,8 +186,9 @@ __device__ void build_code(const uint32_t* f, uint32_t m, uint32_t W, uint32_t L
         }
     }
     T = wave_sum(T);
-    const uint32_t size_huf = huf_head(W) + (T + 7) / 8;
-    if (policy == ZIPNN_AUTO && size_huf >= m) {
+    // a Huffman payload holds at least its head and ceil(T/8) bytes: if even
+    // that is not below raw, AUTO stores the group raw
+    if (policy == ZIPNN_AUTO && huf_head(W) + (T + 7) / 8 >= m) {
         if (lane == 0) {
             EncEntry e;
             e.pad = 0;
@@ -226,14 +232,8 @@ __device__ void build_code(const uint32_t* f, uint32_t m, uint32_t W, uint32_t L
     }
 #pragma unroll
     for (int r = 0; r < 4; r++) codes[lane + 64 * r] = l4[r] ? (rank4[r] | (l4[r] << 16)) : 0u;
-    if (lane == 0) {
-        EncEntry e;
-        e.pad = 0;
-        e.mode = kModeHuf;
-        e.rle = 0;
-        e.bytes = size_huf;
-        *entry = e;
-    }
+    // Huffman candidate: the exact size comes from the request replay
+    if (lane == 0) P.cand = 1;
 }
 
 __device__ inline int find_desc(const uint32_t* prefix, int n_desc, uint32_t g)
@@ -247,14 +247,126 @@ __device__ inline int find_desc(const uint32_t* prefix, int n_desc, uint32_t g)
     return lo;
 }
 
+// Load NB bytes (NB in {2,4,8,16,32,64}) from p into 32-bit words.
+template <int NB>
+__device__ inline void loadNB(const uint8_t* p, uint32_t* w)
+{
+    if constexpr (NB == 2) w[0] = *(const uint16_t*)p;
+    else if constexpr (NB == 4) w[0] = *(const uint32_t*)p;
+    else if constexpr (NB == 8) {
+        uint2 v = *(const uint2*)p;
+        w[0] = v.x;
+        w[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < NB / 16; i++) {
+            uint4 v = *(const uint4*)(p + 16 * i);
+            w[4 * i] = v.x;
+            w[4 * i + 1] = v.y;
+            w[4 * i + 2] = v.z;
+            w[4 * i + 3] = v.w;
+        }
+    }
+}
+
+// The words of group q of a chunk (g elements, XORed with the base), or of the
+// partial last group (zero beyond the chunk's m elements).
+template <int B, int G>
+__device__ inline void group_words(const uint8_t* src, const uint8_t* base, uint32_t q, uint32_t m, uint32_t* wd)
+{
+    constexpr int NB = B * G;
+    constexpr int NW = NB >= 4 ? NB / 4 : 1;
+    const uint32_t e = q * G;
+    if (e + G <= m) {
+        loadNB<NB>(src + uint64_t(e) * B, wd);
+        if (base) {
+            uint32_t bw[NW];
+            loadNB<NB>(base + uint64_t(e) * B, bw);
+#pragma unroll
+            for (int x = 0; x < NW; x++) wd[x] ^= bw[x];
+        }
+    } else {
+#pragma unroll
+        for (int x = 0; x < NW; x++) wd[x] = 0;
+        for (uint32_t jb = 0; jb < (m - e) * B; jb++) {
+            uint32_t v = src[uint64_t(e) * B + jb] ^ (base ? base[uint64_t(e) * B + jb] : 0u);
+            wd[jb >> 2] |= v << (8 * (jb & 3));
+        }
+    }
+}
+
+// byte of stream k of element i of a group's words
+template <int B>
+__device__ inline uint32_t sym_of(const uint32_t* wd, int k, int i)
+{
+    const int jb = i * B + (B - 1 - k);
+    return (wd[jb >> 2] >> (8 * (jb & 3))) & 0xFFu;
+}
+
+// Replay the decoder's word requests for lane group j of one chunk and count
+// the words each Huffman candidate stream takes (returned per stream by lane
+// 0 of the wave).
+template <int B, int G>
+__device__ void count_lane_group(const uint8_t* src, const uint8_t* base, const uint32_t* candmask_p,
+                                 const uint8_t (*lens)[256], uint32_t L, uint32_t j, uint32_t W, uint32_t m,
+                                 uint32_t* words_out)
+{
+    constexpr int NB = B * G;
+    constexpr int NW = NB >= 4 ? NB / 4 : 1;
+    const uint32_t cand = *candmask_p;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t w = 64 * j + lane;
+    const int twoL = int(2 * L);
+    const uint32_t Gtot = (m + G - 1) / G, Gfull = m / G, rem = m - Gfull * G;
+    const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;
+    int cnt[B];
+    uint32_t req[B];
+#pragma unroll
+    for (int k = 0; k < B; k++) cnt[k] = 0, req[k] = 0;
+    for (uint32_t jj = 0; jj < ng; jj++) {
+        const uint32_t q = w + jj * W;
+        const uint32_t gcnt = q < Gfull ? G : rem;
+        uint32_t wd[NW];
+        group_words<B, G>(src, base, q, m, wd);
+#pragma unroll
+        for (int k = 0; k < B; k++) {
+            if (!((cand >> k) & 1)) continue;
+#pragma unroll
+            for (int pr = 0; pr < G / 2; pr++) {
+                if (2u * pr < gcnt) {
+                    if (cnt[k] < twoL) {
+                        cnt[k] += 32;
+                        req[k]++;
+                    }
+                    cnt[k] -= lens[k][sym_of<B>(wd, k, 2 * pr)];
+                    if (2u * pr + 1 < gcnt) cnt[k] -= lens[k][sym_of<B>(wd, k, 2 * pr + 1)];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < B; k++) {
+        const uint32_t tot = wave_sum(req[k]);
+        if (lane == 0) words_out[k] = tot;
+    }
+}
+
+struct AnalyzeTail {
+    uint8_t lens[4][256];
+    uint32_t cand;           // bit k: stream k is a Huffman candidate
+    uint32_t words[4];       // words over all lane groups, per stream
+    uint32_t lg_words[kWaves][4];
+};
+
 __global__ __launch_bounds__(kBlock) void k_analyze(EncDesc one, const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                     EncParams p, EncEntry* __restrict__ entries,
-                                                    CodeWord* __restrict__ codes)
+                                                    CodeWord* __restrict__ codes, uint32_t* __restrict__ nwords)
 {
     __shared__ AnalyzeLds S;
     __shared__ uint32_t hist[4][256];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    __shared__ AnalyzeTail A;
+    const int t = threadIdx.x, wv = t >> 6;
     const uint32_t B = p.B;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
         const int di = descs ? find_desc(chunk_prefix, n_desc, gc) : 0;
@@ -263,7 +375,10 @@ __global__ __launch_bounds__(kBlock) void k_analyze(EncDesc one, const EncDesc* 
         const uint32_t E = p.chunk / B;
         const uint64_t e0 = uint64_t(c) * E;
         const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
+        const uint32_t W = (m + p.S - 1) / p.S;
+        const uint32_t NG = (W + 63) / 64;
         for (uint32_t i = t; i < kWaves * 4 * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
+        if (t < 4) A.words[t] = 0;
         __syncthreads();
         const uint8_t* src = d.src + e0 * B;
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
@@ -282,9 +397,9 @@ __global__ __launch_bounds__(kBlock) void k_analyze(EncDesc one, const EncDesc* 
             }
             const uint32_t wds[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
-                const uint32_t byte = (wds[j >> 2] >> (8 * (j & 3))) & 0xFF;
-                const int k = int(B) - 1 - (j % int(B));   // byte j%B of a word -> stream B-1-j%B
+            for (int jb = 0; jb < 16; jb++) {
+                const uint32_t byte = (wds[jb >> 2] >> (8 * (jb & 3))) & 0xFF;
+                const int k = int(B) - 1 - (jb % int(B));   // byte jb%B of a word -> stream B-1-jb%B
                 atomicAdd(&h[k][byte], 1u);
             }
         }
@@ -299,12 +414,69 @@ __global__ __launch_bounds__(kBlock) void k_analyze(EncDesc one, const EncDesc* 
         }
         __syncthreads();
         if (uint32_t(wv) < B) {
-            const uint32_t W = (m + p.S - 1) / p.S;
             const uint64_t ei = uint64_t(gc) * B + wv;
             build_code(hist[wv], m, W, p.L, p.policy[wv], S.pm[wv], codes + ei * 256, entries + ei);
         }
         __syncthreads();
-        (void)lane;
+        if (t == 0) {
+            uint32_t cm = 0;
+            for (uint32_t k = 0; k < B; k++) cm |= S.pm[k].cand << k;
+            A.cand = cm;
+        }
+        for (uint32_t i = t; i < 4 * 256; i += kBlock) {
+            const uint32_t k = i >> 8;
+            A.lens[k][i & 255] = k < B ? S.pm[k].len[i & 255] : 0;
+        }
+        __syncthreads();
+        if (A.cand) {
+            // replay the word requests, one lane group per wave
+            for (uint32_t j0 = 0; j0 < NG; j0 += kWaves) {
+                const uint32_t j = j0 + wv;
+                if (j < NG) {
+                    switch (B * 16 + p.g) {
+#define ZIPNN_CASE(BB, GG)                                                                       \
+    case BB * 16 + GG:                                                                          \
+        count_lane_group<BB, GG>(src, base, &A.cand, A.lens, p.L, j, W, m, A.lg_words[wv]);     \
+        break;
+                        ZIPNN_CASE(1, 2)
+                        ZIPNN_CASE(1, 4)
+                        ZIPNN_CASE(1, 8)
+                        ZIPNN_CASE(2, 2)
+                        ZIPNN_CASE(2, 4)
+                        ZIPNN_CASE(2, 8)
+                        ZIPNN_CASE(4, 2)
+                        ZIPNN_CASE(4, 4)
+                        ZIPNN_CASE(4, 8)
+#undef ZIPNN_CASE
+                    default:
+                        break;
+                    }
+                    if ((t & 63) == 0) {
+                        for (uint32_t k = 0; k < B; k++) {
+                            if (!((A.cand >> k) & 1)) continue;
+                            nwords[(uint64_t(gc) * B + k) * 64 + j] = A.lg_words[wv][k];
+                            atomicAdd(&A.words[k], A.lg_words[wv][k]);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (uint32_t(t) < B && ((A.cand >> t) & 1)) {
+            const uint32_t size = huf_head(W) + 4 * A.words[t];
+            EncEntry e;
+            e.pad = 0;
+            e.rle = 0;
+            if (p.policy[t] == ZIPNN_AUTO && size >= m) {
+                e.mode = kModeRaw;
+                e.bytes = m;
+            } else {
+                e.mode = kModeHuf;
+                e.bytes = size;
+            }
+            entries[uint64_t(gc) * B + t] = e;
+        }
+        __syncthreads();
     }
 }
 
@@ -328,7 +500,6 @@ __global__ __launch_bounds__(kBlock) void k_place(EncDesc one, const EncDesc* __
         EncEntry en = {0, 0, 0, 0};
         if (e < ne) en = entries[e_first + e];
         uint64_t sz = align16(en.bytes);
-        // inclusive wave scan
         uint64_t inc = sz;
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
@@ -375,239 +546,116 @@ __global__ __launch_bounds__(kBlock) void k_place(EncDesc one, const EncDesc* __
     }
 }
 
-// Load NB bytes (NB in {1,2,4,8,16,32}) from p into 32-bit words.
-template <int NB>
-__device__ inline void loadNB(const uint8_t* p, uint32_t* w)
+// Write the words of lane group j of one Huffman stream k: every lane replays
+// the decoder's rounds; when the decoder would hand this lane a word, the lane
+// encodes its next codes until 32 bits are ready (or its symbols run out) and
+// stores the word at the cursor + its rank among this round's takers.
+template <int B, int G>
+__device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode,
+                                uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out)
 {
-    if constexpr (NB == 1) w[0] = p[0];
-    else if constexpr (NB == 2) w[0] = *(const uint16_t*)p;
-    else if constexpr (NB == 4) w[0] = *(const uint32_t*)p;
-    else if constexpr (NB == 8) {
-        uint2 v = *(const uint2*)p;
-        w[0] = v.x;
-        w[1] = v.y;
-    } else if constexpr (NB == 16) {
-        uint4 v = *(const uint4*)p;
-        w[0] = v.x;
-        w[1] = v.y;
-        w[2] = v.z;
-        w[3] = v.w;
-    } else {
-        uint4 v = *(const uint4*)p, u = *(const uint4*)(p + 16);
-        w[0] = v.x;
-        w[1] = v.y;
-        w[2] = v.z;
-        w[3] = v.w;
-        w[4] = u.x;
-        w[5] = u.y;
-        w[6] = u.z;
-        w[7] = u.w;
+    constexpr int NB = B * G;
+    constexpr int NW = NB >= 4 ? NB / 4 : 1;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t w = 64 * j + lane;
+    const int twoL = int(2 * L);
+    const uint32_t Gtot = (m + G - 1) / G, Gfull = m / G, rem = m - Gfull * G;
+    const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;
+    const uint32_t ng_max = __builtin_amdgcn_readfirstlane(ng);
+    int cnt = 0;             // bits the decoder would hold
+    uint32_t ptr = 0;        // words of this lane group written so far
+    uint64_t eb = 0;         // encoded bits not yet written
+    uint32_t en = 0;
+    uint32_t eq = 0;         // encoder: group index (within the lane) and symbol in it
+    uint32_t ei = 0;
+    uint32_t ew[NW];
+    for (uint32_t jj = 0; jj < ng_max; jj++) {
+        const uint32_t q = w + jj * W;
+        const bool has = jj < ng;
+        const uint32_t gcnt = !has ? 0u : (q < Gfull ? G : rem);
+        uint32_t wd[NW];
+        if (has) group_words<B, G>(src, base, q, m, wd);
+#pragma unroll
+        for (int pr = 0; pr < G / 2; pr++) {
+            const bool part = 2u * pr < gcnt;
+            const bool need = part && cnt < twoL;
+            const uint64_t msk = __ballot(need);
+            const uint32_t below =
+                __builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(msk), 0u));
+            if (need) {
+                while (en < 32 && eq < ng) {
+                    const uint32_t qe = w + eq * W;
+                    const uint32_t ecnt = qe < Gfull ? G : rem;
+                    if (ei == 0) group_words<B, G>(src, base, qe, m, ew);
+                    const uint32_t cw = rcode[sym_of<B>(ew, k, int(ei))];
+                    eb |= uint64_t(cw & 0xFFFFu) << en;
+                    en += cw >> 16;
+                    if (++ei == ecnt) {
+                        ei = 0;
+                        eq++;
+                    }
+                }
+                out[ptr + below] = uint32_t(eb);
+                eb >>= 32;
+                en = en > 32 ? en - 32 : 0;
+                cnt += 32;
+            }
+            ptr += uint32_t(__popcll(msk));
+            if (part) {
+                cnt -= int(rcode[sym_of<B>(wd, k, 2 * pr)] >> 16);
+                if (2u * pr + 1 < gcnt) cnt -= int(rcode[sym_of<B>(wd, k, 2 * pr + 1)] >> 16);
+            }
+        }
     }
-}
-
-template <int G>
-__device__ inline void storeG(uint8_t* p, uint32_t v0, uint32_t v1)
-{
-    if constexpr (G == 1) p[0] = uint8_t(v0);
-    else if constexpr (G == 2) *(uint16_t*)p = uint16_t(v0);
-    else if constexpr (G == 4) *(uint32_t*)p = v0;
-    else *(uint2*)p = make_uint2(v0, v1);
 }
 
 struct PackLds {
     uint32_t rcode[4][256];     // reversed code | length << 16
     uint64_t pay[4];            // absolute payload offset of each stream
     uint32_t mode[4];
-    uint32_t red[kWaves];
-    uint32_t tot[4];
+    uint32_t bytes[4];
+    uint32_t wpre[4][65];       // lane-group word prefix per stream
 };
 
-// Sub-stream passes for one chunk; B, G compile-time.
-template <int B, int G>
-__device__ void pack_chunk(const uint8_t* __restrict__ src, const uint8_t* __restrict__ base, uint8_t* __restrict__ dst,
-                           uint32_t m, uint32_t W, PackLds& P, uint32_t* offs /* [B][W] in LDS */)
+// Raw groups of one chunk: thread t copies elements [16u, 16u+16) of every
+// RAW stream with one 16-byte store each.
+template <int B>
+__device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, const PackLds& P, uint32_t m)
 {
-    int mode[B];
-    uint64_t pay_abs[B];
+    uint32_t rawmask = 0;
+    for (int k = 0; k < B; k++)
+        if (P.mode[k] == kModeRaw) rawmask |= 1u << k;
+    if (!rawmask) return;
+    const uint32_t units = m / 16;
+    for (uint32_t u = threadIdx.x; u < units; u += kBlock) {
+        uint32_t wd[4 * B];
+        loadNB<16 * B>(src + uint64_t(u) * 16 * B, wd);
+        if (base) {
+            uint32_t bw[4 * B];
+            loadNB<16 * B>(base + uint64_t(u) * 16 * B, bw);
 #pragma unroll
-    for (int k = 0; k < B; k++) {
-        mode[k] = __builtin_amdgcn_readfirstlane(P.mode[k]);
-        pay_abs[k] = P.pay[k];
-    }
-    constexpr int NB = B * G;
-    constexpr int NW = NB >= 4 ? NB / 4 : 1;
-    const int t = threadIdx.x;
-    const uint32_t Gfull = m / G;
-    const uint32_t rem = m - Gfull * G;
-    const uint32_t Gall = Gfull + (rem ? 1 : 0);
-    bool any_huf = false;
-#pragma unroll
-    for (int k = 0; k < B; k++) any_huf |= mode[k] == kModeHuf;
-
-    // stream byte i of group word array
-    auto sym_of = [&](const uint32_t* wd, int k, int i) -> uint32_t {
-        const int j = i * B + (B - 1 - k);
-        return (wd[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-    };
-    auto load_words = [&](uint32_t q, uint32_t* wd) {
-        const uint32_t e = q * G;
-        if (q < Gfull) {
-            loadNB<NB>(src + uint64_t(e) * B, wd);
-            if (base) {
-                uint32_t bw[NW];
-                loadNB<NB>(base + uint64_t(e) * B, bw);
-#pragma unroll
-                for (int x = 0; x < NW; x++) wd[x] ^= bw[x];
-            }
-        } else {
-#pragma unroll
-            for (int x = 0; x < NW; x++) wd[x] = 0;
-            for (uint32_t j = 0; j < rem * B; j++) {
-                uint32_t v = src[uint64_t(e) * B + j] ^ (base ? base[uint64_t(e) * B + j] : 0);
-                wd[j >> 2] |= v << (8 * (j & 3));
-            }
-        }
-    };
-    const uint32_t head = huf_head(W);
-    if (any_huf) {
-        // pass A: bit length of every sub-stream
-        for (uint32_t w = t; w < W; w += kBlock) {
-            uint32_t acc[B];
-#pragma unroll
-            for (int k = 0; k < B; k++) acc[k] = 0;
-            for (uint32_t q = w; q < Gall; q += W) {
-                uint32_t wd[NW];
-                load_words(q, wd);
-                const int cnt = q < Gfull ? G : int(rem);
-#pragma unroll
-                for (int k = 0; k < B; k++) {
-                    if (mode[k] != kModeHuf) continue;
-#pragma unroll
-                    for (int i = 0; i < G; i++)
-                        if (i < cnt) acc[k] += P.rcode[k][sym_of(wd, k, i)] >> 16;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < B; k++) offs[k * W + w] = acc[k];
-        }
-        __syncthreads();
-    }
-    // per HUF stream: write the lengths, turn them into start bits in place
-    // (block scan), zero the dwords shared by two sub-streams and the padding
-#pragma unroll
-    for (int k = 0; k < B; k++) {
-        if (mode[k] != kModeHuf) continue;
-        uint8_t* pay = dst + pay_abs[k];
-        uint32_t* bs = (uint32_t*)(pay + head);
-        // block-wide exclusive scan over W in chunks of 256
-        uint32_t carry = 0;
-        for (uint32_t b0 = 0; b0 < W; b0 += kBlock) {
-            const uint32_t w = b0 + t;
-            const uint32_t l = w < W ? offs[k * W + w] : 0;
-            uint32_t inc = l;
-            const int lane = t & 63, wv = t >> 6;
-#pragma unroll
-            for (int dd = 1; dd < 64; dd <<= 1) {
-                uint32_t o = __shfl_up(inc, dd, 64);
-                if (lane >= dd) inc += o;
-            }
-            if (lane == 63) P.red[wv] = inc;
-            __syncthreads();
-            uint32_t pre = carry, tot = carry;
-            for (int i = 0; i < kWaves; i++) {
-                pre += i < wv ? P.red[i] : 0;
-                tot += P.red[i];
-            }
-            __syncthreads();
-            const uint32_t off = pre + inc - l;
-            if (w < W) {
-                offs[k * W + w] = off;
-                ((uint16_t*)(pay + 128))[w] = uint16_t(l);
-                bs[off >> 5] = 0;   // dword holding the start of this sub-stream
-            }
-            carry = tot;
-        }
-        if (t == 0) P.tot[k] = carry;
-        // nibble table
-        if (t < 128) pay[t] = uint8_t((P.rcode[k][2 * t] >> 16) | ((P.rcode[k][2 * t + 1] >> 16) << 4));
-        // zero pad between the lengths and the bitstream
-        for (uint32_t i = 128 + 2 * W + t; i < head; i += kBlock) pay[i] = 0;
-        __syncthreads();
-        // zero from the dword holding the last bit to the aligned end
-        const uint32_t T = P.tot[k];
-        const uint32_t end_bytes = uint32_t(align16(head + (T + 7) / 8));
-        const uint32_t first_dw = T ? (T - 1) >> 5 : 0;
-        for (uint32_t i = first_dw + t; i < (end_bytes - head) / 4; i += kBlock) bs[i] = 0;
-    }
-    // RAW padding
-#pragma unroll
-    for (int k = 0; k < B; k++) {
-        if (mode[k] != kModeRaw) continue;
-        uint8_t* pay = dst + pay_abs[k];
-        for (uint32_t i = m + t; i < uint32_t(align16(m)); i += kBlock) pay[i] = 0;
-    }
-    __threadfence();
-    __syncthreads();
-    // pass B: codes and raw bytes
-    for (uint32_t w = t; w < W; w += kBlock) {
-        uint64_t acc[B];
-        uint32_t nacc[B], di[B];
-        bool first[B];
-#pragma unroll
-        for (int k = 0; k < B; k++) {
-            uint32_t o = (mode[k] == kModeHuf) ? offs[k * W + w] : 0;
-            acc[k] = 0;
-            nacc[k] = o & 31;
-            di[k] = o >> 5;
-            first[k] = (o & 31) != 0;
-        }
-        for (uint32_t q = w; q < Gall; q += W) {
-            uint32_t wd[NW];
-            load_words(q, wd);
-            const int cnt = q < Gfull ? G : int(rem);
-            const uint32_t e = q * G;
-#pragma unroll
-            for (int k = 0; k < B; k++) {
-                if (mode[k] == kModeRaw) {
-                    uint8_t* pay = dst + pay_abs[k];
-                    if (cnt == G) {
-                        uint32_t v0 = 0, v1 = 0;
-#pragma unroll
-                        for (int i = 0; i < G; i++) {
-                            if (i < 4) v0 |= sym_of(wd, k, i) << (8 * i);
-                            else v1 |= sym_of(wd, k, i) << (8 * (i - 4));
-                        }
-                        storeG<G>(pay + e, v0, v1);
-                    } else {
-                        for (int i = 0; i < cnt; i++) pay[e + i] = uint8_t(sym_of(wd, k, i));
-                    }
-                } else if (mode[k] == kModeHuf) {
-                    uint32_t* bs = (uint32_t*)(dst + pay_abs[k] + head);
-#pragma unroll
-                    for (int i = 0; i < G; i++) {
-                        if (i < cnt) {
-                            const uint32_t cw = P.rcode[k][sym_of(wd, k, i)];
-                            acc[k] |= uint64_t(cw & 0xFFFFu) << nacc[k];
-                            nacc[k] += cw >> 16;
-                            if (nacc[k] >= 32) {
-                                if (first[k]) atomicOr(&bs[di[k]], uint32_t(acc[k]));
-                                else bs[di[k]] = uint32_t(acc[k]);
-                                first[k] = false;
-                                acc[k] >>= 32;
-                                nacc[k] -= 32;
-                                di[k]++;
-                            }
-                        }
-                    }
-                }
-            }
+            for (int x = 0; x < 4 * B; x++) wd[x] ^= bw[x];
         }
 #pragma unroll
         for (int k = 0; k < B; k++) {
-            if (mode[k] == kModeHuf && nacc[k] > 0) {
-                uint32_t* bs = (uint32_t*)(dst + pay_abs[k] + head);
-                atomicOr(&bs[di[k]], uint32_t(acc[k]));
+            if (!((rawmask >> k) & 1)) continue;
+            uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < 16; i++) o[i >> 2] |= sym_of<B>(wd, k, i) << (8 * (i & 3));
+            *(uint4*)(dst + P.pay[k] + 16 * u) = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+    }
+    // tail elements, then zero padding to 16 bytes
+    for (uint32_t e = units * 16 + threadIdx.x; e < uint32_t(align16(m)); e += kBlock) {
+#pragma unroll
+        for (int k = 0; k < B; k++) {
+            if (!((rawmask >> k) & 1)) continue;
+            uint32_t v = 0;
+            if (e < m) {
+                const uint64_t o = uint64_t(e) * B + (B - 1 - k);
+                v = src[o] ^ (base ? base[o] : 0u);
             }
+            dst[P.pay[k] + e] = uint8_t(v);
         }
     }
 }
@@ -617,11 +665,11 @@ __global__ __launch_bounds__(kBlock) void k_pack(EncDesc one, const EncDesc* __r
                                                  EncParams p, const EncEntry* __restrict__ entries,
                                                  const CodeWord* __restrict__ codes,
                                                  const uint64_t* __restrict__ offsets,
-                                                 const uint64_t* __restrict__ totals)
+                                                 const uint64_t* __restrict__ totals,
+                                                 const uint32_t* __restrict__ nwords)
 {
     __shared__ PackLds P;
-    extern __shared__ uint32_t offs_dyn[];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, wv = t >> 6;
     const uint32_t B = p.B;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
         const int di = descs ? find_desc(chunk_prefix, n_desc, gc) : 0;
@@ -632,43 +680,73 @@ __global__ __launch_bounds__(kBlock) void k_pack(EncDesc one, const EncDesc* __r
         const uint64_t e0 = uint64_t(c) * E;
         const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
         const uint32_t W = (m + p.S - 1) / p.S;
+        const uint32_t NG = (W + 63) / 64;
+        const uint32_t head = huf_head(W);
         const uint64_t payload_base = 64 + 16ull * d.n_chunks * B;
         for (uint32_t k = 0; k < B; k++) {
             const uint64_t ei = uint64_t(gc) * B + k;
-            const uint32_t mode = entries[ei].mode;
+            const EncEntry en = entries[ei];
             if (t == 0) {
-                P.mode[k] = mode;
+                P.mode[k] = en.mode;
+                P.bytes[k] = en.bytes;
                 P.pay[k] = payload_base + offsets[ei];
             }
-            if (mode == kModeHuf) {
+            if (en.mode == kModeHuf) {
                 const uint32_t cw = codes[ei * 256 + t];
                 const uint32_t l = cw >> 16;
                 P.rcode[k][t] = l ? ((__brev(cw & 0xFFFFu) >> (32 - l)) | (l << 16)) : 0u;
+                if (t < 64) {
+                    const uint32_t nw = uint32_t(t) < NG ? nwords[ei * 64 + t] : 0u;
+                    uint32_t inc = nw;
+#pragma unroll
+                    for (int dd = 1; dd < 64; dd <<= 1) {
+                        uint32_t o = __shfl_up(inc, dd, 64);
+                        if (t >= dd) inc += o;
+                    }
+                    P.wpre[k][t + 1] = inc;
+                    if (t == 0) P.wpre[k][0] = 0;
+                }
             }
         }
         __syncthreads();
         const uint8_t* src = d.src + e0 * B;
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
-        switch (B * 16 + p.g) {
-#define ZIPNN_CASE(BB, GG)                                                                                 \
-    case BB * 16 + GG:                                                                                    \
-        pack_chunk<BB, GG>(src, base, d.dst, m, W, P, offs_dyn);                                          \
+        uint8_t* dst = d.dst;
+        switch (B) {
+        case 1: pack_raw<1>(src, base, dst, P, m); break;
+        case 2: pack_raw<2>(src, base, dst, P, m); break;
+        case 4: pack_raw<4>(src, base, dst, P, m); break;
+        default: break;
+        }
+        for (uint32_t k = 0; k < B; k++) {
+            if (P.mode[k] != kModeHuf) continue;
+            uint8_t* pay = dst + P.pay[k];
+            // head: nibble table, word counts, zero pad; zero pad after words
+            if (t < 128) pay[t] = uint8_t((P.rcode[k][2 * t] >> 16) | ((P.rcode[k][2 * t + 1] >> 16) << 4));
+            if (uint32_t(t) < NG) ((uint32_t*)(pay + 128))[t] = P.wpre[k][t + 1] - P.wpre[k][t];
+            for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
+            for (uint32_t i = P.bytes[k] + t; i < uint32_t(align16(P.bytes[k])); i += kBlock) pay[i] = 0;
+            uint32_t* words = (uint32_t*)(pay + head);
+            for (uint32_t j = wv; j < NG; j += kWaves) {
+                switch (B * 16 + p.g) {
+#define ZIPNN_CASE(BB, GG)                                                                                     \
+    case BB * 16 + GG:                                                                                        \
+        pack_lane_group<BB, GG>(src, base, int(k), P.rcode[k], p.L, j, W, m, words + P.wpre[k][j]);          \
         break;
-            ZIPNN_CASE(1, 1)
-            ZIPNN_CASE(1, 2)
-            ZIPNN_CASE(1, 4)
-            ZIPNN_CASE(1, 8)
-            ZIPNN_CASE(2, 1)
-            ZIPNN_CASE(2, 2)
-            ZIPNN_CASE(2, 4)
-            ZIPNN_CASE(2, 8)
-            ZIPNN_CASE(4, 1)
-            ZIPNN_CASE(4, 2)
-            ZIPNN_CASE(4, 4)
-            ZIPNN_CASE(4, 8)
+                    ZIPNN_CASE(1, 2)
+                    ZIPNN_CASE(1, 4)
+                    ZIPNN_CASE(1, 8)
+                    ZIPNN_CASE(2, 2)
+                    ZIPNN_CASE(2, 4)
+                    ZIPNN_CASE(2, 8)
+                    ZIPNN_CASE(4, 2)
+                    ZIPNN_CASE(4, 4)
+                    ZIPNN_CASE(4, 8)
 #undef ZIPNN_CASE
-        default:
-            break;
+                default:
+                    break;
+                }
+            }
         }
         __syncthreads();
     }
@@ -678,11 +756,11 @@ __global__ __launch_bounds__(kBlock) void k_pack(EncDesc one, const EncDesc* __r
 
 hipError_t launch_analyze(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
                           uint32_t total_chunks, const EncParams& p, EncEntry* entries, CodeWord* codes,
-                          hipStream_t s)
+                          uint32_t* nwords, hipStream_t s)
 {
     if (!total_chunks) return hipSuccess;
     const uint32_t grid = min(total_chunks, 1u << 16);
-    k_analyze<<<grid, kBlock, 0, s>>>(one, d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes);
+    k_analyze<<<grid, kBlock, 0, s>>>(one, d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
     return hipGetLastError();
 }
 
@@ -695,14 +773,12 @@ hipError_t launch_place(const EncDesc& one, const EncDesc* d_descs, int n_desc, 
 
 hipError_t launch_pack(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
                        uint32_t total_chunks, const EncParams& p, const EncEntry* entries, const CodeWord* codes,
-                       const uint64_t* offsets, const uint64_t* d_totals, hipStream_t s)
+                       const uint64_t* offsets, const uint64_t* d_totals, const uint32_t* nwords, hipStream_t s)
 {
     if (!total_chunks) return hipSuccess;
     const uint32_t grid = min(total_chunks, 1u << 16);
-    const uint32_t Wmax = (p.chunk / p.B + p.S - 1) / p.S;
-    const size_t lds = size_t(p.B) * Wmax * sizeof(uint32_t);
-    k_pack<<<grid, kBlock, lds, s>>>(one, d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, offsets,
-                                     d_totals);
+    k_pack<<<grid, kBlock, 0, s>>>(one, d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, offsets,
+                                   d_totals, nwords);
     return hipGetLastError();
 }
 

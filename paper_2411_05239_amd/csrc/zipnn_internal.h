@@ -12,7 +12,9 @@ namespace zipnn {
 constexpr uint32_t kMinChunk = 256;
 constexpr uint32_t kMaxChunk = 4u << 20;
 constexpr uint32_t kMaxS = 4096;
+constexpr uint32_t kMinG = 2;
 constexpr uint32_t kMaxG = 8;
+constexpr uint32_t kLanes = 64;             // sub-streams per lane group (one wave)
 constexpr uint32_t kMinL = 8;
 constexpr uint32_t kMaxL = 11;
 constexpr uint32_t kMaxW = 4096;           // sub-streams per chunk and stream
@@ -33,14 +35,18 @@ __host__ __device__ inline int dtype_bytes(int dt)
 __host__ __device__ inline int check_params(int B, uint32_t chunk, uint32_t S, uint32_t g, uint32_t L)
 {
     if (!B || !pow2(chunk) || chunk < kMinChunk || chunk > kMaxChunk) return ZIPNN_E_INVAL;
-    if (!pow2(g) || g > kMaxG || !pow2(S) || S < g || S > kMaxS) return ZIPNN_E_INVAL;
+    if (!pow2(g) || g < kMinG || g > kMaxG || !pow2(S) || S < g || S > kMaxS) return ZIPNN_E_INVAL;
     if (L < kMinL || L > kMaxL) return ZIPNN_E_INVAL;
     if (chunk / uint32_t(B) / S > kMaxW || chunk / S > kMaxBW) return ZIPNN_E_INVAL;
     return ZIPNN_OK;
 }
 
-// Size of the part of a HUF payload that precedes the bitstream.
-__host__ __device__ inline uint32_t huf_head(uint32_t W) { return uint32_t(align16(128u + 2u * W)); }
+// Size of the part of a HUF payload that precedes its words: the nibble
+// table and one u32 word count per lane group, padded to 16 bytes.
+__host__ __device__ inline uint32_t huf_head(uint32_t W)
+{
+    return uint32_t(align16(128u + 4u * ((W + kLanes - 1) / kLanes)));
+}
 
 struct Header {
     uint64_t n, total, payload_base;
@@ -113,20 +119,21 @@ struct EncParams {
 
 // Launchers (decode.hip / encode.hip).  A null descriptor array means "the
 // single tensor passed by value".
-hipError_t launch_decode_one(const DecDesc& one, int* d_status, int grid, hipStream_t s);
-hipError_t launch_decode_batch(const DecDesc* d_descs, int n_desc, uint64_t* d_item_prefix, int* d_status, int grid,
-                               hipStream_t s);
+// Decode kernels are specialised on (B, g, delta) taken from the header.
+hipError_t launch_decode_one(const Header& h, const DecDesc& one, int* d_status, int grid, hipStream_t s);
+hipError_t launch_decode_batch(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
+                               uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s);
 hipError_t launch_clear_status(int* d_status, hipStream_t s);
 int decode_grid_size(int device);
 
 hipError_t launch_analyze(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
                           uint32_t total_chunks, const EncParams& p, EncEntry* entries, CodeWord* codes,
-                          hipStream_t s);
+                          uint32_t* nwords /* 64 per entry */, hipStream_t s);
 hipError_t launch_place(const EncDesc& one, const EncDesc* d_descs, int n_desc, const EncParams& p,
                         const EncEntry* entries, uint64_t* d_offsets /* per entry */,
                         uint64_t* d_totals /* per desc */, hipStream_t s);
 hipError_t launch_pack(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
                        uint32_t total_chunks, const EncParams& p, const EncEntry* entries, const CodeWord* codes,
-                       const uint64_t* offsets, const uint64_t* d_totals, hipStream_t s);
+                       const uint64_t* offsets, const uint64_t* d_totals, const uint32_t* nwords, hipStream_t s);
 
 }  // namespace zipnn

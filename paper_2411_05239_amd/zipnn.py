@@ -24,7 +24,8 @@ WIDTH = {ZIPNN_BF16: 2, ZIPNN_FP16: 2, ZIPNN_FP32: 4, ZIPNN_FP8_E4M3: 1, ZIPNN_U
 # every symbol declared in include/zipnn.h
 EXPORTS = [
     "zipnn_strerror", "zipnn_ctx_create", "zipnn_ctx_destroy", "zipnn_ctx_status", "zipnn_default_params",
-    "zipnn_check_params", "zipnn_compress_bound", "zipnn_compress", "zipnn_decompress", "zipnn_inspect",
+    "zipnn_check_params", "zipnn_compress_bound", "zipnn_compress", "zipnn_decompress", "zipnn_decompress_async",
+    "zipnn_inspect",
 ]
 
 
@@ -73,6 +74,8 @@ def lib():
         L.zipnn_compress.argtypes = [vp, vp, i32, u64, vp, P(zipnn_params), vp, u64, P(u64), vp]
         L.zipnn_compress.restype = i32
         L.zipnn_decompress.argtypes, L.zipnn_decompress.restype = [vp, vp, u64, vp, vp, u64, vp], i32
+        L.zipnn_decompress_async.argtypes = [vp, ctypes.c_char_p, vp, u64, vp, vp, u64, vp]
+        L.zipnn_decompress_async.restype = i32
         L.zipnn_inspect.argtypes, L.zipnn_inspect.restype = [vp, u64, P(zipnn_info)], i32
         _lib = L
     return _lib
@@ -127,6 +130,12 @@ def zipnn_compress(ctx, src, dtype, n, base, p, dst, dst_cap, stream) -> int:
 
 def zipnn_decompress(ctx, src, src_len, base, dst, dst_cap, stream) -> None:
     _check(lib().zipnn_decompress(ctx, src, src_len, base, dst, dst_cap, stream), "zipnn_decompress")
+
+
+def zipnn_decompress_async(ctx, header: bytes, src, src_len, base, dst, dst_cap, stream) -> None:
+    assert len(header) >= 64
+    _check(lib().zipnn_decompress_async(ctx, bytes(header[:64]), src, src_len, base, dst, dst_cap, stream),
+           "zipnn_decompress_async")
 
 
 def zipnn_inspect(host_bytes: bytes) -> zipnn_info:
@@ -216,12 +225,17 @@ class Codec:
                             out.data_ptr(), out.numel(), self._stream())
         return out[:ln]
 
-    def decompress(self, c, out, base=None, check: bool = True):
+    def decompress(self, c, out, base=None, check: bool = True, header: bytes | None = None):
         """Decompress container c (uint8 device tensor) into `out` (any dtype,
-        n*B bytes).  With check=True, synchronises and raises on a device-side
-        error."""
-        zipnn_decompress(self.ctx, c.data_ptr(), c.numel(), base.data_ptr() if base is not None else None,
-                         out.data_ptr(), out.numel() * out.element_size(), self._stream())
+        n*B bytes).  `header`: host copy of the container's first 64 bytes, to
+        queue the decode without a host round trip.  With check=True,
+        synchronises and raises on a device-side error."""
+        args = (c.data_ptr(), c.numel(), base.data_ptr() if base is not None else None, out.data_ptr(),
+                out.numel() * out.element_size(), self._stream())
+        if header is None:
+            zipnn_decompress(self.ctx, *args)
+        else:
+            zipnn_decompress_async(self.ctx, header, *args)
         if check:
             st = zipnn_ctx_status(self.ctx, self._stream(), clear=True)
             if st != ZIPNN_OK:

@@ -52,7 +52,7 @@ def test_default_params(hiplib):
 
 
 def test_check_params_rejects(hiplib):
-    for kw in [dict(chunk_bytes=1000), dict(chunk_bytes=128), dict(S=3), dict(g=3), dict(g=16), dict(L=7),
+    for kw in [dict(chunk_bytes=1000), dict(chunk_bytes=128), dict(S=3), dict(g=3), dict(g=16), dict(g=1), dict(L=7),
                dict(L=12), dict(S=8192), dict(chunk_bytes=1 << 20, S=64)]:
         p = Z.make_params(Z.ZIPNN_BF16, **kw)
         assert Z.zipnn_check_params(Z.ZIPNN_BF16, p) == Z.ZIPNN_E_INVAL, kw

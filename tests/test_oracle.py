@@ -182,35 +182,39 @@ def test_canonical_codes_prefix_free_and_ordered(oracle_lib):
 
 # ----------------------------------------------------------- hand-derived container
 
-def _read_tiny():
-    rows = [l.split("#")[0].strip() for l in open(os.path.join(GOLD, "tiny_bf16_container.txt"))]
+def _read_fixture(name):
+    rows = [l.split("#")[0].strip() for l in open(os.path.join(GOLD, name))]
     rows = [r for r in rows if r]
-    words, params, size, blob = None, {}, None, None
+    words, params, blob = None, {}, None
     for r in rows:
         k, *v = r.split()
         if k == "input":
             words = _bf16_words(v)
+        elif k == "input_u8_mod3":
+            n = int(v[0])
+            words = np.array([0xFF if e % 3 == 0 else 0 for e in range(n)], dtype=np.uint8)
         elif k == "params":
             for kv in v:
                 a, b = kv.split("=")
                 params[a] = tuple(int(x) for x in b.split(",")) if "," in b else int(b)
         elif k == "size":
-            size = int(v[0])
-            blob = bytearray(size)
+            blob = bytearray(int(v[0]))
         elif k == "at":
             off = int(v[0])
             data = bytes.fromhex("".join(v[1:]))
             blob[off:off + len(data)] = data
+    if not isinstance(params["policy"], tuple):
+        params["policy"] = (params["policy"],)
     return words, params, bytes(blob)
 
 
-def test_tiny_container_matches_hand_derivation(oracle_lib):
-    words, p, expect = _read_tiny()
-    c = oracle.compress(words, p["dtype"], chunk_bytes=p["chunk_bytes"], S=p["S"], g=p["g"], L=p["L"],
-                        policy=p["policy"])
+@pytest.mark.parametrize("name", ["tiny_bf16_container.txt", "tiny_u8_rounds.txt"])
+def test_tiny_containers_match_hand_derivation(oracle_lib, name):
+    words, p, expect = _read_fixture(name)
+    kw = dict(chunk_bytes=p["chunk_bytes"], S=p["S"], g=p["g"], L=p["L"], policy=p["policy"])
+    c = oracle.compress(words, p["dtype"], **kw)
     assert c.tobytes() == expect
-    assert spec.compress(words, p["dtype"], chunk_bytes=p["chunk_bytes"], S=p["S"], g=p["g"], L=p["L"],
-                         policy=p["policy"]) == expect
+    assert spec.compress(words, p["dtype"], **kw) == expect
     assert np.array_equal(oracle.decompress(np.frombuffer(expect, np.uint8)), words.view(np.uint8))
     assert np.array_equal(spec.decompress(expect), words.view(np.uint8))
 
@@ -235,7 +239,7 @@ def test_roundtrip_and_spec_agreement(oracle_lib, dtype, n_extra):
         w = raw.view(np.uint32)
         w[: len(SPECIAL_FP32)] = SPECIAL_FP32
     for policy in [(oracle.AUTO,) * 4, (oracle.HUF,) * 4, (oracle.RAW, oracle.HUF, oracle.AUTO, oracle.HUF)]:
-        for S, gg in [(64, 4), (16, 1), (128, 8)]:
+        for S, gg in [(64, 4), (16, 2), (128, 8), (2, 2)]:
             c = oracle.compress(raw, dtype, chunk_bytes=chunk, S=S, g=gg, policy=policy[:B])
             assert np.array_equal(oracle.decompress(c), raw)
             assert spec.compress(raw, dtype, chunk_bytes=chunk, S=S, g=gg, policy=policy[:B]) == c.tobytes()
@@ -288,24 +292,33 @@ def test_no_expansion_under_auto(oracle_lib):
 
 
 def test_auto_threshold_is_strict(oracle_lib):
-    """AUTO keeps HUF iff align16(128+2W) + ceil(T/8) < m.  Checked on every
-    stream of a sample whose size sits near the boundary."""
+    """AUTO keeps HUF iff the Huffman payload is strictly smaller than raw.
+    The HUF-forced payload of each stream also sits between its entropy-coded
+    bit count and that plus the word padding (<= 2 words per sub-stream)."""
     x = workloads.fp32_rows(64, 8192, seed=1)
-    c = oracle.compress(x, oracle.FP32, chunk_bytes=262144)
+    S = 256
+    auto = oracle.compress(x, oracle.FP32, chunk_bytes=262144, S=S)
+    huf = oracle.compress(x, oracle.FP32, chunk_bytes=262144, S=S, policy=(oracle.HUF,) * 4)
     raw = oracle.as_bytes(x).reshape(-1, 4)
     E = 65536
-    for ch in range(oracle.header(c)["n_chunks"]):
+    W = E // S
+    head = (128 + 4 * ((W + 63) // 64) + 15) // 16 * 16
+    seen = set()
+    for ch in range(oracle.header(auto)["n_chunks"]):
         for k in range(4):
             s = raw[ch * E:(ch + 1) * E, 3 - k]
             f = np.bincount(s, minlength=256)
-            lens = oracle.package_merge(f, 11)
-            T = int((f * lens.astype(np.int64)).sum())
-            size_huf = (128 + 2 * (E // 512) + 15) // 16 * 16 + (T + 7) // 8
-            _, nb, mode, _ = oracle.entry(c, ch, k)
-            if size_huf < E:
-                assert mode == oracle.MODE_HUF and nb == size_huf
+            T = int((f * oracle.package_merge(f, 11).astype(np.int64)).sum())
+            _, nb_h, mode_h, _ = oracle.entry(huf, ch, k)
+            _, nb_a, mode_a, _ = oracle.entry(auto, ch, k)
+            assert mode_h == oracle.MODE_HUF
+            assert head + (T + 7) // 8 <= nb_h <= head + (T + 7) // 8 + 8 * W
+            if nb_h < E:
+                assert (mode_a, nb_a) == (oracle.MODE_HUF, nb_h)
             else:
-                assert mode == oracle.MODE_RAW and nb == E
+                assert (mode_a, nb_a) == (oracle.MODE_RAW, E)
+            seen.add(mode_a)
+    assert seen == {oracle.MODE_HUF, oracle.MODE_RAW}
 
 
 def test_entropy_bounds(oracle_lib):
@@ -413,7 +426,7 @@ def test_truncated_and_small_output_rejected(oracle_lib):
 def test_invalid_params_rejected(oracle_lib):
     x = np.zeros(100, np.uint16)
     for kw in [dict(chunk_bytes=1000), dict(chunk_bytes=128), dict(S=3), dict(g=3), dict(S=2, g=4),
-               dict(L=7), dict(L=12), dict(S=8192), dict(g=16, S=64),
+               dict(L=7), dict(L=12), dict(S=8192), dict(g=16, S=64), dict(g=1),
                dict(chunk_bytes=1 << 20, S=64)]:
         with pytest.raises(oracle.OracleError) as ei:
             oracle.compress(x, oracle.BF16, **kw)
