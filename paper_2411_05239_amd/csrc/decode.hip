@@ -144,11 +144,12 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kDepth = 4;   // groups of raw bytes prefetched ahead per lane
+#define NWIN 3              // 64-word windows of a Huffman word stream held per lane
 
 template <int G>
 struct SlotSize {
     static constexpr int PW = G >= 4 ? G / 4 : 1;                 // packed words per group
-    static constexpr int N = kDepth * PW > 6 ? kDepth * PW : 6;   // registers per stream slot
+    static constexpr int N = kDepth * PW > (NWIN + 3) ? kDepth * PW : (NWIN + 3);
 };
 
 // Uniform (scalar) part of a lane group's Huffman word stream.
@@ -156,14 +157,9 @@ struct WordCursor {
     const uint32_t* p;   // first word of this lane group's stream
     uint32_t last;       // index of its last word
     uint32_t ptr;        // words taken so far
-    uint32_t wb;         // stream index held by lane 0 of window 0 (multiple of 64)
+    uint32_t wb;         // stream index held by lane 0 of the head window (multiple of 64)
+    uint32_t head;       // register of the head window (0..NWIN-1)
 };
-
-// A stream's register slot holds, for a Huffman stream: three 64-word
-// windows (one word per lane: r[0..2]), the buffered bit count r[3] and the
-// 64-bit bit buffer r[4] | r[5] << 32; for a raw stream: the ring of
-// prefetched groups (r[u*PW + x]).  The mode of a stream is fixed for a chunk,
-// so one set of registers serves both.
 
 __device__ inline void huf_init(uint32_t* r, WordCursor& c, const uint32_t* words, uint32_t nwords, uint32_t lane)
 {
@@ -171,47 +167,84 @@ __device__ inline void huf_init(uint32_t* r, WordCursor& c, const uint32_t* word
     c.last = nwords - 1;
     c.ptr = 0;
     c.wb = 0;
-    r[0] = words[min(lane, c.last)];
-    r[1] = words[min(64 + lane, c.last)];
-    r[2] = words[min(128 + lane, c.last)];
-    r[3] = 0;
-    r[4] = 0;
-    r[5] = 0;
+    c.head = 0;
+#pragma unroll
+    for (int i = 0; i < NWIN; i++) r[i] = words[min(64 * i + lane, c.last)];
+    r[NWIN] = 0;
+    r[NWIN + 1] = 0;
+    r[NWIN + 2] = 0;
 }
 
 // One round's word requests: lanes taking part with fewer than 2L buffered
-// bits take the next words of the stream, in lane order.
+// bits take the next words of the stream, in lane order.  The windows form a
+// ring: the head window and the next one are read (chosen by a wave-uniform
+// switch, so only those two registers are touched); when the head is used up
+// its register is reloaded with the window NWIN-1 ahead.
 __device__ inline void huf_take(uint32_t* r, WordCursor& c, bool part, uint32_t twoL, uint32_t lane)
 {
-    const bool need = part && r[3] < twoL;
+    const bool need = part && r[NWIN] < twoL;
     const uint64_t m = __ballot(need);
     const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
     const uint32_t rel = c.ptr - c.wb + below;   // < 128
-    const uint32_t a = __shfl(r[0], int(rel & 63), 64);
-    const uint32_t b = __shfl(r[1], int(rel & 63), 64);
+    const int src = int(rel & 63);
+    uint32_t a = 0, b = 0;
+    switch (c.head) {
+#define ZIPNN_W(i)                                         \
+    case i:                                                \
+        a = __shfl(r[i], src, 64);                         \
+        b = __shfl(r[(i + 1) % NWIN], src, 64);            \
+        break;
+        ZIPNN_W(0) ZIPNN_W(1) ZIPNN_W(2)
+#if NWIN > 3
+        ZIPNN_W(3)
+#endif
+#if NWIN > 4
+        ZIPNN_W(4)
+#endif
+#if NWIN > 5
+        ZIPNN_W(5)
+#endif
+#undef ZIPNN_W
+    }
     const uint32_t word = rel < 64 ? a : b;
     if (need) {
-        const uint64_t x = uint64_t(word) << r[3];
-        r[4] |= uint32_t(x);
-        r[5] |= uint32_t(x >> 32);
-        r[3] += 32;
+        const uint64_t x = uint64_t(word) << r[NWIN];
+        r[NWIN + 1] |= uint32_t(x);
+        r[NWIN + 2] |= uint32_t(x >> 32);
+        r[NWIN] += 32;
     }
     c.ptr += uint32_t(__popcll(m));
     if (c.ptr - c.wb >= 64) {
-        r[0] = r[1];
-        r[1] = r[2];
+        const uint32_t v = c.p[min(c.wb + 64 * NWIN + lane, c.last)];
+        switch (c.head) {
+#define ZIPNN_W(i) \
+    case i:        \
+        r[i] = v;  \
+        break;
+            ZIPNN_W(0) ZIPNN_W(1) ZIPNN_W(2)
+#if NWIN > 3
+            ZIPNN_W(3)
+#endif
+#if NWIN > 4
+            ZIPNN_W(4)
+#endif
+#if NWIN > 5
+            ZIPNN_W(5)
+#endif
+#undef ZIPNN_W
+        }
         c.wb += 64;
-        r[2] = c.p[min(c.wb + 128 + lane, c.last)];
+        c.head = c.head + 1 == NWIN ? 0 : c.head + 1;
     }
 }
 
 __device__ inline uint32_t huf_get(uint32_t* r, const uint16_t* lut, uint32_t mask)
 {
-    const uint32_t e = lut[r[4] & mask];
+    const uint32_t e = lut[r[NWIN + 1] & mask];
     const uint32_t l = e >> 8;
-    r[4] = __builtin_amdgcn_alignbit(r[5], r[4], l);
-    r[5] >>= l;
-    r[3] -= l;
+    r[NWIN + 1] = __builtin_amdgcn_alignbit(r[NWIN + 2], r[NWIN + 1], l);
+    r[NWIN + 2] >>= l;
+    r[NWIN] -= l;
     return e & 0xFFu;
 }
 
