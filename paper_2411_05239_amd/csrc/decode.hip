@@ -288,9 +288,108 @@ __device__ inline void load_words(const uint8_t* b, uint32_t* w)
     }
 }
 
+// Buffer resource over [p, p + bytes): loads past the end return zero and
+// stores past it are dropped.  Offsets of accesses that must not happen are
+// set to kOff, far past any valid range.
+constexpr uint32_t kOff = 0x80000000u;
+
+// Values the same in every lane of the wave, made scalar.
+__device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint64_t uni64(uint64_t v)
+{
+    return uint64_t(uni(uint32_t(v))) | (uint64_t(uni(uint32_t(v >> 32))) << 32);
+}
+template <class T>
+__device__ inline T* uniptr(T* p)
+{
+    return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int NBYTES>
+__device__ inline void buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t* o)
+{
+    if constexpr (NBYTES == 2) o[0] = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 2);
+    else if constexpr (NBYTES == 4) o[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2);
+    else if constexpr (NBYTES == 8) {
+        u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 2);
+        o[0] = v.x;
+        o[1] = v.y;
+    } else if constexpr (NBYTES == 16) {
+        u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    } else {
+        u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2);
+        u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 2);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+        o[4] = u.x;
+        o[5] = u.y;
+        o[6] = u.z;
+        o[7] = u.w;
+    }
+}
+
+template <int NBYTES>
+__device__ inline void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, const uint32_t* w)
+{
+    if constexpr (NBYTES == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0]), r, off, 0, 2);
+    else if constexpr (NBYTES == 4) __builtin_amdgcn_raw_buffer_store_b32(w[0], r, off, 0, 2);
+    else if constexpr (NBYTES == 8) __builtin_amdgcn_raw_buffer_store_b64(u32x2{w[0], w[1]}, r, off, 0, 2);
+    else if constexpr (NBYTES == 16) __builtin_amdgcn_raw_buffer_store_b128(u32x4{w[0], w[1], w[2], w[3]}, r, off, 0, 2);
+    else {
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{w[0], w[1], w[2], w[3]}, r, off, 0, 2);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{w[4], w[5], w[6], w[7]}, r, off + 16, 0, 2);
+    }
+}
+
+// Interleave the B byte groups of G elements back into words (the inverse of
+// byte grouping): pk[k][x] holds symbols 4x..4x+3 of stream k; element i's
+// little-endian word is (s_{B-1}[i], ..., s_1[i], s_0[i]).  v_perm_b32 picks
+// bytes of {S0:S1} (selector 0-3: S1, 4-7: S0).
+template <int B, int G>
+__device__ inline void merge_words(const uint32_t (*pk)[SlotSize<G>::PW], uint32_t* ow)
+{
+    constexpr int PW = SlotSize<G>::PW;
+    if constexpr (B == 1) {
+#pragma unroll
+        for (int x = 0; x < PW; x++) ow[x] = pk[0][x];
+    } else if constexpr (B == 2) {
+#pragma unroll
+        for (int x = 0; x < PW; x++) {
+            ow[2 * x] = __builtin_amdgcn_perm(pk[0][x], pk[1][x], 0x05010400u);
+            if constexpr (G >= 4) ow[2 * x + 1] = __builtin_amdgcn_perm(pk[0][x], pk[1][x], 0x07030602u);
+        }
+    } else {
+#pragma unroll
+        for (int x = 0; x < PW; x++) {
+            const uint32_t lo01 = __builtin_amdgcn_perm(pk[0][x], pk[1][x], 0x05010400u);
+            const uint32_t lo23 = __builtin_amdgcn_perm(pk[2][x], pk[3][x], 0x05010400u);
+            ow[4 * x] = __builtin_amdgcn_perm(lo01, lo23, 0x05040100u);
+            ow[4 * x + 1] = __builtin_amdgcn_perm(lo01, lo23, 0x07060302u);
+            if constexpr (G >= 4) {
+                const uint32_t hi01 = __builtin_amdgcn_perm(pk[0][x], pk[1][x], 0x07030602u);
+                const uint32_t hi23 = __builtin_amdgcn_perm(pk[2][x], pk[3][x], 0x07030602u);
+                ow[4 * x + 2] = __builtin_amdgcn_perm(hi01, hi23, 0x05040100u);
+                ow[4 * x + 3] = __builtin_amdgcn_perm(hi01, hi23, 0x07060302u);
+            }
+        }
+    }
+}
+
 // Decode lane group j of one chunk: every stream's symbols of the lane's
 // sub-stream, merged into words and stored.  Raw bytes (and the XOR base) of
 // a lane's groups are fetched kDepth groups ahead through a register ring.
+// While every lane of the group still has a full group of g symbols the loop
+// runs without per-lane conditions; the last groups take the general path.
 template <int B, int G, bool DELTA>
 __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemState& st,
                                   const uint16_t (*lut)[kLutSize], const uint32_t (*wprefix)[65], uint32_t L,
@@ -302,6 +401,13 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
     constexpr int PW = SlotSize<G>::PW;
     constexpr int NS = SlotSize<G>::N;
     constexpr int BD = DELTA ? kDepth : 1;
+    src = uniptr(src);
+    out = uniptr(out);
+    base = uniptr(base);
+    j = uni(j);
+    W = uni(W);
+    m = uni(m);
+    L = uni(L);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = 64 * j + lane;
     const uint32_t mask = (1u << L) - 1, twoL = 2 * L;
@@ -309,17 +415,27 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
     const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;     // groups of this lane
     const uint32_t nfull = (w < W && w < Gfull) ? (Gfull - 1 - w) / W + 1 : 0; // full ones
     const uint32_t ng_max = __builtin_amdgcn_readfirstlane(ng);            // lane 0 has the most
+    // full groups of the last lane of the group: every lane has at least these
+    const uint32_t w_last = min(W, 64 * j + 64) - 1;
+    const uint32_t nfull_all = w_last < Gfull ? (Gfull - 1 - w_last) / W + 1 : 0;
+    const uint32_t n_fast = (64 * j + 64 <= W) ? nfull_all / kDepth * kDepth : 0;
     int mode[B];
     uint32_t rlev[B];
     const uint8_t* pay[B];
+    __amdgpu_buffer_rsrc_t rr[B];
     WordCursor cur[B];
     uint32_t slot[B][NS];
     uint32_t bring[BD][NW];
+    const __amdgpu_buffer_rsrc_t ro = rsrc(out, m * B);
+    const __amdgpu_buffer_rsrc_t rb = rsrc(DELTA ? base : out, m * B);
+    // byte offset of this lane's group jj in a raw payload: (w + jj*W)*G
+    auto raw_off = [&](uint32_t jj) { return jj < nfull ? (w + jj * W) * G : kOff; };
 #pragma unroll
     for (int k = 0; k < B; k++) {
         mode[k] = __builtin_amdgcn_readfirstlane(st.mode[k]);
         rlev[k] = st.rle[k] * 0x01010101u;
-        pay[k] = src + st.pay[k];
+        pay[k] = src + uni64(st.pay[k]);
+        rr[k] = rsrc(pay[k], mode[k] == kModeRaw ? m : 0u);
 #pragma unroll
         for (int x = 0; x < NS; x++) slot[k][x] = 0;
         if (mode[k] == kModeHuf) {
@@ -329,19 +445,57 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
             huf_init(slot[k], cur[k], words + s0, s1 - s0, lane);
         } else if (mode[k] == kModeRaw) {
 #pragma unroll
-            for (int u = 0; u < kDepth; u++)
-                if (uint32_t(u) < nfull) raw_load<G>(pay[k] + (w + u * W) * G, &slot[k][u * PW]);
+            for (int u = 0; u < kDepth; u++) buf_load<G>(rr[k], raw_off(u), &slot[k][u * PW]);
         }
     }
     if constexpr (DELTA) {
 #pragma unroll
         for (int u = 0; u < kDepth; u++) {
-#pragma unroll
-            for (int x = 0; x < NW; x++) bring[u][x] = 0;
-            if (uint32_t(u) < nfull) load_words<NB>(base + uint64_t(w + u * W) * G * B, bring[u]);
+            const uint32_t o = raw_off(u);
+            buf_load<NB>(rb, o == kOff ? kOff : o * B, bring[u]);
         }
     }
-    for (uint32_t j0 = 0; j0 < ng_max; j0 += kDepth) {
+    // fast path: all 64 lanes have full groups j0 .. j0+kDepth-1
+    for (uint32_t j0 = 0; j0 < n_fast; j0 += kDepth) {
+#pragma unroll
+        for (int u = 0; u < kDepth; u++) {
+            const uint32_t jj = j0 + u;
+            const uint32_t off = (w + jj * W) * G;
+            const uint32_t offn = raw_off(jj + kDepth);
+            uint32_t pk[B][PW];
+#pragma unroll
+            for (int k = 0; k < B; k++) {
+                if (mode[k] == kModeRaw) {
+#pragma unroll
+                    for (int x = 0; x < PW; x++) pk[k][x] = slot[k][u * PW + x];
+                    buf_load<G>(rr[k], offn, &slot[k][u * PW]);
+                } else if (mode[k] == kModeRle) {
+#pragma unroll
+                    for (int x = 0; x < PW; x++) pk[k][x] = rlev[k];
+                } else {
+#pragma unroll
+                    for (int x = 0; x < PW; x++) pk[k][x] = 0;
+#pragma unroll
+                    for (int pr = 0; pr < G / 2; pr++) {
+                        huf_take(slot[k], cur[k], true, twoL, lane);
+                        const uint32_t s0 = huf_get(slot[k], lut[k], mask);
+                        const uint32_t s1 = huf_get(slot[k], lut[k], mask);
+                        pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
+                    }
+                }
+            }
+            uint32_t ow[NW];
+            merge_words<B, G>(pk, ow);
+            if constexpr (DELTA) {
+#pragma unroll
+                for (int x = 0; x < NW; x++) ow[x] ^= bring[u][x];
+                buf_load<NB>(rb, offn == kOff ? kOff : offn * B, bring[u]);
+            }
+            buf_store<NB>(ro, off * B, ow);
+        }
+    }
+    // general path: the remaining groups, with per-lane conditions
+    for (uint32_t j0 = n_fast; j0 < ng_max; j0 += kDepth) {
 #pragma unroll
         for (int u = 0; u < kDepth; u++) {
             const uint32_t jj = j0 + u;
@@ -349,18 +503,16 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
             const bool has = jj < ng;
             const bool full = jj < nfull;
             const uint32_t gcnt = full ? G : (has ? rem : 0);
-            const uint32_t qn = q + kDepth * W;
-            const bool okn = jj + kDepth < nfull;
+            const uint32_t offn = raw_off(jj + kDepth);
             uint32_t pk[B][PW];
 #pragma unroll
             for (int k = 0; k < B; k++) {
 #pragma unroll
                 for (int x = 0; x < PW; x++) pk[k][x] = 0;
                 if (mode[k] == kModeRaw) {
-                    // take this group from the ring, refill the slot kDepth ahead
 #pragma unroll
                     for (int x = 0; x < PW; x++) pk[k][x] = slot[k][u * PW + x];
-                    if (okn) raw_load<G>(pay[k] + qn * G, &slot[k][u * PW]);
+                    buf_load<G>(rr[k], offn, &slot[k][u * PW]);
                 } else if (mode[k] == kModeRle) {
 #pragma unroll
                     for (int x = 0; x < PW; x++) pk[k][x] = rlev[k];
@@ -378,20 +530,14 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
                 }
             }
             uint32_t ow[NW];
-#pragma unroll
-            for (int x = 0; x < NW; x++) ow[x] = 0;
+            merge_words<B, G>(pk, ow);
             if constexpr (DELTA) {
 #pragma unroll
-                for (int x = 0; x < NW; x++) ow[x] = bring[u][x];
-                if (okn) load_words<NB>(base + uint64_t(qn) * G * B, bring[u]);
+                for (int x = 0; x < NW; x++) ow[x] ^= bring[u][x];
+                buf_load<NB>(rb, offn == kOff ? kOff : offn * B, bring[u]);
             }
             if (full) {
-#pragma unroll
-                for (int jb = 0; jb < NB; jb++) {
-                    const int i = jb / B, b = jb % B, k = B - 1 - b;
-                    ow[jb >> 2] ^= ((pk[k][i >> 2] >> (8 * (i & 3))) & 0xFFu) << (8 * (jb & 3));
-                }
-                store_words<NB>(out + uint64_t(q) * G * B, ow);
+                buf_store<NB>(ro, q * G * B, ow);
             } else if (has) {
                 // the partial last group of a tensor: one byte at a time
                 const uint32_t e = q * G;
