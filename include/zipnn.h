@@ -168,6 +168,51 @@ int zipnn_decompress(zipnn_ctx ctx, const void* src, uint64_t src_len, const voi
 int zipnn_decompress_async(zipnn_ctx ctx, const void* header_host, const void* src, uint64_t src_len,
                            const void* base, void* dst, uint64_t dst_cap, void* stream);
 
+/* ---------------------------------------------------------------- batches
+ * A checkpoint is many tensors: they are compressed into one arena, the
+ * per-tensor containers back to back in tensor order, each starting at a
+ * 16-byte aligned offset, with the whole-model offsets kept by the caller
+ * (the paper's map "for the whole model" that allows parallel decompression,
+ * §V-A "Metadata and parallelism").  Every kernel is launched once for all
+ * chunks of all tensors. */
+
+typedef struct {
+    const void* src;       /* device pointer to the tensor */
+    uint64_t n_elems;
+    const void* base;      /* device pointer to its XOR base, or NULL */
+} zipnn_tensor_in;
+
+/* Compress tensors[0..n) (all of `dtype`, host array of device pointers) into
+ * the device arena (arena_cap bytes; enough is the sum over tensors of
+ * zipnn_compress_bound + 15).  offsets (host, n+1 entries) receives the
+ * offset of each container and, last, the arena bytes used.  Blocking; the
+ * containers are byte-identical to per-tensor zipnn_compress calls. */
+int zipnn_compress_batch(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, const zipnn_params* p,
+                         void* arena, uint64_t arena_cap, uint64_t* offsets, void* stream);
+
+typedef struct zipnn_batch_s* zipnn_batch;
+
+/* Prepare the decompression of the n containers of a device arena (offsets:
+ * host, n+1 entries as returned by zipnn_compress_batch) into dst[i] (host
+ * array of device pointers, dst_cap[i] bytes each), XORing with base[i] for
+ * delta containers (base may be NULL when no container is a delta).  Reads
+ * and checks every header (blocking), uploads the descriptor tables and
+ * records the launches (one per kernel class of (B, g, delta)) in a hipGraph.
+ * The arena and outputs must stay valid while the batch is used. */
+int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets, int n, void* const* dst,
+                       const uint64_t* dst_cap, const void* const* base, zipnn_batch* out);
+
+/* Queue the prepared decompression on `stream` (graph replay; asynchronous).
+ * Device-side checks report through the context status. */
+int zipnn_batch_decompress(zipnn_batch b, void* stream);
+
+/* Wait for the device, then release the batch. NULL is ignored. */
+void zipnn_batch_destroy(zipnn_batch b);
+
+/* One-shot: create, decompress on `stream`, wait, destroy. */
+int zipnn_decompress_batch(zipnn_ctx ctx, const void* arena, const uint64_t* offsets, int n, void* const* dst,
+                           const uint64_t* dst_cap, const void* const* base, void* stream);
+
 /* Validate a container's header and map from HOST memory (len bytes: at
  * least the header and the map) and summarise it in *out. */
 int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out);

@@ -1,8 +1,11 @@
 // Host runtime behind include/zipnn.h: contexts, argument checks, scratch
 // management, kernel launches and host-side container inspection.
+#include <map>
 #include <mutex>
 #include <new>
 #include <string.h>
+#include <tuple>
+#include <vector>
 
 #include "zipnn_internal.h"
 
@@ -187,56 +190,97 @@ uint64_t zipnn_compress_bound(int dtype, uint64_t n, const zipnn_params* p)
     return 64 + 16 * nc * B + nc * B * (per_stream > E + 16 ? per_stream : E + 16);
 }
 
-int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n, const void* base, const zipnn_params* p,
-                   void* dst, uint64_t dst_cap, uint64_t* dst_len, void* stream)
+// Encode tensors[0..n) (all of one dtype) into `arena`; offsets_host gets the
+// n+1 arena offsets.  Blocking.
+static int encode_tensors(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, int n, const zipnn_params* p,
+                          void* arena, uint64_t cap, uint64_t* offsets_host, hipStream_t s)
 {
-    if (!ctx || !dst || !dst_len || (!src && n)) return ZIPNN_E_INVAL;
-    if (zipnn_check_params(dtype, p) != ZIPNN_OK) return ZIPNN_E_INVAL;
-    if (!aligned16(src) || !aligned16(dst) || !aligned16(base)) return ZIPNN_E_INVAL;
+    if (zipnn_check_params(dtype, p) != ZIPNN_OK || n < 1 || !arena || !offsets_host) return ZIPNN_E_INVAL;
+    if (!aligned16(arena)) return ZIPNN_E_INVAL;
     const uint32_t B = uint32_t(dtype_bytes(dtype));
     const uint64_t E = p->chunk_bytes / B;
-    const uint64_t nc = (n + E - 1) / E;
-    if (nc > 0xFFFFFFFFull) return ZIPNN_E_INVAL;
-    if (64 + 16 * nc * B > dst_cap) return ZIPNN_E_NOSPACE;
+    uint64_t total_chunks = 0, map_bytes = 0;
+    for (int i = 0; i < n; i++) {
+        if ((!t[i].src && t[i].n_elems) || !aligned16(t[i].src) || !aligned16(t[i].base)) return ZIPNN_E_INVAL;
+        const uint64_t nc = (t[i].n_elems + E - 1) / E;
+        total_chunks += nc;
+        map_bytes += align16(64 + 16 * nc * B);
+    }
+    if (total_chunks > 0xFFFFFFFFull) return ZIPNN_E_INVAL;
+    if (map_bytes > cap) return ZIPNN_E_NOSPACE;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
-    hipStream_t s = (hipStream_t)stream;
-    const size_t ne = size_t(nc) * B;
+    const size_t ne = size_t(total_chunks) * B;
     const size_t off_entries = 0;
     const size_t off_codes = align256(off_entries + ne * sizeof(EncEntry));
     const size_t off_offsets = align256(off_codes + ne * 256 * sizeof(CodeWord));
     const size_t off_nwords = align256(off_offsets + ne * sizeof(uint64_t));
     const size_t off_totals = align256(off_nwords + ne * 64 * sizeof(uint32_t));
-    const size_t need = off_totals + 256;
+    const size_t off_aoff = align256(off_totals + size_t(n) * sizeof(uint64_t));
+    const size_t off_descs = align256(off_aoff + size_t(n + 1) * sizeof(uint64_t));
+    const size_t off_prefix = align256(off_descs + size_t(n) * sizeof(EncDesc));
+    const size_t need = off_prefix + size_t(n + 1) * sizeof(uint32_t) + 256;
     int rc = grow_scratch(ctx, need);
     if (rc) return rc;
+    // host staging (pinned): descriptors, chunk prefix, then the arena offsets
+    const size_t stage_bytes = size_t(n) * sizeof(EncDesc) + size_t(n + 1) * sizeof(uint32_t) +
+                               size_t(n + 1) * sizeof(uint64_t) + 64;
+    rc = grow_pinned(ctx, stage_bytes / sizeof(uint64_t) + 1);
+    if (rc) return rc;
+    EncDesc* hd = (EncDesc*)ctx->h_total;
+    uint32_t* hp = (uint32_t*)(hd + n);
+    uint64_t* ho = (uint64_t*)align16(uint64_t(hp + n + 1));
+    uint32_t run = 0;
+    for (int i = 0; i < n; i++) {
+        const uint64_t nc = (t[i].n_elems + E - 1) / E;
+        hd[i].src = (const uint8_t*)t[i].src;
+        hd[i].base = (const uint8_t*)t[i].base;
+        hd[i].dst = nullptr;
+        hd[i].dst_cap = 0;
+        hd[i].n = t[i].n_elems;
+        hd[i].chunk0 = run;
+        hd[i].n_chunks = uint32_t(nc);
+        hp[i] = run;
+        run += uint32_t(nc);
+    }
+    hp[n] = run;
     uint8_t* sc = (uint8_t*)ctx->d_scratch;
-    EncEntry* entries = (EncEntry*)(sc + off_entries);
-    CodeWord* codes = (CodeWord*)(sc + off_codes);
-    uint64_t* offsets = (uint64_t*)(sc + off_offsets);
-    uint32_t* nwords = (uint32_t*)(sc + off_nwords);
-    uint64_t* totals = (uint64_t*)(sc + off_totals);
+    EncDesc* d_descs = (EncDesc*)(sc + off_descs);
+    uint32_t* d_prefix = (uint32_t*)(sc + off_prefix);
+    uint64_t* d_aoff = (uint64_t*)(sc + off_aoff);
     EncParams ep = make_params(dtype, *p);
-    ep.flags = base ? kFlagDelta : 0;
-    EncDesc one;
-    one.src = (const uint8_t*)src;
-    one.base = (const uint8_t*)base;
-    one.dst = (uint8_t*)dst;
-    one.dst_cap = dst_cap;
-    one.n = n;
-    one.chunk0 = 0;
-    one.n_chunks = uint32_t(nc);
-    if (launch_analyze(one, nullptr, 1, nullptr, uint32_t(nc), ep, entries, codes, nwords, s) != hipSuccess ||
-        launch_place(one, nullptr, 1, ep, entries, offsets, totals, s) != hipSuccess ||
-        launch_pack(one, nullptr, 1, nullptr, uint32_t(nc), ep, entries, codes, offsets, totals, nwords, s) !=
-            hipSuccess ||
-        hipMemcpyAsync(ctx->h_total, totals, sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (hipMemcpyAsync(d_descs, hd, size_t(n) * sizeof(EncDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d_prefix, hp, size_t(n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_encode(d_descs, n, d_prefix, uint32_t(total_chunks), ep, (uint8_t*)arena, cap,
+                      (EncEntry*)(sc + off_entries), (CodeWord*)(sc + off_codes), (uint32_t*)(sc + off_nwords),
+                      (uint64_t*)(sc + off_offsets), (uint64_t*)(sc + off_totals), d_aoff, s) != hipSuccess ||
+        hipMemcpyAsync(ho, d_aoff, size_t(n + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return ZIPNN_E_HIP;
-    const uint64_t total = ctx->h_total[0];
-    if (total > dst_cap) return ZIPNN_E_NOSPACE;
-    *dst_len = total;
+    if (ho[n] > cap) return ZIPNN_E_NOSPACE;
+    memcpy(offsets_host, ho, size_t(n + 1) * sizeof(uint64_t));
     return ZIPNN_OK;
+}
+
+int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n, const void* base, const zipnn_params* p,
+                   void* dst, uint64_t dst_cap, uint64_t* dst_len, void* stream)
+{
+    if (!ctx || !dst || !dst_len || (!src && n)) return ZIPNN_E_INVAL;
+    zipnn_tensor_in t;
+    t.src = src;
+    t.n_elems = n;
+    t.base = base;
+    uint64_t off[2];
+    const int rc = encode_tensors(ctx, dtype, &t, 1, p, dst, dst_cap, off, (hipStream_t)stream);
+    if (rc == ZIPNN_OK) *dst_len = off[1];
+    return rc;
+}
+
+int zipnn_compress_batch(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, const zipnn_params* p,
+                         void* arena, uint64_t arena_cap, uint64_t* offsets, void* stream)
+{
+    if (!ctx || !tensors) return ZIPNN_E_INVAL;
+    return encode_tensors(ctx, dtype, tensors, n, p, arena, arena_cap, offsets, (hipStream_t)stream);
 }
 
 static int decompress_common(zipnn_ctx ctx, const uint32_t* hdr_words, const void* src, uint64_t src_len,
@@ -288,6 +332,154 @@ int zipnn_decompress_async(zipnn_ctx ctx, const void* header_host, const void* s
     uint32_t w[16];
     memcpy(w, header_host, 64);
     return decompress_common(ctx, w, src, src_len, base, dst, dst_cap, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------ prepared batches
+
+struct zipnn_batch_s {
+    struct Class {
+        uint32_t B, G;
+        bool delta;
+        int n;
+        DecDesc* d_descs;
+        uint64_t* d_prefix;
+    };
+    zipnn_ctx ctx = nullptr;
+    std::vector<Class> classes;
+    void* d_mem = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static hipError_t batch_launch(zipnn_batch b, hipStream_t s)
+{
+    for (auto& c : b->classes) {
+        hipError_t e = launch_decode_batch(c.B, c.G, c.delta, c.d_descs, c.n, c.d_prefix, b->ctx->d_status,
+                                           b->ctx->dec_grid, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets, int n, void* const* dst,
+                       const uint64_t* dst_cap, const void* const* base, zipnn_batch* out)
+{
+    if (!ctx || !arena || !offsets || !dst || !dst_cap || !out || n < 1) return ZIPNN_E_INVAL;
+    *out = nullptr;
+    if (!aligned16(arena)) return ZIPNN_E_INVAL;
+    for (int i = 0; i < n; i++) {
+        if ((offsets[i] & 15) || offsets[i + 1] < offsets[i] + 64) return ZIPNN_E_INVAL;
+        if (!aligned16(dst[i]) || (base && !aligned16(base[i]))) return ZIPNN_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    // headers -> host, in one gather
+    int rc = grow_scratch(ctx, size_t(n + 1) * 8 + size_t(n) * 64 + 256);
+    if (rc) return rc;
+    rc = grow_pinned(ctx, size_t(n) * 8 + 8);
+    if (rc) return rc;
+    uint64_t* d_offs = (uint64_t*)ctx->d_scratch;
+    uint8_t* d_hdr = (uint8_t*)ctx->d_scratch + align256(size_t(n + 1) * 8);
+    hipStream_t s0 = nullptr;
+    if (hipMemcpyAsync(d_offs, offsets, size_t(n + 1) * 8, hipMemcpyHostToDevice, s0) != hipSuccess ||
+        launch_gather_headers((const uint8_t*)arena, d_offs, n, d_hdr, s0) != hipSuccess ||
+        hipMemcpyAsync(ctx->h_total, d_hdr, size_t(n) * 64, hipMemcpyDeviceToHost, s0) != hipSuccess ||
+        hipStreamSynchronize(s0) != hipSuccess)
+        return ZIPNN_E_HIP;
+    // group the tensors by kernel class (B, g, delta)
+    std::map<std::tuple<uint32_t, uint32_t, bool>, std::vector<DecDesc>> groups;
+    for (int i = 0; i < n; i++) {
+        Header h;
+        rc = parse_header((const uint32_t*)((const uint8_t*)ctx->h_total + 64 * size_t(i)), offsets[i + 1] - offsets[i],
+                          h);
+        if (rc) return rc;
+        const bool delta = (h.flags & kFlagDelta) != 0;
+        const void* bi = base ? base[i] : nullptr;
+        if (delta != (bi != nullptr)) return ZIPNN_E_INVAL;
+        if (h.n * h.B > dst_cap[i]) return ZIPNN_E_NOSPACE;
+        if (h.n_chunks == 0) continue;
+        DecDesc d;
+        d.src = (const uint8_t*)arena + offsets[i];
+        d.src_len = offsets[i + 1] - offsets[i];
+        d.base = (const uint8_t*)bi;
+        d.dst = (uint8_t*)dst[i];
+        d.dst_cap = dst_cap[i];
+        groups[std::make_tuple(h.B, h.g, delta)].push_back(d);
+    }
+    zipnn_batch b = new (std::nothrow) zipnn_batch_s;
+    if (!b) return ZIPNN_E_NOMEM;
+    b->ctx = ctx;
+    size_t bytes = 0;
+    for (auto& kv : groups) bytes += align256(kv.second.size() * sizeof(DecDesc)) + align256((kv.second.size() + 1) * 8);
+    if (bytes && hipMalloc(&b->d_mem, bytes) != hipSuccess) {
+        delete b;
+        return ZIPNN_E_NOMEM;
+    }
+    size_t off = 0;
+    for (auto& kv : groups) {
+        zipnn_batch_s::Class c;
+        c.B = std::get<0>(kv.first);
+        c.G = std::get<1>(kv.first);
+        c.delta = std::get<2>(kv.first);
+        c.n = int(kv.second.size());
+        c.d_descs = (DecDesc*)((uint8_t*)b->d_mem + off);
+        off += align256(kv.second.size() * sizeof(DecDesc));
+        c.d_prefix = (uint64_t*)((uint8_t*)b->d_mem + off);
+        off += align256((kv.second.size() + 1) * 8);
+        if (hipMemcpy(c.d_descs, kv.second.data(), kv.second.size() * sizeof(DecDesc), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            zipnn_batch_destroy(b);
+            return ZIPNN_E_HIP;
+        }
+        b->classes.push_back(c);
+    }
+    // capture the launches once; every decompress replays the graph
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        zipnn_batch_destroy(b);
+        return ZIPNN_E_HIP;
+    }
+    const hipError_t le = batch_launch(b, b->cap);
+    const hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
+    if (le != hipSuccess || ce != hipSuccess || hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+        zipnn_batch_destroy(b);
+        return ZIPNN_E_HIP;
+    }
+    *out = b;
+    return ZIPNN_OK;
+}
+
+int zipnn_batch_decompress(zipnn_batch b, void* stream)
+{
+    if (!b) return ZIPNN_E_INVAL;
+    DeviceGuard g(b->ctx->device);
+    if (b->classes.empty()) return ZIPNN_OK;
+    return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? ZIPNN_OK : ZIPNN_E_HIP;
+}
+
+void zipnn_batch_destroy(zipnn_batch b)
+{
+    if (!b) return;
+    DeviceGuard g(b->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->d_mem) (void)hipFree(b->d_mem);
+    delete b;
+}
+
+int zipnn_decompress_batch(zipnn_ctx ctx, const void* arena, const uint64_t* offsets, int n, void* const* dst,
+                           const uint64_t* dst_cap, const void* const* base, void* stream)
+{
+    zipnn_batch b = nullptr;
+    int rc = zipnn_batch_create(ctx, arena, offsets, n, dst, dst_cap, base, &b);
+    if (rc) return rc;
+    rc = zipnn_batch_decompress(b, stream);
+    if (rc == ZIPNN_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = ZIPNN_E_HIP;
+    zipnn_batch_destroy(b);
+    return rc;
 }
 
 int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out)

@@ -796,6 +796,15 @@ __global__ __launch_bounds__(kBlock) void k_plan(const DecDesc* __restrict__ des
 
 __global__ void k_clear(int* p) { *p = 0; }
 
+// Copy the 64-byte header of every container of an arena to `out`.
+__global__ void k_gather_headers(const uint8_t* __restrict__ arena, const uint64_t* __restrict__ offs, int n,
+                                 uint4* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * n) return;
+    out[i] = *(const uint4*)(arena + offs[i >> 2] + 16 * (i & 3));
+}
+
 template <int B, int G, bool D>
 hipError_t launch_k(const DecDesc& one, const DecDesc* descs, int n, const uint64_t* prefix, int* st, int grid,
                     hipStream_t s)
@@ -844,6 +853,12 @@ hipError_t launch_decode_batch(uint32_t B, uint32_t G, bool delta, const DecDesc
     if (e != hipSuccess) return e;
     DecDesc none = {};
     return dispatch(B, G, delta, none, d_descs, n_desc, d_item_prefix, d_status, grid, s);
+}
+
+hipError_t launch_gather_headers(const uint8_t* arena, const uint64_t* d_offs, int n, void* d_out, hipStream_t s)
+{
+    k_gather_headers<<<(4 * n + 255) / 256, 256, 0, s>>>(arena, d_offs, n, (uint4*)d_out);
+    return hipGetLastError();
 }
 
 hipError_t launch_clear_status(int* d_status, hipStream_t s)

@@ -358,7 +358,7 @@ struct AnalyzeTail {
     uint32_t lg_words[kWaves][4];
 };
 
-__global__ __launch_bounds__(kBlock) void k_analyze(EncDesc one, const EncDesc* __restrict__ descs, int n_desc,
+__global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                     EncParams p, EncEntry* __restrict__ entries,
                                                     CodeWord* __restrict__ codes, uint32_t* __restrict__ nwords)
@@ -369,9 +369,9 @@ __global__ __launch_bounds__(kBlock) void k_analyze(EncDesc one, const EncDesc* 
     const int t = threadIdx.x, wv = t >> 6;
     const uint32_t B = p.B;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
-        const int di = descs ? find_desc(chunk_prefix, n_desc, gc) : 0;
-        const EncDesc d = descs ? descs[di] : one;
-        const uint32_t c = gc - (descs ? chunk_prefix[di] : 0);
+        const int di = find_desc(chunk_prefix, n_desc, gc);
+        const EncDesc d = descs[di];
+        const uint32_t c = gc - chunk_prefix[di];
         const uint32_t E = p.chunk / B;
         const uint64_t e0 = uint64_t(c) * E;
         const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
@@ -480,26 +480,24 @@ __global__ __launch_bounds__(kBlock) void k_analyze(EncDesc one, const EncDesc* 
     }
 }
 
-// One workgroup per tensor: offsets of its entries and its header + map.
-__global__ __launch_bounds__(kBlock) void k_place(EncDesc one, const EncDesc* __restrict__ descs, EncParams p,
+// One workgroup per tensor: offsets of its entries (16-byte aligned, in
+// chunk-major order) and the tensor's container size.
+__global__ __launch_bounds__(kBlock) void k_place(const EncDesc* __restrict__ descs, EncParams p,
                                                   const EncEntry* __restrict__ entries, uint64_t* __restrict__ offsets,
                                                   uint64_t* __restrict__ totals)
 {
     __shared__ uint64_t red[kWaves];
     __shared__ uint64_t carry;
-    const EncDesc d = descs ? descs[blockIdx.x] : one;
+    const EncDesc d = descs[blockIdx.x];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t B = p.B;
     const uint64_t ne = uint64_t(d.n_chunks) * B;
     const uint64_t e_first = uint64_t(d.chunk0) * B;
-    const uint64_t payload_base = 64 + 16 * ne;
     if (t == 0) carry = 0;
     __syncthreads();
     for (uint64_t b0 = 0; b0 < ne; b0 += kBlock) {
         const uint64_t e = b0 + t;
-        EncEntry en = {0, 0, 0, 0};
-        if (e < ne) en = entries[e_first + e];
-        uint64_t sz = align16(en.bytes);
+        const uint64_t sz = e < ne ? align16(entries[e_first + e].bytes) : 0;
         uint64_t inc = sz;
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
@@ -510,23 +508,63 @@ __global__ __launch_bounds__(kBlock) void k_place(EncDesc one, const EncDesc* __
         __syncthreads();
         uint64_t pre = carry;
         for (int i = 0; i < wv; i++) pre += red[i];
-        const uint64_t off = pre + inc - sz;
-        if (e < ne) {
-            offsets[e_first + e] = off;
-            uint4 ent;
-            ent.x = uint32_t(off);
-            ent.y = uint32_t(off >> 32);
-            ent.z = en.bytes;
-            ent.w = uint32_t(en.mode) | (uint32_t(en.rle) << 8);
-            *(uint4*)(d.dst + 64 + 16 * e) = ent;
+        if (e < ne) offsets[e_first + e] = pre + inc - sz;
+        __syncthreads();
+        if (t == kBlock - 1) carry = pre + inc;
+        __syncthreads();
+    }
+    if (t == 0) totals[blockIdx.x] = 64 + 16 * ne + carry;
+}
+
+// One workgroup: the tensors' containers are laid out back to back in the
+// arena (each 16-byte aligned, in tensor order); sets each descriptor's dst,
+// writes every header, and records the arena offsets (n+1 of them).  If the
+// arena is too small nothing is written and the recorded end says so.
+__global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, int n_desc, EncParams p,
+                                                  uint8_t* __restrict__ arena, uint64_t cap,
+                                                  const uint64_t* __restrict__ totals,
+                                                  uint64_t* __restrict__ arena_off)
+{
+    __shared__ uint64_t red[kWaves];
+    __shared__ uint64_t carry;
+    __shared__ uint64_t end_sh;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t B = p.B;
+    // pass 1: offsets
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < n_desc; b0 += kBlock) {
+        const int i = b0 + t;
+        const uint64_t sz = i < n_desc ? align16(totals[i]) : 0;
+        uint64_t inc = sz;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            uint64_t o = __shfl_up(inc, dd, 64);
+            if (lane >= dd) inc += o;
         }
+        if (lane == 63) red[wv] = inc;
+        __syncthreads();
+        uint64_t pre = carry;
+        for (int w = 0; w < wv; w++) pre += red[w];
+        if (i < n_desc) arena_off[i] = pre + inc - sz;
         __syncthreads();
         if (t == kBlock - 1) carry = pre + inc;
         __syncthreads();
     }
     if (t == 0) {
-        const uint64_t total = payload_base + carry;
-        totals[blockIdx.x] = total;
+        // the last container needs only its own bytes, not the alignment
+        end_sh = n_desc ? arena_off[n_desc - 1] + totals[n_desc - 1] : 0;
+        arena_off[n_desc] = end_sh;
+    }
+    __syncthreads();
+    const bool fits = end_sh <= cap;
+    for (int i = t; i < n_desc; i += kBlock) {
+        EncDesc d = descs[i];
+        d.dst = arena + arena_off[i];
+        d.dst_cap = fits ? totals[i] : 0;   // pack skips tensors whose dst_cap is short
+        descs[i] = d;
+        if (!fits) continue;
+        const uint64_t total = totals[i];
         uint32_t h[16];
         h[0] = 0x314E4E5Au;
         h[1] = 1u | (p.dtype << 16) | (B << 24);
@@ -540,9 +578,9 @@ __global__ __launch_bounds__(kBlock) void k_place(EncDesc one, const EncDesc* __
         h[9] = uint32_t(total >> 32);
         h[10] = 0;
         for (uint32_t k = 0; k < B; k++) h[10] |= uint32_t(p.policy[k]) << (8 * k);
-        for (int i = 11; i < 16; i++) h[i] = 0;
+        for (int x = 11; x < 16; x++) h[x] = 0;
         uint4* o = (uint4*)d.dst;
-        for (int i = 0; i < 4; i++) o[i] = make_uint4(h[4 * i], h[4 * i + 1], h[4 * i + 2], h[4 * i + 3]);
+        for (int x = 0; x < 4; x++) o[x] = make_uint4(h[4 * x], h[4 * x + 1], h[4 * x + 2], h[4 * x + 3]);
     }
 }
 
@@ -660,7 +698,7 @@ __device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pack(EncDesc one, const EncDesc* __restrict__ descs, int n_desc,
+__global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ descs, int n_desc,
                                                  const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                  EncParams p, const EncEntry* __restrict__ entries,
                                                  const CodeWord* __restrict__ codes,
@@ -672,10 +710,10 @@ __global__ __launch_bounds__(kBlock) void k_pack(EncDesc one, const EncDesc* __r
     const int t = threadIdx.x, wv = t >> 6;
     const uint32_t B = p.B;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
-        const int di = descs ? find_desc(chunk_prefix, n_desc, gc) : 0;
-        const EncDesc d = descs ? descs[di] : one;
+        const int di = find_desc(chunk_prefix, n_desc, gc);
+        const EncDesc d = descs[di];
         if (totals[di] > d.dst_cap) continue;   // too small: the host reports it
-        const uint32_t c = gc - (descs ? chunk_prefix[di] : 0);
+        const uint32_t c = gc - chunk_prefix[di];
         const uint32_t E = p.chunk / B;
         const uint64_t e0 = uint64_t(c) * E;
         const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
@@ -690,6 +728,13 @@ __global__ __launch_bounds__(kBlock) void k_pack(EncDesc one, const EncDesc* __r
                 P.mode[k] = en.mode;
                 P.bytes[k] = en.bytes;
                 P.pay[k] = payload_base + offsets[ei];
+                // this chunk's map entry
+                uint4 ent;
+                ent.x = uint32_t(offsets[ei]);
+                ent.y = uint32_t(offsets[ei] >> 32);
+                ent.z = en.bytes;
+                ent.w = uint32_t(en.mode) | (uint32_t(en.rle) << 8);
+                *(uint4*)(d.dst + 64 + 16 * (uint64_t(c) * B + k)) = ent;
             }
             if (en.mode == kModeHuf) {
                 const uint32_t cw = codes[ei * 256 + t];
@@ -754,32 +799,25 @@ __global__ __launch_bounds__(kBlock) void k_pack(EncDesc one, const EncDesc* __r
 
 }  // namespace
 
-hipError_t launch_analyze(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
-                          uint32_t total_chunks, const EncParams& p, EncEntry* entries, CodeWord* codes,
-                          uint32_t* nwords, hipStream_t s)
+hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix, uint32_t total_chunks,
+                         const EncParams& p, uint8_t* arena, uint64_t cap, EncEntry* entries, CodeWord* codes,
+                         uint32_t* nwords, uint64_t* offsets, uint64_t* totals, uint64_t* arena_off, hipStream_t s)
 {
-    if (!total_chunks) return hipSuccess;
-    const uint32_t grid = min(total_chunks, 1u << 16);
-    k_analyze<<<grid, kBlock, 0, s>>>(one, d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
-    return hipGetLastError();
-}
-
-hipError_t launch_place(const EncDesc& one, const EncDesc* d_descs, int n_desc, const EncParams& p,
-                        const EncEntry* entries, uint64_t* d_offsets, uint64_t* d_totals, hipStream_t s)
-{
-    k_place<<<n_desc, kBlock, 0, s>>>(one, d_descs, p, entries, d_offsets, d_totals);
-    return hipGetLastError();
-}
-
-hipError_t launch_pack(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
-                       uint32_t total_chunks, const EncParams& p, const EncEntry* entries, const CodeWord* codes,
-                       const uint64_t* offsets, const uint64_t* d_totals, const uint32_t* nwords, hipStream_t s)
-{
-    if (!total_chunks) return hipSuccess;
-    const uint32_t grid = min(total_chunks, 1u << 16);
-    k_pack<<<grid, kBlock, 0, s>>>(one, d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, offsets,
-                                   d_totals, nwords);
-    return hipGetLastError();
+    const uint32_t grid = min(max(total_chunks, 1u), 1u << 16);
+    if (total_chunks) {
+        k_analyze<<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
+        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    }
+    k_place<<<n_desc, kBlock, 0, s>>>(d_descs, p, entries, offsets, totals);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    k_arena<<<1, kBlock, 0, s>>>(d_descs, n_desc, p, arena, cap, totals, arena_off);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    if (total_chunks) {
+        k_pack<<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, offsets,
+                                       totals, nwords);
+        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    }
+    return hipSuccess;
 }
 
 }  // namespace zipnn

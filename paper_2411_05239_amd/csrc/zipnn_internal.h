@@ -124,16 +124,14 @@ hipError_t launch_decode_one(const Header& h, const DecDesc& one, int* d_status,
 hipError_t launch_decode_batch(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
                                uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s);
 hipError_t launch_clear_status(int* d_status, hipStream_t s);
+hipError_t launch_gather_headers(const uint8_t* arena, const uint64_t* d_offs, int n, void* d_out, hipStream_t s);
 int decode_grid_size(int device);
 
-hipError_t launch_analyze(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
-                          uint32_t total_chunks, const EncParams& p, EncEntry* entries, CodeWord* codes,
-                          uint32_t* nwords /* 64 per entry */, hipStream_t s);
-hipError_t launch_place(const EncDesc& one, const EncDesc* d_descs, int n_desc, const EncParams& p,
-                        const EncEntry* entries, uint64_t* d_offsets /* per entry */,
-                        uint64_t* d_totals /* per desc */, hipStream_t s);
-hipError_t launch_pack(const EncDesc& one, const EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix,
-                       uint32_t total_chunks, const EncParams& p, const EncEntry* entries, const CodeWord* codes,
-                       const uint64_t* offsets, const uint64_t* d_totals, const uint32_t* nwords, hipStream_t s);
+// Compress n_desc tensors (descriptors and chunk prefix in device memory)
+// into `arena`: analyze -> place -> arena layout (dst of every descriptor,
+// headers, arena_off[n_desc+1]) -> pack (maps and payloads).
+hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix, uint32_t total_chunks,
+                         const EncParams& p, uint8_t* arena, uint64_t cap, EncEntry* entries, CodeWord* codes,
+                         uint32_t* nwords, uint64_t* offsets, uint64_t* totals, uint64_t* arena_off, hipStream_t s);
 
 }  // namespace zipnn

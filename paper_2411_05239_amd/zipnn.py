@@ -25,7 +25,8 @@ WIDTH = {ZIPNN_BF16: 2, ZIPNN_FP16: 2, ZIPNN_FP32: 4, ZIPNN_FP8_E4M3: 1, ZIPNN_U
 EXPORTS = [
     "zipnn_strerror", "zipnn_ctx_create", "zipnn_ctx_destroy", "zipnn_ctx_status", "zipnn_default_params",
     "zipnn_check_params", "zipnn_compress_bound", "zipnn_compress", "zipnn_decompress", "zipnn_decompress_async",
-    "zipnn_inspect",
+    "zipnn_inspect", "zipnn_compress_batch", "zipnn_batch_create", "zipnn_batch_decompress", "zipnn_batch_destroy",
+    "zipnn_decompress_batch",
 ]
 
 
@@ -50,6 +51,10 @@ class zipnn_info(ctypes.Structure):
                 ("total_bytes", ctypes.c_uint64), ("n_chunks", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32),
                 ("S", ctypes.c_uint32), ("g", ctypes.c_uint32), ("L", ctypes.c_uint32), ("is_delta", ctypes.c_int),
                 ("bytes_by_mode", ctypes.c_uint64 * 3), ("entries_by_mode", ctypes.c_uint64 * 3)]
+
+
+class zipnn_tensor_in(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("n_elems", ctypes.c_uint64), ("base", ctypes.c_void_p)]
 
 
 _lib = None
@@ -77,6 +82,14 @@ def lib():
         L.zipnn_decompress_async.argtypes = [vp, ctypes.c_char_p, vp, u64, vp, vp, u64, vp]
         L.zipnn_decompress_async.restype = i32
         L.zipnn_inspect.argtypes, L.zipnn_inspect.restype = [vp, u64, P(zipnn_info)], i32
+        L.zipnn_compress_batch.argtypes = [vp, i32, P(zipnn_tensor_in), i32, P(zipnn_params), vp, u64, P(u64), vp]
+        L.zipnn_compress_batch.restype = i32
+        L.zipnn_batch_create.argtypes = [vp, vp, P(u64), i32, P(vp), P(u64), P(vp), P(vp)]
+        L.zipnn_batch_create.restype = i32
+        L.zipnn_batch_decompress.argtypes, L.zipnn_batch_decompress.restype = [vp, vp], i32
+        L.zipnn_batch_destroy.argtypes, L.zipnn_batch_destroy.restype = [vp], None
+        L.zipnn_decompress_batch.argtypes = [vp, vp, P(u64), i32, P(vp), P(u64), P(vp), vp]
+        L.zipnn_decompress_batch.restype = i32
         _lib = L
     return _lib
 
@@ -143,6 +156,46 @@ def zipnn_inspect(host_bytes: bytes) -> zipnn_info:
     buf = ctypes.create_string_buffer(bytes(host_bytes), len(host_bytes))
     _check(lib().zipnn_inspect(buf, len(host_bytes), ctypes.byref(info)), "zipnn_inspect")
     return info
+
+
+def _u64s(vals):
+    return (ctypes.c_uint64 * len(vals))(*vals)
+
+
+def _ptrs(vals):
+    return (ctypes.c_void_p * len(vals))(*[v if v else None for v in vals])
+
+
+def zipnn_compress_batch(ctx, dtype, srcs, ns, bases, p, arena, arena_cap, stream) -> list:
+    n = len(srcs)
+    ts = (zipnn_tensor_in * n)(*[zipnn_tensor_in(s_, n_, b_) for s_, n_, b_ in zip(srcs, ns, bases)])
+    offs = (ctypes.c_uint64 * (n + 1))()
+    _check(lib().zipnn_compress_batch(ctx, dtype, ts, n, ctypes.byref(p), arena, arena_cap, offs, stream),
+           "zipnn_compress_batch")
+    return list(offs)
+
+
+def zipnn_batch_create(ctx, arena, offsets, dsts, caps, bases=None) -> int:
+    n = len(dsts)
+    h = ctypes.c_void_p()
+    _check(lib().zipnn_batch_create(ctx, arena, _u64s(offsets), n, _ptrs(dsts), _u64s(caps),
+                                    _ptrs(bases) if bases is not None else None, ctypes.byref(h)),
+           "zipnn_batch_create")
+    return h.value
+
+
+def zipnn_batch_decompress(b, stream) -> None:
+    _check(lib().zipnn_batch_decompress(b, stream), "zipnn_batch_decompress")
+
+
+def zipnn_batch_destroy(b) -> None:
+    lib().zipnn_batch_destroy(b)
+
+
+def zipnn_decompress_batch(ctx, arena, offsets, dsts, caps, bases, stream) -> None:
+    _check(lib().zipnn_decompress_batch(ctx, arena, _u64s(offsets), len(dsts), _ptrs(dsts), _u64s(caps),
+                                        _ptrs(bases) if bases is not None else None, stream),
+           "zipnn_decompress_batch")
 
 
 # ---------------------------------------------------------------- tensor helpers
@@ -242,5 +295,56 @@ class Codec:
                 raise ZipnnError(st, "zipnn_decompress (device)")
         return out
 
+    def compress_batch(self, xs, params: zipnn_params | None = None, bases=None, arena=None):
+        """Compress device tensors xs (one dtype) into one arena.
+        Returns (arena uint8 tensor, offsets list of n+1)."""
+        import torch
+
+        dt = torch_dtype_code(xs[0].dtype)
+        p = params or zipnn_default_params(dt)
+        xs = [x.contiguous() for x in xs]
+        bases = [None] * len(xs) if bases is None else [b.contiguous() if b is not None else None for b in bases]
+        cap = sum(zipnn_compress_bound(dt, x.numel(), p) + 15 for x in xs)
+        if arena is None or arena.numel() < cap:
+            arena = torch.empty(cap, dtype=torch.uint8, device=xs[0].device)
+        offs = zipnn_compress_batch(self.ctx, dt, [x.data_ptr() for x in xs], [x.numel() for x in xs],
+                                    [b.data_ptr() if b is not None else None for b in bases], p, arena.data_ptr(),
+                                    arena.numel(), self._stream())
+        return arena, offs
+
+    def prepare_batch(self, arena, offsets, outs, bases=None) -> "Batch":
+        return Batch(self, arena, offsets, outs, bases)
+
     def status(self, clear: bool = True) -> int:
         return zipnn_ctx_status(self.ctx, self._stream(), clear)
+
+
+class Batch:
+    """A prepared batched decompression (descriptor tables on the device and a
+    captured hipGraph); run() replays it on the current stream."""
+
+    def __init__(self, codec: Codec, arena, offsets, outs, bases=None):
+        self.codec = codec
+        self._keep = (arena, list(outs), bases)
+        self.h = zipnn_batch_create(codec.ctx, arena.data_ptr(), offsets, [o.data_ptr() for o in outs],
+                                    [o.numel() * o.element_size() for o in outs],
+                                    None if bases is None else [b.data_ptr() if b is not None else None
+                                                                for b in bases])
+
+    def run(self, check: bool = False):
+        zipnn_batch_decompress(self.h, Codec._stream())
+        if check:
+            st = self.codec.status(clear=True)
+            if st != ZIPNN_OK:
+                raise ZipnnError(st, "batch decompress (device)")
+
+    def close(self):
+        if self.h:
+            zipnn_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,141 @@
+"""Batched encode/decode (one launch per kernel for all tensors of a
+checkpoint) against per-tensor calls and the oracle; graph replays of the
+prepared batch; mixed kernel classes; XOR deltas.  Zero differing bytes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_05239_amd import workloads
+from paper_2411_05239_amd import zipnn as Z
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def codec():
+    c = Z.Codec(0)
+    yield c
+    c.close()
+
+
+def _kw(p):
+    return dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy))
+
+
+def _u8(t):
+    return t.contiguous().view(torch.uint8).reshape(-1)
+
+
+def _small_checkpoint(seed0=50):
+    """A scaled-down decoder checkpoint: same kinds of tensors (weights,
+    norms, an embedding), sizes cut so the oracle finishes in seconds, plus an
+    empty tensor and ragged sizes."""
+    specs = workloads.checkpoint_8b_specs(layers=2, hidden=256, kv=64, ffn=896, vocab=3001, seed0=seed0)
+    xs = [workloads.make_tensor(s) for s in specs]
+    xs.insert(3, torch.empty(0, dtype=torch.bfloat16))
+    xs.append(workloads.bf16_normal(131072 * 2 + 5, seed=seed0 + 99))
+    return xs
+
+
+def test_batch_equals_per_tensor_and_oracle(codec):
+    xs = _small_checkpoint()
+    p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=65536)
+    dev = [x.cuda() for x in xs]
+    arena, offs = codec.compress_batch(dev, p)
+    a = arena.cpu().numpy()
+    print("tensors", len(xs), "arena bytes", offs[-1], flush=True)
+    for i, x in enumerate(xs):
+        assert offs[i] % 16 == 0
+        total = int.from_bytes(a[offs[i] + 32: offs[i] + 40].tobytes(), "little")   # header: container size
+        ci = a[offs[i]: offs[i] + total]
+        ref = oracle.compress(x, oracle.BF16, **_kw(p))
+        assert np.array_equal(ci, ref), i
+        solo = codec.compress(dev[i], p).cpu().numpy()
+        assert np.array_equal(solo, ref), i
+    outs = [torch.empty_like(x) for x in dev]
+    Z.zipnn_decompress_batch(codec.ctx, arena.data_ptr(), offs, [o.data_ptr() for o in outs],
+                             [o.numel() * 2 for o in outs], None, codec._stream())
+    assert codec.status() == Z.ZIPNN_OK
+    for o, x in zip(outs, dev):
+        assert torch.equal(_u8(o), _u8(x))
+
+
+def test_prepared_batch_graph_replays(codec):
+    xs = [x.cuda() for x in _small_checkpoint(seed0=70)]
+    p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=65536)
+    arena, offs = codec.compress_batch(xs, p)
+    outs = [torch.zeros_like(x) for x in xs]
+    b = codec.prepare_batch(arena, offs, outs)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(rep + 1)   # eager work between replays
+        torch.cuda.synchronize()
+        b.run(check=True)
+        torch.cuda.synchronize()
+        for o, x in zip(outs, xs):
+            assert torch.equal(_u8(o), _u8(x)), rep
+    b.close()
+
+
+def test_batch_mixed_classes(codec):
+    """BF16 (g=4), FP32, FP8 and a BF16 g=8 container in one arena: one
+    launch per (B, g, delta) class."""
+    xb = workloads.bf16_normal(300_001, seed=1).cuda()
+    xf = workloads.fp32_rows(3, 50_000, seed=2).reshape(-1).cuda()
+    x8 = workloads.make_corpus_tensor(workloads.CorpusItem(0, "fp8", 400_000, 3)).cuda()
+    xg = workloads.bf16_normal(200_000, seed=4).cuda()
+    cs = [codec.compress(xb, Z.zipnn_default_params(Z.ZIPNN_BF16)),
+          codec.compress(xf, Z.zipnn_default_params(Z.ZIPNN_FP32)),
+          codec.compress(x8, Z.zipnn_default_params(Z.ZIPNN_FP8_E4M3)),
+          codec.compress(xg, Z.make_params(Z.ZIPNN_BF16, g=8))]
+    offs = [0]
+    for c in cs:
+        offs.append(offs[-1] + (c.numel() + 15) // 16 * 16)
+    arena = torch.zeros(offs[-1], dtype=torch.uint8, device="cuda")
+    for c, o in zip(cs, offs):
+        arena[o: o + c.numel()] = c
+    xs = [xb, xf, x8, xg]
+    outs = [torch.empty_like(x) for x in xs]
+    b = codec.prepare_batch(arena, offs, outs)
+    b.run(check=True)
+    torch.cuda.synchronize()
+    for o, x in zip(outs, xs):
+        assert torch.equal(_u8(o), _u8(x))
+    b.close()
+
+
+def test_batch_xor_delta(codec):
+    base = [x.cuda() for x in _small_checkpoint(seed0=90)]
+    ft = [workloads.finetune_delta(x, seed=2000 + i) if x.numel() else x.clone() for i, x in enumerate(base)]
+    p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=65536, policy=[Z.ZIPNN_HUF, Z.ZIPNN_HUF])
+    arena, offs = codec.compress_batch(ft, p, bases=base)
+    a = arena.cpu().numpy()
+    for i in (0, 1, len(base) - 1):
+        ref = oracle.compress(ft[i].cpu(), oracle.BF16, base=base[i].cpu(), **_kw(p))
+        assert np.array_equal(a[offs[i]: offs[i] + ref.size], ref), i
+    outs = [torch.empty_like(x) for x in ft]
+    b = codec.prepare_batch(arena, offs, outs, bases=base)
+    b.run(check=True)
+    torch.cuda.synchronize()
+    for o, x in zip(outs, ft):
+        assert torch.equal(_u8(o), _u8(x))
+    b.close()
+    assert offs[-1] < 0.25 * sum(x.numel() * 2 for x in ft)
+
+
+def test_batch_errors(codec):
+    xs = [workloads.bf16_normal(70_000, seed=5).cuda()]
+    arena, offs = codec.compress_batch(xs, Z.zipnn_default_params(Z.ZIPNN_BF16))
+    out = torch.empty_like(xs[0])
+    with pytest.raises(Z.ZipnnError) as ei:       # output too small
+        Z.zipnn_batch_create(codec.ctx, arena.data_ptr(), offs, [out.data_ptr()], [out.numel() * 2 - 2])
+    assert ei.value.code == Z.ZIPNN_E_NOSPACE
+    with pytest.raises(Z.ZipnnError) as ei:       # misaligned offset
+        Z.zipnn_batch_create(codec.ctx, arena.data_ptr(), [8, offs[1]], [out.data_ptr()], [out.numel() * 2])
+    assert ei.value.code == Z.ZIPNN_E_INVAL
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(Z.ZipnnError) as ei:       # arena too small
+        Z.zipnn_compress_batch(codec.ctx, Z.ZIPNN_BF16, [xs[0].data_ptr()], [xs[0].numel()], [None],
+                               Z.zipnn_default_params(Z.ZIPNN_BF16), small.data_ptr(), 64, codec._stream())
+    assert ei.value.code == Z.ZIPNN_E_NOSPACE
