@@ -213,6 +213,27 @@ void zipnn_batch_destroy(zipnn_batch b);
 int zipnn_decompress_batch(zipnn_ctx ctx, const void* arena, const uint64_t* offsets, int n, void* const* dst,
                            const uint64_t* dst_cap, const void* const* base, void* stream);
 
+/* ---------------------------------------------------------------- autotuner */
+
+typedef struct {
+    zipnn_params params;
+    double ratio;          /* container bytes / input bytes on the sample */
+    double decode_gbps;    /* uncompressed GB/s of the batched (graph) decode */
+    double encode_gbps;    /* uncompressed GB/s of the batched encode */
+} zipnn_tune_entry;
+
+/* Pick format parameters for a set of tensors of `dtype` by measurement on
+ * this GPU: a sample (tensors in order, up to sample_bytes) is compressed and
+ * batch-decompressed under every candidate chunk size (64 KiB .. 1 MiB) and
+ * sub-stream length S (chunk elements / 128 .. / 1024), with `policy` (NULL:
+ * AUTO).  *best gets the fastest decode among the candidates whose ratio is
+ * within (1 + max_ratio_loss) of the best ratio seen; entries[0..max_entries)
+ * receive the measurements (*n_entries = how many candidates ran).  Blocking;
+ * allocates and frees its own sample buffers. */
+int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, uint64_t sample_bytes,
+                   double max_ratio_loss, const uint8_t* policy, zipnn_params* best, zipnn_tune_entry* entries,
+                   int max_entries, int* n_entries);
+
 /* Validate a container's header and map from HOST memory (len bytes: at
  * least the header and the map) and summarise it in *out. */
 int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out);

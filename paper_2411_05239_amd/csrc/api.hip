@@ -1,5 +1,6 @@
 // Host runtime behind include/zipnn.h: contexts, argument checks, scratch
 // management, kernel launches and host-side container inspection.
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
@@ -480,6 +481,125 @@ int zipnn_decompress_batch(zipnn_ctx ctx, const void* arena, const uint64_t* off
     if (rc == ZIPNN_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = ZIPNN_E_HIP;
     zipnn_batch_destroy(b);
     return rc;
+}
+
+// ------------------------------------------------------------ autotuner
+
+int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, uint64_t sample_bytes,
+                   double max_ratio_loss, const uint8_t* policy, zipnn_params* best, zipnn_tune_entry* entries,
+                   int max_entries, int* n_entries)
+{
+    const int B = dtype_bytes(dtype);
+    if (!ctx || !tensors || n < 1 || !best || !B || max_ratio_loss < 0) return ZIPNN_E_INVAL;
+    // the sample: tensors in order, the last one cut, up to sample_bytes
+    std::vector<zipnn_tensor_in> smp;
+    uint64_t sbytes = 0;
+    for (int i = 0; i < n && sbytes < sample_bytes; i++) {
+        zipnn_tensor_in t = tensors[i];
+        const uint64_t room = (sample_bytes - sbytes) / uint64_t(B);
+        if (t.n_elems > room) t.n_elems = room;
+        if (!t.n_elems) continue;
+        smp.push_back(t);
+        sbytes += t.n_elems * uint64_t(B);
+    }
+    if (smp.empty()) return ZIPNN_E_INVAL;
+    // candidate formats: chunk size x sub-stream length
+    std::vector<zipnn_params> cands;
+    for (uint32_t chunk = 64u << 10; chunk <= (1u << 20); chunk <<= 1) {
+        const uint32_t E = chunk / uint32_t(B);
+        for (uint32_t div = 128; div <= 1024; div <<= 1) {
+            zipnn_params p;
+            zipnn_default_params(dtype, &p);
+            p.chunk_bytes = chunk;
+            p.substream_syms = uint16_t(std::max<uint32_t>(4, E / div));
+            if (policy)
+                for (int k = 0; k < 4; k++) p.policy[k] = policy[k];
+            if (zipnn_check_params(dtype, &p) == ZIPNN_OK) cands.push_back(p);
+        }
+    }
+    DeviceGuard g(ctx->device);
+    uint64_t cap = 0;
+    for (const auto& p : cands) {
+        uint64_t c = 0;
+        for (const auto& t : smp) c += zipnn_compress_bound(dtype, t.n_elems, &p) + 16;
+        cap = std::max(cap, c);
+    }
+    void* arena = nullptr;
+    void* outs = nullptr;
+    if (hipMalloc(&arena, cap) != hipSuccess) return ZIPNN_E_NOMEM;
+    if (hipMalloc(&outs, align256(sbytes) + 256 * smp.size()) != hipSuccess) {
+        (void)hipFree(arena);
+        return ZIPNN_E_NOMEM;
+    }
+    std::vector<void*> dst(smp.size());
+    std::vector<uint64_t> caps(smp.size());
+    std::vector<const void*> bases(smp.size());
+    bool any_base = false;
+    {
+        uint64_t o = 0;
+        for (size_t i = 0; i < smp.size(); i++) {
+            dst[i] = (uint8_t*)outs + o;
+            caps[i] = smp[i].n_elems * uint64_t(B);
+            bases[i] = smp[i].base;
+            any_base |= smp[i].base != nullptr;
+            o += align256(caps[i]);
+        }
+    }
+    hipStream_t s = nullptr;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    std::vector<zipnn_tune_entry> res;
+    int rc = ZIPNN_OK;
+    std::vector<uint64_t> offs(smp.size() + 1);
+    for (const auto& p : cands) {
+        (void)hipEventRecord(e0, s);
+        rc = zipnn_compress_batch(ctx, dtype, smp.data(), int(smp.size()), &p, arena, cap, offs.data(), s);
+        (void)hipEventRecord(e1, s);
+        if (rc) break;
+        (void)hipEventSynchronize(e1);
+        float enc_ms = 0;
+        (void)hipEventElapsedTime(&enc_ms, e0, e1);
+        zipnn_batch b = nullptr;
+        rc = zipnn_batch_create(ctx, arena, offs.data(), int(smp.size()), dst.data(), caps.data(),
+                                any_base ? bases.data() : nullptr, &b);
+        if (rc) break;
+        float best_ms = 1e30f;
+        for (int r = 0; r < 4; r++) {
+            (void)hipEventRecord(e0, s);
+            (void)zipnn_batch_decompress(b, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) best_ms = std::min(best_ms, ms);   // first run warms up
+        }
+        zipnn_batch_destroy(b);
+        zipnn_tune_entry te;
+        te.params = p;
+        te.ratio = double(offs.back()) / double(sbytes);
+        te.decode_gbps = double(sbytes) / (double(best_ms) * 1e6);
+        te.encode_gbps = double(sbytes) / (double(enc_ms) * 1e6);
+        res.push_back(te);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(arena);
+    (void)hipFree(outs);
+    if (rc) return rc;
+    if (zipnn_ctx_status(ctx, nullptr, 1) != ZIPNN_OK) return ZIPNN_E_CORRUPT;
+    // fastest decode among the candidates within the allowed ratio loss
+    double best_ratio = 1e30;
+    for (const auto& r : res) best_ratio = std::min(best_ratio, r.ratio);
+    int pick = -1;
+    for (size_t i = 0; i < res.size(); i++)
+        if (res[i].ratio <= best_ratio * (1.0 + max_ratio_loss) && (pick < 0 || res[i].decode_gbps > res[pick].decode_gbps))
+            pick = int(i);
+    *best = res[pick].params;
+    if (n_entries) *n_entries = int(res.size());
+    if (entries)
+        for (int i = 0; i < std::min(max_entries, int(res.size())); i++) entries[i] = res[i];
+    return ZIPNN_OK;
 }
 
 int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out)

@@ -143,151 +143,6 @@ __device__ bool build_lut(const uint8_t* table, uint32_t L, uint16_t* lut, LutTm
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kDepth = 4;   // groups of raw bytes prefetched ahead per lane
-#define NWIN 3              // 64-word windows of a Huffman word stream held per lane
-
-template <int G>
-struct SlotSize {
-    static constexpr int PW = G >= 4 ? G / 4 : 1;                 // packed words per group
-    static constexpr int N = kDepth * PW > (NWIN + 3) ? kDepth * PW : (NWIN + 3);
-};
-
-// Uniform (scalar) part of a lane group's Huffman word stream.
-struct WordCursor {
-    const uint32_t* p;   // first word of this lane group's stream
-    uint32_t last;       // index of its last word
-    uint32_t ptr;        // words taken so far
-    uint32_t wb;         // stream index held by lane 0 of the head window (multiple of 64)
-    uint32_t head;       // register of the head window (0..NWIN-1)
-};
-
-__device__ inline void huf_init(uint32_t* r, WordCursor& c, const uint32_t* words, uint32_t nwords, uint32_t lane)
-{
-    c.p = words;
-    c.last = nwords - 1;
-    c.ptr = 0;
-    c.wb = 0;
-    c.head = 0;
-#pragma unroll
-    for (int i = 0; i < NWIN; i++) r[i] = words[min(64 * i + lane, c.last)];
-    r[NWIN] = 0;
-    r[NWIN + 1] = 0;
-    r[NWIN + 2] = 0;
-}
-
-// One round's word requests: lanes taking part with fewer than 2L buffered
-// bits take the next words of the stream, in lane order.  The windows form a
-// ring: the head window and the next one are read (chosen by a wave-uniform
-// switch, so only those two registers are touched); when the head is used up
-// its register is reloaded with the window NWIN-1 ahead.
-__device__ inline void huf_take(uint32_t* r, WordCursor& c, bool part, uint32_t twoL, uint32_t lane)
-{
-    const bool need = part && r[NWIN] < twoL;
-    const uint64_t m = __ballot(need);
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-    const uint32_t rel = c.ptr - c.wb + below;   // < 128
-    const int src = int(rel & 63);
-    uint32_t a = 0, b = 0;
-    switch (c.head) {
-#define ZIPNN_W(i)                                         \
-    case i:                                                \
-        a = __shfl(r[i], src, 64);                         \
-        b = __shfl(r[(i + 1) % NWIN], src, 64);            \
-        break;
-        ZIPNN_W(0) ZIPNN_W(1) ZIPNN_W(2)
-#if NWIN > 3
-        ZIPNN_W(3)
-#endif
-#if NWIN > 4
-        ZIPNN_W(4)
-#endif
-#if NWIN > 5
-        ZIPNN_W(5)
-#endif
-#undef ZIPNN_W
-    }
-    const uint32_t word = rel < 64 ? a : b;
-    if (need) {
-        const uint64_t x = uint64_t(word) << r[NWIN];
-        r[NWIN + 1] |= uint32_t(x);
-        r[NWIN + 2] |= uint32_t(x >> 32);
-        r[NWIN] += 32;
-    }
-    c.ptr += uint32_t(__popcll(m));
-    if (c.ptr - c.wb >= 64) {
-        const uint32_t v = c.p[min(c.wb + 64 * NWIN + lane, c.last)];
-        switch (c.head) {
-#define ZIPNN_W(i) \
-    case i:        \
-        r[i] = v;  \
-        break;
-            ZIPNN_W(0) ZIPNN_W(1) ZIPNN_W(2)
-#if NWIN > 3
-            ZIPNN_W(3)
-#endif
-#if NWIN > 4
-            ZIPNN_W(4)
-#endif
-#if NWIN > 5
-            ZIPNN_W(5)
-#endif
-#undef ZIPNN_W
-        }
-        c.wb += 64;
-        c.head = c.head + 1 == NWIN ? 0 : c.head + 1;
-    }
-}
-
-__device__ inline uint32_t huf_get(uint32_t* r, const uint16_t* lut, uint32_t mask)
-{
-    const uint32_t e = lut[r[NWIN + 1] & mask];
-    const uint32_t l = e >> 8;
-    r[NWIN + 1] = __builtin_amdgcn_alignbit(r[NWIN + 2], r[NWIN + 1], l);
-    r[NWIN + 2] >>= l;
-    r[NWIN] -= l;
-    return e & 0xFFu;
-}
-
-template <int G>
-__device__ inline void raw_load(const uint8_t* p, uint32_t* o)
-{
-    if constexpr (G == 2) o[0] = *(const uint16_t*)p;
-    else if constexpr (G == 4) o[0] = __builtin_nontemporal_load((const uint32_t*)p);
-    else {
-        u32x2 v = __builtin_nontemporal_load((const u32x2*)p);
-        o[0] = v.x;
-        o[1] = v.y;
-    }
-}
-
-template <int NB>
-__device__ inline void store_words(uint8_t* d, const uint32_t* w)
-{
-    if constexpr (NB == 2) *(uint16_t*)d = uint16_t(w[0]);
-    else if constexpr (NB == 4) __builtin_nontemporal_store(w[0], (uint32_t*)d);
-    else if constexpr (NB == 8) __builtin_nontemporal_store(u32x2{w[0], w[1]}, (u32x2*)d);
-    else if constexpr (NB == 16) __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, (u32x4*)d);
-    else {
-        __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, (u32x4*)d);
-        __builtin_nontemporal_store(u32x4{w[4], w[5], w[6], w[7]}, (u32x4*)(d + 16));
-    }
-}
-
-template <int NB>
-__device__ inline void load_words(const uint8_t* b, uint32_t* w)
-{
-    if constexpr (NB == 2) w[0] = *(const uint16_t*)b;
-    else if constexpr (NB == 4) w[0] = __builtin_nontemporal_load((const uint32_t*)b);
-    else {
-#pragma unroll
-        for (int i = 0; i < NB / 8; i++) {
-            u32x2 v = __builtin_nontemporal_load((const u32x2*)(b + 8 * i));
-            w[2 * i] = v.x;
-            w[2 * i + 1] = v.y;
-        }
-    }
-}
-
 // Buffer resource over [p, p + bytes): loads past the end return zero and
 // stores past it are dropped.  Offsets of accesses that must not happen are
 // set to kOff, far past any valid range.
@@ -351,14 +206,155 @@ __device__ inline void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, const u
     }
 }
 
+constexpr int kDepth = 4;   // groups of raw bytes prefetched ahead per lane
+
+// Words of a lane group's Huffman stream pass through a ring in LDS (per
+// wave and stream) of RW words: two halves of RW/2.  When the read cursor has
+// used up the older half, the block fetched one half earlier (held per lane
+// in registers) is written there and the next block is fetched, so a fetch
+// has a whole half of the ring's consumption to arrive.
+template <int B>
+struct Ring {
+    static constexpr int RW = B == 4 ? 256 : 512;   // words per ring
+    static constexpr int PN = RW / 128;             // words per lane of a pending half block
+};
+
+template <int B, int G>
+struct SlotSize {
+    static constexpr int PW = G >= 4 ? G / 4 : 1;                 // packed words per group
+    static constexpr int HUF = Ring<B>::PN + 3;                   // pending block, count, 64-bit buffer
+    static constexpr int N = kDepth * PW > HUF ? kDepth * PW : HUF;
+};
+
+// Uniform (scalar) state of a lane group's Huffman word stream.
+struct WordCursor {
+    __amdgpu_buffer_rsrc_t rs;   // this lane group's words
+    uint32_t* ring;              // this wave's ring for the stream (LDS)
+    uint32_t ptr;                // words taken so far
+    uint32_t rb;                 // stream index of the ring's oldest word (multiple of RW/2)
+};
+
+// A stream's register slot holds, for a Huffman stream: the pending block
+// r[0..PN), the buffered bit count r[PN] and the 64-bit bit buffer
+// r[PN+1] | r[PN+2] << 32; for a raw stream: the ring of prefetched groups
+// (r[u*PW + x]).  The mode of a stream is fixed for a chunk, so one set of
+// registers serves both.
+
+template <int B>
+__device__ inline void pend_load(uint32_t* r, const WordCursor& c, uint32_t first, uint32_t lane)
+{
+    constexpr int PN = Ring<B>::PN;
+    buf_load<4 * PN>(c.rs, (first + PN * lane) * 4, r);
+}
+
+template <int B>
+__device__ inline void huf_init(uint32_t* r, WordCursor& c, const uint32_t* words, uint32_t nwords, uint32_t lane,
+                                uint32_t* ring)
+{
+    constexpr int RW = Ring<B>::RW, PN = Ring<B>::PN;
+    c.rs = rsrc(words, nwords * 4);
+    c.ring = ring;
+    c.ptr = 0;
+    c.rb = 0;
+    // fill the ring with words [0, RW), then fetch [RW, RW + RW/2)
+    uint32_t v[2 * PN];
+    buf_load<8 * PN>(c.rs, 2 * PN * lane * 4, v);
+#pragma unroll
+    for (int x = 0; x < 2 * PN; x++) ring[2 * PN * lane + x] = v[x];
+    pend_load<B>(r, c, RW, lane);
+    r[PN] = 0;
+    r[PN + 1] = 0;
+    r[PN + 2] = 0;
+}
+
+// One round's word requests: lanes taking part with fewer than 2L buffered
+// bits take the next words of the stream, in lane order (a ballot and a
+// prefix popcount give each lane its word).
+template <int B>
+__device__ inline void huf_take(uint32_t* r, WordCursor& c, bool part, uint32_t twoL, uint32_t lane)
+{
+    constexpr int RW = Ring<B>::RW, PN = Ring<B>::PN;
+    const bool need = part && r[PN] < twoL;
+    const uint64_t m = __ballot(need);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    if (need) {
+        const uint32_t word = c.ring[(c.ptr + below) & (RW - 1)];
+        const uint64_t x = uint64_t(word) << r[PN];
+        r[PN + 1] |= uint32_t(x);
+        r[PN + 2] |= uint32_t(x >> 32);
+        r[PN] += 32;
+    }
+    c.ptr += uint32_t(__popcll(m));
+    if (c.ptr - c.rb >= RW / 2) {
+        // the older half is used up: it receives the pending block
+        uint32_t* half = c.ring + (c.rb & (RW - 1));
+#pragma unroll
+        for (int x = 0; x < PN; x++) half[PN * lane + x] = r[x];
+        c.rb += RW / 2;
+        pend_load<B>(r, c, c.rb + RW, lane);
+    }
+}
+
+template <int B>
+__device__ inline uint32_t huf_get(uint32_t* r, const uint16_t* lut, uint32_t mask)
+{
+    constexpr int PN = Ring<B>::PN;
+    const uint32_t e = lut[r[PN + 1] & mask];
+    const uint32_t l = e >> 8;
+    r[PN + 1] = __builtin_amdgcn_alignbit(r[PN + 2], r[PN + 1], l);
+    r[PN + 2] >>= l;
+    r[PN] -= l;
+    return e & 0xFFu;
+}
+
+template <int G>
+__device__ inline void raw_load(const uint8_t* p, uint32_t* o)
+{
+    if constexpr (G == 2) o[0] = *(const uint16_t*)p;
+    else if constexpr (G == 4) o[0] = __builtin_nontemporal_load((const uint32_t*)p);
+    else {
+        u32x2 v = __builtin_nontemporal_load((const u32x2*)p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+}
+
+template <int NB>
+__device__ inline void store_words(uint8_t* d, const uint32_t* w)
+{
+    if constexpr (NB == 2) *(uint16_t*)d = uint16_t(w[0]);
+    else if constexpr (NB == 4) __builtin_nontemporal_store(w[0], (uint32_t*)d);
+    else if constexpr (NB == 8) __builtin_nontemporal_store(u32x2{w[0], w[1]}, (u32x2*)d);
+    else if constexpr (NB == 16) __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, (u32x4*)d);
+    else {
+        __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, (u32x4*)d);
+        __builtin_nontemporal_store(u32x4{w[4], w[5], w[6], w[7]}, (u32x4*)(d + 16));
+    }
+}
+
+template <int NB>
+__device__ inline void load_words(const uint8_t* b, uint32_t* w)
+{
+    if constexpr (NB == 2) w[0] = *(const uint16_t*)b;
+    else if constexpr (NB == 4) w[0] = __builtin_nontemporal_load((const uint32_t*)b);
+    else {
+#pragma unroll
+        for (int i = 0; i < NB / 8; i++) {
+            u32x2 v = __builtin_nontemporal_load((const u32x2*)(b + 8 * i));
+            w[2 * i] = v.x;
+            w[2 * i + 1] = v.y;
+        }
+    }
+}
+
 // Interleave the B byte groups of G elements back into words (the inverse of
 // byte grouping): pk[k][x] holds symbols 4x..4x+3 of stream k; element i's
 // little-endian word is (s_{B-1}[i], ..., s_1[i], s_0[i]).  v_perm_b32 picks
 // bytes of {S0:S1} (selector 0-3: S1, 4-7: S0).
 template <int B, int G>
-__device__ inline void merge_words(const uint32_t (*pk)[SlotSize<G>::PW], uint32_t* ow)
+__device__ inline void merge_words(const uint32_t (*pk)[G >= 4 ? G / 4 : 1], uint32_t* ow)
 {
-    constexpr int PW = SlotSize<G>::PW;
+    constexpr int PW = G >= 4 ? G / 4 : 1;
     if constexpr (B == 1) {
 #pragma unroll
         for (int x = 0; x < PW; x++) ow[x] = pk[0][x];
@@ -391,15 +387,15 @@ __device__ inline void merge_words(const uint32_t (*pk)[SlotSize<G>::PW], uint32
 // While every lane of the group still has a full group of g symbols the loop
 // runs without per-lane conditions; the last groups take the general path.
 template <int B, int G, bool DELTA>
-__device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemState& st,
+__device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemState& st, uint32_t* wring,
                                   const uint16_t (*lut)[kLutSize], const uint32_t (*wprefix)[65], uint32_t L,
                                   uint32_t j, uint32_t W, uint32_t m, uint8_t* __restrict__ out,
                                   const uint8_t* __restrict__ base, int* status)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
-    constexpr int PW = SlotSize<G>::PW;
-    constexpr int NS = SlotSize<G>::N;
+    constexpr int PW = SlotSize<B, G>::PW;
+    constexpr int NS = SlotSize<B, G>::N;
     constexpr int BD = DELTA ? kDepth : 1;
     src = uniptr(src);
     out = uniptr(out);
@@ -424,6 +420,7 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
     const uint8_t* pay[B];
     __amdgpu_buffer_rsrc_t rr[B];
     WordCursor cur[B];
+    uint32_t nw[B];
     uint32_t slot[B][NS];
     uint32_t bring[BD][NW];
     const __amdgpu_buffer_rsrc_t ro = rsrc(out, m * B);
@@ -442,7 +439,8 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
             const uint32_t* words = (const uint32_t*)(pay[k] + huf_head(W));
             const uint32_t s0 = __builtin_amdgcn_readfirstlane(wprefix[k][j]);
             const uint32_t s1 = __builtin_amdgcn_readfirstlane(wprefix[k][j + 1]);
-            huf_init(slot[k], cur[k], words + s0, s1 - s0, lane);
+            nw[k] = s1 - s0;
+            huf_init<B>(slot[k], cur[k], words + s0, s1 - s0, lane, wring + (k * 4 + (threadIdx.x >> 6)) * Ring<B>::RW);
         } else if (mode[k] == kModeRaw) {
 #pragma unroll
             for (int u = 0; u < kDepth; u++) buf_load<G>(rr[k], raw_off(u), &slot[k][u * PW]);
@@ -477,9 +475,9 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
                     for (int x = 0; x < PW; x++) pk[k][x] = 0;
 #pragma unroll
                     for (int pr = 0; pr < G / 2; pr++) {
-                        huf_take(slot[k], cur[k], true, twoL, lane);
-                        const uint32_t s0 = huf_get(slot[k], lut[k], mask);
-                        const uint32_t s1 = huf_get(slot[k], lut[k], mask);
+                        huf_take<B>(slot[k], cur[k], true, twoL, lane);
+                        const uint32_t s0 = huf_get<B>(slot[k], lut[k], mask);
+                        const uint32_t s1 = huf_get<B>(slot[k], lut[k], mask);
                         pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
                     }
                 }
@@ -520,11 +518,11 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
 #pragma unroll
                     for (int pr = 0; pr < G / 2; pr++) {
                         const bool part = 2u * pr < gcnt;
-                        huf_take(slot[k], cur[k], part, twoL, lane);
+                        huf_take<B>(slot[k], cur[k], part, twoL, lane);
                         if (part) {
-                            pk[k][(2 * pr) >> 2] |= huf_get(slot[k], lut[k], mask) << (8 * ((2 * pr) & 3));
+                            pk[k][(2 * pr) >> 2] |= huf_get<B>(slot[k], lut[k], mask) << (8 * ((2 * pr) & 3));
                             if (2u * pr + 1 < gcnt)
-                                pk[k][(2 * pr + 1) >> 2] |= huf_get(slot[k], lut[k], mask) << (8 * ((2 * pr + 1) & 3));
+                                pk[k][(2 * pr + 1) >> 2] |= huf_get<B>(slot[k], lut[k], mask) << (8 * ((2 * pr + 1) & 3));
                         }
                     }
                 }
@@ -563,7 +561,7 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
     }
 #pragma unroll
     for (int k = 0; k < B; k++)
-        if (mode[k] == kModeHuf && cur[k].ptr != cur[k].last + 1 && lane == 0) set_status(status, ZIPNN_E_CORRUPT);
+        if (mode[k] == kModeHuf && cur[k].ptr != nw[k] && lane == 0) set_status(status, ZIPNN_E_CORRUPT);
 }
 
 // Parse one tensor's header on the device and size its work.
@@ -610,7 +608,7 @@ __device__ bool load_tensor(const DecDesc& d, int di, TensorState& ts, int* stat
 // lookup table, the lane groups' word counts are checked and prefixed, then
 // every wave decodes its lane group.
 template <int B, int G, bool DELTA>
-__device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c, uint32_t slice,
+__device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c, uint32_t slice, uint32_t* wring,
                             uint16_t (*lut)[kLutSize], uint32_t (*wprefix)[65], LutTmp& T, ItemState& st,
                             int* status)
 {
@@ -690,7 +688,7 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
     if (j < NG) {
         uint8_t* out = d.dst + uint64_t(c) * h.E * B;
         const uint8_t* base = DELTA ? d.base + uint64_t(c) * h.E * B : nullptr;
-        decode_lane_group<B, G, DELTA>(d.src, st, lut, wprefix, h.L, j, W, m, out, base, status);
+        decode_lane_group<B, G, DELTA>(d.src, st, wring, lut, wprefix, h.L, j, W, m, out, base, status);
     }
     __syncthreads();
 }
@@ -705,6 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecDesc one, const DecDesc* _
 {
     __shared__ uint16_t lut[B][kLutSize];
     __shared__ uint32_t wprefix[B][65];
+    __shared__ uint32_t wring[B * 4 * Ring<B>::RW];
     __shared__ LutTmp T;
     __shared__ ItemState st;
     __shared__ TensorState ts;
@@ -756,7 +755,7 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecDesc one, const DecDesc* _
             c = ts.h.n_chunks - 1;
             slice = uint32_t(local - full_items);
         }
-        decode_item<B, G, DELTA>(descs[ts.desc], ts, c, slice, lut, wprefix, T, st, status);
+        decode_item<B, G, DELTA>(descs[ts.desc], ts, c, slice, wring, lut, wprefix, T, st, status);
     }
 }
 

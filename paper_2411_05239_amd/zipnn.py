@@ -26,7 +26,7 @@ EXPORTS = [
     "zipnn_strerror", "zipnn_ctx_create", "zipnn_ctx_destroy", "zipnn_ctx_status", "zipnn_default_params",
     "zipnn_check_params", "zipnn_compress_bound", "zipnn_compress", "zipnn_decompress", "zipnn_decompress_async",
     "zipnn_inspect", "zipnn_compress_batch", "zipnn_batch_create", "zipnn_batch_decompress", "zipnn_batch_destroy",
-    "zipnn_decompress_batch",
+    "zipnn_decompress_batch", "zipnn_autotune",
 ]
 
 
@@ -51,6 +51,11 @@ class zipnn_info(ctypes.Structure):
                 ("total_bytes", ctypes.c_uint64), ("n_chunks", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32),
                 ("S", ctypes.c_uint32), ("g", ctypes.c_uint32), ("L", ctypes.c_uint32), ("is_delta", ctypes.c_int),
                 ("bytes_by_mode", ctypes.c_uint64 * 3), ("entries_by_mode", ctypes.c_uint64 * 3)]
+
+
+class zipnn_tune_entry(ctypes.Structure):
+    _fields_ = [("params", zipnn_params), ("ratio", ctypes.c_double), ("decode_gbps", ctypes.c_double),
+                ("encode_gbps", ctypes.c_double)]
 
 
 class zipnn_tensor_in(ctypes.Structure):
@@ -90,6 +95,9 @@ def lib():
         L.zipnn_batch_destroy.argtypes, L.zipnn_batch_destroy.restype = [vp], None
         L.zipnn_decompress_batch.argtypes = [vp, vp, P(u64), i32, P(vp), P(u64), P(vp), vp]
         L.zipnn_decompress_batch.restype = i32
+        L.zipnn_autotune.argtypes = [vp, i32, P(zipnn_tensor_in), i32, u64, ctypes.c_double, vp, P(zipnn_params),
+                                     P(zipnn_tune_entry), i32, P(i32)]
+        L.zipnn_autotune.restype = i32
         _lib = L
     return _lib
 
@@ -196,6 +204,19 @@ def zipnn_decompress_batch(ctx, arena, offsets, dsts, caps, bases, stream) -> No
     _check(lib().zipnn_decompress_batch(ctx, arena, _u64s(offsets), len(dsts), _ptrs(dsts), _u64s(caps),
                                         _ptrs(bases) if bases is not None else None, stream),
            "zipnn_decompress_batch")
+
+
+def zipnn_autotune(ctx, dtype, srcs, ns, bases, sample_bytes, max_ratio_loss, policy=None):
+    """-> (best zipnn_params, list of zipnn_tune_entry)"""
+    n = len(srcs)
+    ts = (zipnn_tensor_in * n)(*[zipnn_tensor_in(s_, n_, b_) for s_, n_, b_ in zip(srcs, ns, bases)])
+    best = zipnn_params()
+    ents = (zipnn_tune_entry * 64)()
+    cnt = ctypes.c_int(0)
+    pol = (ctypes.c_uint8 * 4)(*policy) if policy is not None else None
+    _check(lib().zipnn_autotune(ctx, dtype, ts, n, sample_bytes, max_ratio_loss, pol, ctypes.byref(best), ents, 64,
+                                ctypes.byref(cnt)), "zipnn_autotune")
+    return best, [ents[i] for i in range(cnt.value)]
 
 
 # ---------------------------------------------------------------- tensor helpers
