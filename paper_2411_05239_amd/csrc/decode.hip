@@ -414,7 +414,7 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
     // full groups of the last lane of the group: every lane has at least these
     const uint32_t w_last = min(W, 64 * j + 64) - 1;
     const uint32_t nfull_all = w_last < Gfull ? (Gfull - 1 - w_last) / W + 1 : 0;
-    const uint32_t n_fast = (64 * j + 64 <= W) ? nfull_all / kDepth * kDepth : 0;
+    uint32_t n_fast = (64 * j + 64 <= W) ? nfull_all / kDepth * kDepth : 0;
     int mode[B];
     uint32_t rlev[B];
     const uint8_t* pay[B];
@@ -453,44 +453,62 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
             buf_load<NB>(rb, o == kOff ? kOff : o * B, bring[u]);
         }
     }
-    // fast path: all 64 lanes have full groups j0 .. j0+kDepth-1
-    for (uint32_t j0 = 0; j0 < n_fast; j0 += kDepth) {
+    // fast path: all 64 lanes have full groups j0 .. j0+kDepth-1 and every
+    // stream is Huffman or raw.  HM is the set of Huffman streams, or -1 for
+    // a set without its own copy of the loop, tested per stream at run time.
+    auto fast = [&](auto hm_const) {
+        constexpr int HM = decltype(hm_const)::value;
+        for (uint32_t j0 = 0; j0 < n_fast; j0 += kDepth) {
 #pragma unroll
-        for (int u = 0; u < kDepth; u++) {
-            const uint32_t jj = j0 + u;
-            const uint32_t off = (w + jj * W) * G;
-            const uint32_t offn = raw_off(jj + kDepth);
-            uint32_t pk[B][PW];
+            for (int u = 0; u < kDepth; u++) {
+                const uint32_t jj = j0 + u;
+                const uint32_t off = (w + jj * W) * G;
+                const uint32_t offn = raw_off(jj + kDepth);
+                uint32_t pk[B][PW];
 #pragma unroll
-            for (int k = 0; k < B; k++) {
-                if (mode[k] == kModeRaw) {
+                for (int k = 0; k < B; k++) {
+                    const bool is_huf = HM >= 0 ? ((HM >> k) & 1) != 0 : mode[k] == kModeHuf;
+                    if (!is_huf) {
 #pragma unroll
-                    for (int x = 0; x < PW; x++) pk[k][x] = slot[k][u * PW + x];
-                    buf_load<G>(rr[k], offn, &slot[k][u * PW]);
-                } else if (mode[k] == kModeRle) {
+                        for (int x = 0; x < PW; x++) pk[k][x] = slot[k][u * PW + x];
+                        buf_load<G>(rr[k], offn, &slot[k][u * PW]);
+                    } else {
 #pragma unroll
-                    for (int x = 0; x < PW; x++) pk[k][x] = rlev[k];
-                } else {
+                        for (int x = 0; x < PW; x++) pk[k][x] = 0;
 #pragma unroll
-                    for (int x = 0; x < PW; x++) pk[k][x] = 0;
-#pragma unroll
-                    for (int pr = 0; pr < G / 2; pr++) {
-                        huf_take<B>(slot[k], cur[k], true, twoL, lane);
-                        const uint32_t s0 = huf_get<B>(slot[k], lut[k], mask);
-                        const uint32_t s1 = huf_get<B>(slot[k], lut[k], mask);
-                        pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
+                        for (int pr = 0; pr < G / 2; pr++) {
+                            huf_take<B>(slot[k], cur[k], true, twoL, lane);
+                            const uint32_t s0 = huf_get<B>(slot[k], lut[k], mask);
+                            const uint32_t s1 = huf_get<B>(slot[k], lut[k], mask);
+                            pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
+                        }
                     }
                 }
-            }
-            uint32_t ow[NW];
-            merge_words<B, G>(pk, ow);
-            if constexpr (DELTA) {
+                uint32_t ow[NW];
+                merge_words<B, G>(pk, ow);
+                if constexpr (DELTA) {
 #pragma unroll
-                for (int x = 0; x < NW; x++) ow[x] ^= bring[u][x];
-                buf_load<NB>(rb, offn == kOff ? kOff : offn * B, bring[u]);
+                    for (int x = 0; x < NW; x++) ow[x] ^= bring[u][x];
+                    buf_load<NB>(rb, offn == kOff ? kOff : offn * B, bring[u]);
+                }
+                buf_store<NB>(ro, off * B, ow);
             }
-            buf_store<NB>(ro, off * B, ow);
         }
+    };
+    {
+        uint32_t hm = 0;
+        bool other = false;
+#pragma unroll
+        for (int k = 0; k < B; k++) {
+            hm |= uint32_t(mode[k] == kModeHuf) << k;
+            other |= mode[k] == kModeRle;
+        }
+        using std::integral_constant;
+        if (other) n_fast = 0;   // chunks with a single-valued stream take the general path
+        else if (hm == 1) fast(integral_constant<int, 1>{});
+        else if (hm == 0) fast(integral_constant<int, 0>{});
+        else if (B >= 2 && hm == 3) fast(integral_constant<int, B >= 2 ? 3 : -1>{});
+        else fast(integral_constant<int, -1>{});
     }
     // general path: the remaining groups, with per-lane conditions
     for (uint32_t j0 = n_fast; j0 < ng_max; j0 += kDepth) {
@@ -697,8 +715,12 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
 // descs[0..n_desc) whose per-tensor item counts k_plan prefixed.  Every tensor
 // of a launch has B-byte words, groups of G and (for DELTA) an XOR base; a
 // header that disagrees is reported as ZIPNN_E_FORMAT.
+// Four waves per SIMD (at most 128 VGPRs) keep enough lanes in flight to
+// hide LDS and memory latency; the widest words with the largest groups get
+// the registers of two waves instead of spilling (16-byte groups with an
+// XOR base count as wide).
 template <int B, int G, bool DELTA>
-__global__ __launch_bounds__(kBlock) void k_decode(DecDesc one, const DecDesc* __restrict__ descs, int n_desc,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B * G >= (DELTA ? 16 : 32) ? 2 : 4, 8))) void k_decode(DecDesc one, const DecDesc* __restrict__ descs, int n_desc,
                                                    const uint64_t* __restrict__ item_prefix, int* status)
 {
     __shared__ uint16_t lut[B][kLutSize];
