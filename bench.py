@@ -57,13 +57,13 @@ def make_workload(name: str):
     from paper_2411_05239_amd import workloads
     from paper_2411_05239_amd import zipnn as Z
 
-    if name == "c1":
+    if name == "fp32_256mb":
         x = workloads.fp32_rows(8192, 8192, seed=1)
         p = Z.zipnn_default_params(Z.ZIPNN_FP32)
         desc = {"workload": "fp32_8192x8192_rowsigma_loguniform_1e-3_1e-1", "dtype": "fp32", "elements": x.numel(),
                 "bytes": x.numel() * 4, "chunk_bytes": p.chunk_bytes, "S": p.substream_syms, "g": p.group,
                 "L": p.max_code_len, "policy": "auto"}
-    elif name == "c0":
+    elif name == "bf16_8mb":
         x = workloads.bf16_normal(4_194_304, seed=0)
         p = Z.make_params(Z.ZIPNN_BF16, policy=[Z.ZIPNN_HUF, Z.ZIPNN_RAW])
         desc = {"workload": "bf16_4194304_normal_0.02", "dtype": "bf16", "elements": x.numel(),
@@ -333,7 +333,7 @@ def run_checkpoint(args, delta: bool):
     dec_avg = statistics.mean(dec_ms)
     alg = C + U + (U if delta else 0)
     achieved = alg / (dec_avg * 1e-3) / 1e9
-    name = "c3" if delta else "c2"
+    name = "ckpt8b_delta" if delta else "ckpt8b"
     rec = {
         "metric": "decode GB/s at bit-exact roundtrip (uncompressed bytes / decode time); encode GB/s beside it",
         "value": round(U / (dec_avg * 1e-3) / 1e9, 2),
@@ -363,12 +363,158 @@ def run_checkpoint(args, delta: bool):
     print(json.dumps(rec))
 
 
+def _pct(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(round(q * (len(v) - 1))))] if v else None
+
+
+def _serve_pass(Z, srv, handles, sizes, rate, count, seed):
+    """Open loop: Poisson arrivals at `rate`; each request names a corpus item
+    drawn uniformly.  A submitter thread keeps the schedule; this thread takes
+    completions and releases them.  Returns latency stats."""
+    import threading
+
+    import torch
+
+    from paper_2411_05239_amd import workloads
+
+    arr = workloads.poisson_arrivals(rate, count, seed)
+    g = torch.Generator().manual_seed(seed)
+    pick = torch.randint(0, len(handles), (count,), generator=g).tolist()
+    t0 = Z.zipnn_clock() + 0.05
+    tickets = {}
+    lock = threading.Lock()
+
+    def submitter():
+        for k in range(count):
+            ta = t0 + arr[k]
+            wait = ta - Z.zipnn_clock()
+            if wait > 5e-4:
+                time.sleep(wait - 3e-4)
+            while Z.zipnn_clock() < ta:
+                pass
+            tk = srv.submit(handles[pick[k]], ta)
+            with lock:
+                tickets[tk] = pick[k]
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, nbytes, t_last, n_done = [], 0, t0, 0
+    ph = {"admit": [], "launch": [], "run": []}
+    deadline = time.monotonic() + 120
+    while n_done < count and time.monotonic() < deadline:
+        tk = srv.next_done(0.5)
+        if tk is None:
+            continue
+        st, _, tm = srv.poll(tk)
+        if st != Z.ZIPNN_OK:
+            raise SystemExit(f"served request failed: {st}")
+        with lock:
+            i = tickets.get(tk)
+        srv.release(tk)
+        lat.append(tm.t_done - tm.t_arrive)
+        ph["admit"].append(tm.t_admit - tm.t_arrive)
+        ph["launch"].append(tm.t_launch - tm.t_admit)
+        ph["run"].append(tm.t_done - tm.t_launch)
+        nbytes += sizes[i] if i is not None else 0
+        t_last = max(t_last, tm.t_done)
+        n_done += 1
+    th.join()
+    span = t_last - t0
+    return {"rate": rate, "requests": n_done, "p50_ms": round(_pct(lat, 0.5) * 1e3, 3),
+            "p99_ms": round(_pct(lat, 0.99) * 1e3, 3), "mean_ms": round(statistics.mean(lat) * 1e3, 3),
+            "GBps": round(nbytes / span / 1e9, 2), "offered_GBps": round(rate * statistics.mean(sizes) / 1e9, 2),
+            "p50_phase_ms": {k: round(_pct(v, 0.5) * 1e3, 4) for k, v in ph.items()},
+            "p99_phase_ms": {k: round(_pct(v, 0.99) * 1e3, 4) for k, v in ph.items()}}
+
+
+def run_serve(args):
+    """Serving loop: a corpus of 128 tensors (64 KiB - 1 GiB log-uniform,
+    60/30/10 BF16/FP32/FP8) resident compressed; Poisson request streams at
+    rates 100 - 5000/s decoded by the continuous-batching server and by the
+    same server launching one decode per request; then a closed-loop pass
+    (every item requested at once) whose results are checked byte for byte
+    against the original tensors."""
+    import torch
+
+    from paper_2411_05239_amd import workloads
+    from paper_2411_05239_amd import zipnn as Z
+
+    sys.setswitchinterval(2e-4)   # the submitter and the completion threads share the interpreter
+    codec = Z.Codec(0)
+    items = workloads.serving_corpus()
+    xs, cs = [], []
+    for it in items:
+        x = workloads.make_corpus_tensor(it, device="cuda")
+        c = codec.compress(x).clone()
+        xs.append(x)
+        cs.append(c)
+    torch.cuda.synchronize()
+    sizes = [x.numel() * x.element_size() for x in xs]
+    U, C = sum(sizes), sum(c.numel() for c in cs)
+    rates = [100, 200, 500, 1000, 2000, 5000]
+    res = {}
+    closed = {}
+    for mode, name in [(Z.ZIPNN_SERVE_CONTINUOUS, "continuous"), (Z.ZIPNN_SERVE_PER_REQUEST, "per_request")]:
+        srv = Z.Server(codec, pool_bytes=16 << 30, max_inflight=256, mode=mode)
+        handles = [srv.register(c) for c in cs]
+        # closed loop: all items at t=0, every result checked
+        t0 = Z.zipnn_clock()
+        tks = {srv.submit(h, t0): i for i, h in enumerate(handles)}
+        lat, t_last, ok, got = [], t0, True, []
+        while len(got) < len(tks):
+            tk = srv.next_done(5.0)
+            if tk is None:
+                raise SystemExit("closed-loop pass stalled")
+            st, _, tm = srv.poll(tk)
+            ok &= st == Z.ZIPNN_OK
+            lat.append(tm.t_done - tm.t_arrive)
+            t_last = max(t_last, tm.t_done)
+            got.append(tk)
+        # every output stays in the pool until checked against the original tensor
+        for tk in got:
+            i = tks[tk]
+            ok &= bool(torch.equal(srv.output(tk, handles[i]), xs[i].contiguous().view(torch.uint8).reshape(-1)))
+            srv.release(tk)
+        closed[name] = {"requests": len(tks), "seconds": round(t_last - t0, 4),
+                        "GBps": round(U / (t_last - t0) / 1e9, 2), "p50_ms": round(_pct(lat, 0.5) * 1e3, 3),
+                        "p99_ms": round(_pct(lat, 0.99) * 1e3, 3), "all_equal_original": ok}
+        res[name] = []
+        for ri, rate in enumerate(rates):
+            count = int(min(4000, max(200, rate * args.serve_seconds)))
+            res[name].append(_serve_pass(Z, srv, handles, sizes, rate, count, 4000 + ri))
+            print(json.dumps({"progress": name, **res[name][-1]}), file=sys.stderr, flush=True)
+        st = Z.zipnn_server_stats(srv.h)
+        closed[name]["iterations"] = st.iterations
+        srv.close()
+    alg = C + U
+    cl = closed["continuous"]
+    rec = {
+        "metric": "decode GB/s at bit-exact roundtrip; batched-serving vs plain p99 latency",
+        "value": cl["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(cl["seconds"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "serving_corpus_128_tensors_64KiB_1GiB_bf16_fp32_fp8", "bytes": U,
+                   "compressed_bytes": C, "pool_bytes": 16 << 30, "chunks_per_iter": 2048, "rates": rates},
+        "closed_loop": closed,
+        "open_loop": res,
+        "roofline": {"bound": "hbm", "achieved": round(alg / cl["seconds"] / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(alg / cl["seconds"] / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "k_decode (server iterations; wall clock of the closed-loop pass)",
+                     "algorithmic_bytes_per_launch": alg},
+    }
+    codec.close()
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3"])
+    ap.add_argument("--workload", default="fp32_256mb",
+                    choices=["bf16_8mb", "fp32_256mb", "ckpt8b", "ckpt8b_delta", "serve"])
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=4.0)
     ap.add_argument("--decode-only", action="store_true", help="time decode launches only (for profiling)")
@@ -376,8 +522,10 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this codec build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
-    if args.workload in ("c2", "c3"):
-        run_checkpoint(args, delta=args.workload == "c3")
+    if args.workload == "serve":
+        run_serve(args)
+    elif args.workload in ("ckpt8b", "ckpt8b_delta"):
+        run_checkpoint(args, delta=args.workload == "ckpt8b_delta")
     else:
         run_single(args)
 

@@ -234,6 +234,87 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
                    double max_ratio_loss, const uint8_t* policy, zipnn_params* best, zipnn_tune_entry* entries,
                    int max_entries, int* n_entries);
 
+/* ------------------------------------------------------------------ serving
+ *
+ * A decompression server: containers registered once stay resident in
+ * device memory; requests to decompress them arrive at any time and their
+ * outputs are placed in a device pool of fixed size owned by the server.
+ * Requests are admitted in arrival order while the pool has room for the
+ * output (and fewer than max_inflight are admitted).  A scheduler thread
+ * runs decode iterations on a private stream, keeping two in flight: in
+ * ZIPNN_SERVE_CONTINUOUS mode an iteration takes the not yet decoded chunks
+ * of every admitted request (fewest remaining first) up to chunks_per_iter,
+ * so a request that arrives while others decode joins the next iteration and
+ * a large one spans several; ZIPNN_SERVE_PER_REQUEST runs one iteration per
+ * request holding all of its chunks (the plain per-request launch).  Chunks
+ * decode independently given the map (paper §V-A), so the bytes of a result
+ * do not depend on what else was in its iterations.  Every call is
+ * thread-safe.  Times are seconds on the host monotonic clock (zipnn_clock). */
+
+typedef struct zipnn_server_s* zipnn_server;
+
+typedef enum { ZIPNN_SERVE_CONTINUOUS = 0, ZIPNN_SERVE_PER_REQUEST = 1 } zipnn_serve_mode;
+
+typedef struct {
+    uint64_t pool_bytes;        /* output pool (device memory allocated at create) */
+    int max_inflight;           /* admitted requests not yet released, at most */
+    uint32_t chunks_per_iter;   /* CONTINUOUS: chunk cap of one iteration (0: 2048) */
+    int mode;                   /* zipnn_serve_mode */
+} zipnn_server_config;
+
+typedef struct {
+    double t_arrive;   /* given at submit (or the submit time) */
+    double t_admit;    /* output space granted */
+    double t_launch;   /* first iteration holding one of its chunks queued */
+    double t_done;     /* the iteration holding its last chunk seen complete */
+} zipnn_timing;
+
+typedef struct {
+    uint64_t submitted, completed, released;
+    uint64_t iterations;      /* decode iterations launched */
+    uint64_t chunks;          /* chunks decoded */
+    uint64_t bytes_out;       /* uncompressed bytes of completed requests */
+    uint64_t pool_in_use, pool_peak;
+    int active_peak;          /* most admitted requests at once */
+} zipnn_server_counters;
+
+/* Seconds on the clock the server stamps (CLOCK_MONOTONIC). */
+double zipnn_clock(void);
+
+/* Create a server on ctx's device (the context must outlive it). */
+int zipnn_server_create(zipnn_ctx ctx, const zipnn_server_config* cfg, zipnn_server* out);
+
+/* Stop the scheduler after the iterations in flight, free the pool.  Output
+ * pointers handed out become invalid.  NULL is ignored. */
+void zipnn_server_destroy(zipnn_server srv);
+
+/* Register a container resident in device memory (src_len bytes; for a delta
+ * container, base: the device XOR base, else NULL).  The header is read and
+ * checked (blocking); the container and base must stay valid and unchanged
+ * while the server lives.  *handle names it in submit. */
+int zipnn_server_register(zipnn_server srv, const void* src, uint64_t src_len, const void* base, uint32_t* handle);
+
+/* Ask for one decompression of a registered container; t_arrive <= 0 means
+ * now.  Returns at once with *ticket; ZIPNN_E_NOSPACE if the output can never
+ * fit the pool. */
+int zipnn_server_submit(zipnn_server srv, uint32_t handle, double t_arrive, uint64_t* ticket);
+
+/* ZIPNN_E_BUSY while the request is pending; once done, its status (OK, or
+ * the error the device reported for one of its iterations), *out = its output
+ * in the pool (n * B bytes) and *t its timing (either may be NULL). */
+int zipnn_server_poll(zipnn_server srv, uint64_t ticket, void** out, zipnn_timing* t);
+
+/* Wait up to timeout_s for a completed request not yet returned by this call
+ * and give its ticket; ZIPNN_E_BUSY on time-out. */
+int zipnn_server_next_done(zipnn_server srv, double timeout_s, uint64_t* ticket);
+
+/* Give a completed request's output space back to the pool and forget it;
+ * ZIPNN_E_BUSY if it is not done. */
+int zipnn_server_release(zipnn_server srv, uint64_t ticket);
+
+/* Counters since create. */
+int zipnn_server_stats(zipnn_server srv, zipnn_server_counters* out);
+
 /* Validate a container's header and map from HOST memory (len bytes: at
  * least the header and the map) and summarise it in *out. */
 int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out);

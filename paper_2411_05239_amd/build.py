@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libzipnn_hip.so")
-SOURCES = ["decode.hip", "encode.hip", "api.hip"]
+SOURCES = ["decode.hip", "encode.hip", "api.hip", "server.hip"]
 ARCH = os.environ.get("ZIPNN_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -12,18 +12,6 @@
 
 using namespace zipnn;
 
-struct zipnn_ctx_s {
-    int device = 0;
-    int dec_grid = 1024;
-    int* d_status = nullptr;      // sticky device-side status
-    int* h_status = nullptr;      // pinned
-    uint64_t* h_total = nullptr;  // pinned, encode sizes
-    size_t h_total_cap = 0;
-    void* d_scratch = nullptr;    // encode scratch (grown on demand)
-    size_t scratch_cap = 0;
-    std::mutex mu;                // serialises users of the scratch
-};
-
 namespace {
 
 struct DeviceGuard {
@@ -301,6 +289,9 @@ static int decompress_common(zipnn_ctx ctx, const uint32_t* hdr_words, const voi
     one.base = (const uint8_t*)base;
     one.dst = (uint8_t*)dst;
     one.dst_cap = dst_cap;
+    one.c_begin = 0;
+    one.c_end = kAllChunks;
+    one.status = nullptr;
     if (launch_decode_one(h, one, ctx->d_status, ctx->dec_grid, s) != hipSuccess) return ZIPNN_E_HIP;
     return ZIPNN_OK;
 }
@@ -406,6 +397,9 @@ int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets
         d.base = (const uint8_t*)bi;
         d.dst = (uint8_t*)dst[i];
         d.dst_cap = dst_cap[i];
+        d.c_begin = 0;
+        d.c_end = kAllChunks;
+        d.status = nullptr;
         groups[std::make_tuple(h.B, h.g, delta)].push_back(d);
     }
     zipnn_batch b = new (std::nothrow) zipnn_batch_s;

@@ -53,9 +53,7 @@ struct TensorState {
     Header h;
     int desc;
     int valid;
-    uint32_t slices_full;  // slices per full chunk
-    uint32_t slices_last;
-    uint64_t items;
+    ItemPlan p;
 };
 
 __device__ inline void set_status(int* st, int code) { atomicCAS(st, 0, code); }
@@ -607,18 +605,12 @@ __device__ bool load_tensor(const DecDesc& d, int di, TensorState& ts, int* stat
     }
     ts.desc = di;
     ts.valid = rc == ZIPNN_OK;
-    ts.items = 0;
+    ts.p.items = 0;
     if (rc != ZIPNN_OK) {
         if (report) set_status(status, rc);
         return false;
     }
-    const uint32_t Wf = (ts.h.E + ts.h.S - 1) / ts.h.S;
-    ts.slices_full = (Wf + kBlock - 1) / kBlock;
-    if (ts.h.n_chunks == 0) return true;
-    const uint64_t m_last = ts.h.n - uint64_t(ts.h.n_chunks - 1) * ts.h.E;
-    const uint32_t Wl = uint32_t((m_last + ts.h.S - 1) / ts.h.S);
-    ts.slices_last = (Wl + kBlock - 1) / kBlock;
-    ts.items = uint64_t(ts.h.n_chunks - 1) * ts.slices_full + ts.slices_last;
+    ts.p = plan_items(ts.h, d.c_begin, d.c_end);
     return true;
 }
 
@@ -746,7 +738,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B * G >=
                 ts.valid = 0;
                 if (blockIdx.x == 0) set_status(status, ZIPNN_E_FORMAT);
             }
-            n_items_sh = ts.valid ? ts.items : 0;
+            n_items_sh = ts.valid ? ts.p.items : 0;
         } else {
             n_items_sh = item_prefix[n_desc];
         }
@@ -768,16 +760,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B * G >=
             __syncthreads();
         }
         const uint64_t local = item - (item_prefix ? item_prefix[ts.desc] : 0);
-        const uint32_t full_items = (ts.h.n_chunks - 1) * ts.slices_full;
+        const uint64_t full_items = uint64_t(ts.p.full_chunks) * ts.p.slices_full;
         uint32_t c, slice;
         if (local < full_items) {
-            c = uint32_t(local / ts.slices_full);
-            slice = uint32_t(local % ts.slices_full);
+            c = ts.p.c0 + uint32_t(local / ts.p.slices_full);
+            slice = uint32_t(local % ts.p.slices_full);
         } else {
             c = ts.h.n_chunks - 1;
             slice = uint32_t(local - full_items);
         }
-        decode_item<B, G, DELTA>(descs[ts.desc], ts, c, slice, wring, lut, wprefix, T, st, status);
+        const DecDesc& d = descs[ts.desc];
+        decode_item<B, G, DELTA>(d, ts, c, slice, wring, lut, wprefix, T, st, d.status ? d.status : status);
     }
 }
 
@@ -806,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(const DecDesc* __restrict__ des
             uint64_t run = carry;
             for (int j = 0; j < kBlock && b0 + j < n_desc; j++) {
                 prefix[b0 + j] = run;
-                run += tsv[j].valid ? tsv[j].items : 0;
+                run += tsv[j].valid ? tsv[j].p.items : 0;
             }
             carry = run;
             if (b0 + kBlock >= n_desc) prefix[n_desc] = run;
@@ -872,6 +865,13 @@ hipError_t launch_decode_batch(uint32_t B, uint32_t G, bool delta, const DecDesc
     k_plan<<<1, kBlock, 0, s>>>(d_descs, n_desc, B, G, delta ? 1u : 0u, d_item_prefix, d_status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    DecDesc none = {};
+    return dispatch(B, G, delta, none, d_descs, n_desc, d_item_prefix, d_status, grid, s);
+}
+
+hipError_t launch_decode_planned(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
+                                 const uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s)
+{
     DecDesc none = {};
     return dispatch(B, G, delta, none, d_descs, n_desc, d_item_prefix, d_status, grid, s);
 }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <mutex>
 #include <stdint.h>
 
 #include "zipnn.h"
@@ -86,9 +87,13 @@ struct DecDesc {
     const uint8_t* src;
     uint64_t src_len;
     const uint8_t* base;   // XOR base or nullptr
-    uint8_t* dst;
+    uint8_t* dst;          // the whole tensor's output (chunk c lands at c * chunk_bytes)
     uint64_t dst_cap;
+    uint32_t c_begin;      // chunks [c_begin, min(c_end, n_chunks)) are decoded
+    uint32_t c_end;
+    int* status;           // where corruption found in its chunks is reported (nullptr: the launch's)
 };
+constexpr uint32_t kAllChunks = 0xFFFFFFFFu;
 
 // One tensor of a (possibly batched) encode.
 struct EncDesc {
@@ -117,12 +122,51 @@ struct EncParams {
     uint8_t policy[4];
 };
 
+// Work items of a decode descriptor: one item per (chunk, slice of kBlock
+// sub-streams) over the chunks [c_begin, min(c_end, n_chunks)); the
+// tensor's last chunk may have fewer sub-streams than the others.
+struct ItemPlan {
+    uint32_t slices_full;  // slices per full chunk
+    uint32_t slices_last;  // slices of the tensor's last chunk, when the range holds it
+    uint32_t c0;           // first chunk of the range
+    uint32_t full_chunks;  // chunks of the range with slices_full slices
+    uint64_t items;
+};
+
+__host__ __device__ inline ItemPlan plan_items(const Header& h, uint32_t c_begin, uint32_t c_end)
+{
+    ItemPlan p;
+    const uint32_t Wf = (h.E + h.S - 1) / h.S;
+    p.slices_full = (Wf + kBlock - 1) / kBlock;
+    p.slices_last = 0;
+    p.c0 = 0;
+    p.full_chunks = 0;
+    p.items = 0;
+    const uint32_t c1 = c_end < h.n_chunks ? c_end : h.n_chunks;
+    if (c_begin >= c1) return p;
+    p.c0 = c_begin;
+    if (c1 < h.n_chunks) {
+        p.full_chunks = c1 - c_begin;
+    } else {
+        p.full_chunks = c1 - 1 - c_begin;
+        const uint64_t m_last = h.n - uint64_t(h.n_chunks - 1) * h.E;
+        const uint32_t Wl = uint32_t((m_last + h.S - 1) / h.S);
+        p.slices_last = (Wl + kBlock - 1) / kBlock;
+    }
+    p.items = uint64_t(p.full_chunks) * p.slices_full + p.slices_last;
+    return p;
+}
+
 // Launchers (decode.hip / encode.hip).  A null descriptor array means "the
 // single tensor passed by value".
 // Decode kernels are specialised on (B, g, delta) taken from the header.
 hipError_t launch_decode_one(const Header& h, const DecDesc& one, int* d_status, int grid, hipStream_t s);
 hipError_t launch_decode_batch(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
                                uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s);
+// Batched decode whose item prefix (plan_items per descriptor) was computed
+// on the host and copied beside the descriptors.
+hipError_t launch_decode_planned(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
+                                 const uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s);
 hipError_t launch_clear_status(int* d_status, hipStream_t s);
 hipError_t launch_gather_headers(const uint8_t* arena, const uint64_t* d_offs, int n, void* d_out, hipStream_t s);
 int decode_grid_size(int device);
@@ -135,3 +179,17 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
                          uint32_t* nwords, uint64_t* offsets, uint64_t* totals, uint64_t* arena_off, hipStream_t s);
 
 }  // namespace zipnn
+
+// A codec context: the device it runs on, the sticky device-side status and
+// the encoder's scratch (grown on demand, serialised by `mu`).
+struct zipnn_ctx_s {
+    int device = 0;
+    int dec_grid = 1024;
+    int* d_status = nullptr;      // sticky device-side status
+    int* h_status = nullptr;      // pinned
+    uint64_t* h_total = nullptr;  // pinned, encode sizes
+    size_t h_total_cap = 0;
+    void* d_scratch = nullptr;    // encode scratch (grown on demand)
+    size_t scratch_cap = 0;
+    std::mutex mu;                // serialises users of the scratch
+};

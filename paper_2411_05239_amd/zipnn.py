@@ -26,8 +26,11 @@ EXPORTS = [
     "zipnn_strerror", "zipnn_ctx_create", "zipnn_ctx_destroy", "zipnn_ctx_status", "zipnn_default_params",
     "zipnn_check_params", "zipnn_compress_bound", "zipnn_compress", "zipnn_decompress", "zipnn_decompress_async",
     "zipnn_inspect", "zipnn_compress_batch", "zipnn_batch_create", "zipnn_batch_decompress", "zipnn_batch_destroy",
-    "zipnn_decompress_batch", "zipnn_autotune",
+    "zipnn_decompress_batch", "zipnn_autotune", "zipnn_clock", "zipnn_server_create", "zipnn_server_destroy",
+    "zipnn_server_register", "zipnn_server_submit", "zipnn_server_poll", "zipnn_server_next_done",
+    "zipnn_server_release", "zipnn_server_stats",
 ]
+ZIPNN_SERVE_CONTINUOUS, ZIPNN_SERVE_PER_REQUEST = 0, 1
 
 
 class ZipnnError(RuntimeError):
@@ -60,6 +63,22 @@ class zipnn_tune_entry(ctypes.Structure):
 
 class zipnn_tensor_in(ctypes.Structure):
     _fields_ = [("src", ctypes.c_void_p), ("n_elems", ctypes.c_uint64), ("base", ctypes.c_void_p)]
+
+
+class zipnn_server_config(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int), ("chunks_per_iter", ctypes.c_uint32),
+                ("mode", ctypes.c_int)]
+
+
+class zipnn_timing(ctypes.Structure):
+    _fields_ = [("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class zipnn_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("released", ctypes.c_uint64),
+                ("iterations", ctypes.c_uint64), ("chunks", ctypes.c_uint64), ("bytes_out", ctypes.c_uint64),
+                ("pool_in_use", ctypes.c_uint64), ("pool_peak", ctypes.c_uint64), ("active_peak", ctypes.c_int)]
 
 
 _lib = None
@@ -98,6 +117,20 @@ def lib():
         L.zipnn_autotune.argtypes = [vp, i32, P(zipnn_tensor_in), i32, u64, ctypes.c_double, vp, P(zipnn_params),
                                      P(zipnn_tune_entry), i32, P(i32)]
         L.zipnn_autotune.restype = i32
+        L.zipnn_clock.argtypes, L.zipnn_clock.restype = [], ctypes.c_double
+        L.zipnn_server_create.argtypes = [vp, P(zipnn_server_config), P(vp)]
+        L.zipnn_server_create.restype = i32
+        L.zipnn_server_destroy.argtypes, L.zipnn_server_destroy.restype = [vp], None
+        L.zipnn_server_register.argtypes = [vp, vp, u64, vp, P(ctypes.c_uint32)]
+        L.zipnn_server_register.restype = i32
+        L.zipnn_server_submit.argtypes = [vp, ctypes.c_uint32, ctypes.c_double, P(u64)]
+        L.zipnn_server_submit.restype = i32
+        L.zipnn_server_poll.argtypes, L.zipnn_server_poll.restype = [vp, u64, P(vp), P(zipnn_timing)], i32
+        L.zipnn_server_next_done.argtypes = [vp, ctypes.c_double, P(u64)]
+        L.zipnn_server_next_done.restype = i32
+        L.zipnn_server_release.argtypes, L.zipnn_server_release.restype = [vp, u64], i32
+        L.zipnn_server_stats.argtypes = [vp, P(zipnn_server_counters)]
+        L.zipnn_server_stats.restype = i32
         _lib = L
     return _lib
 
@@ -217,6 +250,66 @@ def zipnn_autotune(ctx, dtype, srcs, ns, bases, sample_bytes, max_ratio_loss, po
     _check(lib().zipnn_autotune(ctx, dtype, ts, n, sample_bytes, max_ratio_loss, pol, ctypes.byref(best), ents, 64,
                                 ctypes.byref(cnt)), "zipnn_autotune")
     return best, [ents[i] for i in range(cnt.value)]
+
+
+def zipnn_clock() -> float:
+    return lib().zipnn_clock()
+
+
+def zipnn_server_create(ctx, pool_bytes: int, max_inflight: int, chunks_per_iter: int = 0,
+                        mode: int = ZIPNN_SERVE_CONTINUOUS) -> int:
+    cfg = zipnn_server_config(pool_bytes, max_inflight, chunks_per_iter, mode)
+    h = ctypes.c_void_p()
+    _check(lib().zipnn_server_create(ctx, ctypes.byref(cfg), ctypes.byref(h)), "zipnn_server_create")
+    return h.value
+
+
+def zipnn_server_destroy(srv) -> None:
+    lib().zipnn_server_destroy(srv)
+
+
+def zipnn_server_register(srv, src, src_len, base=None) -> int:
+    h = ctypes.c_uint32(0)
+    _check(lib().zipnn_server_register(srv, src, src_len, base, ctypes.byref(h)), "zipnn_server_register")
+    return h.value
+
+
+def zipnn_server_submit(srv, handle: int, t_arrive: float = 0.0) -> int:
+    t = ctypes.c_uint64(0)
+    _check(lib().zipnn_server_submit(srv, handle, t_arrive, ctypes.byref(t)), "zipnn_server_submit")
+    return t.value
+
+
+def zipnn_server_poll(srv, ticket: int):
+    """-> None while pending, else (status, output device pointer, zipnn_timing)."""
+    out = ctypes.c_void_p()
+    t = zipnn_timing()
+    rc = lib().zipnn_server_poll(srv, ticket, ctypes.byref(out), ctypes.byref(t))
+    if rc == ZIPNN_E_BUSY:
+        return None
+    if rc == ZIPNN_E_INVAL:
+        raise ZipnnError(rc, "zipnn_server_poll")
+    return rc, out.value, t
+
+
+def zipnn_server_next_done(srv, timeout_s: float):
+    """-> ticket of a completed request, or None on time-out."""
+    t = ctypes.c_uint64(0)
+    rc = lib().zipnn_server_next_done(srv, timeout_s, ctypes.byref(t))
+    if rc == ZIPNN_E_BUSY:
+        return None
+    _check(rc, "zipnn_server_next_done")
+    return t.value
+
+
+def zipnn_server_release(srv, ticket: int) -> None:
+    _check(lib().zipnn_server_release(srv, ticket), "zipnn_server_release")
+
+
+def zipnn_server_stats(srv) -> zipnn_server_counters:
+    c = zipnn_server_counters()
+    _check(lib().zipnn_server_stats(srv, ctypes.byref(c)), "zipnn_server_stats")
+    return c
 
 
 # ---------------------------------------------------------------- tensor helpers
@@ -362,6 +455,83 @@ class Batch:
     def close(self):
         if self.h:
             zipnn_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DeviceBytes:
+    """A device byte range exposed through __cuda_array_interface__ so that
+    torch can view it without a copy."""
+
+    def __init__(self, ptr: int, nbytes: int):
+        self.__cuda_array_interface__ = {"shape": (nbytes,), "typestr": "|u1", "data": (ptr, False), "version": 3,
+                                         "strides": None}
+
+
+class Server:
+    """Front end of a zipnn decompression server (continuous batching over
+    containers resident in device memory)."""
+
+    def __init__(self, codec: Codec, pool_bytes: int, max_inflight: int = 256, chunks_per_iter: int = 0,
+                 mode: int = ZIPNN_SERVE_CONTINUOUS):
+        self.codec = codec
+        self.h = zipnn_server_create(codec.ctx, pool_bytes, max_inflight, chunks_per_iter, mode)
+        self._keep = []
+        self._nbytes = {}
+
+    def register(self, container, base=None) -> int:
+        """container: uint8 device tensor holding one container (kept alive
+        by the server object)."""
+        self._keep.append((container, base))
+        hd = zipnn_server_register(self.h, container.data_ptr(), container.numel(),
+                                   base.data_ptr() if base is not None else None)
+        import struct
+
+        hdr = container[:64].cpu().numpy().tobytes()
+        B, n = hdr[7], struct.unpack_from("<Q", hdr, 8)[0]   # header: u8 B at 7, u64 n_elems at 8
+        self._nbytes[hd] = n * B
+        return hd
+
+    def submit(self, handle: int, t_arrive: float = 0.0) -> int:
+        return zipnn_server_submit(self.h, handle, t_arrive)
+
+    def poll(self, ticket: int):
+        return zipnn_server_poll(self.h, ticket)
+
+    def next_done(self, timeout_s: float = 1.0):
+        return zipnn_server_next_done(self.h, timeout_s)
+
+    def output(self, ticket: int, handle: int, dtype=None):
+        """View of a completed request's output (valid until release)."""
+        import torch
+
+        r = self.poll(ticket)
+        if r is None:
+            raise ZipnnError(ZIPNN_E_BUSY, "Server.output")
+        st, ptr, _ = r
+        if st != ZIPNN_OK:
+            raise ZipnnError(st, "Server.output")
+        n = self._nbytes[handle]
+        if n == 0:
+            v = torch.empty(0, dtype=torch.uint8, device=f"cuda:{self.codec.device}")
+        else:
+            v = torch.as_tensor(_DeviceBytes(ptr, n), device=f"cuda:{self.codec.device}")
+        return v if dtype is None else v.view(dtype)
+
+    def release(self, ticket: int) -> None:
+        zipnn_server_release(self.h, ticket)
+
+    def stats(self) -> zipnn_server_counters:
+        return zipnn_server_stats(self.h)
+
+    def close(self):
+        if self.h:
+            zipnn_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

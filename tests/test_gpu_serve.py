@@ -1,0 +1,182 @@
+"""GPU tests of the decompression server (continuous batching): every result
+equals the original tensor bytes and the solo per-tensor decode, whatever
+mix of requests shares its iterations; admission by free pool bytes; the
+per-request mode; error attribution to the request that holds a corrupt
+container."""
+import time
+
+import pytest
+import torch
+
+from paper_2411_05239_amd import workloads
+from paper_2411_05239_amd import zipnn as Z
+
+pytestmark = pytest.mark.gpu
+
+
+def _u8(t):
+    return t.contiguous().view(torch.uint8).reshape(-1)
+
+
+@pytest.fixture(scope="module")
+def codec():
+    c = Z.Codec(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def corpus(codec):
+    """Small mixed corpus: BF16 / FP32 / FP8, sizes from 64 KiB to 6 MiB,
+    ragged element counts, two chunk sizes, one XOR delta, one empty."""
+    items = workloads.serving_corpus(count=14, seed=3100, min_bytes=64 << 10, max_bytes=6 << 20)
+    out = []
+    for it in items:
+        x = workloads.make_corpus_tensor(it, device="cuda")
+        x = x[: max(1, x.numel() - (it.index * 37) % 1000)]   # ragged tails
+        dt = Z.torch_dtype_code(x.dtype)
+        p = Z.make_params(dt, chunk_bytes=65536 if it.index % 3 == 0 else 262144)
+        c = codec.compress(x, p).clone()
+        out.append(dict(x=x, c=c, base=None))
+    w = workloads.bf16_normal(700_001, seed=3150, device="cuda")
+    ft = workloads.finetune_delta(w, seed=3151)
+    c = codec.compress(ft, Z.make_params(Z.ZIPNN_BF16, policy=[1, 1]), base=w).clone()
+    out.append(dict(x=ft, c=c, base=w))
+    e = torch.empty(0, dtype=torch.bfloat16, device="cuda")
+    out.append(dict(x=e, c=codec.compress(e).clone(), base=None))
+    torch.cuda.synchronize()
+    # solo decodes: the reference each served result must equal
+    for d in out:
+        o = torch.empty_like(d["x"])
+        if d["x"].numel():
+            codec.decompress(d["c"], o, base=d["base"])
+        d["solo"] = o
+        assert torch.equal(_u8(o), _u8(d["x"]))
+    return out
+
+
+def _drain(srv, tickets, corpus, handles):
+    """Wait for every ticket, check its bytes against the solo decode, release."""
+    want = dict(tickets)
+    seen = {}
+    t_end = time.monotonic() + 60
+    while len(seen) < len(want):
+        assert time.monotonic() < t_end, f"{len(want) - len(seen)} requests never completed"
+        tk = srv.next_done(1.0)
+        if tk is None or tk not in want:
+            continue
+        i = want[tk]
+        st, ptr, tm = srv.poll(tk)
+        assert st == Z.ZIPNN_OK, (i, st)
+        assert tm.t_arrive <= tm.t_admit <= tm.t_launch <= tm.t_done
+        got = srv.output(tk, handles[i])
+        assert torch.equal(got, _u8(corpus[i]["solo"])), f"item {i} differs from its solo decode"
+        seen[tk] = tm
+        srv.release(tk)
+    return seen
+
+
+@pytest.mark.parametrize("mode,cap", [(Z.ZIPNN_SERVE_CONTINUOUS, 7), (Z.ZIPNN_SERVE_CONTINUOUS, 0),
+                                      (Z.ZIPNN_SERVE_PER_REQUEST, 0)])
+def test_mix_equals_solo(codec, corpus, mode, cap):
+    srv = Z.Server(codec, pool_bytes=256 << 20, max_inflight=64, chunks_per_iter=cap, mode=mode)
+    handles = [srv.register(d["c"], d["base"]) for d in corpus]
+    # a burst of every item three times, interleaved, then single arrivals
+    tickets = []
+    for rep in range(3):
+        for i in range(len(corpus)):
+            j = (i * 5 + rep) % len(corpus)
+            tickets.append((srv.submit(handles[j]), j))
+    _drain(srv, tickets, corpus, handles)
+    for i in range(len(corpus)):
+        tk = srv.submit(handles[i])
+        _drain(srv, [(tk, i)], corpus, handles)
+    st = srv.stats()
+    assert st.submitted == st.completed == st.released == 4 * len(corpus)
+    assert st.pool_in_use == 0
+    if mode == Z.ZIPNN_SERVE_CONTINUOUS and cap == 7:
+        # small chunk cap: iterations mixed requests and large ones spanned several
+        assert st.iterations > len(corpus)
+    srv.close()
+
+
+def test_admission_by_pool_bytes(codec, corpus):
+    # pool for about two of the largest outputs: requests wait for releases
+    big = max(d["x"].numel() * d["x"].element_size() for d in corpus)
+    srv = Z.Server(codec, pool_bytes=2 * big + (1 << 20), max_inflight=64)
+    handles = [srv.register(d["c"], d["base"]) for d in corpus]
+    tickets = [(srv.submit(handles[i]), i) for i in range(len(corpus))]
+    _drain(srv, tickets, corpus, handles)
+    st = srv.stats()
+    assert st.pool_peak <= 2 * big + (1 << 20)
+    assert st.completed == len(corpus)
+    srv.close()
+
+
+def test_max_inflight_limits_admission(codec, corpus):
+    srv = Z.Server(codec, pool_bytes=256 << 20, max_inflight=2)
+    handles = [srv.register(d["c"], d["base"]) for d in corpus]
+    tickets = [(srv.submit(handles[i]), i) for i in range(len(corpus))]
+    _drain(srv, tickets, corpus, handles)
+    assert srv.stats().active_peak <= 2
+    srv.close()
+
+
+def test_request_larger_than_pool(codec, corpus):
+    i = max(range(len(corpus)), key=lambda k: corpus[k]["x"].numel() * corpus[k]["x"].element_size())
+    nb = corpus[i]["x"].numel() * corpus[i]["x"].element_size()
+    srv = Z.Server(codec, pool_bytes=nb // 2, max_inflight=4)
+    h = srv.register(corpus[i]["c"])
+    with pytest.raises(Z.ZipnnError) as ei:
+        srv.submit(h)
+    assert ei.value.code == Z.ZIPNN_E_NOSPACE
+    srv.close()
+
+
+def test_register_rejects(codec, corpus):
+    srv = Z.Server(codec, pool_bytes=1 << 20)
+    d = corpus[-2]   # the delta container
+    with pytest.raises(Z.ZipnnError):
+        srv.register(d["c"])                     # delta without its base
+    bad = d["c"].clone()
+    bad[0] ^= 0xFF
+    with pytest.raises(Z.ZipnnError):
+        srv.register(bad, d["base"])             # not a header
+    with pytest.raises(Z.ZipnnError):
+        srv.submit(12345)                        # unknown handle
+    srv.close()
+
+
+def test_corruption_is_reported_to_its_request_only(codec, corpus):
+    # flip a payload byte inside a Huffman stream of one container
+    i = next(k for k, d in enumerate(corpus) if d["x"].dtype == torch.bfloat16 and d["x"].numel() > 200_000
+             and d["base"] is None)
+    c = corpus[i]["c"].clone()
+    info = Z.zipnn_inspect(c[:64 + 16 * 4096].cpu().numpy().tobytes())
+    hb = c.cpu().numpy()
+    base = 64 + 16 * info.n_chunks * info.B
+    # first HUF entry: offset of its word stream after the head
+    import struct
+
+    for e in range(info.n_chunks * info.B):
+        off, nbytes, mode = struct.unpack_from("<QIB", hb, 64 + 16 * e)
+        if mode == 1:
+            break
+    # the word count of lane group 0 (after the 128 bytes of code lengths):
+    # the counts no longer add up to the payload size
+    c[base + off + 128] ^= 0x01
+    srv = Z.Server(codec, pool_bytes=256 << 20, max_inflight=64)
+    handles = [srv.register(d["c"], d["base"]) for d in corpus]
+    hbad = srv.register(c)
+    tickets = [(srv.submit(handles[j]), j) for j in range(len(corpus))]
+    tbad = srv.submit(hbad)
+    tickets2 = [(srv.submit(handles[j]), j) for j in range(len(corpus))]
+    deadline = time.monotonic() + 60
+    while srv.poll(tbad) is None:
+        assert time.monotonic() < deadline
+        time.sleep(0.001)
+    st, _, _ = srv.poll(tbad)
+    assert st == Z.ZIPNN_E_CORRUPT
+    srv.release(tbad)
+    _drain(srv, tickets + tickets2, corpus, handles)
+    srv.close()
