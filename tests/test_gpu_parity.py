@@ -52,7 +52,7 @@ def roundtrip(codec, x_cpu, p, base_cpu=None, nthreads=8):
     return c_gpu
 
 
-def test_c0_bf16_8mb(codec):
+def test_bf16_8mb_huf_raw(codec):
     """Single BF16 tensor, 4,194,304 elements ~ N(0, 0.02); s0 HUF, s1 RAW."""
     x = workloads.bf16_normal(4_194_304, seed=0)
     p = Z.make_params(Z.ZIPNN_BF16, policy=[Z.ZIPNN_HUF, Z.ZIPNN_RAW])
@@ -60,13 +60,13 @@ def test_c0_bf16_8mb(codec):
     assert 0.66 < c.numel() / (2 * x.numel()) < 0.68
 
 
-def test_c1_fp32_reduced(codec):
+def test_fp32_rows_reduced(codec):
     x = workloads.fp32_rows(64, 8192, seed=1)
     roundtrip(codec, x, Z.zipnn_default_params(Z.ZIPNN_FP32))
 
 
 @pytest.mark.slow
-def test_c1_fp32_256mb_full(codec):
+def test_fp32_8192x8192_full(codec):
     """The full FP32 workload: 8192 x 8192, row sigma log-uniform in [1e-3, 1e-1]."""
     x = workloads.fp32_rows(8192, 8192, seed=1)
     c = roundtrip(codec, x, Z.zipnn_default_params(Z.ZIPNN_FP32), nthreads=16)
