@@ -215,6 +215,7 @@ template <int B>
 struct Ring {
     static constexpr int RW = B == 4 ? 256 : 512;   // words per ring
     static constexpr int PN = RW / 128;             // words per lane of a pending half block
+    static constexpr int CHECK = RW / 128;          // rounds between refill checks, at most
 };
 
 template <int B, int G>
@@ -269,20 +270,27 @@ __device__ inline void huf_init(uint32_t* r, WordCursor& c, const uint32_t* word
 // bits take the next words of the stream, in lane order (a ballot and a
 // prefix popcount give each lane its word).
 template <int B>
-__device__ inline void huf_take(uint32_t* r, WordCursor& c, bool part, uint32_t twoL, uint32_t lane)
+__device__ inline void huf_take(uint32_t* r, WordCursor& c, bool part, uint32_t twoL)
 {
     constexpr int RW = Ring<B>::RW, PN = Ring<B>::PN;
     const bool need = part && r[PN] < twoL;
     const uint64_t m = __ballot(need);
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-    if (need) {
-        const uint32_t word = c.ring[(c.ptr + below) & (RW - 1)];
-        const uint64_t x = uint64_t(word) << r[PN];
-        r[PN + 1] |= uint32_t(x);
-        r[PN + 2] |= uint32_t(x >> 32);
-        r[PN] += 32;
-    }
+    // ring index of this lane's word: the cursor plus the needing lanes below
+    const uint32_t idx = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), c.ptr));
+    const uint32_t word = c.ring[idx & (RW - 1)];   // every lane reads; only the needing ones keep it
+    const uint64_t x = uint64_t(need ? word : 0u) << r[PN];
+    r[PN + 1] |= uint32_t(x);
+    r[PN + 2] |= uint32_t(x >> 32);
+    r[PN] += need ? 32u : 0u;
     c.ptr += uint32_t(__popcll(m));
+}
+
+// Called at least every Ring<B>::CHECK rounds: a round takes at most 64
+// words, so between checks the reads stay inside the ring's RW words.
+template <int B>
+__device__ inline void huf_refill(uint32_t* r, WordCursor& c, uint32_t lane)
+{
+    constexpr int RW = Ring<B>::RW, PN = Ring<B>::PN;
     if (c.ptr - c.rb >= RW / 2) {
         // the older half is used up: it receives the pending block
         uint32_t* half = c.ring + (c.rb & (RW - 1));
@@ -475,10 +483,11 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
                         for (int x = 0; x < PW; x++) pk[k][x] = 0;
 #pragma unroll
                         for (int pr = 0; pr < G / 2; pr++) {
-                            huf_take<B>(slot[k], cur[k], true, twoL, lane);
+                            huf_take<B>(slot[k], cur[k], true, twoL);
                             const uint32_t s0 = huf_get<B>(slot[k], lut[k], mask);
                             const uint32_t s1 = huf_get<B>(slot[k], lut[k], mask);
                             pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
+                            if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1) huf_refill<B>(slot[k], cur[k], lane);
                         }
                     }
                 }
@@ -534,12 +543,13 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
 #pragma unroll
                     for (int pr = 0; pr < G / 2; pr++) {
                         const bool part = 2u * pr < gcnt;
-                        huf_take<B>(slot[k], cur[k], part, twoL, lane);
+                        huf_take<B>(slot[k], cur[k], part, twoL);
                         if (part) {
                             pk[k][(2 * pr) >> 2] |= huf_get<B>(slot[k], lut[k], mask) << (8 * ((2 * pr) & 3));
                             if (2u * pr + 1 < gcnt)
                                 pk[k][(2 * pr + 1) >> 2] |= huf_get<B>(slot[k], lut[k], mask) << (8 * ((2 * pr + 1) & 3));
                         }
+                        if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1) huf_refill<B>(slot[k], cur[k], lane);
                     }
                 }
             }

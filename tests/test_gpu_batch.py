@@ -139,3 +139,60 @@ def test_batch_errors(codec):
         Z.zipnn_compress_batch(codec.ctx, Z.ZIPNN_BF16, [xs[0].data_ptr()], [xs[0].numel()], [None],
                                Z.zipnn_default_params(Z.ZIPNN_BF16), small.data_ptr(), 64, codec._stream())
     assert ei.value.code == Z.ZIPNN_E_NOSPACE
+
+
+def _sample_indices(n):
+    """Tensors whose containers the oracle recomputes at full size: the
+    embedding, the first layer's tensors, every 17th tensor and the head."""
+    return sorted(set([0, 1, 2, 3, 4, 5, 6, 7, 8, 9] + list(range(0, n, 17)) + [n - 2, n - 1]))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("chunk,S", [(262144, 512), (1048576, 2048)])
+def test_checkpoint_8b_full(codec, chunk, S):
+    """The full 8B-shaped BF16 checkpoint (291 tensors, 16.06 GB) in the
+    batched configuration the benchmark times: one encode launch chain, one
+    prepared (graph) decode.  Every tensor round-trips bit-exactly; sampled
+    containers equal the oracle's bytes."""
+    specs = workloads.checkpoint_8b_specs()
+    xs = [workloads.make_tensor(sp, device="cuda") for sp in specs]
+    p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=chunk, S=S)
+    arena, offs = codec.compress_batch(xs, p)
+    outs = [torch.empty_like(x) for x in xs]
+    b = codec.prepare_batch(arena, offs, outs)
+    b.run(check=True)
+    torch.cuda.synchronize()
+    for i, (o, x) in enumerate(zip(outs, xs)):
+        assert torch.equal(_u8(o), _u8(x)), i
+    del outs
+    b.close()
+    for i in _sample_indices(len(xs)):
+        print("oracle check tensor", i, specs[i].name, flush=True)
+        ref = oracle.compress(xs[i].cpu(), oracle.BF16, nthreads=16, **_kw(p))
+        got = arena[offs[i]: offs[i] + ref.size].cpu().numpy()
+        assert np.array_equal(got, ref), i
+
+
+@pytest.mark.slow
+def test_checkpoint_8b_delta_full(codec):
+    """The full XOR-delta checkpoint: fine-tuned copy against the base, both
+    streams Huffman; every tensor reconstructs bit-exactly; sampled containers
+    equal the oracle's."""
+    specs = workloads.checkpoint_8b_specs()
+    base = [workloads.make_tensor(sp, device="cuda") for sp in specs]
+    ft = [workloads.finetune_delta(w, seed=2000 + i) for i, w in enumerate(base)]
+    p = Z.make_params(Z.ZIPNN_BF16, policy=[Z.ZIPNN_HUF, Z.ZIPNN_HUF])
+    arena, offs = codec.compress_batch(ft, p, base)
+    outs = [torch.empty_like(x) for x in ft]
+    b = codec.prepare_batch(arena, offs, outs, base)
+    b.run(check=True)
+    torch.cuda.synchronize()
+    for i, (o, x) in enumerate(zip(outs, ft)):
+        assert torch.equal(_u8(o), _u8(x)), i
+    del outs
+    b.close()
+    for i in _sample_indices(len(ft))[::3]:
+        print("oracle check delta tensor", i, specs[i].name, flush=True)
+        ref = oracle.compress(ft[i].cpu(), oracle.BF16, base=base[i].cpu(), nthreads=16, **_kw(p))
+        got = arena[offs[i]: offs[i] + ref.size].cpu().numpy()
+        assert np.array_equal(got, ref), i
