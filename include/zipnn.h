@@ -25,9 +25,11 @@
  *     u32 chunk_bytes | u16 S | u8 g | u8 L | u32 flags (bit0 = XOR delta) |
  *     u32 n_chunks | u64 total_bytes | u8 policy[4] | 20 zero bytes
  *   map: n_chunks*B entries of 16 B, chunk-major: u64 payload offset (from
- *     payload_base = 64 + 16*n_chunks*B) | u32 bytes | u8 mode (0 RAW, 1 HUF,
+ *     payload_base = align128(64 + 16*n_chunks*B), or 64 with no chunks; the
+ *     gap after the map is zero) | u32 bytes | u8 mode (0 RAW, 1 HUF,
  *     2 RLE) | u8 RLE value | u16 0
- *   payloads: in map order, each at a 16-byte aligned offset, zero padded.
+ *   payloads: in map order, each at a 128-byte aligned offset (a stream
+ *     never shares a 128-byte memory line with another), zero padded.
  *     RAW = the m stream bytes.  RLE = nothing.  HUF = 128 B of 4-bit code
  *     lengths | u32 word count of each of the NG = ceil(W/64) lane groups |
  *     zero pad to align16(128+4*NG) | the lane groups' word streams.
@@ -171,7 +173,7 @@ int zipnn_decompress_async(zipnn_ctx ctx, const void* header_host, const void* s
 /* ---------------------------------------------------------------- batches
  * A checkpoint is many tensors: they are compressed into one arena, the
  * per-tensor containers back to back in tensor order, each starting at a
- * 16-byte aligned offset, with the whole-model offsets kept by the caller
+ * 128-byte aligned offset, with the whole-model offsets kept by the caller
  * (the paper's map "for the whole model" that allows parallel decompression,
  * §V-A "Metadata and parallelism").  Every kernel is launched once for all
  * chunks of all tensors. */

@@ -32,6 +32,12 @@ LIB_PATH = os.path.join(_HERE, "libzipnn_oracle.so")
 OK, E_INVAL, E_FORMAT, E_CORRUPT, E_NOSPACE, E_NOMEM = 0, -1, -2, -3, -4, -5
 BF16, FP16, FP32, FP8_E4M3, U8 = 1, 2, 3, 4, 5
 WIDTH = {BF16: 2, FP16: 2, FP32: 4, FP8_E4M3: 1, U8: 1}
+PAY_ALIGN = 128   # payload alignment from the container start (ORC_PAY_ALIGN)
+
+
+def payload_base(n_chunks: int, B: int) -> int:
+    """Offset of a container's payload area: header + map, aligned."""
+    return -(-(64 + 16 * n_chunks * B) // PAY_ALIGN) * PAY_ALIGN if n_chunks else 64
 AUTO, HUF, RAW = 0, 1, 2
 MODE_RAW, MODE_HUF, MODE_RLE = 0, 1, 2
 

@@ -99,6 +99,17 @@ def _a16(x: int) -> int:
     return (x + 15) // 16 * 16
 
 
+PAY_ALIGN = 128   # payloads start at multiples of 128 bytes from the container start
+
+
+def _apay(x: int) -> int:
+    return (x + PAY_ALIGN - 1) // PAY_ALIGN * PAY_ALIGN
+
+
+def _payload_base(n_chunks: int, B: int) -> int:
+    return _apay(64 + 16 * n_chunks * B) if n_chunks else 64
+
+
 LANES = 64
 
 
@@ -189,20 +200,20 @@ def compress(words: np.ndarray, dtype: int, *, base: np.ndarray | None = None, c
         chunk = raw[c * E * B: min(n, (c + 1) * E) * B]
         for k, s in enumerate(split(chunk, B)):
             entries.append(encode_stream(s, S, g, L, policy[k]))
-    payload_base = 64 + 16 * len(entries)
+    payload_base = _payload_base(n_chunks, B)
     body = bytearray()
     mp = bytearray()
     for mode, rle, p in entries:
         mp += struct.pack("<QIBBH", len(body), len(p), mode, rle, 0)
         if p:
             body += p
-            body += bytes(_a16(len(body)) - len(body))
+            body += bytes(_apay(len(body)) - len(body))
     total = payload_base + len(body)
     pol = bytes(list(policy[:B]) + [0] * (4 - B))
     hdr = b"ZNN1" + struct.pack("<HBBQIHBBIIQ", 1, dtype, B, n, chunk_bytes, S, g, L,
                                 1 if base is not None else 0, n_chunks, total) + pol + bytes(20)
     assert len(hdr) == 64
-    return bytes(hdr + mp + body)
+    return bytes(hdr + mp + bytes(payload_base - 64 - len(mp)) + body)
 
 
 def decompress(blob: bytes, base: np.ndarray | None = None) -> np.ndarray:
@@ -210,7 +221,7 @@ def decompress(blob: bytes, base: np.ndarray | None = None) -> np.ndarray:
         raise SpecError("magic")
     (ver, dtype, B, n, chunk_bytes, S, g, L, flags, n_chunks, total) = struct.unpack("<HBBQIHBBIIQ", blob[4:40])
     E = chunk_bytes // B
-    payload_base = 64 + 16 * n_chunks * B
+    payload_base = _payload_base(n_chunks, B)
     out = np.zeros(n * B, dtype=np.uint8)
     for c in range(n_chunks):
         m = min(n, (c + 1) * E) - c * E

@@ -52,6 +52,17 @@ static int is_pow2(uint64_t v) { return v != 0 && (v & (v - 1)) == 0; }
 
 static uint64_t align16(uint64_t v) { return (v + 15u) & ~(uint64_t)15u; }
 
+/* Payloads start at multiples of ORC_PAY_ALIGN bytes from the container
+ * start, so that a stream never shares a 128-byte memory line with another. */
+static uint64_t align_pay(uint64_t v) { return (v + (ORC_PAY_ALIGN - 1)) & ~(uint64_t)(ORC_PAY_ALIGN - 1); }
+
+/* Offset of the payload area: after the header and the map, aligned; a
+ * tensor with no chunks is the header alone. */
+static uint64_t payload_base_of(uint64_t n_chunks, int B)
+{
+    return n_chunks ? align_pay(64 + 16 * n_chunks * (uint64_t)B) : 64;
+}
+
 static void put_u16(uint8_t* p, uint16_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
 static void put_u32(uint8_t* p, uint32_t v) { for (int i = 0; i < 4; i++) p[i] = (uint8_t)(v >> (8 * i)); }
 static void put_u64(uint8_t* p, uint64_t v) { for (int i = 0; i < 8; i++) p[i] = (uint8_t)(v >> (8 * i)); }
@@ -584,8 +595,8 @@ uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes, uint32_
     /* per stream: a raw copy, or (HUF forced) the head plus at most L <= 11
      * bits per symbol and two extra words per sub-stream; plus alignment */
     uint64_t huf = 128 + 4 * (W / ORC_LANES + 1) + 16 + (E * 11 + 7) / 8 + 8 * W + 8;
-    uint64_t per_stream = (huf > E ? huf : E) + 16;
-    return 64 + nc * (uint64_t)B * (16 + per_stream);
+    uint64_t per_stream = (huf > E ? huf : E) + ORC_PAY_ALIGN;
+    return 64 + ORC_PAY_ALIGN + nc * (uint64_t)B * (16 + per_stream);
 }
 
 int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, uint32_t chunk_bytes,
@@ -628,12 +639,12 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
     pthread_mutex_destroy(&J.mu);
     rc = J.rc;
 
-    /* placement: chunk-major order, every payload 16-byte aligned */
-    uint64_t payload_base = 64 + 16 * (uint64_t)n_chunks * B;
+    /* placement: chunk-major order, every payload aligned */
+    uint64_t payload_base = payload_base_of(n_chunks, B);
     uint64_t cur = 0;
     if (rc == ORC_OK) {
         for (uint64_t e = 0; e < (uint64_t)n_chunks * B; e++)
-            if (J.outs[e].bytes) cur = align16(cur + J.outs[e].bytes);
+            if (J.outs[e].bytes) cur = align_pay(cur + J.outs[e].bytes);
         if (payload_base + cur > dst_cap) rc = ORC_E_NOSPACE;
     }
     if (rc == ORC_OK) {
@@ -662,7 +673,7 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
             ent[13] = o->mode == ORC_MODE_RLE ? o->rle : 0;
             if (o->bytes) {
                 memcpy(dst + payload_base + cur, o->payload, o->bytes);
-                cur = align16(cur + o->bytes);
+                cur = align_pay(cur + o->bytes);
             }
         }
         *dst_len = total;
@@ -695,7 +706,7 @@ int orc_parse_header(const void* src_v, uint64_t src_len, orc_header* h)
         if (src[i]) return ORC_E_FORMAT;
     uint64_t E = h->chunk_bytes / h->B;
     if ((h->n + E - 1) / E != h->n_chunks) return ORC_E_FORMAT;
-    uint64_t payload_base = 64 + 16 * (uint64_t)h->n_chunks * h->B;
+    uint64_t payload_base = payload_base_of(h->n_chunks, h->B);
     if (h->total < payload_base || h->total > src_len) return ORC_E_FORMAT;
     return ORC_OK;
 }
@@ -716,7 +727,7 @@ static int decode_chunk(dec_job* J, uint32_t c)
     uint64_t E = h->chunk_bytes / h->B;
     uint64_t e0 = (uint64_t)c * E;
     uint64_t m = h->n - e0 < E ? h->n - e0 : E;
-    uint64_t payload_base = 64 + 16 * (uint64_t)h->n_chunks * h->B;
+    uint64_t payload_base = payload_base_of(h->n_chunks, h->B);
     uint8_t* s = (uint8_t*)malloc(m);
     uint8_t* words = (uint8_t*)malloc(m * h->B);
     if (!s || !words) {
@@ -771,11 +782,11 @@ static void* dec_worker(void* arg)
 }
 
 /* Check every map entry before touching a payload: modes, sizes and the
- * exact chunk-major, 16-byte-aligned placement. */
+ * exact chunk-major, aligned placement. */
 static int check_map(const uint8_t* src, const orc_header* h)
 {
     uint64_t E = h->chunk_bytes / h->B;
-    uint64_t payload_base = 64 + 16 * (uint64_t)h->n_chunks * h->B;
+    uint64_t payload_base = payload_base_of(h->n_chunks, h->B);
     uint64_t cur = 0;
     for (uint64_t c = 0; c < h->n_chunks; c++) {
         uint64_t m = h->n - c * E < E ? h->n - c * E : E;
@@ -797,7 +808,7 @@ static int check_map(const uint8_t* src, const orc_header* h)
                 return ORC_E_CORRUPT;
             }
             if (payload_base + off + bytes > h->total) return ORC_E_CORRUPT;
-            if (bytes) cur = align16(cur + bytes);
+            if (bytes) cur = align_pay(cur + bytes);
         }
     }
     if (payload_base + cur != h->total) return ORC_E_CORRUPT;
@@ -839,7 +850,7 @@ int orc_entry(const void* src_v, uint64_t src_len, uint32_t chunk, int k, uint64
     if (rc) return rc;
     if (chunk >= h.n_chunks || k < 0 || k >= h.B) return ORC_E_INVAL;
     const uint8_t* ent = src + 64 + 16 * ((uint64_t)chunk * h.B + k);
-    *off_abs = 64 + 16 * (uint64_t)h.n_chunks * h.B + get_u64(ent);
+    *off_abs = payload_base_of(h.n_chunks, h.B) + get_u64(ent);
     *bytes = get_u32(ent + 8);
     *mode = ent[12];
     *rle = ent[13];

@@ -10,9 +10,10 @@
  *     32 u64 total_bytes   40 u8 policy[4]        44..63 zero
  *   map at 64: n_chunks*B entries of 16 bytes, chunk-major (entry c*B+k):
  *     u64 offset from payload_base | u32 bytes | u8 mode | u8 rle value | u16 0
- *   payload_base = 64 + 16*n_chunks*B; payloads in map order, each starting
- *   at a 16-byte aligned offset; padding is zero; RLE entries have no bytes
- *   and carry the running offset; total_bytes = payload_base + aligned end.
+ *   payload_base = align128(64 + 16*n_chunks*B) (64 when n_chunks = 0);
+ *   payloads in map order, each starting at a 128-byte aligned offset;
+ *   padding is zero; RLE entries have no bytes and carry the running offset;
+ *   total_bytes = payload_base + aligned end.
  *   RAW payload: the m stream bytes.
  *   HUF payload: 128 bytes of 4-bit code lengths (byte i = l[2i] | l[2i+1]<<4)
  *     | u32 word count of each of the NG = ceil(W/64) lane groups | zero pad
@@ -57,6 +58,7 @@ enum { ORC_FLAG_DELTA = 1 };
 #define ORC_MAX_BW 8192u
 #define ORC_MIN_L 8u
 #define ORC_MAX_L 11u
+#define ORC_PAY_ALIGN 128u   /* payload alignment from the container start */
 
 typedef struct {
     int dtype, B;

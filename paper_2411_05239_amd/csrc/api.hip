@@ -175,8 +175,8 @@ uint64_t zipnn_compress_bound(int dtype, uint64_t n, const zipnn_params* p)
     const uint64_t W = (E + p->substream_syms - 1) / p->substream_syms;
     // AUTO never exceeds raw; HUF-forced may reach head + L bits per symbol
     // plus two words of padding per sub-stream
-    const uint64_t per_stream = huf_head(uint32_t(W)) + (E * p->max_code_len + 7) / 8 + 8 * W + 16;
-    return 64 + 16 * nc * B + nc * B * (per_stream > E + 16 ? per_stream : E + 16);
+    const uint64_t per_stream = huf_head(uint32_t(W)) + (E * p->max_code_len + 7) / 8 + 8 * W;
+    return 64 + kPayAlign + 16 * nc * B + nc * B * ((per_stream > E ? per_stream : E) + kPayAlign);
 }
 
 // Encode tensors[0..n) (all of one dtype) into `arena`; offsets_host gets the
@@ -193,7 +193,7 @@ static int encode_tensors(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, in
         if ((!t[i].src && t[i].n_elems) || !aligned16(t[i].src) || !aligned16(t[i].base)) return ZIPNN_E_INVAL;
         const uint64_t nc = (t[i].n_elems + E - 1) / E;
         total_chunks += nc;
-        map_bytes += align16(64 + 16 * nc * B);
+        map_bytes += payload_base_of(nc, B);
     }
     if (total_chunks > 0xFFFFFFFFull) return ZIPNN_E_INVAL;
     if (map_bytes > cap) return ZIPNN_E_NOSPACE;
@@ -515,7 +515,7 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
     uint64_t cap = 0;
     for (const auto& p : cands) {
         uint64_t c = 0;
-        for (const auto& t : smp) c += zipnn_compress_bound(dtype, t.n_elems, &p) + 16;
+        for (const auto& t : smp) c += zipnn_compress_bound(dtype, t.n_elems, &p) + kPayAlign;
         cap = std::max(cap, c);
     }
     void* arena = nullptr;
@@ -608,7 +608,7 @@ int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out)
     // caller may pass only the header and the map
     int rc = parse_header(w, ~0ull, h);
     if (rc) return rc;
-    const uint64_t map_end = h.payload_base;
+    const uint64_t map_end = 64 + 16ull * h.n_chunks * h.B;
     if (len < map_end) return ZIPNN_E_FORMAT;
     const uint8_t* b = (const uint8_t*)host_buf;
     uint64_t cur = 0;
@@ -626,7 +626,7 @@ int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out)
             if (mode == kModeRaw && (bytes != m || rle)) return ZIPNN_E_CORRUPT;
             if (mode == kModeRle && bytes) return ZIPNN_E_CORRUPT;
             if (mode == kModeHuf && (bytes < huf_head(W) + (m + 7) / 8 || rle)) return ZIPNN_E_CORRUPT;
-            cur += align16(bytes);
+            cur += align_pay(bytes);
             out->bytes_by_mode[mode] += bytes;
             out->entries_by_mode[mode] += 1;
         }

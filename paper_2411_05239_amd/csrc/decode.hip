@@ -650,17 +650,17 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
         if (mode == kModeRaw && (bytes != m || rle)) err = 1;
         if (mode == kModeRle && bytes != 0) err = 1;
         if (mode == kModeHuf && (bytes < huf_head(W) + 4 || ((bytes - huf_head(W)) & 3) || rle)) err = 1;
-        if (off & 15) err = 1;
+        if (off & (kPayAlign - 1)) err = 1;
         // the exact placement: this entry starts where its predecessor ends
         uint64_t expect = 0;
         if (e > 0) {
             const uint4 pe = *(const uint4*)(d.src + 64 + 16 * (e - 1));
             const uint64_t poff = uint64_t(pe.x) | (uint64_t(pe.y) << 32);
-            expect = poff + align16(pe.z);
+            expect = poff + align_pay(pe.z);
         }
         if (off != expect) err = 1;
         if (h.payload_base + off + bytes > h.total) err = 1;
-        if (e + 1 == uint64_t(h.n_chunks) * B && h.payload_base + off + align16(bytes) != h.total) err = 1;
+        if (e + 1 == uint64_t(h.n_chunks) * B && h.payload_base + off + align_pay(bytes) != h.total) err = 1;
         st.pay[t] = h.payload_base + off;
         st.bytes[t] = bytes;
         st.mode[t] = mode;

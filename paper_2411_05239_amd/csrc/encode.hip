@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_place(const EncDesc* __restrict__ de
     __syncthreads();
     for (uint64_t b0 = 0; b0 < ne; b0 += kBlock) {
         const uint64_t e = b0 + t;
-        const uint64_t sz = e < ne ? align16(entries[e_first + e].bytes) : 0;
+        const uint64_t sz = e < ne ? align_pay(entries[e_first + e].bytes) : 0;
         uint64_t inc = sz;
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
@@ -513,11 +513,11 @@ __global__ __launch_bounds__(kBlock) void k_place(const EncDesc* __restrict__ de
         if (t == kBlock - 1) carry = pre + inc;
         __syncthreads();
     }
-    if (t == 0) totals[blockIdx.x] = 64 + 16 * ne + carry;
+    if (t == 0) totals[blockIdx.x] = payload_base_of(d.n_chunks, B) + carry;
 }
 
 // One workgroup: the tensors' containers are laid out back to back in the
-// arena (each 16-byte aligned, in tensor order); sets each descriptor's dst,
+// arena (each at a kPayAlign-aligned offset, in tensor order); sets each descriptor's dst,
 // writes every header, and records the arena offsets (n+1 of them).  If the
 // arena is too small nothing is written and the recorded end says so.
 __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, int n_desc, EncParams p,
@@ -535,7 +535,7 @@ __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, i
     __syncthreads();
     for (int b0 = 0; b0 < n_desc; b0 += kBlock) {
         const int i = b0 + t;
-        const uint64_t sz = i < n_desc ? align16(totals[i]) : 0;
+        const uint64_t sz = i < n_desc ? align_pay(totals[i]) : 0;
         uint64_t inc = sz;
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
@@ -581,6 +581,9 @@ __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, i
         for (int x = 11; x < 16; x++) h[x] = 0;
         uint4* o = (uint4*)d.dst;
         for (int x = 0; x < 4; x++) o[x] = make_uint4(h[4 * x], h[4 * x + 1], h[4 * x + 2], h[4 * x + 3]);
+        // zero padding between the map and the aligned payload area
+        const uint64_t map_end = 64 + 16ull * d.n_chunks * B, pb = payload_base_of(d.n_chunks, B);
+        for (uint64_t x = map_end / 16; x < pb / 16; x++) o[x] = make_uint4(0, 0, 0, 0);
     }
 }
 
@@ -683,8 +686,8 @@ __device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, 
             *(uint4*)(dst + P.pay[k] + 16 * u) = make_uint4(o[0], o[1], o[2], o[3]);
         }
     }
-    // tail elements, then zero padding to 16 bytes
-    for (uint32_t e = units * 16 + threadIdx.x; e < uint32_t(align16(m)); e += kBlock) {
+    // tail elements, then zero padding to the payload alignment
+    for (uint32_t e = units * 16 + threadIdx.x; e < uint32_t(align_pay(m)); e += kBlock) {
 #pragma unroll
         for (int k = 0; k < B; k++) {
             if (!((rawmask >> k) & 1)) continue;
@@ -720,7 +723,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
         const uint32_t W = (m + p.S - 1) / p.S;
         const uint32_t NG = (W + 63) / 64;
         const uint32_t head = huf_head(W);
-        const uint64_t payload_base = 64 + 16ull * d.n_chunks * B;
+        const uint64_t payload_base = payload_base_of(d.n_chunks, B);
         for (uint32_t k = 0; k < B; k++) {
             const uint64_t ei = uint64_t(gc) * B + k;
             const EncEntry en = entries[ei];
@@ -770,7 +773,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
             if (t < 128) pay[t] = uint8_t((P.rcode[k][2 * t] >> 16) | ((P.rcode[k][2 * t + 1] >> 16) << 4));
             if (uint32_t(t) < NG) ((uint32_t*)(pay + 128))[t] = P.wpre[k][t + 1] - P.wpre[k][t];
             for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
-            for (uint32_t i = P.bytes[k] + t; i < uint32_t(align16(P.bytes[k])); i += kBlock) pay[i] = 0;
+            for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
             uint32_t* words = (uint32_t*)(pay + head);
             for (uint32_t j = wv; j < NG; j += kWaves) {
                 switch (B * 16 + p.g) {

@@ -26,6 +26,17 @@ constexpr int kModeRaw = 0, kModeHuf = 1, kModeRle = 2;
 constexpr int kBlock = 256;                 // threads per workgroup (4 waves)
 
 __host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15u) & ~uint64_t(15); }
+
+// Payloads start at multiples of kPayAlign bytes from the container start (and
+// containers at such offsets in a batch arena), so that two streams never
+// share a 128-byte memory line.
+constexpr uint64_t kPayAlign = 128;
+__host__ __device__ inline uint64_t align_pay(uint64_t v) { return (v + kPayAlign - 1) & ~(kPayAlign - 1); }
+// Offset of the payload area: header + map, aligned (64 with no chunks).
+__host__ __device__ inline uint64_t payload_base_of(uint64_t n_chunks, uint64_t B)
+{
+    return n_chunks ? align_pay(64 + 16 * n_chunks * B) : 64;
+}
 __host__ __device__ inline bool pow2(uint64_t v) { return v && !(v & (v - 1)); }
 
 __host__ __device__ inline int dtype_bytes(int dt)
@@ -77,7 +88,7 @@ __host__ __device__ inline int parse_header(const uint32_t* w, uint64_t src_len,
         if (w[i]) return ZIPNN_E_FORMAT;
     h.E = h.chunk / h.B;
     if ((h.n + h.E - 1) / h.E != h.n_chunks) return ZIPNN_E_FORMAT;
-    h.payload_base = 64 + 16ull * h.n_chunks * h.B;
+    h.payload_base = payload_base_of(h.n_chunks, h.B);
     if (h.total < h.payload_base || h.total > src_len) return ZIPNN_E_FORMAT;
     return ZIPNN_OK;
 }

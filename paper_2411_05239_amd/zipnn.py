@@ -418,7 +418,7 @@ class Codec:
         p = params or zipnn_default_params(dt)
         xs = [x.contiguous() for x in xs]
         bases = [None] * len(xs) if bases is None else [b.contiguous() if b is not None else None for b in bases]
-        cap = sum(zipnn_compress_bound(dt, x.numel(), p) + 15 for x in xs)
+        cap = sum(zipnn_compress_bound(dt, x.numel(), p) + 127 for x in xs)   # containers start 128-aligned
         if arena is None or arena.numel() < cap:
             arena = torch.empty(cap, dtype=torch.uint8, device=xs[0].device)
         offs = zipnn_compress_batch(self.ctx, dt, [x.data_ptr() for x in xs], [x.numel() for x in xs],

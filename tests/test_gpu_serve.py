@@ -8,6 +8,7 @@ import time
 import pytest
 import torch
 
+import oracle
 from paper_2411_05239_amd import workloads
 from paper_2411_05239_amd import zipnn as Z
 
@@ -154,7 +155,7 @@ def test_corruption_is_reported_to_its_request_only(codec, corpus):
     c = corpus[i]["c"].clone()
     info = Z.zipnn_inspect(c[:64 + 16 * 4096].cpu().numpy().tobytes())
     hb = c.cpu().numpy()
-    base = 64 + 16 * info.n_chunks * info.B
+    base = oracle.payload_base(info.n_chunks, info.B)
     # first HUF entry: offset of its word stream after the head
     import struct
 

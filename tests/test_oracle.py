@@ -272,7 +272,7 @@ def test_uniform_random_is_raw_and_constant_is_rle(oracle_lib):
             assert oracle.entry(c, ch, k)[2] == oracle.MODE_RAW
     z = np.full(4 * 65536, 0x3C, np.uint8)
     c = oracle.compress(z, oracle.FP32, chunk_bytes=65536, policy=(oracle.HUF,) * 4)
-    assert c.size == 64 + 16 * 4 * 4
+    assert c.size == oracle.payload_base(4, 4) == 384
     for ch in range(4):
         for k in range(4):
             _, nb, mode, rle = oracle.entry(c, ch, k)
@@ -288,7 +288,7 @@ def test_no_expansion_under_auto(oracle_lib):
         u = rng.integers(0, 256, size=B * 50_000, dtype=np.uint8)
         c = oracle.compress(u, dtype, chunk_bytes=4096)
         nc = oracle.header(c)["n_chunks"]
-        assert c.size <= u.size + 64 + 16 * nc * B + 15 * nc * B
+        assert c.size <= u.size + oracle.payload_base(nc, B) + (oracle.PAY_ALIGN - 1) * nc * B
 
 
 def test_auto_threshold_is_strict(oracle_lib):
@@ -362,7 +362,7 @@ def test_xor_delta_roundtrip(oracle_lib):
     # x XOR x = 0: every stream collapses to RLE 0
     c0 = oracle.compress(w, oracle.BF16, base=w, chunk_bytes=16384, policy=(oracle.HUF, oracle.HUF))
     nc = oracle.header(c0)["n_chunks"]
-    assert c0.size == 64 + 16 * nc * 2
+    assert c0.size == oracle.payload_base(nc, 2)
     with pytest.raises(oracle.OracleError):
         oracle.decompress(c)  # a delta container needs its base
 
