@@ -21,6 +21,8 @@
 //              consecutive slots (ballot + prefix popcount), encoding codes
 //              ahead just far enough to fill that word.  Every byte of the
 //              payload extent, padding included, is written; no atomics.
+#include <type_traits>
+
 #include "zipnn_internal.h"
 
 namespace zipnn {
@@ -118,6 +120,31 @@ __device__ void build_code(const uint32_t* f, uint32_t m, uint32_t W, uint32_t L
             *entry = e;
         }
         return;
+    }
+    if (policy == ZIPNN_AUTO) {
+        // Any prefix code spends at least the empirical entropy, sum f log2(m/f)
+        // bits.  If even that bound gives a payload no smaller than the raw
+        // bytes, AUTO stores the stream raw, and the code need not be built
+        // (the decision is the one the exact size would give).
+        double h = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+            if (fv[r]) h += double(fv[r]) * (log2(double(m)) - log2(double(fv[r])));
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
+        const double lb = h * (1.0 - 1e-12) - 1.0;   // margin for the rounding of the sum
+        const uint64_t words_lb = lb > 0.0 ? uint64_t(ceil(lb / 32.0)) : 0u;
+        if (uint64_t(huf_head(W)) + 4 * words_lb >= m) {
+            if (lane == 0) {
+                EncEntry e;
+                e.pad = 0;
+                e.mode = kModeRaw;
+                e.rle = 0;
+                e.bytes = m;
+                *entry = e;
+            }
+            return;
+        }
     }
     // sort the leaves by key = f << 8 | symbol (f < 2^24 since m <= 2^22)
 #pragma unroll
@@ -286,11 +313,19 @@ __device__ inline void group_words(const uint8_t* src, const uint8_t* base, uint
             for (int x = 0; x < NW; x++) wd[x] ^= bw[x];
         }
     } else {
+        // the partial last group: bytes past the chunk's m elements are zero
+        const uint32_t nb = (m - e) * B;
 #pragma unroll
-        for (int x = 0; x < NW; x++) wd[x] = 0;
-        for (uint32_t jb = 0; jb < (m - e) * B; jb++) {
-            uint32_t v = src[uint64_t(e) * B + jb] ^ (base ? base[uint64_t(e) * B + jb] : 0u);
-            wd[jb >> 2] |= v << (8 * (jb & 3));
+        for (int x = 0; x < NW; x++) {
+            wd[x] = 0;
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const uint32_t jb = 4 * x + b;
+                if (jb < nb) {
+                    const uint32_t v = src[uint64_t(e) * B + jb] ^ (base ? base[uint64_t(e) * B + jb] : 0u);
+                    wd[x] |= v << (8 * b);
+                }
+            }
         }
     }
 }
@@ -323,23 +358,31 @@ __device__ void count_lane_group(const uint8_t* src, const uint8_t* base, const 
     uint32_t req[B];
 #pragma unroll
     for (int k = 0; k < B; k++) cnt[k] = 0, req[k] = 0;
-    for (uint32_t jj = 0; jj < ng; jj++) {
-        const uint32_t q = w + jj * W;
-        const uint32_t gcnt = q < Gfull ? G : rem;
-        uint32_t wd[NW];
-        group_words<B, G>(src, base, q, m, wd);
+    constexpr uint32_t CB = NW >= 8 ? 4 : 8;   // groups in flight per lane
+    for (uint32_t j0 = 0; j0 < ng; j0 += CB) {
+        uint32_t wds[CB][NW];
 #pragma unroll
-        for (int k = 0; k < B; k++) {
-            if (!((cand >> k) & 1)) continue;
+        for (uint32_t u = 0; u < CB; u++)
+            if (j0 + u < ng) group_words<B, G>(src, base, w + (j0 + u) * W, m, wds[u]);
 #pragma unroll
-            for (int pr = 0; pr < G / 2; pr++) {
-                if (2u * pr < gcnt) {
-                    if (cnt[k] < twoL) {
-                        cnt[k] += 32;
-                        req[k]++;
+        for (uint32_t u = 0; u < CB; u++) {
+            const uint32_t jj = j0 + u;
+            const uint32_t q = w + jj * W;
+            const uint32_t gcnt = jj >= ng ? 0u : (q < Gfull ? G : rem);
+            const uint32_t* wd = wds[u];
+#pragma unroll
+            for (int k = 0; k < B; k++) {
+                if (!((cand >> k) & 1)) continue;
+#pragma unroll
+                for (int pr = 0; pr < G / 2; pr++) {
+                    if (2u * pr < gcnt) {
+                        if (cnt[k] < twoL) {
+                            cnt[k] += 32;
+                            req[k]++;
+                        }
+                        cnt[k] -= lens[k][sym_of<B>(wd, k, 2 * pr)];
+                        if (2u * pr + 1 < gcnt) cnt[k] -= lens[k][sym_of<B>(wd, k, 2 * pr + 1)];
                     }
-                    cnt[k] -= lens[k][sym_of<B>(wd, k, 2 * pr)];
-                    if (2u * pr + 1 < gcnt) cnt[k] -= lens[k][sym_of<B>(wd, k, 2 * pr + 1)];
                 }
             }
         }
@@ -358,6 +401,7 @@ struct AnalyzeTail {
     uint32_t lg_words[kWaves][4];
 };
 
+template <int BB>
 __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                     EncParams p, EncEntry* __restrict__ entries,
@@ -367,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
     __shared__ uint32_t hist[4][256];
     __shared__ AnalyzeTail A;
     const int t = threadIdx.x, wv = t >> 6;
-    const uint32_t B = p.B;
+    constexpr uint32_t B = BB;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
         const int di = find_desc(chunk_prefix, n_desc, gc);
         const EncDesc d = descs[di];
@@ -386,22 +430,74 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
         uint32_t(*h)[256] = S.hist[wv];
         // 16-byte vectors; the element boundary is aligned since 16 % B == 0
         const uint32_t nvec = nbytes / 16;
-        for (uint32_t v = t; v < nvec; v += kBlock) {
-            uint4 x = ((const uint4*)src)[v];
+        // a stream whose bytes agree across an eighth of the wave's lanes in
+        // the first vector is taken as skewed: there, the lanes holding the
+        // first active lane's value add together, since LDS atomics on one
+        // bin serialise (the rule only changes how the counts are summed)
+        uint32_t skew = 0;
+        if (uint32_t(t) < nvec) {
+            uint4 x = ((const uint4*)src)[t];
             if (base) {
-                uint4 y = ((const uint4*)base)[v];
+                const uint4 y = ((const uint4*)base)[t];
                 x.x ^= y.x;
-                x.y ^= y.y;
-                x.z ^= y.z;
-                x.w ^= y.w;
             }
-            const uint32_t wds[4] = {x.x, x.y, x.z, x.w};
+            for (uint32_t k = 0; k < B; k++) {
+                const uint32_t byte = (x.x >> (8 * (B - 1 - k))) & 0xFFu;
+                const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
+                if (__popcll(__ballot(byte == hot)) >= 8) skew |= 1u << k;
+            }
+        }
+        skew = __builtin_amdgcn_readfirstlane(skew);
+        // SK: the skewed streams, known here (or -1: tested per byte)
+        auto count = [&](auto sk_const) {
+            constexpr int SK = decltype(sk_const)::value;
+            constexpr uint32_t HB = 8;   // vectors in flight per lane
+            for (uint32_t v0 = t; v0 < nvec; v0 += HB * kBlock) {
+              uint4 xs[HB];
 #pragma unroll
-            for (int jb = 0; jb < 16; jb++) {
-                const uint32_t byte = (wds[jb >> 2] >> (8 * (jb & 3))) & 0xFF;
-                const int k = int(B) - 1 - (jb % int(B));   // byte jb%B of a word -> stream B-1-jb%B
-                atomicAdd(&h[k][byte], 1u);
+              for (uint32_t i = 0; i < HB; i++) {
+                  const uint32_t v = v0 + i * kBlock;
+                  if (v < nvec) {
+                      xs[i] = ((const uint4*)src)[v];
+                      if (base) {
+                          const uint4 y = ((const uint4*)base)[v];
+                          xs[i].x ^= y.x;
+                          xs[i].y ^= y.y;
+                          xs[i].z ^= y.z;
+                          xs[i].w ^= y.w;
+                      }
+                  }
+              }
+#pragma unroll
+              for (uint32_t i = 0; i < HB; i++) {
+                if (v0 + i * kBlock < nvec) {
+                const uint32_t wds[4] = {xs[i].x, xs[i].y, xs[i].z, xs[i].w};
+#pragma unroll
+                for (int jb = 0; jb < 16; jb++) {
+                    const uint32_t byte = (wds[jb >> 2] >> (8 * (jb & 3))) & 0xFF;
+                    const int k = int(B) - 1 - (jb % int(B));   // byte jb%B of a word -> stream B-1-jb%B
+                    const bool sk = SK >= 0 ? ((SK >> k) & 1) != 0 : ((skew >> k) & 1) != 0;
+                    if (sk) {
+                        const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
+                        const uint64_t msk = __ballot(byte == hot);
+                        if (byte != hot) atomicAdd(&h[k][byte], 1u);
+                        else if (__builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo(uint32_t(msk), 0u)) == 0)
+                            atomicAdd(&h[k][hot], uint32_t(__popcll(msk)));
+                    } else {
+                        atomicAdd(&h[k][byte], 1u);
+                    }
+                }
+                }
+              }
             }
+        };
+        {
+            using std::integral_constant;
+            if (skew == 0) count(integral_constant<int, 0>{});
+            else if (skew == 1) count(integral_constant<int, 1>{});
+            else if (B >= 2 && skew == 3) count(integral_constant<int, B >= 2 ? 3 : -1>{});
+            else count(integral_constant<int, -1>{});
         }
         for (uint32_t b = nvec * 16 + t; b < nbytes; b += kBlock) {
             uint32_t byte = src[b] ^ (base ? base[b] : 0);
@@ -587,64 +683,128 @@ __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, i
     }
 }
 
-// Write the words of lane group j of one Huffman stream k: every lane replays
-// the decoder's rounds; when the decoder would hand this lane a word, the lane
-// encodes its next codes until 32 bits are ready (or its symbols run out) and
-// stores the word at the cursor + its rank among this round's takers.
+// Write the words of lane group j of one Huffman stream k, in lock-step.  An
+// encoder runs LG groups ahead of a model of the decoder: every step it
+// encodes the lane's group jj + LG into a per-lane queue of finished words in
+// LDS (after the lane's last group the partial word is flushed) and keeps
+// that group's code lengths in a per-lane ring.  The decoder model then plays
+// step jj's rounds from the lengths: a lane that the decoder serves in a
+// round pops its next queued word (zero once the lane's codes are used up)
+// and stores it at the cursor + its rank among the round's takers.  When the
+// decoder takes a word it holds fewer than 2L bits, so it asks for at most
+// 2L - 1 + 32 <= 53 bits past what it has consumed; the encoder is at least
+// LG*G + 2 >= 58 symbols (of >= 1 bit) ahead, so the word is always complete.
+template <int G>
+struct PackShape {
+    static constexpr uint32_t LG = (56 + G - 1) / G;                            // lead in groups
+    static constexpr uint32_t LR = LG + 1 <= 8 ? 8 : (LG + 1 <= 16 ? 16 : 32);  // ring of lengths
+    static constexpr uint32_t Q = 32;   // queued words per lane (at most 24 are ever waiting)
+    static constexpr uint32_t LB = G / 2;   // bytes of one group's lengths (4 bits each)
+};
+constexpr uint32_t kPackQ = 32;
+constexpr uint32_t kPackLenBytes = 32 * 64;   // per wave: LR * 64 lanes * LB = 32 * 64 bytes for every g
+
 template <int B, int G>
 __device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode,
-                                uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out)
+                                uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out, uint32_t* qring,
+                                uint8_t* lring)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
+    constexpr uint32_t LG = PackShape<G>::LG, LR = PackShape<G>::LR, Q = PackShape<G>::Q, LB = PackShape<G>::LB;
+    constexpr uint32_t kPf = 4;   // groups of input prefetched ahead of the encoder
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = 64 * j + lane;
     const int twoL = int(2 * L);
     const uint32_t Gtot = (m + G - 1) / G, Gfull = m / G, rem = m - Gfull * G;
     const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;
-    const uint32_t ng_max = __builtin_amdgcn_readfirstlane(ng);
-    int cnt = 0;             // bits the decoder would hold
-    uint32_t ptr = 0;        // words of this lane group written so far
-    uint64_t eb = 0;         // encoded bits not yet written
+    const uint32_t ng_max = __builtin_amdgcn_readfirstlane(ng);   // lane 0 has the most
+
+    uint64_t eb = 0;   // encoder: bits not yet in a queued word
     uint32_t en = 0;
-    uint32_t eq = 0;         // encoder: group index (within the lane) and symbol in it
-    uint32_t ei = 0;
-    uint32_t ew[NW];
-    for (uint32_t jj = 0; jj < ng_max; jj++) {
-        const uint32_t q = w + jj * W;
-        const bool has = jj < ng;
-        const uint32_t gcnt = !has ? 0u : (q < Gfull ? G : rem);
-        uint32_t wd[NW];
-        if (has) group_words<B, G>(src, base, q, m, wd);
+    uint32_t qt = 0;   // words queued
+    auto load = [&](uint32_t e, uint32_t* wd) {
+        if (e < ng) group_words<B, G>(src, base, w + e * W, m, wd);
+    };
+    auto encode = [&](uint32_t e, const uint32_t* wd) {
+        if (e >= ng) return;
+        const uint32_t ecnt = w + e * W < Gfull ? G : rem;
+        uint32_t lens = 0;
 #pragma unroll
-        for (int pr = 0; pr < G / 2; pr++) {
-            const bool part = 2u * pr < gcnt;
-            const bool need = part && cnt < twoL;
-            const uint64_t msk = __ballot(need);
-            const uint32_t below =
-                __builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(msk), 0u));
-            if (need) {
-                while (en < 32 && eq < ng) {
-                    const uint32_t qe = w + eq * W;
-                    const uint32_t ecnt = qe < Gfull ? G : rem;
-                    if (ei == 0) group_words<B, G>(src, base, qe, m, ew);
-                    const uint32_t cw = rcode[sym_of<B>(ew, k, int(ei))];
-                    eb |= uint64_t(cw & 0xFFFFu) << en;
-                    en += cw >> 16;
-                    if (++ei == ecnt) {
-                        ei = 0;
-                        eq++;
+        for (int i = 0; i < G; i++) {
+            if (uint32_t(i) < ecnt) {
+                const uint32_t cw = rcode[sym_of<B>(wd, k, i)];
+                const uint32_t l = cw >> 16;
+                eb |= uint64_t(cw & 0xFFFFu) << en;
+                en += l;
+                lens |= l << (4 * i);
+                if (en >= 32) {
+                    qring[(qt & (Q - 1)) * 64 + lane] = uint32_t(eb);
+                    qt++;
+                    eb >>= 32;
+                    en -= 32;
+                }
+            }
+        }
+        uint8_t* lp = lring + ((e & (LR - 1)) * 64 + lane) * LB;
+        if constexpr (LB == 1) *lp = uint8_t(lens);
+        else if constexpr (LB == 2) *reinterpret_cast<uint16_t*>(lp) = uint16_t(lens);
+        else *reinterpret_cast<uint32_t*>(lp) = lens;
+        if (e + 1 == ng && en > 0) {
+            qring[(qt & (Q - 1)) * 64 + lane] = uint32_t(eb);
+            qt++;
+            eb = 0;
+            en = 0;
+        }
+    };
+    // prologue: the first LG groups
+    for (uint32_t e0 = 0; e0 < LG; e0 += kPf) {
+        uint32_t wd[kPf][NW];
+#pragma unroll
+        for (uint32_t u = 0; u < kPf; u++)
+            if (e0 + u < LG) load(e0 + u, wd[u]);
+#pragma unroll
+        for (uint32_t u = 0; u < kPf; u++)
+            if (e0 + u < LG) encode(e0 + u, wd[u]);
+    }
+    uint32_t pf[kPf][NW];
+#pragma unroll
+    for (uint32_t u = 0; u < kPf; u++) load(LG + u, pf[u]);
+    uint32_t qh = 0;   // words taken
+    int cnt = 0;       // bits the decoder holds
+    uint32_t ptr = 0;  // words of this lane group written
+    for (uint32_t j0 = 0; j0 < ng_max; j0 += kPf) {
+#pragma unroll
+        for (uint32_t u = 0; u < kPf; u++) {
+            const uint32_t jj = j0 + u;
+            if (jj < ng_max) {
+                encode(jj + LG, pf[u]);
+                load(jj + LG + kPf, pf[u]);
+                const uint32_t gcnt = jj < ng ? (w + jj * W < Gfull ? G : rem) : 0u;
+                const uint8_t* lp = lring + ((jj & (LR - 1)) * 64 + lane) * LB;
+                uint32_t lens;
+                if constexpr (LB == 1) lens = *lp;
+                else if constexpr (LB == 2) lens = *reinterpret_cast<const uint16_t*>(lp);
+                else lens = *reinterpret_cast<const uint32_t*>(lp);
+#pragma unroll
+                for (int pr = 0; pr < G / 2; pr++) {
+                    const bool part = 2u * pr < gcnt;
+                    const bool need = part && cnt < twoL;
+                    const uint64_t msk = __ballot(need);
+                    const uint32_t idx = __builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo(uint32_t(msk), ptr));
+                    const uint32_t qw = qring[(qh & (Q - 1)) * 64 + lane];
+                    if (need) {
+                        out[idx] = qh < qt ? qw : 0u;
+                        qh++;
+                        cnt += 32;
+                    }
+                    ptr += uint32_t(__popcll(msk));
+                    if (part) {
+                        cnt -= int((lens >> (8 * pr)) & 15u);
+                        if (2u * pr + 1 < gcnt) cnt -= int((lens >> (8 * pr + 4)) & 15u);
                     }
                 }
-                out[ptr + below] = uint32_t(eb);
-                eb >>= 32;
-                en = en > 32 ? en - 32 : 0;
-                cnt += 32;
-            }
-            ptr += uint32_t(__popcll(msk));
-            if (part) {
-                cnt -= int(rcode[sym_of<B>(wd, k, 2 * pr)] >> 16);
-                if (2u * pr + 1 < gcnt) cnt -= int(rcode[sym_of<B>(wd, k, 2 * pr + 1)] >> 16);
             }
         }
     }
@@ -668,22 +828,33 @@ __device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, 
         if (P.mode[k] == kModeRaw) rawmask |= 1u << k;
     if (!rawmask) return;
     const uint32_t units = m / 16;
-    for (uint32_t u = threadIdx.x; u < units; u += kBlock) {
-        uint32_t wd[4 * B];
-        loadNB<16 * B>(src + uint64_t(u) * 16 * B, wd);
-        if (base) {
-            uint32_t bw[4 * B];
-            loadNB<16 * B>(base + uint64_t(u) * 16 * B, bw);
+    constexpr uint32_t RB = B == 4 ? 2 : (B == 2 ? 4 : 8);   // units in flight per thread
+    for (uint32_t u0 = threadIdx.x; u0 < units; u0 += RB * kBlock) {
+        uint32_t wds[RB][4 * B];
 #pragma unroll
-            for (int x = 0; x < 4 * B; x++) wd[x] ^= bw[x];
+        for (uint32_t r = 0; r < RB; r++) {
+            const uint32_t u = u0 + r * kBlock;
+            if (u < units) {
+                loadNB<16 * B>(src + uint64_t(u) * 16 * B, wds[r]);
+                if (base) {
+                    uint32_t bw[4 * B];
+                    loadNB<16 * B>(base + uint64_t(u) * 16 * B, bw);
+#pragma unroll
+                    for (int x = 0; x < 4 * B; x++) wds[r][x] ^= bw[x];
+                }
+            }
         }
 #pragma unroll
-        for (int k = 0; k < B; k++) {
-            if (!((rawmask >> k) & 1)) continue;
-            uint32_t o[4] = {0, 0, 0, 0};
+        for (uint32_t r = 0; r < RB; r++) {
+            const uint32_t u = u0 + r * kBlock;
 #pragma unroll
-            for (int i = 0; i < 16; i++) o[i >> 2] |= sym_of<B>(wd, k, i) << (8 * (i & 3));
-            *(uint4*)(dst + P.pay[k] + 16 * u) = make_uint4(o[0], o[1], o[2], o[3]);
+            for (int k = 0; k < B; k++) {
+                if (!((rawmask >> k) & 1) || u >= units) continue;
+                uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int i = 0; i < 16; i++) o[i >> 2] |= sym_of<B>(wds[r], k, i) << (8 * (i & 3));
+                *(uint4*)(dst + P.pay[k] + 16 * u) = make_uint4(o[0], o[1], o[2], o[3]);
+            }
         }
     }
     // tail elements, then zero padding to the payload alignment
@@ -701,6 +872,7 @@ __device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, 
     }
 }
 
+template <int BB, int GG>
 __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ descs, int n_desc,
                                                  const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                  EncParams p, const EncEntry* __restrict__ entries,
@@ -710,8 +882,10 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
                                                  const uint32_t* __restrict__ nwords)
 {
     __shared__ PackLds P;
+    __shared__ uint32_t qpool[kWaves][kPackQ * 64];
+    __shared__ __align__(16) uint8_t lpool[kWaves][kPackLenBytes];
     const int t = threadIdx.x, wv = t >> 6;
-    const uint32_t B = p.B;
+    constexpr uint32_t B = BB;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
         const int di = find_desc(chunk_prefix, n_desc, gc);
         const EncDesc d = descs[di];
@@ -760,12 +934,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
         const uint8_t* src = d.src + e0 * B;
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
         uint8_t* dst = d.dst;
-        switch (B) {
-        case 1: pack_raw<1>(src, base, dst, P, m); break;
-        case 2: pack_raw<2>(src, base, dst, P, m); break;
-        case 4: pack_raw<4>(src, base, dst, P, m); break;
-        default: break;
-        }
+        pack_raw<BB>(src, base, dst, P, m);
         for (uint32_t k = 0; k < B; k++) {
             if (P.mode[k] != kModeHuf) continue;
             uint8_t* pay = dst + P.pay[k];
@@ -775,26 +944,9 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
             for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
             for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
             uint32_t* words = (uint32_t*)(pay + head);
-            for (uint32_t j = wv; j < NG; j += kWaves) {
-                switch (B * 16 + p.g) {
-#define ZIPNN_CASE(BB, GG)                                                                                     \
-    case BB * 16 + GG:                                                                                        \
-        pack_lane_group<BB, GG>(src, base, int(k), P.rcode[k], p.L, j, W, m, words + P.wpre[k][j]);          \
-        break;
-                    ZIPNN_CASE(1, 2)
-                    ZIPNN_CASE(1, 4)
-                    ZIPNN_CASE(1, 8)
-                    ZIPNN_CASE(2, 2)
-                    ZIPNN_CASE(2, 4)
-                    ZIPNN_CASE(2, 8)
-                    ZIPNN_CASE(4, 2)
-                    ZIPNN_CASE(4, 4)
-                    ZIPNN_CASE(4, 8)
-#undef ZIPNN_CASE
-                default:
-                    break;
-                }
-            }
+            for (uint32_t j = wv; j < NG; j += kWaves)
+                pack_lane_group<BB, GG>(src, base, int(k), P.rcode[k], p.L, j, W, m, words + P.wpre[k][j], qpool[wv],
+                                        lpool[wv]);
         }
         __syncthreads();
     }
@@ -808,7 +960,10 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
 {
     const uint32_t grid = min(max(total_chunks, 1u), 1u << 16);
     if (total_chunks) {
-        k_analyze<<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
+        if (p.B == 1) k_analyze<1><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
+        else if (p.B == 2) k_analyze<2><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
+        else if (p.B == 4) k_analyze<4><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
+        else return hipErrorInvalidValue;
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     }
     k_place<<<n_desc, kBlock, 0, s>>>(d_descs, p, entries, offsets, totals);
@@ -816,8 +971,18 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
     k_arena<<<1, kBlock, 0, s>>>(d_descs, n_desc, p, arena, cap, totals, arena_off);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     if (total_chunks) {
-        k_pack<<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, offsets,
-                                       totals, nwords);
+        bool launched = false;
+#define ZIPNN_PACK(B_, G_)                                                                                       \
+    if (!launched && p.B == B_ && p.g == G_) {                                                                  \
+        k_pack<B_, G_><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, \
+                                               offsets, totals, nwords);                                        \
+        launched = true;                                                                                        \
+    }
+        ZIPNN_PACK(1, 2) ZIPNN_PACK(1, 4) ZIPNN_PACK(1, 8)
+        ZIPNN_PACK(2, 2) ZIPNN_PACK(2, 4) ZIPNN_PACK(2, 8)
+        ZIPNN_PACK(4, 2) ZIPNN_PACK(4, 4) ZIPNN_PACK(4, 8)
+#undef ZIPNN_PACK
+        if (!launched) return hipErrorInvalidValue;
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     }
     return hipSuccess;
