@@ -36,7 +36,7 @@ struct PmWave {                 // package-merge workspace of one wave
     uint32_t pk[256];           // package weights of the current level
     uint32_t cur[512];          // current list weights
     uint16_t pos[kMaxL][256];   // position of leaf i in the list of each level
-    uint32_t key[256];
+    alignas(16) uint32_t key[256];
     uint8_t len[256];           // code length per symbol
     uint32_t cnt[16];
     uint32_t cand;              // 1: Huffman candidate (size decided by the replay)
@@ -150,14 +150,27 @@ __device__ void build_code(const uint32_t* f, uint32_t m, uint32_t W, uint32_t L
 #pragma unroll
     for (int r = 0; r < 4; r++) P.key[lane + 64 * r] = fv[r] ? ((fv[r] << 8) | uint32_t(lane + 64 * r)) : 0xFFFFFFFFu;
     __builtin_amdgcn_wave_barrier();
+    {
+        // rank of each key among all 256 (keys are distinct): four keys per
+        // 16-byte LDS read, shared by the lane's four symbols
+        uint32_t k4[4], rank[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-        if (fv[r]) {
-            const uint32_t k = P.key[lane + 64 * r];
-            uint32_t rank = 0;
-            for (int s = 0; s < 256; s++) rank += P.key[s] < k;
-            P.leafw[rank] = fv[r];
-            P.leafsym[rank] = uint16_t(lane + 64 * r);
+        for (int r = 0; r < 4; r++) k4[r] = P.key[lane + 64 * r];
+        const uint4* kv = reinterpret_cast<const uint4*>(P.key);
+#pragma unroll 4
+        for (int s = 0; s < 64; s++) {
+            const uint4 kk = kv[s];
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                rank[r] += uint32_t(kk.x < k4[r]) + uint32_t(kk.y < k4[r]) + uint32_t(kk.z < k4[r]) +
+                           uint32_t(kk.w < k4[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            if (fv[r]) {
+                P.leafw[rank[r]] = fv[r];
+                P.leafsym[rank[r]] = uint16_t(lane + 64 * r);
+            }
         }
     }
     __builtin_amdgcn_wave_barrier();
