@@ -38,8 +38,8 @@ PAY_ALIGN = 128   # payload alignment from the container start (ORC_PAY_ALIGN)
 def payload_base(n_chunks: int, B: int) -> int:
     """Offset of a container's payload area: header + map, aligned."""
     return -(-(64 + 16 * n_chunks * B) // PAY_ALIGN) * PAY_ALIGN if n_chunks else 64
-AUTO, HUF, RAW = 0, 1, 2
-MODE_RAW, MODE_HUF, MODE_RLE = 0, 1, 2
+AUTO, HUF, RAW, ZG = 0, 1, 2, 3
+MODE_RAW, MODE_HUF, MODE_RLE, MODE_ZG = 0, 1, 2, 3
 
 
 class OracleError(RuntimeError):

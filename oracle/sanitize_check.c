@@ -50,7 +50,7 @@ int main(void)
         const uint32_t L = 8 + rnd() % 4;
         const uint64_t n = (uint64_t)(rnd() % 4) * E + (rnd() % 5);
         uint8_t policy[4];
-        for (int k = 0; k < 4; k++) policy[k] = (uint8_t)(rnd() % 3);
+        for (int k = 0; k < 4; k++) policy[k] = (uint8_t)(rnd() % 4);
         const uint64_t nb = n * (uint64_t)B;
         uint8_t* x = (uint8_t*)malloc(nb + 1);
         uint8_t* base = (rnd() & 1) ? (uint8_t*)malloc(nb + 1) : NULL;

@@ -13,7 +13,9 @@ Steps (ZipNN, arXiv 2411.05239):
   codes    -- canonical codes by walking the symbols in (length, symbol) order
               (code_{i+1} = (code_i + 1) << (l_{i+1} - l_i)), equivalent to
               RFC 1951 §3.2.2;
-  modes    -- RAW / RLE / HUF per byte-group (§III-B, §V-A);
+  modes    -- RAW / RLE / HUF / ZG per byte-group (§III-B, §IV-B, §V-A);
+  schedule -- the lock-step word order as a sort of (step, pair, lane) events
+              rather than nested loops;
   layout   -- 64-byte header, 16-byte map entries, 16-byte aligned payloads
               (the container described in ``zipnn_oracle.h``).
 """
@@ -24,8 +26,8 @@ import struct
 import numpy as np
 
 WIDTH = {1: 2, 2: 2, 3: 4, 4: 1, 5: 1}
-AUTO, HUF, RAW = 0, 1, 2
-MODE_RAW, MODE_HUF, MODE_RLE = 0, 1, 2
+AUTO, HUF, RAW, ZG = 0, 1, 2, 3
+MODE_RAW, MODE_HUF, MODE_RLE, MODE_ZG = 0, 1, 2, 3
 
 
 class SpecError(ValueError):
@@ -113,36 +115,61 @@ def _payload_base(n_chunks: int, B: int) -> int:
 LANES = 64
 
 
-def _substreams(m: int, S: int, g: int) -> list[list[int]]:
-    """Element indices of each sub-stream: group q of g symbols -> q mod W."""
+def _events(m: int, S: int, g: int, coded) -> list[list[tuple[int, list[int]]]]:
+    """Per lane group, the decode events in lock-step order.
+
+    Group q of g symbols belongs to sub-stream w = q mod W (lane w mod 64 of
+    lane group w div 64) and is its (q div W)-th group: its step.  A coded
+    group contributes one event per pair of symbols; sorting the events by
+    (step, pair, lane) gives the order in which the lanes of a lane group
+    decode, and so the order of their word requests."""
     W = -(-m // S)
-    subs = [[] for _ in range(W)]
+    per_group = [[] for _ in range(-(-W // LANES))]
     for q in range(-(-m // g)):
-        subs[q % W].extend(range(q * g, min(q * g + g, m)))
-    return subs
+        if not coded(q):
+            continue
+        w, step = q % W, q // W
+        idx = list(range(q * g, min(q * g + g, m)))
+        for pr in range(0, len(idx), 2):
+            per_group[w // LANES].append(((step, pr, w % LANES), idx[pr:pr + 2]))
+    return [[(key[2], idx) for key, idx in sorted(ev)] for ev in per_group]
 
 
-def _request_schedule(n_syms: list[int], lens_of, L: int) -> list[list[int]]:
-    """For one lane group: per round, the lanes (ascending) that take a word.
-    A lane with symbols left in round r takes a word when it buffers < 2L bits,
-    then consumes the code lengths of its symbols 2r and 2r+1."""
-    buffered = [0] * len(n_syms)
-    schedule = []
-    for r in range(max((n + 1) // 2 for n in n_syms)):
-        takers = []
-        for lane, n in enumerate(n_syms):
-            if 2 * r >= n:
-                continue
-            if buffered[lane] < 2 * L:
-                takers.append(lane)
-                buffered[lane] += 32
-            buffered[lane] -= sum(lens_of(lane, t) for t in (2 * r, 2 * r + 1) if t < n)
-        schedule.append(takers)
-    return schedule
+def _huf_payload(sym: np.ndarray, S: int, g: int, L: int, lengths: dict[int, int], bitmap: bytes | None) -> bytes:
+    m = len(sym)
+    codes = canonical(lengths)
+    if bitmap is None:
+        coded = lambda q: True
+    else:
+        coded = lambda q: (bitmap[q // 8] >> (q % 8)) & 1
+    counts_out, words_out = [], []
+    for events in _events(m, S, g, coded):
+        # each lane's bit string (a Python int, bit i = i-th stream bit)
+        acc, nbits = {}, {}
+        for lane, idx in events:
+            for e in idx:
+                c, l = codes[int(sym[e])]
+                for b in range(l):
+                    acc[lane] = acc.get(lane, 0) | (((c >> (l - 1 - b)) & 1) << nbits.get(lane, 0))
+                    nbits[lane] = nbits.get(lane, 0) + 1
+        buffered, nxt, stream = {}, {}, []
+        for lane, idx in events:
+            if buffered.get(lane, 0) < 2 * L:
+                stream.append((acc.get(lane, 0) >> (32 * nxt.get(lane, 0))) & 0xFFFFFFFF)
+                nxt[lane] = nxt.get(lane, 0) + 1
+                buffered[lane] = buffered.get(lane, 0) + 32
+            buffered[lane] -= sum(lengths[int(sym[e])] for e in idx)
+        counts_out.append(len(stream))
+        words_out.extend(stream)
+    NG = -(-(-(-m // S)) // LANES)
+    H = _a16(128 + 4 * NG)
+    table = bytes(lengths.get(2 * i, 0) | (lengths.get(2 * i + 1, 0) << 4) for i in range(128))
+    head = table + struct.pack(f"<{NG}I", *counts_out)
+    return head + bytes(H - len(head)) + (bitmap or b"") + struct.pack(f"<{len(words_out)}I", *words_out)
 
 
 def encode_stream(sym: np.ndarray, S: int, g: int, L: int, policy: int) -> tuple[int, int, bytes]:
-    """-> (mode, rle value, payload bytes)"""
+    """-> (mode, rle / fill value, payload bytes)"""
     m = len(sym)
     if policy == RAW:
         return MODE_RAW, 0, sym.tobytes()
@@ -150,40 +177,35 @@ def encode_stream(sym: np.ndarray, S: int, g: int, L: int, policy: int) -> tuple
     present = [s for s in range(256) if counts[s]]
     if len(present) == 1:
         return MODE_RLE, present[0], b""
-    lengths = pm_lengths({s: int(counts[s]) for s in present}, L)
-    codes = canonical(lengths)
-    subs = _substreams(m, S, g)
-    W = len(subs)
-    NG = -(-W // LANES)
-    H = _a16(128 + 4 * NG)
-    counts_out, words_out = [], []
-    for j in range(NG):
-        group = subs[LANES * j: LANES * j + LANES]
-        # each lane's bit string (as a Python int, bit i = i-th stream bit)
-        lane_words = []
-        for idx in group:
-            acc, nbits = 0, 0
-            for e in idx:
-                c, l = codes[int(sym[e])]
-                for b in range(l):
-                    acc |= ((c >> (l - 1 - b)) & 1) << nbits
-                    nbits += 1
-            lane_words.append([(acc >> (32 * k)) & 0xFFFFFFFF for k in range(nbits // 32 + 3)])
-        sched = _request_schedule([len(x) for x in group], lambda lane, t: lengths[int(sym[group[lane][t]])], L)
-        nxt = [0] * len(group)
-        stream = []
-        for takers in sched:
-            for lane in takers:
-                stream.append(lane_words[lane][nxt[lane]])
-                nxt[lane] += 1
-        counts_out.append(len(stream))
-        words_out.extend(stream)
-    table = bytes(lengths.get(2 * i, 0) | (lengths.get(2 * i + 1, 0) << 4) for i in range(128))
-    head = table + struct.pack(f"<{NG}I", *counts_out)
-    payload = head + bytes(H - len(head)) + struct.pack(f"<{len(words_out)}I", *words_out)
-    if policy == AUTO and len(payload) >= m:
-        return MODE_RAW, 0, sym.tobytes()
-    return MODE_HUF, 0, payload
+    options = []   # (bytes, preference, mode, value, payload)
+    if policy != ZG:
+        lengths = pm_lengths({s: int(counts[s]) for s in present}, L)
+        huf = _huf_payload(sym, S, g, L, lengths, None)
+        options.append((len(huf), 1, MODE_HUF, 0, huf))
+    z = int(np.argmax(counts))   # first maximum: the smallest most frequent value
+    if policy == ZG or (policy == AUTO and 2 * int(counts[z]) >= m):
+        G = -(-m // g)
+        marked = [q for q in range(G) if np.any(sym[q * g: q * g + g] != z)]
+        bitmap = bytearray(_a16(-(-G // 8)))
+        for q in marked:
+            bitmap[q // 8] |= 1 << (q % 8)
+        sub = np.concatenate([sym[q * g: q * g + g] for q in marked]) if marked else sym[:0]
+        counts2 = np.bincount(sub, minlength=256)
+        present2 = [s for s in range(256) if counts2[s]]
+        if len(present2) >= 2:
+            lengths2 = pm_lengths({s: int(counts2[s]) for s in present2}, L)
+            zg = _huf_payload(sym, S, g, L, lengths2, bytes(bitmap))
+            options.append((len(zg), 2, MODE_ZG, z, zg))
+        elif policy == ZG:   # nothing for ZG to code with two values: HUF
+            lengths = pm_lengths({s: int(counts[s]) for s in present}, L)
+            huf = _huf_payload(sym, S, g, L, lengths, None)
+            options.append((len(huf), 1, MODE_HUF, 0, huf))
+    if policy == AUTO:
+        options.append((m, 0, MODE_RAW, 0, sym.tobytes()))
+        _, _, mode, value, payload = min(options, key=lambda o: (o[0], o[1]))
+        return mode, value, payload
+    _, _, mode, value, payload = max(options, key=lambda o: o[1])   # a forced policy: ZG over HUF
+    return mode, value, payload
 
 
 def compress(words: np.ndarray, dtype: int, *, base: np.ndarray | None = None, chunk_bytes: int = 262144,
@@ -233,53 +255,61 @@ def decompress(blob: bytes, base: np.ndarray | None = None) -> np.ndarray:
                 streams.append(np.frombuffer(p, dtype=np.uint8).copy())
             elif mode == MODE_RLE:
                 streams.append(np.full(m, rle, dtype=np.uint8))
+            elif mode == MODE_HUF:
+                streams.append(_decode_huf(p, m, S, g, L, None))
+            elif mode == MODE_ZG:
+                streams.append(_decode_huf(p, m, S, g, L, rle))
             else:
-                streams.append(_decode_huf(p, m, S, g, L))
+                raise SpecError("mode")
         out[c * E * B: (c * E + m) * B] = merge(streams, B)
     if base is not None:
         out ^= np.ascontiguousarray(base).view(np.uint8).reshape(-1)
     return out
 
 
-def _decode_huf(p: bytes, m: int, S: int, g: int, L: int) -> np.ndarray:
+def _decode_huf(p: bytes, m: int, S: int, g: int, L: int, fill: int | None) -> np.ndarray:
+    """HUF payload (fill None) or ZG payload (groups left out of the bitmap
+    are all `fill`)."""
     lengths = {}
     for i in range(128):
         for s, l in ((2 * i, p[i] & 15), (2 * i + 1, p[i] >> 4)):
             if l:
                 lengths[s] = l
     book = {(l, c): s for s, (c, l) in canonical(lengths).items()}
-    subs = _substreams(m, S, g)
-    W = len(subs)
+    W = -(-m // S)
     NG = -(-W // LANES)
     H = _a16(128 + 4 * NG)
-    nwords = struct.unpack(f"<{NG}I", p[128:128 + 4 * NG])
-    words = struct.unpack(f"<{(len(p) - H) // 4}I", p[H:])
     out = np.zeros(m, dtype=np.uint8)
+    if fill is None:
+        coded = lambda q: True
+        start = H
+    else:
+        G = -(-m // g)
+        start = H + _a16(-(-G // 8))
+        bitmap = p[H:start]
+        coded = lambda q: (bitmap[q // 8] >> (q % 8)) & 1
+        for q in range(G):
+            if not coded(q):
+                out[q * g: q * g + g] = fill
+    nwords = struct.unpack(f"<{NG}I", p[128:128 + 4 * NG])
+    words = struct.unpack(f"<{(len(p) - start) // 4}I", p[start:])
     pos = 0
-    for j in range(NG):
-        group = subs[LANES * j: LANES * j + LANES]
-        bits = [0] * len(group)       # received bits, as an int per lane
-        have = [0] * len(group)       # received bit count
-        used = [0] * len(group)       # consumed bit count
-        for r in range(max((len(x) + 1) // 2 for x in group)):
-            for lane, idx in enumerate(group):
-                if 2 * r >= len(idx):
-                    continue
-                if have[lane] - used[lane] < 2 * L:
-                    bits[lane] |= words[pos] << have[lane]
-                    have[lane] += 32
-                    pos += 1
-                for t in (2 * r, 2 * r + 1):
-                    if t >= len(idx):
-                        break
-                    c, l = 0, 0
-                    while (l, c) not in book:
-                        if l >= L:
-                            raise SpecError("bad code")
-                        c = (c << 1) | ((bits[lane] >> used[lane]) & 1)
-                        used[lane] += 1
-                        l += 1
-                    out[idx[t]] = book[(l, c)]
+    for j, events in enumerate(_events(m, S, g, coded)):
+        bits, have, used = {}, {}, {}   # per lane: received bits, their count, bits consumed
+        for lane, idx in events:
+            if have.get(lane, 0) - used.get(lane, 0) < 2 * L:
+                bits[lane] = bits.get(lane, 0) | (words[pos] << have.get(lane, 0))
+                have[lane] = have.get(lane, 0) + 32
+                pos += 1
+            for e in idx:
+                c, l = 0, 0
+                while (l, c) not in book:
+                    if l >= L:
+                        raise SpecError("bad code")
+                    c = (c << 1) | ((bits[lane] >> used.get(lane, 0)) & 1)
+                    used[lane] = used.get(lane, 0) + 1
+                    l += 1
+                out[e] = book[(l, c)]
         if pos != sum(nwords[: j + 1]):
             raise SpecError("word count")
     return out

@@ -257,32 +257,31 @@ static uint64_t huf_head_bytes(uint64_t W)
     return align16(128 + 4 * ((W + ORC_LANES - 1) / ORC_LANES));
 }
 
-/* Element indices (within the chunk) of the symbols of sub-stream w, in
- * order: the groups q = w, w+W, w+2W, ... of g consecutive symbols, the last
- * group of the chunk possibly shorter.  Returns how many. */
-static uint64_t substream_symbols(uint64_t m, uint64_t W, uint64_t g, uint64_t w, uint64_t* idx)
+/* Bytes of the group bitmap of a ZG payload: one bit per group of g symbols,
+ * zero padded to 16. */
+static uint64_t zg_bitmap_bytes(uint64_t m, uint32_t g)
 {
-    uint64_t G = (m + g - 1) / g, n = 0;
-    for (uint64_t q = w; q < G; q += W) {
-        uint64_t j_end = (q + 1) * g < m ? (q + 1) * g : m;
-        for (uint64_t j = q * g; j < j_end; j++) idx[n++] = j;
-    }
-    return n;
+    return align16(((m + g - 1) / g + 7) / 8);
 }
 
-/* Build the HUF payload of m symbols with the given code lengths.
+/* Build the Huffman payload of m symbols with the given code lengths.  With
+ * flags == NULL (HUF) every group of g symbols is coded; otherwise (ZG) only
+ * the groups q with flags[q] set, and the group bitmap follows the head.
  *
- * Sub-stream w holds the codes of its symbols back to back; its bit sequence
- * is cut into 32-bit words (word k = bits 32k..32k+31, zero past the end).
- * The sub-streams are taken 64 at a time (a lane group: sub-stream 64j+l is
- * lane l of group j) and the words of one lane group are stored in the order
- * in which a decoder that runs its 64 lanes in lock-step asks for them:
- * in round r every lane that still has symbols decodes its symbols 2r and
- * 2r+1; right before that, a lane whose bit buffer holds fewer than 2L bits
- * takes its next word.  Within a round the lanes take words in lane order.
- * A lane may take one word past its last code bit (all zero). */
+ * Sub-stream w holds the codes of its coded symbols back to back; its bit
+ * sequence is cut into 32-bit words (word k = bits 32k..32k+31, zero past
+ * the end).  The sub-streams are taken 64 at a time (a lane group:
+ * sub-stream 64j+l is lane l of group j) and the words of one lane group are
+ * stored in the order in which a decoder that runs its 64 lanes in lock-step
+ * asks for them: at step s every lane decodes its s-th group (group
+ * w + s*W), pair by pair; for pair p, every lane whose group exists, is
+ * coded and has a symbol 2p first takes its next word if its bit buffer holds
+ * fewer than 2L bits (lanes in order), then decodes symbols 2p and 2p+1 of
+ * the group.  A lane may take one word past its last code bit (all zero).
+ * For HUF this is the order of rounds r = s*g/2 + p over every lane's own
+ * symbols, since only a chunk's last group can be short. */
 static int huf_payload(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g, int L, const uint8_t len[256],
-                       stream_out* out)
+                       const uint8_t* flags, stream_out* out)
 {
     uint32_t code[256];
     orc_canonical_codes(len, L, code);
@@ -290,66 +289,82 @@ static int huf_payload(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g, i
     uint64_t NG = (W + ORC_LANES - 1) / ORC_LANES;
     uint64_t H = huf_head_bytes(W);
     uint64_t G = (m + g - 1) / g;
-    uint64_t nmax = ((G + W - 1) / W) * g;                    /* symbols of the longest sub-stream */
+    uint64_t BM = flags ? zg_bitmap_bytes(m, g) : 0;
+    uint64_t steps = (G + W - 1) / W;                         /* groups of the longest sub-stream */
+    uint64_t nmax = steps * g;                                /* symbols of the longest sub-stream */
     uint64_t lane_bytes = (nmax * (uint64_t)L + 7) / 8 + 8;   /* room for one extra zero word */
     uint64_t max_words = W * ((nmax * (uint64_t)L + 31) / 32 + 2);
-    uint8_t* p = (uint8_t*)calloc(H + 4 * max_words, 1);
-    uint64_t* idx = (uint64_t*)malloc(sizeof(uint64_t) * ORC_LANES * (nmax ? nmax : 1));
+    uint8_t* p = (uint8_t*)calloc(H + BM + 4 * max_words, 1);
     uint8_t* bits = (uint8_t*)malloc(ORC_LANES * lane_bytes);
-    if (!p || !idx || !bits) {
+    if (!p || !bits) {
         free(p);
-        free(idx);
         free(bits);
         return ORC_E_NOMEM;
     }
     for (int i = 0; i < 128; i++) p[i] = (uint8_t)(len[2 * i] | (len[2 * i + 1] << 4));
+    if (flags)
+        for (uint64_t q = 0; q < G; q++)
+            if (flags[q]) p[H + q / 8] |= (uint8_t)(1u << (q % 8));
+    uint8_t* words = p + H + BM;
     uint64_t wpos = 0;
     for (uint64_t j = 0; j < NG; j++) {
         uint64_t lanes = W - ORC_LANES * j < ORC_LANES ? W - ORC_LANES * j : ORC_LANES;
-        uint64_t n[ORC_LANES], taken[ORC_LANES], rounds = 0;
+        uint64_t taken[ORC_LANES];
         int cnt[ORC_LANES];
         memset(bits, 0, ORC_LANES * lane_bytes);
         for (uint64_t l = 0; l < lanes; l++) {
-            uint64_t* ix = idx + l * nmax;
-            n[l] = substream_symbols(m, W, g, ORC_LANES * j + l, ix);
             uint64_t pos = 0;
-            for (uint64_t t = 0; t < n[l]; t++) put_code(bits + l * lane_bytes, &pos, code[sym[ix[t]]], len[sym[ix[t]]]);
+            for (uint64_t q = ORC_LANES * j + l; q < G; q += W) {
+                if (flags && !flags[q]) continue;
+                uint64_t end = (q + 1) * g < m ? (q + 1) * g : m;
+                for (uint64_t e = q * g; e < end; e++) put_code(bits + l * lane_bytes, &pos, code[sym[e]], len[sym[e]]);
+            }
             taken[l] = 0;
             cnt[l] = 0;
-            if ((n[l] + 1) / 2 > rounds) rounds = (n[l] + 1) / 2;
         }
         uint64_t start = wpos;
-        for (uint64_t r = 0; r < rounds; r++) {
-            for (uint64_t l = 0; l < lanes; l++) {
-                if (2 * r >= n[l]) continue;
-                if (cnt[l] < 2 * L) {
-                    uint32_t word = get_u32(bits + l * lane_bytes + 4 * taken[l]);
-                    put_u32(p + H + 4 * wpos, word);
-                    wpos++;
-                    taken[l]++;
-                    cnt[l] += 32;
+        for (uint64_t st = 0; st < steps; st++) {
+            for (uint32_t pr = 0; 2 * pr < g; pr++) {
+                for (uint64_t l = 0; l < lanes; l++) {
+                    uint64_t q = ORC_LANES * j + l + st * W;
+                    if (q >= G || (flags && !flags[q])) continue;
+                    uint64_t gcnt = (q + 1) * g <= m ? g : m - q * g;
+                    if (2 * pr >= gcnt) continue;
+                    if (cnt[l] < 2 * L) {
+                        put_u32(words + 4 * wpos, get_u32(bits + l * lane_bytes + 4 * taken[l]));
+                        wpos++;
+                        taken[l]++;
+                        cnt[l] += 32;
+                    }
+                    cnt[l] -= len[sym[q * g + 2 * pr]];
+                    if (2 * pr + 1 < gcnt) cnt[l] -= len[sym[q * g + 2 * pr + 1]];
                 }
-                const uint64_t* ix = idx + l * nmax;
-                cnt[l] -= len[sym[ix[2 * r]]];
-                if (2 * r + 1 < n[l]) cnt[l] -= len[sym[ix[2 * r + 1]]];
             }
         }
         put_u32(p + 128 + 4 * j, (uint32_t)(wpos - start));
     }
-    free(idx);
     free(bits);
-    out->mode = ORC_MODE_HUF;
-    out->bytes = H + 4 * wpos;
+    out->mode = flags ? ORC_MODE_ZG : ORC_MODE_HUF;
+    out->bytes = H + BM + 4 * wpos;
     out->payload = p;
     return ORC_OK;
 }
 
 /* Encode one byte-group (stream) of one chunk: m symbols.  The method
- * decision is made per byte-group (paper §V-A): RAW when the policy says so;
- * RLE when the stream holds a single value (paper §III-B: a zero stream is
- * replaced by a header -- generalised to any single value); otherwise the
- * Huffman payload, kept under AUTO only if it is strictly smaller than the
- * raw bytes (paper §III-B, §V-B: incompressible groups are stored). */
+ * decision is made per byte-group (paper §V-A):
+ *   - RAW when the policy says so;
+ *   - RLE when the stream holds a single value (paper §III-B: a zero stream
+ *     is replaced by a header -- generalised to any single value);
+ *   - HUF: Huffman coding of every symbol (paper §III-A);
+ *   - ZG: the stream's most frequent value z (smallest on ties) fills every
+ *     group of g symbols made of z alone; a bitmap marks the other groups,
+ *     whose symbols are Huffman coded.  This is the zero-aware coding of
+ *     deltas (paper §IV-B: mostly unchanged bytes, whose XOR is zero) done
+ *     without an LZ stage.
+ * Under AUTO the smallest of RAW, HUF and (when z fills at least half of the
+ * symbols) ZG is kept, ties going to RAW, then HUF; incompressible groups
+ * stay raw (paper §III-B, §V-B).  Policy HUF forces HUF; policy ZG forces
+ * ZG when the coded groups hold two distinct values at least, else HUF. */
 static int encode_stream(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g, int L, int policy,
                          stream_out* out)
 {
@@ -359,27 +374,87 @@ static int encode_stream(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g,
     memset(f, 0, sizeof(f));
     for (uint64_t j = 0; j < m; j++) f[sym[j]]++;
     int distinct = 0;
-    int only = 0;
-    for (int s = 0; s < 256; s++)
+    int only = 0, z = 0;
+    for (int s = 0; s < 256; s++) {
         if (f[s]) {
             distinct++;
             only = s;
         }
+        if (f[s] > f[z]) z = s;
+    }
     if (distinct == 1) {
         out->mode = ORC_MODE_RLE;
         out->rle = (uint8_t)only;
         out->bytes = 0;
         return ORC_OK;
     }
-    uint8_t len[256];
-    int rc = orc_package_merge(f, L, len);
-    if (rc < 0) return rc;
-    rc = huf_payload(sym, m, S, g, L, len, out);
-    if (rc != ORC_OK) return rc;
-    if (policy == ORC_POLICY_AUTO && out->bytes >= m) {
-        free(out->payload);
-        out->payload = NULL;
-        goto raw;
+    stream_out huf, zg;
+    memset(&huf, 0, sizeof(huf));
+    memset(&zg, 0, sizeof(zg));
+    int have_huf = 0, have_zg = 0;
+    if (policy != ORC_POLICY_ZG) {
+        uint8_t len[256];
+        int rc = orc_package_merge(f, L, len);
+        if (rc < 0) return rc;
+        rc = huf_payload(sym, m, S, g, L, len, NULL, &huf);
+        if (rc != ORC_OK) return rc;
+        have_huf = 1;
+    }
+    if (policy == ORC_POLICY_ZG || (policy == ORC_POLICY_AUTO && 2 * f[z] >= m)) {
+        uint64_t G = (m + g - 1) / g;
+        uint8_t* flags = (uint8_t*)calloc(G ? G : 1, 1);
+        uint64_t f2[256];
+        memset(f2, 0, sizeof(f2));
+        if (!flags) return ORC_E_NOMEM;
+        for (uint64_t q = 0; q < G; q++) {
+            uint64_t end = (q + 1) * g < m ? (q + 1) * g : m;
+            for (uint64_t e = q * g; e < end; e++)
+                if (sym[e] != z) flags[q] = 1;
+            if (flags[q])
+                for (uint64_t e = q * g; e < end; e++) f2[sym[e]]++;
+        }
+        int d2 = 0;
+        for (int s = 0; s < 256; s++) d2 += f2[s] != 0;
+        if (d2 >= 2) {
+            uint8_t len2[256];
+            int rc = orc_package_merge(f2, L, len2);
+            if (rc >= 0) rc = huf_payload(sym, m, S, g, L, len2, flags, &zg);
+            if (rc < 0) {
+                free(flags);
+                free(huf.payload);
+                return rc;
+            }
+            zg.rle = (uint8_t)z;
+            have_zg = 1;
+        }
+        free(flags);
+        if (!have_zg && !have_huf) {   /* forced ZG without two coded values: HUF */
+            uint8_t len[256];
+            int rc = orc_package_merge(f, L, len);
+            if (rc >= 0) rc = huf_payload(sym, m, S, g, L, len, NULL, &huf);
+            if (rc < 0) return rc;
+            have_huf = 1;
+        }
+    }
+    if (policy == ORC_POLICY_AUTO) {
+        uint64_t best = m;
+        int pick = 0;   /* 0 raw, 1 huf, 2 zg */
+        if (have_huf && huf.bytes < best) {
+            best = huf.bytes;
+            pick = 1;
+        }
+        if (have_zg && zg.bytes < best) pick = 2;
+        if (pick != 1) free(huf.payload);
+        if (pick != 2) free(zg.payload);
+        if (pick == 0) goto raw;
+        *out = pick == 1 ? huf : zg;
+        return ORC_OK;
+    }
+    if (have_zg) {
+        free(huf.payload);
+        *out = zg;
+    } else {
+        *out = huf;
     }
     return ORC_OK;
 
@@ -392,16 +467,20 @@ raw:
     return ORC_OK;
 }
 
-/* Decode a Huffman payload of m symbols by replaying the lock-step rounds
- * described at huf_payload: each lane collects the words it takes, and reads
- * its codes one bit at a time from them.  Returns ORC_OK or ORC_E_CORRUPT. */
-static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, uint32_t g, int L,
-                      uint8_t* sym)
+/* Decode a Huffman (zg = 0) or ZG (zg = 1, fill value z) payload of m
+ * symbols by replaying the lock-step steps and pairs described at
+ * huf_payload: each lane collects the words it takes, and reads its codes
+ * one bit at a time from them; the groups a ZG bitmap leaves unmarked are
+ * filled with z.  Returns ORC_OK or ORC_E_CORRUPT. */
+static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, uint32_t g, int L, int zg,
+                      uint8_t z, uint8_t* sym)
 {
     uint64_t W = (m + S - 1) / S;
     uint64_t NG = (W + ORC_LANES - 1) / ORC_LANES;
     uint64_t H = huf_head_bytes(W);
-    if (bytes < H) return ORC_E_CORRUPT;
+    uint64_t G = (m + g - 1) / g;
+    uint64_t BM = zg ? zg_bitmap_bytes(m, g) : 0;
+    if (bytes < H + BM) return ORC_E_CORRUPT;
     uint8_t len[256];
     for (int i = 0; i < 128; i++) {
         len[2 * i] = p[i] & 15;
@@ -420,9 +499,13 @@ static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, 
     if (n_coded < 2 || kraft != ((uint64_t)1 << L)) return ORC_E_CORRUPT;
     for (uint64_t i = 128 + 4 * NG; i < H; i++)
         if (p[i] != 0) return ORC_E_CORRUPT;
+    /* bitmap: no bit past the last group */
+    for (uint64_t q = G; q < 8 * BM; q++)
+        if ((p[H + q / 8] >> (q % 8)) & 1) return ORC_E_CORRUPT;
     uint64_t total = 0;
     for (uint64_t j = 0; j < NG; j++) total += get_u32(p + 128 + 4 * j);
-    if (bytes != H + 4 * total) return ORC_E_CORRUPT;
+    if (bytes != H + BM + 4 * total) return ORC_E_CORRUPT;
+    const uint8_t* words = p + H + BM;
 
     /* canonical decoding tables: symbols sorted by (length, symbol) and the
      * count of codes of each length */
@@ -435,71 +518,72 @@ static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, 
                 sorted[ns++] = s;
                 count[l]++;
             }
-    uint64_t G = (m + g - 1) / g;
-    uint64_t nmax = ((G + W - 1) / W) * g;
+    uint64_t steps = (G + W - 1) / W;
+    uint64_t nmax = steps * g;
     uint64_t max_take = (nmax * (uint64_t)L + 2 * L) / 32 + 2;   /* words a lane can take */
-    uint64_t* idx = (uint64_t*)malloc(sizeof(uint64_t) * ORC_LANES * (nmax ? nmax : 1));
     uint32_t* got = (uint32_t*)malloc(sizeof(uint32_t) * ORC_LANES * max_take);
-    if (!idx || !got) {
-        free(idx);
-        free(got);
-        return ORC_E_NOMEM;
-    }
+    if (!got) return ORC_E_NOMEM;
     int rc = ORC_OK;
     uint64_t wpos = 0;
     for (uint64_t j = 0; j < NG && rc == ORC_OK; j++) {
         uint64_t lanes = W - ORC_LANES * j < ORC_LANES ? W - ORC_LANES * j : ORC_LANES;
-        uint64_t n[ORC_LANES], taken[ORC_LANES], bitpos[ORC_LANES], rounds = 0;
+        uint64_t taken[ORC_LANES], bitpos[ORC_LANES];
         int cnt[ORC_LANES];
         for (uint64_t l = 0; l < lanes; l++) {
-            n[l] = substream_symbols(m, W, g, ORC_LANES * j + l, idx + l * nmax);
             taken[l] = bitpos[l] = 0;
             cnt[l] = 0;
-            if ((n[l] + 1) / 2 > rounds) rounds = (n[l] + 1) / 2;
         }
         uint64_t end = wpos + get_u32(p + 128 + 4 * j);
-        for (uint64_t r = 0; r < rounds && rc == ORC_OK; r++) {
-            for (uint64_t l = 0; l < lanes && rc == ORC_OK; l++) {
-                if (2 * r >= n[l]) continue;
-                if (cnt[l] < 2 * L) {
-                    if (wpos >= end || taken[l] >= max_take) {
-                        rc = ORC_E_CORRUPT;
-                        break;
+        for (uint64_t st = 0; st < steps && rc == ORC_OK; st++) {
+            for (uint32_t pr = 0; 2 * pr < g && rc == ORC_OK; pr++) {
+                for (uint64_t l = 0; l < lanes && rc == ORC_OK; l++) {
+                    uint64_t q = ORC_LANES * j + l + st * W;
+                    if (q >= G) continue;
+                    uint64_t gcnt = (q + 1) * g <= m ? g : m - q * g;
+                    if (zg && !((p[H + q / 8] >> (q % 8)) & 1)) {
+                        if (pr == 0) memset(sym + q * g, z, gcnt);   /* an unmarked group */
+                        continue;
                     }
-                    got[l * max_take + taken[l]++] = get_u32(p + H + 4 * wpos++);
-                    cnt[l] += 32;
-                }
-                for (uint64_t t = 2 * r; t < 2 * r + 2 && t < n[l]; t++) {
-                    /* read code bits one at a time; after l bits, the code
-                     * value minus the first code of length l is the index
-                     * among the symbols of length l if below their count */
-                    int codev = 0, first = 0, index = 0, found = -1;
-                    for (int b = 1; b <= L; b++) {
-                        if (bitpos[l] >= 32 * taken[l]) break;
-                        uint32_t wd = got[l * max_take + bitpos[l] / 32];
-                        codev |= (int)((wd >> (bitpos[l] % 32)) & 1u);
-                        bitpos[l]++;
-                        cnt[l]--;
-                        if (codev - first < count[b]) {
-                            found = sorted[index + codev - first];
+                    if (2 * pr >= gcnt) continue;
+                    if (cnt[l] < 2 * L) {
+                        if (wpos >= end || taken[l] >= max_take) {
+                            rc = ORC_E_CORRUPT;
                             break;
                         }
-                        index += count[b];
-                        first += count[b];
-                        first <<= 1;
-                        codev <<= 1;
+                        got[l * max_take + taken[l]++] = get_u32(words + 4 * wpos++);
+                        cnt[l] += 32;
                     }
-                    if (found < 0) {
-                        rc = ORC_E_CORRUPT;
-                        break;
+                    for (uint64_t t = 2 * pr; t < 2 * pr + 2 && t < gcnt; t++) {
+                        /* read code bits one at a time; after l bits, the code
+                         * value minus the first code of length l is the index
+                         * among the symbols of length l if below their count */
+                        int codev = 0, first = 0, index = 0, found = -1;
+                        for (int b = 1; b <= L; b++) {
+                            if (bitpos[l] >= 32 * taken[l]) break;
+                            uint32_t wd = got[l * max_take + bitpos[l] / 32];
+                            codev |= (int)((wd >> (bitpos[l] % 32)) & 1u);
+                            bitpos[l]++;
+                            cnt[l]--;
+                            if (codev - first < count[b]) {
+                                found = sorted[index + codev - first];
+                                break;
+                            }
+                            index += count[b];
+                            first += count[b];
+                            first <<= 1;
+                            codev <<= 1;
+                        }
+                        if (found < 0) {
+                            rc = ORC_E_CORRUPT;
+                            break;
+                        }
+                        sym[q * g + t] = (uint8_t)found;
                     }
-                    sym[idx[l * nmax + t]] = (uint8_t)found;
                 }
             }
         }
         if (rc == ORC_OK && wpos != end) rc = ORC_E_CORRUPT;   /* every word taken exactly */
     }
-    free(idx);
     free(got);
     return rc;
 }
@@ -592,9 +676,10 @@ uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes, uint32_
     uint64_t E = chunk_bytes / (uint64_t)B;
     uint64_t nc = (n + E - 1) / E;
     uint64_t W = (E + S - 1) / S;
-    /* per stream: a raw copy, or (HUF forced) the head plus at most L <= 11
-     * bits per symbol and two extra words per sub-stream; plus alignment */
-    uint64_t huf = 128 + 4 * (W / ORC_LANES + 1) + 16 + (E * 11 + 7) / 8 + 8 * W + 8;
+    /* per stream: a raw copy, or (HUF or ZG forced) the head, a ZG bitmap of
+     * at most one bit per two symbols, at most L <= 11 bits per symbol and
+     * two extra words per sub-stream; plus alignment */
+    uint64_t huf = 128 + 4 * (W / ORC_LANES + 1) + 16 + (E / 16 + 16) + (E * 11 + 7) / 8 + 8 * W + 8;
     uint64_t per_stream = (huf > E ? huf : E) + ORC_PAY_ALIGN;
     return 64 + ORC_PAY_ALIGN + nc * (uint64_t)B * (16 + per_stream);
 }
@@ -613,7 +698,7 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
     uint8_t policy[4] = {0, 0, 0, 0};
     for (int k = 0; k < B; k++) {
         policy[k] = policy_in ? policy_in[k] : ORC_POLICY_AUTO;
-        if (policy[k] > ORC_POLICY_RAW) return ORC_E_INVAL;
+        if (policy[k] > ORC_POLICY_ZG) return ORC_E_INVAL;
     }
     uint32_t E = chunk_bytes / (uint32_t)B;
     uint64_t nc64 = (n + E - 1) / E;
@@ -670,7 +755,7 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
             put_u64(ent, cur);
             put_u32(ent + 8, (uint32_t)o->bytes);
             ent[12] = (uint8_t)o->mode;
-            ent[13] = o->mode == ORC_MODE_RLE ? o->rle : 0;
+            ent[13] = o->mode == ORC_MODE_RLE || o->mode == ORC_MODE_ZG ? o->rle : 0;
             if (o->bytes) {
                 memcpy(dst + payload_base + cur, o->payload, o->bytes);
                 cur = align_pay(cur + o->bytes);
@@ -747,7 +832,7 @@ static int decode_chunk(dec_job* J, uint32_t c)
         } else if (mode == ORC_MODE_RLE) {
             memset(s, ent[13], m);
         } else {
-            rc = decode_huf(p, bytes, m, h->S, h->g, h->L, s);
+            rc = decode_huf(p, bytes, m, h->S, h->g, h->L, mode == ORC_MODE_ZG, ent[13], s);
         }
         if (rc == ORC_OK) merge_stream(s, m, h->B, k, words);
     }
@@ -804,6 +889,8 @@ static int check_map(const uint8_t* src, const orc_header* h)
                 if (bytes != 0) return ORC_E_CORRUPT;
             } else if (mode == ORC_MODE_HUF) {
                 if (bytes < huf_head_bytes(W) || ent[13]) return ORC_E_CORRUPT;
+            } else if (mode == ORC_MODE_ZG) {
+                if (bytes < huf_head_bytes(W) + zg_bitmap_bytes(m, h->g)) return ORC_E_CORRUPT;
             } else {
                 return ORC_E_CORRUPT;
             }

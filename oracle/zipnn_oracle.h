@@ -9,7 +9,8 @@
  *     23 u8 L              24 u32 flags (bit0: XOR delta)         28 u32 n_chunks
  *     32 u64 total_bytes   40 u8 policy[4]        44..63 zero
  *   map at 64: n_chunks*B entries of 16 bytes, chunk-major (entry c*B+k):
- *     u64 offset from payload_base | u32 bytes | u8 mode | u8 rle value | u16 0
+ *     u64 offset from payload_base | u32 bytes | u8 mode | u8 value | u16 0
+ *     (value: the RLE byte, or the ZG fill byte; zero otherwise)
  *   payload_base = align128(64 + 16*n_chunks*B) (64 when n_chunks = 0);
  *   payloads in map order, each starting at a 128-byte aligned offset;
  *   padding is zero; RLE entries have no bytes and carry the running offset;
@@ -22,9 +23,15 @@
  *     sub-stream q mod W; sub-stream 64j+l is lane l of lane group j.  A
  *     sub-stream's codes (most significant bit first, LSB-first packing) are
  *     cut into 32-bit words; a lane group's words are stored in the order a
- *     lock-step decoder of its 64 lanes takes them: in round r each lane with
- *     symbols left takes its next word if it holds fewer than 2L bits (lanes
- *     in order), then decodes its symbols 2r and 2r+1.
+ *     lock-step decoder of its 64 lanes takes them: at step s each lane
+ *     decodes its group w + s*W pair by pair; for each pair, every lane whose
+ *     group exists and has that pair takes its next word if it holds fewer
+ *     than 2L bits (lanes in order), then decodes the pair.
+ *   ZG payload (fill value z in the map): the HUF head | a bitmap of the
+ *     G = ceil(m/g) groups, bit q (byte q/8, bit q%8) set when group q holds
+ *     a symbol other than z, zero padded to align16(ceil(G/8)) | the word
+ *     streams as for HUF, where only marked groups are coded and take part in
+ *     the steps; unmarked groups decode to z.
  */
 #ifndef ZIPNN_ORACLE_H
 #define ZIPNN_ORACLE_H
@@ -44,8 +51,8 @@ enum {
     ORC_E_NOMEM = -5
 };
 enum { ORC_BF16 = 1, ORC_FP16 = 2, ORC_FP32 = 3, ORC_FP8_E4M3 = 4, ORC_U8 = 5 };
-enum { ORC_POLICY_AUTO = 0, ORC_POLICY_HUF = 1, ORC_POLICY_RAW = 2 };
-enum { ORC_MODE_RAW = 0, ORC_MODE_HUF = 1, ORC_MODE_RLE = 2 };
+enum { ORC_POLICY_AUTO = 0, ORC_POLICY_HUF = 1, ORC_POLICY_RAW = 2, ORC_POLICY_ZG = 3 };
+enum { ORC_MODE_RAW = 0, ORC_MODE_HUF = 1, ORC_MODE_RLE = 2, ORC_MODE_ZG = 3 };
 enum { ORC_FLAG_DELTA = 1 };
 
 #define ORC_MIN_CHUNK 256u

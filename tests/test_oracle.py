@@ -193,6 +193,11 @@ def _read_fixture(name):
         elif k == "input_u8_mod3":
             n = int(v[0])
             words = np.array([0xFF if e % 3 == 0 else 0 for e in range(n)], dtype=np.uint8)
+        elif k == "input_u8_fill":
+            words = np.full(int(v[0]), int(v[1], 16), dtype=np.uint8)
+        elif k == "set":
+            data = bytes.fromhex("".join(v[1:]))
+            words[int(v[0]):int(v[0]) + len(data)] = np.frombuffer(data, np.uint8)
         elif k == "params":
             for kv in v:
                 a, b = kv.split("=")
@@ -208,7 +213,7 @@ def _read_fixture(name):
     return words, params, bytes(blob)
 
 
-@pytest.mark.parametrize("name", ["tiny_bf16_container.txt", "tiny_u8_rounds.txt"])
+@pytest.mark.parametrize("name", ["tiny_bf16_container.txt", "tiny_u8_rounds.txt", "tiny_u8_zg.txt"])
 def test_tiny_containers_match_hand_derivation(oracle_lib, name):
     words, p, expect = _read_fixture(name)
     kw = dict(chunk_bytes=p["chunk_bytes"], S=p["S"], g=p["g"], L=p["L"], policy=p["policy"])
@@ -431,3 +436,105 @@ def test_invalid_params_rejected(oracle_lib):
         with pytest.raises(oracle.OracleError) as ei:
             oracle.compress(x, oracle.BF16, **kw)
         assert ei.value.code == oracle.E_INVAL
+
+
+# ----------------------------------------------------------- ZG (zero-aware delta coding)
+
+def _zg_closed_form(s, g, L):
+    """Fill value, bitmap bytes and coded bit count of one stream, computed
+    with numpy from the definition: z = most frequent value (smallest on
+    ties), a group is marked when it holds any value other than z, and the
+    symbols of marked groups are coded with the optimal length-limited code
+    of their own histogram."""
+    f = np.bincount(s, minlength=256)
+    z = int(np.flatnonzero(f == f.max())[0])
+    G = -(-len(s) // g)
+    pad = np.full(G * g, z, np.uint8)
+    pad[: len(s)] = s
+    marked = (pad.reshape(G, g) != z).any(axis=1)
+    bitmap = np.packbits(marked, bitorder="little").tobytes()
+    coded = pad.reshape(G, g)[marked].reshape(-1)
+    if marked.any() and marked[-1] and len(s) % g:   # the padding is not coded
+        coded = coded[: len(coded) - (G * g - len(s))]
+    f2 = np.bincount(coded, minlength=256)
+    T2 = int((f2 * oracle.package_merge(f2, L).astype(np.int64)).sum()) if (f2 > 0).sum() >= 2 else None
+    return z, bitmap, T2, (f2 > 0).sum()
+
+
+def test_zg_matches_closed_form_and_auto_picks_smallest(oracle_lib):
+    """On XOR deltas of a sparse fine-tune (paper §IV-B), forced-ZG streams
+    carry z in the map and the bitmap given by the definition, their size lies
+    between the coded bit count and that plus the word padding, and AUTO keeps
+    the smallest of RAW, HUF and ZG (ZG only when z fills half the stream)."""
+    w = workloads.bf16_normal(4 * 8192 + 37, seed=21)
+    ft = workloads.finetune_delta(w, seed=22)
+    raw = oracle.as_bytes(ft) ^ oracle.as_bytes(w)
+    S, g, L, chunk = 256, 4, 11, 16384
+    kw = dict(chunk_bytes=chunk, S=S, g=g, L=L)
+    zg = oracle.compress(raw, oracle.BF16, policy=(oracle.ZG,) * 2, **kw)
+    huf = oracle.compress(raw, oracle.BF16, policy=(oracle.HUF,) * 2, **kw)
+    auto = oracle.compress(raw, oracle.BF16, **kw)
+    assert np.array_equal(oracle.decompress(zg), raw)
+    assert np.array_equal(oracle.decompress(auto), raw)
+    pairs = raw.reshape(-1, 2)
+    E = chunk // 2
+    picked = set()
+    for ch in range(oracle.header(zg)["n_chunks"]):
+        for k in range(2):
+            s = pairs[ch * E:(ch + 1) * E, 1 - k]
+            m = len(s)
+            z, bitmap, T2, d2 = _zg_closed_form(s, g, L)
+            off, nb, mode, val = oracle.entry(zg, ch, k)
+            if len(np.unique(s)) == 1:
+                assert mode == oracle.MODE_RLE
+                continue
+            if d2 < 2:
+                assert mode == oracle.MODE_HUF
+                continue
+            assert (mode, val) == (oracle.MODE_ZG, z)
+            W = -(-m // S)
+            H = (128 + 4 * ((W + 63) // 64) + 15) // 16 * 16
+            BM = (len(bitmap) + 15) // 16 * 16
+            assert bytes(zg[off + H: off + H + len(bitmap)]) == bitmap
+            assert not zg[off + H + len(bitmap): off + H + BM].any()
+            assert H + BM + (T2 + 7) // 8 <= nb <= H + BM + (T2 + 7) // 8 + 8 * W
+            _, nb_h, mode_h, _ = oracle.entry(huf, ch, k)
+            assert mode_h == oracle.MODE_HUF
+            _, nb_a, mode_a, val_a = oracle.entry(auto, ch, k)
+            f = np.bincount(s, minlength=256)
+            best = min([(m, 0, oracle.MODE_RAW), (nb_h, 1, oracle.MODE_HUF)]
+                       + ([(nb, 2, oracle.MODE_ZG)] if 2 * f[z] >= m else []))
+            assert (nb_a, mode_a) == (best[0], best[2])
+            picked.add(mode_a)
+    assert oracle.MODE_ZG in picked   # the sparse low byte of the delta
+
+
+def test_zg_needs_half_the_stream(oracle_lib):
+    """AUTO never picks ZG when the most frequent value fills less than half
+    of the stream, even where ZG would be smaller; at exactly half it may."""
+    rng = np.random.default_rng(5)
+    m = 8192
+    for zeros, allowed in [(m // 2 - 1, False), (m // 2, True)]:
+        s = rng.integers(1, 3, size=m, dtype=np.uint8)
+        s[:zeros] = 0   # whole groups of zeros first: ZG would code only the rest
+        kw = dict(chunk_bytes=m, g=8)
+        nz = oracle.entry(oracle.compress(s, oracle.U8, policy=(oracle.ZG,), **kw), 0, 0)[1]
+        nh = oracle.entry(oracle.compress(s, oracle.U8, policy=(oracle.HUF,), **kw), 0, 0)[1]
+        assert nz < nh < m
+        mode = oracle.entry(oracle.compress(s, oracle.U8, **kw), 0, 0)[2]
+        assert mode == (oracle.MODE_ZG if allowed else oracle.MODE_HUF)
+
+
+def test_corrupt_zg_rejected(oracle_lib):
+    words, p, blob = _read_fixture("tiny_u8_zg.txt")
+    good = np.frombuffer(blob, np.uint8).copy()
+    assert np.array_equal(oracle.decompress(good), words)
+    for pos, val in [(272 + 2, 0x01),    # a bitmap bit past the last group
+                     (272, 0x42 | 0x01),  # one more marked group: words run short
+                     (272, 0x40),         # one fewer marked group: words left over
+                     (64 + 8, 0x20)]:     # payload shorter than head + bitmap
+        d = good.copy()
+        d[pos] = val
+        with pytest.raises(oracle.OracleError) as ei:
+            oracle.decompress(d)
+        assert ei.value.code in (oracle.E_CORRUPT, oracle.E_FORMAT)

@@ -26,7 +26,7 @@ def cases(draw):
     n_chunks = draw(st.integers(min_value=0, max_value=3))
     n = max(0, n_chunks * E + draw(st.integers(min_value=-2, max_value=2)))
     kind = draw(st.sampled_from(["normal", "uniform", "constant", "sparse", "special"]))
-    policy = tuple(draw(st.sampled_from([oracle.AUTO, oracle.HUF, oracle.RAW])) for _ in range(B))
+    policy = tuple(draw(st.sampled_from([oracle.AUTO, oracle.HUF, oracle.RAW, oracle.ZG])) for _ in range(B))
     with_base = draw(st.booleans())
     seed = draw(st.integers(min_value=0, max_value=2**31 - 1))
     return dtype, B, chunk, S, g, L, n, kind, policy, with_base, seed
