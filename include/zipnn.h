@@ -17,7 +17,10 @@
  *   - a map holding metadata per chunk and per byte-group allows parallel
  *     decompression of the variable-size chunks (§V-A "Metadata and
  *     parallelism");
- *   - a tensor may be stored as the XOR delta against a base (§IV-B).
+ *   - a tensor may be stored as the XOR delta against a base (§IV-B); the
+ *     bytes of a delta are mostly unchanged (zero after the XOR), which the
+ *     ZG mode below codes without an LZ stage: groups made of the fill value
+ *     alone are marked absent in a bitmap and cost one bit each.
  *
  * Container bytes (little-endian; identical to what the CPU reference codec
  * of this project writes):
@@ -27,19 +30,27 @@
  *   map: n_chunks*B entries of 16 B, chunk-major: u64 payload offset (from
  *     payload_base = align128(64 + 16*n_chunks*B), or 64 with no chunks; the
  *     gap after the map is zero) | u32 bytes | u8 mode (0 RAW, 1 HUF,
- *     2 RLE) | u8 RLE value | u16 0
+ *     2 RLE, 3 ZG) | u8 value (the RLE byte, or the ZG fill byte; else 0) |
+ *     u16 0
  *   payloads: in map order, each at a 128-byte aligned offset (a stream
  *     never shares a 128-byte memory line with another), zero padded.
  *     RAW = the m stream bytes.  RLE = nothing.  HUF = 128 B of 4-bit code
  *     lengths | u32 word count of each of the NG = ceil(W/64) lane groups |
  *     zero pad to align16(128+4*NG) | the lane groups' word streams.
+ *     ZG = the HUF head | a bitmap of the G = ceil(m/g) groups of g symbols
+ *     (bit q in byte q/8, bit q%8), set when group q holds a symbol other
+ *     than the fill value z, zero padded to align16(ceil(G/8)) | the word
+ *     streams, laid out as for HUF over the marked groups only (unmarked
+ *     groups decode to z and take no part in the steps below).
  *   Huffman layout: W = ceil(m/S) sub-streams; group q of g consecutive
  *   symbols belongs to sub-stream q mod W; sub-stream 64j+l is lane l of lane
  *   group j.  A sub-stream's canonical codes (most significant bit first,
  *   packed LSB-first) are cut into 32-bit words, and a lane group's words are
  *   stored in the order its 64 lanes take them when decoding in lock-step:
- *   in round r every lane with symbols left takes its next word if it holds
- *   fewer than 2L bits (lanes in order), then decodes its symbols 2r, 2r+1.
+ *   at step s every lane decodes its group w + s*W pair by pair; for each
+ *   pair, every lane whose group exists (and, in ZG, is marked) takes its
+ *   next word if it holds fewer than 2L bits (lanes in order), then decodes
+ *   the pair.
  *   Stream k of element j is byte B-1-k of the little-endian word.  Codes are
  *   optimal among prefix codes with lengths <= L (package-merge, ties by
  *   (frequency, symbol)) and assigned in canonical (length, symbol) order.
@@ -81,9 +92,13 @@ typedef enum {
 } zipnn_dtype;
 
 typedef enum {
-    ZIPNN_AUTO = 0,        /* HUF if strictly smaller than raw, RLE if single-valued, else RAW */
+    ZIPNN_AUTO = 0,        /* the smallest of RAW, HUF and (when the most frequent byte fills at
+                              least half of the stream) ZG, ties to RAW then HUF; RLE if
+                              single-valued */
     ZIPNN_HUF = 1,         /* always Huffman (RLE if single-valued) */
-    ZIPNN_RAW = 2          /* always stored */
+    ZIPNN_RAW = 2,         /* always stored */
+    ZIPNN_ZG = 3           /* always ZG (HUF when the marked groups hold one value; RLE if
+                              single-valued) */
 } zipnn_policy;
 
 /* Format parameters (they change the container bytes and are stored in it).
@@ -111,8 +126,8 @@ typedef struct {
     uint32_t chunk_bytes;
     uint32_t S, g, L;
     int is_delta;
-    uint64_t bytes_by_mode[3];    /* payload bytes in RAW, HUF, RLE entries */
-    uint64_t entries_by_mode[3];  /* entry counts per mode */
+    uint64_t bytes_by_mode[4];    /* payload bytes in RAW, HUF, RLE, ZG entries */
+    uint64_t entries_by_mode[4];  /* entry counts per mode */
 } zipnn_info;
 
 typedef struct zipnn_ctx_s* zipnn_ctx;

@@ -232,8 +232,9 @@ def compress(words: np.ndarray, dtype: int, *, base: np.ndarray | None = None, c
             body += bytes(_apay(len(body)) - len(body))
     total = payload_base + len(body)
     pol = bytes(list(policy[:B]) + [0] * (4 - B))
+    flags = (1 if base is not None else 0) | (2 if any(e[0] == MODE_ZG for e in entries) else 0)
     hdr = b"ZNN1" + struct.pack("<HBBQIHBBIIQ", 1, dtype, B, n, chunk_bytes, S, g, L,
-                                1 if base is not None else 0, n_chunks, total) + pol + bytes(20)
+                                flags, n_chunks, total) + pol + bytes(20)
     assert len(hdr) == 64
     return bytes(hdr + mp + bytes(payload_base - 64 - len(mp)) + body)
 
@@ -258,6 +259,8 @@ def decompress(blob: bytes, base: np.ndarray | None = None) -> np.ndarray:
             elif mode == MODE_HUF:
                 streams.append(_decode_huf(p, m, S, g, L, None))
             elif mode == MODE_ZG:
+                if not flags & 2:
+                    raise SpecError("ZG entry without the header flag")
                 streams.append(_decode_huf(p, m, S, g, L, rle))
             else:
                 raise SpecError("mode")

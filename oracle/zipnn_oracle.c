@@ -744,7 +744,10 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
         put_u16(dst + 20, (uint16_t)S);
         dst[22] = (uint8_t)g;
         dst[23] = (uint8_t)L;
-        put_u32(dst + 24, base ? ORC_FLAG_DELTA : 0);
+        uint32_t fl = base ? ORC_FLAG_DELTA : 0;
+        for (uint64_t e = 0; e < (uint64_t)n_chunks * B; e++)
+            if (J.outs[e].mode == ORC_MODE_ZG) fl |= ORC_FLAG_ZG;
+        put_u32(dst + 24, fl);
         put_u32(dst + 28, n_chunks);
         put_u64(dst + 32, total);
         for (int k = 0; k < 4; k++) dst[40 + k] = policy[k];
@@ -786,7 +789,7 @@ int orc_parse_header(const void* src_v, uint64_t src_len, orc_header* h)
     for (int k = 0; k < 4; k++) h->policy[k] = src[40 + k];
     if (dtype_width(h->dtype) == 0 || dtype_width(h->dtype) != h->B) return ORC_E_FORMAT;
     if (orc_check_params(h->B, h->chunk_bytes, h->S, h->g, h->L) != ORC_OK) return ORC_E_FORMAT;
-    if (h->flags & ~(uint32_t)ORC_FLAG_DELTA) return ORC_E_FORMAT;
+    if (h->flags & ~(uint32_t)(ORC_FLAG_DELTA | ORC_FLAG_ZG)) return ORC_E_FORMAT;
     for (int i = 44; i < 64; i++)
         if (src[i]) return ORC_E_FORMAT;
     uint64_t E = h->chunk_bytes / h->B;
@@ -890,7 +893,9 @@ static int check_map(const uint8_t* src, const orc_header* h)
             } else if (mode == ORC_MODE_HUF) {
                 if (bytes < huf_head_bytes(W) || ent[13]) return ORC_E_CORRUPT;
             } else if (mode == ORC_MODE_ZG) {
-                if (bytes < huf_head_bytes(W) + zg_bitmap_bytes(m, h->g)) return ORC_E_CORRUPT;
+                /* a ZG entry needs the header's ZG flag */
+                if (!(h->flags & ORC_FLAG_ZG) || bytes < huf_head_bytes(W) + zg_bitmap_bytes(m, h->g))
+                    return ORC_E_CORRUPT;
             } else {
                 return ORC_E_CORRUPT;
             }

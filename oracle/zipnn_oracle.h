@@ -6,8 +6,10 @@
  *   header, 64 bytes:
  *     0  "ZNN1"            4  u16 version = 1     6  u8 dtype     7  u8 B
  *     8  u64 n_elems       16 u32 chunk_bytes     20 u16 S        22 u8 g
- *     23 u8 L              24 u32 flags (bit0: XOR delta)         28 u32 n_chunks
+ *     23 u8 L              24 u32 flags                           28 u32 n_chunks
  *     32 u64 total_bytes   40 u8 policy[4]        44..63 zero
+ *   flags: bit0 XOR delta; bit1 the map holds ZG entries (written when it
+ *     does; a ZG entry without it is corrupt); other bits zero.
  *   map at 64: n_chunks*B entries of 16 bytes, chunk-major (entry c*B+k):
  *     u64 offset from payload_base | u32 bytes | u8 mode | u8 value | u16 0
  *     (value: the RLE byte, or the ZG fill byte; zero otherwise)
@@ -53,7 +55,7 @@ enum {
 enum { ORC_BF16 = 1, ORC_FP16 = 2, ORC_FP32 = 3, ORC_FP8_E4M3 = 4, ORC_U8 = 5 };
 enum { ORC_POLICY_AUTO = 0, ORC_POLICY_HUF = 1, ORC_POLICY_RAW = 2, ORC_POLICY_ZG = 3 };
 enum { ORC_MODE_RAW = 0, ORC_MODE_HUF = 1, ORC_MODE_RLE = 2, ORC_MODE_ZG = 3 };
-enum { ORC_FLAG_DELTA = 1 };
+enum { ORC_FLAG_DELTA = 1, ORC_FLAG_ZG = 2 };
 
 #define ORC_MIN_CHUNK 256u
 #define ORC_MAX_CHUNK (4u << 20)

@@ -162,7 +162,7 @@ int zipnn_check_params(int dtype, const zipnn_params* p)
     if (check_params(B, p->chunk_bytes, p->substream_syms, p->group, p->max_code_len) != ZIPNN_OK)
         return ZIPNN_E_INVAL;
     for (int k = 0; k < B; k++)
-        if (p->policy[k] > ZIPNN_RAW) return ZIPNN_E_INVAL;
+        if (p->policy[k] > ZIPNN_ZG) return ZIPNN_E_INVAL;
     return ZIPNN_OK;
 }
 
@@ -173,9 +173,11 @@ uint64_t zipnn_compress_bound(int dtype, uint64_t n, const zipnn_params* p)
     const uint64_t E = p->chunk_bytes / B;
     const uint64_t nc = (n + E - 1) / E;
     const uint64_t W = (E + p->substream_syms - 1) / p->substream_syms;
-    // AUTO never exceeds raw; HUF-forced may reach head + L bits per symbol
-    // plus two words of padding per sub-stream
-    const uint64_t per_stream = huf_head(uint32_t(W)) + (E * p->max_code_len + 7) / 8 + 8 * W;
+    // AUTO never exceeds raw; HUF- or ZG-forced may reach head + a bitmap of
+    // one bit per two symbols + L bits per symbol plus two words of padding
+    // per sub-stream
+    const uint64_t per_stream =
+        huf_head(uint32_t(W)) + (E / 16 + 16) + (E * p->max_code_len + 7) / 8 + 8 * W;
     return 64 + kPayAlign + 16 * nc * B + nc * B * ((per_stream > E ? per_stream : E) + kPayAlign);
 }
 
@@ -229,6 +231,8 @@ static int encode_tensors(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, in
         hd[i].n = t[i].n_elems;
         hd[i].chunk0 = run;
         hd[i].n_chunks = uint32_t(nc);
+        hd[i].has_zg = 0;
+        hd[i].pad = 0;
         hp[i] = run;
         run += uint32_t(nc);
     }
@@ -330,8 +334,7 @@ int zipnn_decompress_async(zipnn_ctx ctx, const void* header_host, const void* s
 
 struct zipnn_batch_s {
     struct Class {
-        uint32_t B, G;
-        bool delta;
+        DecClass k;
         int n;
         DecDesc* d_descs;
         uint64_t* d_prefix;
@@ -347,8 +350,7 @@ struct zipnn_batch_s {
 static hipError_t batch_launch(zipnn_batch b, hipStream_t s)
 {
     for (auto& c : b->classes) {
-        hipError_t e = launch_decode_batch(c.B, c.G, c.delta, c.d_descs, c.n, c.d_prefix, b->ctx->d_status,
-                                           b->ctx->dec_grid, s);
+        hipError_t e = launch_decode_batch(c.k, c.d_descs, c.n, c.d_prefix, b->ctx->d_status, b->ctx->dec_grid, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -379,8 +381,8 @@ int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets
         hipMemcpyAsync(ctx->h_total, d_hdr, size_t(n) * 64, hipMemcpyDeviceToHost, s0) != hipSuccess ||
         hipStreamSynchronize(s0) != hipSuccess)
         return ZIPNN_E_HIP;
-    // group the tensors by kernel class (B, g, delta)
-    std::map<std::tuple<uint32_t, uint32_t, bool>, std::vector<DecDesc>> groups;
+    // group the tensors by kernel class (B, g, delta, zg)
+    std::map<std::tuple<uint32_t, uint32_t, bool, bool>, std::vector<DecDesc>> groups;
     for (int i = 0; i < n; i++) {
         Header h;
         rc = parse_header((const uint32_t*)((const uint8_t*)ctx->h_total + 64 * size_t(i)), offsets[i + 1] - offsets[i],
@@ -400,7 +402,7 @@ int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets
         d.c_begin = 0;
         d.c_end = kAllChunks;
         d.status = nullptr;
-        groups[std::make_tuple(h.B, h.g, delta)].push_back(d);
+        groups[std::make_tuple(h.B, h.g, delta, (h.flags & kFlagZg) != 0)].push_back(d);
     }
     zipnn_batch b = new (std::nothrow) zipnn_batch_s;
     if (!b) return ZIPNN_E_NOMEM;
@@ -414,9 +416,7 @@ int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets
     size_t off = 0;
     for (auto& kv : groups) {
         zipnn_batch_s::Class c;
-        c.B = std::get<0>(kv.first);
-        c.G = std::get<1>(kv.first);
-        c.delta = std::get<2>(kv.first);
+        c.k = DecClass{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first)};
         c.n = int(kv.second.size());
         c.d_descs = (DecDesc*)((uint8_t*)b->d_mem + off);
         off += align256(kv.second.size() * sizeof(DecDesc));
@@ -622,10 +622,11 @@ int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out)
             memcpy(&off, e, 8);
             memcpy(&bytes, e + 8, 4);
             const uint32_t mode = e[12], rle = e[13];
-            if (e[14] || e[15] || mode > 2 || off != cur) return ZIPNN_E_CORRUPT;
+            if (e[14] || e[15] || mode > 3 || off != cur) return ZIPNN_E_CORRUPT;
             if (mode == kModeRaw && (bytes != m || rle)) return ZIPNN_E_CORRUPT;
             if (mode == kModeRle && bytes) return ZIPNN_E_CORRUPT;
             if (mode == kModeHuf && (bytes < huf_head(W) + (m + 7) / 8 || rle)) return ZIPNN_E_CORRUPT;
+            if (mode == kModeZg && bytes < huf_head(W) + zg_bitmap(uint32_t(m), h.g)) return ZIPNN_E_CORRUPT;
             cur += align_pay(bytes);
             out->bytes_by_mode[mode] += bytes;
             out->entries_by_mode[mode] += 1;

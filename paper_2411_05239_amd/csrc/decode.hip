@@ -15,13 +15,20 @@
 // contiguous bytes per group.
 //
 // A lane group's Huffman words are stored in the order its 64 lanes take them
-// when they run in lock-step (round r: a lane holding fewer than 2L bits takes
-// a word, then decodes its symbols 2r and 2r+1), so in every round the lanes
-// that need a word read CONSECUTIVE words: the wave ballots the request, each
-// lane's word index is the popcount of the requesting lanes below it, and the
-// wave's read cursor advances by the ballot's popcount.  The words come from
-// three 64-word windows held one per lane in registers (ds_bpermute picks a
-// lane's word), refilled two windows ahead with coalesced 256-byte loads.
+// when they run in lock-step (step s, pair p: a lane holding fewer than 2L
+// bits takes a word, then decodes symbols 2p and 2p+1 of its group s), so in
+// every round the lanes that need a word read CONSECUTIVE words: the wave
+// ballots the request, each lane's word index is the popcount of the
+// requesting lanes below it, and the wave's read cursor advances by the
+// ballot's popcount.  The words pass through a ring in LDS refilled half a
+// ring ahead with coalesced loads.
+//
+// A ZG stream (zero-aware coding of deltas) adds a bitmap of the groups that
+// hold a value other than the fill value z: unmarked groups are z and take no
+// part.  The 64 bits of one step of a lane group are contiguous in the
+// bitmap; for a batch of 32 steps from J, lane l holds half l/32 of the bits
+// of step J + l%32 (one register per stream), and every step reads its two
+// halves with v_readlane.
 //
 // Any failed check records ZIPNN_E_CORRUPT / ZIPNN_E_FORMAT in the sticky
 // status word; the decoder never reads outside [src, src+total_bytes) and
@@ -313,6 +320,20 @@ __device__ inline uint32_t huf_get(uint32_t* r, const uint16_t* lut, uint32_t ma
     return e & 0xFFu;
 }
 
+// huf_get for a lane that may not take part (a ZG group made of z alone):
+// the table is read, but the bits are consumed only when `on`.
+template <int B>
+__device__ inline uint32_t huf_get_if(uint32_t* r, const uint16_t* lut, uint32_t mask, bool on)
+{
+    constexpr int PN = Ring<B>::PN;
+    const uint32_t e = lut[r[PN + 1] & mask];
+    const uint32_t l = on ? e >> 8 : 0u;
+    r[PN + 1] = __builtin_amdgcn_alignbit(r[PN + 2], r[PN + 1], l);
+    r[PN + 2] >>= l;
+    r[PN] -= l;
+    return e & 0xFFu;
+}
+
 template <int G>
 __device__ inline void raw_load(const uint8_t* p, uint32_t* o)
 {
@@ -392,8 +413,8 @@ __device__ inline void merge_words(const uint32_t (*pk)[G >= 4 ? G / 4 : 1], uin
 // a lane's groups are fetched kDepth groups ahead through a register ring.
 // While every lane of the group still has a full group of g symbols the loop
 // runs without per-lane conditions; the last groups take the general path.
-template <int B, int G, bool DELTA>
-__device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemState& st, uint32_t* wring,
+template <int B, int G, bool DELTA, bool ZGK>
+__device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* __restrict__ src, const ItemState& st, uint32_t* wring,
                                   const uint16_t (*lut)[kLutSize], const uint32_t (*wprefix)[65], uint32_t L,
                                   uint32_t j, uint32_t W, uint32_t m, uint8_t* __restrict__ out,
                                   const uint8_t* __restrict__ base, int* status)
@@ -429,10 +450,24 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
     uint32_t nw[B];
     uint32_t slot[B][NS];
     uint32_t bring[BD][NW];
+    uint32_t zwin[B];   // ZG: bits of the current batch of 32 steps
+    uint32_t zJ = 0;    // first step of the batch
     const __amdgpu_buffer_rsrc_t ro = rsrc(out, m * B);
     const __amdgpu_buffer_rsrc_t rb = rsrc(DELTA ? base : out, m * B);
     // byte offset of this lane's group jj in a raw payload: (w + jj*W)*G
     auto raw_off = [&](uint32_t jj) { return jj < nfull ? (w + jj * W) * G : kOff; };
+    // ZG: lane l loads bits 32(l/32) .. +31 of step J + l%32 of this lane
+    // group, i.e. bits 64j + (J + l%32)W + 32(l/32) onwards of the bitmap
+    auto zload = [&](int k, uint32_t J) __attribute__((always_inline)) {
+        const __amdgpu_buffer_rsrc_t zr = rsrc(pay[k] + huf_head(W), zg_bitmap(m, G));
+        const uint32_t s = J + (lane & 31);
+        const uint32_t b0 = 64 * j + s * W + 32 * (lane >> 5);
+        const uint32_t o = s < ng_max ? (b0 >> 5) * 4 : kOff;
+        uint32_t d0, d1;
+        buf_load<4>(zr, o, &d0);
+        buf_load<4>(zr, o == kOff ? kOff : o + 4, &d1);
+        zwin[k] = __builtin_amdgcn_alignbit(d1, d0, b0 & 31);
+    };
 #pragma unroll
     for (int k = 0; k < B; k++) {
         mode[k] = __builtin_amdgcn_readfirstlane(st.mode[k]);
@@ -441,8 +476,12 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
         rr[k] = rsrc(pay[k], mode[k] == kModeRaw ? m : 0u);
 #pragma unroll
         for (int x = 0; x < NS; x++) slot[k][x] = 0;
-        if (mode[k] == kModeHuf) {
-            const uint32_t* words = (const uint32_t*)(pay[k] + huf_head(W));
+        zwin[k] = 0;
+        const bool zg = (ZGK && mode[k] == kModeZg);
+        const uint32_t bm = zg ? zg_bitmap(m, G) : 0u;
+        if (zg) zload(k, 0);
+        if (mode[k] == kModeHuf || zg) {
+            const uint32_t* words = (const uint32_t*)(pay[k] + huf_head(W) + bm);
             const uint32_t s0 = __builtin_amdgcn_readfirstlane(wprefix[k][j]);
             const uint32_t s1 = __builtin_amdgcn_readfirstlane(wprefix[k][j + 1]);
             nw[k] = s1 - s0;
@@ -459,25 +498,63 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
             buf_load<NB>(rb, o == kOff ? kOff : o * B, bring[u]);
         }
     }
+    // ZG: at step jj (the steps are visited in order, kDepth at a time),
+    // whether this lane's group is marked; every 32 steps the next batch of
+    // bits is loaded
+    auto zstep = [&](uint32_t jj, uint32_t zm) __attribute__((always_inline)) {
+        if (jj == zJ + 32) {
+            zJ += 32;
+#pragma unroll
+            for (int k = 0; k < B; k++)
+                if ((zm >> k) & 1) zload(k, zJ);
+        }
+    };
+    auto zflag = [&](int k, uint32_t jj) __attribute__((always_inline)) {
+        const uint32_t sidx = uni(jj - zJ);
+        const uint32_t lo = __builtin_amdgcn_readlane(zwin[k], sidx);
+        const uint32_t hi = __builtin_amdgcn_readlane(zwin[k], sidx + 32);
+        return (((lane < 32 ? lo : hi) >> (lane & 31)) & 1u) != 0;
+    };
+    uint32_t zm_all = 0;
+#pragma unroll
+    for (int k = 0; k < B; k++) zm_all |= uint32_t((ZGK && mode[k] == kModeZg)) << k;
     // fast path: all 64 lanes have full groups j0 .. j0+kDepth-1 and every
-    // stream is Huffman or raw.  HM is the set of Huffman streams, or -1 for
-    // a set without its own copy of the loop, tested per stream at run time.
-    auto fast = [&](auto hm_const) {
+    // stream is Huffman, ZG or raw.  HM is the set of Huffman and ZG streams
+    // and ZM that of the ZG ones, or -1 for sets without their own copy of
+    // the loop, tested per stream at run time.
+    auto fast = [&](auto hm_const, auto zm_const) __attribute__((always_inline)) {
         constexpr int HM = decltype(hm_const)::value;
+        constexpr int ZM = decltype(zm_const)::value;
         for (uint32_t j0 = 0; j0 < n_fast; j0 += kDepth) {
 #pragma unroll
             for (int u = 0; u < kDepth; u++) {
                 const uint32_t jj = j0 + u;
                 const uint32_t off = (w + jj * W) * G;
                 const uint32_t offn = raw_off(jj + kDepth);
+                if (ZM != 0 && u == 0) zstep(jj, ZM >= 0 ? uint32_t(ZM) : zm_all);
                 uint32_t pk[B][PW];
 #pragma unroll
                 for (int k = 0; k < B; k++) {
-                    const bool is_huf = HM >= 0 ? ((HM >> k) & 1) != 0 : mode[k] == kModeHuf;
+                    const bool is_huf = HM >= 0 ? ((HM >> k) & 1) != 0 : (mode[k] == kModeHuf || (ZGK && mode[k] == kModeZg));
+                    const bool is_zg = ZM >= 0 ? ((ZM >> k) & 1) != 0 : (ZGK && mode[k] == kModeZg);
                     if (!is_huf) {
 #pragma unroll
                         for (int x = 0; x < PW; x++) pk[k][x] = slot[k][u * PW + x];
                         buf_load<G>(rr[k], offn, &slot[k][u * PW]);
+                    } else if (is_zg) {
+                        const bool on = zflag(k, jj);
+#pragma unroll
+                        for (int x = 0; x < PW; x++) pk[k][x] = 0;
+#pragma unroll
+                        for (int pr = 0; pr < G / 2; pr++) {
+                            huf_take<B>(slot[k], cur[k], on, twoL);
+                            const uint32_t s0 = huf_get_if<B>(slot[k], lut[k], mask, on);
+                            const uint32_t s1 = huf_get_if<B>(slot[k], lut[k], mask, on);
+                            pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
+                            if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1) huf_refill<B>(slot[k], cur[k], lane);
+                        }
+#pragma unroll
+                        for (int x = 0; x < PW; x++) pk[k][x] = on ? pk[k][x] : rlev[k];
                     } else {
 #pragma unroll
                         for (int x = 0; x < PW; x++) pk[k][x] = 0;
@@ -507,15 +584,20 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
         bool other = false;
 #pragma unroll
         for (int k = 0; k < B; k++) {
-            hm |= uint32_t(mode[k] == kModeHuf) << k;
+            hm |= uint32_t(mode[k] == kModeHuf || (ZGK && mode[k] == kModeZg)) << k;
             other |= mode[k] == kModeRle;
         }
+        const uint32_t zm = zm_all;
         using std::integral_constant;
+        using I = int;
         if (other) n_fast = 0;   // chunks with a single-valued stream take the general path
-        else if (hm == 1) fast(integral_constant<int, 1>{});
-        else if (hm == 0) fast(integral_constant<int, 0>{});
-        else if (B >= 2 && hm == 3) fast(integral_constant<int, B >= 2 ? 3 : -1>{});
-        else fast(integral_constant<int, -1>{});
+        else if (zm == 0 && hm == 1) fast(integral_constant<I, 1>{}, integral_constant<I, 0>{});
+        else if (zm == 0 && hm == 0) fast(integral_constant<I, 0>{}, integral_constant<I, 0>{});
+        else if (zm == 0 && B >= 2 && hm == 3) fast(integral_constant<I, B >= 2 ? 3 : -1>{}, integral_constant<I, 0>{});
+        else if (zm == 1 && hm == 1) fast(integral_constant<I, 1>{}, integral_constant<I, 1>{});
+        else if (B >= 2 && zm == 3 && hm == 3)
+            fast(integral_constant<I, B >= 2 ? 3 : -1>{}, integral_constant<I, B >= 2 ? 3 : -1>{});
+        else fast(integral_constant<I, -1>{}, integral_constant<I, -1>{});
     }
     // general path: the remaining groups, with per-lane conditions
     for (uint32_t j0 = n_fast; j0 < ng_max; j0 += kDepth) {
@@ -527,11 +609,19 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
             const bool full = jj < nfull;
             const uint32_t gcnt = full ? G : (has ? rem : 0);
             const uint32_t offn = raw_off(jj + kDepth);
+            if (zm_all && u == 0) zstep(jj, zm_all);
             uint32_t pk[B][PW];
 #pragma unroll
             for (int k = 0; k < B; k++) {
 #pragma unroll
                 for (int x = 0; x < PW; x++) pk[k][x] = 0;
+                // a ZG group made of z alone takes no part in the rounds.  The
+                // flag is read with every lane active (a branch on `has` could
+                // reload the window for some lanes only, and v_readlane would
+                // then read a lane that was not loaded).
+                const bool zg = ZGK && mode[k] == kModeZg;
+                const bool flag = zg ? zflag(k, jj) : true;
+                const bool on = !zg || (has & flag);
                 if (mode[k] == kModeRaw) {
 #pragma unroll
                     for (int x = 0; x < PW; x++) pk[k][x] = slot[k][u * PW + x];
@@ -542,7 +632,7 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
                 } else {
 #pragma unroll
                     for (int pr = 0; pr < G / 2; pr++) {
-                        const bool part = 2u * pr < gcnt;
+                        const bool part = on && 2u * pr < gcnt;
                         huf_take<B>(slot[k], cur[k], part, twoL);
                         if (part) {
                             pk[k][(2 * pr) >> 2] |= huf_get<B>(slot[k], lut[k], mask) << (8 * ((2 * pr) & 3));
@@ -550,6 +640,10 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
                                 pk[k][(2 * pr + 1) >> 2] |= huf_get<B>(slot[k], lut[k], mask) << (8 * ((2 * pr + 1) & 3));
                         }
                         if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1) huf_refill<B>(slot[k], cur[k], lane);
+                    }
+                    if (!on) {
+#pragma unroll
+                        for (int x = 0; x < PW; x++) pk[k][x] = rlev[k];
                     }
                 }
             }
@@ -587,7 +681,8 @@ __device__ void decode_lane_group(const uint8_t* __restrict__ src, const ItemSta
     }
 #pragma unroll
     for (int k = 0; k < B; k++)
-        if (mode[k] == kModeHuf && cur[k].ptr != nw[k] && lane == 0) set_status(status, ZIPNN_E_CORRUPT);
+        if ((mode[k] == kModeHuf || (ZGK && mode[k] == kModeZg)) && cur[k].ptr != nw[k] && lane == 0)
+            set_status(status, ZIPNN_E_CORRUPT);
 }
 
 // Parse one tensor's header on the device and size its work.
@@ -627,8 +722,8 @@ __device__ bool load_tensor(const DecDesc& d, int di, TensorState& ts, int* stat
 // One item: the B map entries are checked, each Huffman table becomes an LDS
 // lookup table, the lane groups' word counts are checked and prefixed, then
 // every wave decodes its lane group.
-template <int B, int G, bool DELTA>
-__device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c, uint32_t slice, uint32_t* wring,
+template <int B, int G, bool DELTA, bool ZGK>
+__device__ __attribute__((always_inline)) void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c, uint32_t slice, uint32_t* wring,
                             uint16_t (*lut)[kLutSize], uint32_t (*wprefix)[65], LutTmp& T, ItemState& st,
                             int* status)
 {
@@ -646,10 +741,13 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
         const uint32_t bytes = ent.z;
         const uint32_t mode = ent.w & 0xFF, rle = (ent.w >> 8) & 0xFF;
         int err = 0;
-        if ((ent.w >> 16) != 0 || mode > 2) err = 1;
+        if ((ent.w >> 16) != 0 || mode > 3) err = 1;
         if (mode == kModeRaw && (bytes != m || rle)) err = 1;
         if (mode == kModeRle && bytes != 0) err = 1;
         if (mode == kModeHuf && (bytes < huf_head(W) + 4 || ((bytes - huf_head(W)) & 3) || rle)) err = 1;
+        if (mode == kModeZg && (!ZGK || !(h.flags & kFlagZg) || bytes < huf_head(W) + zg_bitmap(m, h.g) ||
+                                ((bytes - huf_head(W)) & 3)))
+            err = 1;
         if (off & (kPayAlign - 1)) err = 1;
         // the exact placement: this entry starts where its predecessor ends
         uint64_t expect = 0;
@@ -673,8 +771,10 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
     __syncthreads();
     if (st.err) return;
     for (int k = 0; k < B; k++) {
-        if (st.mode[k] != kModeHuf) continue;
+        const bool zg = st.mode[k] == kModeZg;
+        if (st.mode[k] != kModeHuf && !zg) continue;
         const uint8_t* p = d.src + st.pay[k];
+        const uint32_t bm = zg ? zg_bitmap(m, h.g) : 0u;
         if (!build_lut(p, h.L, lut[k], T)) {
             if (t == 0) {
                 st.err = 1;
@@ -684,17 +784,23 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
             return;
         }
         // word counts of the lane groups -> start of each lane group's words;
-        // every lane takes at least one word, and together they use the
-        // payload exactly
+        // in HUF every lane takes at least one word; together they use the
+        // payload exactly.  A ZG bitmap has no bit past the last group.
         if (t < 64) {
-            const uint32_t lanes_here = (uint32_t(t) < NG) ? min(64u, W - 64u * t) : 0u;
+            const uint32_t lanes_here = (uint32_t(t) < NG && !zg) ? min(64u, W - 64u * t) : 0u;
             const uint32_t nw = (uint32_t(t) < NG) ? ((const uint32_t*)(p + 128))[t] : 0u;
             const uint32_t inc = wave_incl_scan(nw);
             wprefix[k][t + 1] = inc;
             if (t == 0) wprefix[k][0] = 0;
-            const bool bad = nw < lanes_here;
+            bool bad = nw < lanes_here;
+            const uint32_t Gtot = (m + h.g - 1) / h.g;
+            for (uint32_t i = Gtot / 8 + t; i < bm; i += 64) {
+                uint32_t v = p[huf_head(W) + i];
+                if (i == Gtot / 8) v &= ~((1u << (Gtot & 7)) - 1u);
+                bad |= v != 0;
+            }
             const uint32_t total = __shfl(inc, 63, 64);
-            if (__ballot(bad) != 0ull || uint64_t(total) * 4 + huf_head(W) != st.bytes[k]) {
+            if (__ballot(bad) != 0ull || uint64_t(total) * 4 + huf_head(W) + bm != st.bytes[k]) {
                 if (t == 0) {
                     st.err = 1;
                     set_status(status, ZIPNN_E_CORRUPT);
@@ -708,20 +814,21 @@ __device__ void decode_item(const DecDesc& d, const TensorState& ts, uint32_t c,
     if (j < NG) {
         uint8_t* out = d.dst + uint64_t(c) * h.E * B;
         const uint8_t* base = DELTA ? d.base + uint64_t(c) * h.E * B : nullptr;
-        decode_lane_group<B, G, DELTA>(d.src, st, wring, lut, wprefix, h.L, j, W, m, out, base, status);
+        decode_lane_group<B, G, DELTA, ZGK>(d.src, st, wring, lut, wprefix, h.L, j, W, m, out, base, status);
     }
     __syncthreads();
 }
 
 // `descs` == nullptr: decode the single tensor `one`; otherwise the batch
 // descs[0..n_desc) whose per-tensor item counts k_plan prefixed.  Every tensor
-// of a launch has B-byte words, groups of G and (for DELTA) an XOR base; a
-// header that disagrees is reported as ZIPNN_E_FORMAT.
+// of a launch has B-byte words, groups of G, (for DELTA) an XOR base and (for
+// ZGK) the header's ZG flag; a header that disagrees is reported as
+// ZIPNN_E_FORMAT.
 // Four waves per SIMD (at most 128 VGPRs) keep enough lanes in flight to
 // hide LDS and memory latency; the widest words with the largest groups get
 // the registers of two waves instead of spilling (16-byte groups with an
 // XOR base count as wide).
-template <int B, int G, bool DELTA>
+template <int B, int G, bool DELTA, bool ZGK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B * G >= (DELTA ? 16 : 32) ? 2 : 4, 8))) void k_decode(DecDesc one, const DecDesc* __restrict__ descs, int n_desc,
                                                    const uint64_t* __restrict__ item_prefix, int* status)
 {
@@ -738,7 +845,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B * G >=
         item_prefix = nullptr;
     }
     auto matches = [&](const TensorState& x) {
-        return x.h.B == uint32_t(B) && x.h.g == uint32_t(G) && ((x.h.flags & kFlagDelta) != 0) == DELTA;
+        return x.h.B == uint32_t(B) && x.h.g == uint32_t(G) && ((x.h.flags & kFlagDelta) != 0) == DELTA &&
+               ((x.h.flags & kFlagZg) != 0) == ZGK;
     };
     if (threadIdx.x == 0) {
         ts.desc = -1;
@@ -780,16 +888,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B * G >=
             slice = uint32_t(local - full_items);
         }
         const DecDesc& d = descs[ts.desc];
-        decode_item<B, G, DELTA>(d, ts, c, slice, wring, lut, wprefix, T, st, d.status ? d.status : status);
+        decode_item<B, G, DELTA, ZGK>(d, ts, c, slice, wring, lut, wprefix, T, st, d.status ? d.status : status);
     }
 }
 
 // Batched plan: items per tensor -> exclusive prefix (one workgroup).  A
 // tensor whose header is invalid or does not match (B, G, DELTA) gets no
 // items and is reported.
-__global__ __launch_bounds__(kBlock) void k_plan(const DecDesc* __restrict__ descs, int n_desc, uint32_t B,
-                                                 uint32_t G, uint32_t delta, uint64_t* __restrict__ prefix,
-                                                 int* status)
+__global__ __launch_bounds__(kBlock) void k_plan(const DecDesc* __restrict__ descs, int n_desc, DecClass k,
+                                                 uint64_t* __restrict__ prefix, int* status)
 {
     __shared__ TensorState tsv[kBlock];
     __shared__ uint64_t carry;
@@ -799,7 +906,8 @@ __global__ __launch_bounds__(kBlock) void k_plan(const DecDesc* __restrict__ des
         const int i = b0 + threadIdx.x;
         if (i < n_desc && load_tensor(descs[i], i, tsv[threadIdx.x], status, true)) {
             const Header& h = tsv[threadIdx.x].h;
-            if (h.B != B || h.g != G || ((h.flags & kFlagDelta) != 0) != (delta != 0)) {
+            const DecClass x = dec_class(h);
+            if (x.B != k.B || x.G != k.G || x.delta != k.delta || x.zg != k.zg) {
                 tsv[threadIdx.x].valid = 0;
                 set_status(status, ZIPNN_E_FORMAT);
             }
@@ -829,21 +937,25 @@ __global__ void k_gather_headers(const uint8_t* __restrict__ arena, const uint64
     out[i] = *(const uint4*)(arena + offs[i >> 2] + 16 * (i & 3));
 }
 
-template <int B, int G, bool D>
+template <int B, int G, bool D, bool Z>
 hipError_t launch_k(const DecDesc& one, const DecDesc* descs, int n, const uint64_t* prefix, int* st, int grid,
                     hipStream_t s)
 {
-    k_decode<B, G, D><<<grid, kBlock, 0, s>>>(one, descs, n, prefix, st);
+    k_decode<B, G, D, Z><<<grid, kBlock, 0, s>>>(one, descs, n, prefix, st);
     return hipGetLastError();
 }
 
-hipError_t dispatch(uint32_t B, uint32_t G, bool delta, const DecDesc& one, const DecDesc* descs, int n,
-                    const uint64_t* prefix, int* st, int grid, hipStream_t s)
+hipError_t dispatch(const DecClass& k, const DecDesc& one, const DecDesc* descs, int n, const uint64_t* prefix,
+                    int* st, int grid, hipStream_t s)
 {
-#define ZIPNN_K(BB, GG)                                                                              \
-    if (B == BB && G == GG)                                                                         \
-        return delta ? launch_k<BB, GG, true>(one, descs, n, prefix, st, grid, s)                   \
-                     : launch_k<BB, GG, false>(one, descs, n, prefix, st, grid, s);
+#define ZIPNN_K(BB, GG)                                                                                       \
+    if (k.B == BB && k.G == GG) {                                                                            \
+        if (k.zg)                                                                                            \
+            return k.delta ? launch_k<BB, GG, true, true>(one, descs, n, prefix, st, grid, s)                \
+                           : launch_k<BB, GG, false, true>(one, descs, n, prefix, st, grid, s);              \
+        return k.delta ? launch_k<BB, GG, true, false>(one, descs, n, prefix, st, grid, s)                   \
+                       : launch_k<BB, GG, false, false>(one, descs, n, prefix, st, grid, s);                 \
+    }
     ZIPNN_K(1, 2) ZIPNN_K(1, 4) ZIPNN_K(1, 8)
     ZIPNN_K(2, 2) ZIPNN_K(2, 4) ZIPNN_K(2, 8)
     ZIPNN_K(4, 2) ZIPNN_K(4, 4) ZIPNN_K(4, 8)
@@ -858,7 +970,7 @@ int decode_grid_size(int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 1024;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode<2, 4, false>, kBlock, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode<2, 4, false, false>, kBlock, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 4;
     return prop.multiProcessorCount * per_cu;
@@ -866,24 +978,24 @@ int decode_grid_size(int device)
 
 hipError_t launch_decode_one(const Header& h, const DecDesc& one, int* d_status, int grid, hipStream_t s)
 {
-    return dispatch(h.B, h.g, (h.flags & kFlagDelta) != 0, one, nullptr, 1, nullptr, d_status, grid, s);
+    return dispatch(dec_class(h), one, nullptr, 1, nullptr, d_status, grid, s);
 }
 
-hipError_t launch_decode_batch(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
-                               uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s)
+hipError_t launch_decode_batch(const DecClass& k, const DecDesc* d_descs, int n_desc, uint64_t* d_item_prefix,
+                               int* d_status, int grid, hipStream_t s)
 {
-    k_plan<<<1, kBlock, 0, s>>>(d_descs, n_desc, B, G, delta ? 1u : 0u, d_item_prefix, d_status);
+    k_plan<<<1, kBlock, 0, s>>>(d_descs, n_desc, k, d_item_prefix, d_status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     DecDesc none = {};
-    return dispatch(B, G, delta, none, d_descs, n_desc, d_item_prefix, d_status, grid, s);
+    return dispatch(k, none, d_descs, n_desc, d_item_prefix, d_status, grid, s);
 }
 
-hipError_t launch_decode_planned(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
+hipError_t launch_decode_planned(const DecClass& k, const DecDesc* d_descs, int n_desc,
                                  const uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s)
 {
     DecDesc none = {};
-    return dispatch(B, G, delta, none, d_descs, n_desc, d_item_prefix, d_status, grid, s);
+    return dispatch(k, none, d_descs, n_desc, d_item_prefix, d_status, grid, s);
 }
 
 hipError_t launch_gather_headers(const uint8_t* arena, const uint64_t* d_offs, int n, void* d_out, hipStream_t s)

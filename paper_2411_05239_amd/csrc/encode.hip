@@ -11,9 +11,10 @@
 //              lock-step word requests lane group by lane group, which gives
 //              the exact payload size, so AUTO keeps Huffman only when it is
 //              strictly smaller than raw (paper §III-B, §V-A).
-//   k_place    one workgroup per tensor: exclusive scan of the 16-byte aligned
+//   k_place    one workgroup per tensor: exclusive scan of the 128-byte aligned
 //              payload sizes in chunk-major order -> map entries and header
-//              (the map that enables parallel decode, paper §V-A).
+//              (the map that enables parallel decode, paper §V-A), and whether
+//              the map holds ZG entries (a header flag).
 //   k_pack     one workgroup per chunk: raw groups are copied with 16-byte
 //              stores; for a Huffman group, wave v writes lane groups v, v+4,
 //              ...: its lanes replay the same rounds, and in every round the
@@ -38,13 +39,12 @@ struct PmWave {                 // package-merge workspace of one wave
     uint16_t pos[kMaxL][256];   // position of leaf i in the list of each level
     alignas(16) uint32_t key[256];
     uint8_t len[256];           // code length per symbol
-    uint32_t cnt[16];
-    uint32_t cand;              // 1: Huffman candidate (size decided by the replay)
 };
 
 union AnalyzeLds {
-    uint32_t hist[kWaves][4][256];   // per-wave sub-histograms (phase 1)
-    PmWave pm[kWaves];               // per-wave code construction (phases 2, 3)
+    uint32_t hist[kWaves][4][256];   // per-wave sub-histograms (counting passes)
+    PmWave pm[kWaves];               // per-wave code construction
+    uint32_t lgw[2][4][64];          // words per lane group: HUF, ZG (replay)
 };
 
 __device__ inline uint32_t wave_sum(uint32_t v)
@@ -76,8 +76,11 @@ __device__ inline uint32_t count_le(const uint32_t* a, uint32_t n, uint32_t x)
     return lo;
 }
 
-// Build the code of one byte group with one wave.  f[] is the histogram.
-// Writes codes[256] (canonical code | length << 16) and the entry.
+// Optimal code lengths <= L for the histogram held in registers (fv[r] =
+// f[lane + 64 r], at least two symbols with f > 0, `tot` = sum of f) into
+// P.len, by one wave.  With `shortcut` (policy AUTO) it returns false as soon
+// as a lower bound of the payload (`head` bytes + the coded bits) shows that
+// it cannot be smaller than `raw` bytes; the lengths are then not built.
 //
 // Package-merge with lists made of leaves and packages: list 0 = the leaves
 // sorted by (f, symbol); list d = the leaves merged with the packages of
@@ -88,63 +91,27 @@ __device__ inline uint32_t count_le(const uint32_t* a, uint32_t n, uint32_t x)
 // first m items of a list select the first 2*(their count) items of the list
 // below; leaf i is selected at a level iff i < (leaves among the selected
 // items), so its length is the number of such levels.
-__device__ void build_code(const uint32_t* f, uint32_t m, uint32_t W, uint32_t L, int policy, PmWave& P,
-                           CodeWord* codes, EncEntry* entry)
+__device__ bool build_lengths(const uint32_t* fv, uint32_t tot, uint32_t raw, uint32_t head, uint32_t L,
+                              bool shortcut, PmWave& P)
 {
     const int lane = threadIdx.x & 63;
-    uint32_t fv[4];
     uint32_t d = 0;
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-        fv[r] = f[lane + 64 * r];
-        d += __popcll(__ballot(fv[r] > 0));
-    }
-    for (int r = 0; r < 4; r++) codes[lane + 64 * r] = 0;
-    if (lane == 0) P.cand = 0;
-    if (policy == ZIPNN_RAW || d <= 1) {
-        if (lane == 0) {
-            EncEntry e;
-            e.pad = 0;
-            if (policy != ZIPNN_RAW && d == 1) {
-                uint32_t v = 0;
-                for (int s = 0; s < 256; s++)
-                    if (f[s]) v = s;
-                e.mode = kModeRle;
-                e.rle = uint8_t(v);
-                e.bytes = 0;
-            } else {
-                e.mode = kModeRaw;
-                e.rle = 0;
-                e.bytes = m;
-            }
-            *entry = e;
-        }
-        return;
-    }
-    if (policy == ZIPNN_AUTO) {
-        // Any prefix code spends at least the empirical entropy, sum f log2(m/f)
+    for (int r = 0; r < 4; r++) d += __popcll(__ballot(fv[r] > 0));
+    if (shortcut) {
+        // Any prefix code spends at least the empirical entropy, sum f log2(tot/f)
         // bits.  If even that bound gives a payload no smaller than the raw
-        // bytes, AUTO stores the stream raw, and the code need not be built
-        // (the decision is the one the exact size would give).
+        // bytes, AUTO cannot keep this code (the decision is the one the exact
+        // size would give), and it need not be built.
         double h = 0.0;
 #pragma unroll
         for (int r = 0; r < 4; r++)
-            if (fv[r]) h += double(fv[r]) * (log2(double(m)) - log2(double(fv[r])));
+            if (fv[r]) h += double(fv[r]) * (log2(double(tot)) - log2(double(fv[r])));
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
         const double lb = h * (1.0 - 1e-12) - 1.0;   // margin for the rounding of the sum
         const uint64_t words_lb = lb > 0.0 ? uint64_t(ceil(lb / 32.0)) : 0u;
-        if (uint64_t(huf_head(W)) + 4 * words_lb >= m) {
-            if (lane == 0) {
-                EncEntry e;
-                e.pad = 0;
-                e.mode = kModeRaw;
-                e.rle = 0;
-                e.bytes = m;
-                *entry = e;
-            }
-            return;
-        }
+        if (uint64_t(head) + 4 * words_lb >= raw) return false;
     }
     // sort the leaves by key = f << 8 | symbol (f < 2^24 since m <= 2^22)
 #pragma unroll
@@ -226,54 +193,37 @@ __device__ void build_code(const uint32_t* f, uint32_t m, uint32_t W, uint32_t L
         }
     }
     T = wave_sum(T);
-    // a Huffman payload holds at least its head and ceil(T/8) bytes: if even
-    // that is not below raw, AUTO stores the group raw
-    if (policy == ZIPNN_AUTO && huf_head(W) + (T + 7) / 8 >= m) {
-        if (lane == 0) {
-            EncEntry e;
-            e.pad = 0;
-            e.mode = kModeRaw;
-            e.rle = 0;
-            e.bytes = m;
-            *entry = e;
-        }
-        return;
-    }
     __builtin_amdgcn_wave_barrier();
-    // canonical codes: first code of each length, then rank within a length
-    // in increasing symbol order
+    // the payload holds at least its head and ceil(T/8) bytes
+    return !(shortcut && head + (T + 7) / 8 >= raw);
+}
+
+// Canonical codes (RFC 1951 §3.2.2) of the lengths len[256], by one wave:
+// codes[s] = code | length << 16 (0 for absent symbols).  The first code of
+// each length follows from the counts of the shorter ones; within a length
+// the codes follow the symbol order.
+__device__ void canonical_codes(const uint8_t* len, uint32_t L, CodeWord* codes)
+{
+    const int lane = threadIdx.x & 63;
     uint32_t l4[4];
 #pragma unroll
-    for (int r = 0; r < 4; r++) l4[r] = P.len[lane + 64 * r];
-    if (lane < 16) P.cnt[lane] = 0;
-    __builtin_amdgcn_wave_barrier();
+    for (int r = 0; r < 4; r++) l4[r] = len[lane + 64 * r];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t rank4[4] = {0, 0, 0, 0};
-    for (uint32_t len = 1; len <= L; len++) {
+    uint32_t code4[4] = {0, 0, 0, 0};
+    uint32_t first = 0, prev = 0;
+    for (uint32_t l = 1; l <= L; l++) {
+        first = (first + prev) << 1;
         uint32_t run = 0;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            uint64_t msk = __ballot(l4[r] == len);
-            if (l4[r] == len) rank4[r] = run + __popcll(msk & lt_mask);
+            const uint64_t msk = __ballot(l4[r] == l);
+            if (l4[r] == l) code4[r] = first + run + __popcll(msk & lt_mask);
             run += __popcll(msk);
         }
-        if (lane == 0) P.cnt[len] = run;
-    }
-    __builtin_amdgcn_wave_barrier();
-    {
-        uint32_t code = 0, prev = 0;
-        for (uint32_t len = 1; len <= L; len++) {
-            code = (code + prev) << 1;
-            prev = P.cnt[len];
-#pragma unroll
-            for (int r = 0; r < 4; r++)
-                if (l4[r] == len) rank4[r] += code;
-        }
+        prev = run;
     }
 #pragma unroll
-    for (int r = 0; r < 4; r++) codes[lane + 64 * r] = l4[r] ? (rank4[r] | (l4[r] << 16)) : 0u;
-    // Huffman candidate: the exact size comes from the request replay
-    if (lane == 0) P.cand = 1;
+    for (int r = 0; r < 4; r++) codes[lane + 64 * r] = l4[r] ? (code4[r] | (l4[r] << 16)) : 0u;
 }
 
 __device__ inline int find_desc(const uint32_t* prefix, int n_desc, uint32_t g)
@@ -351,26 +301,78 @@ __device__ inline uint32_t sym_of(const uint32_t* wd, int k, int i)
     return (wd[jb >> 2] >> (8 * (jb & 3))) & 0xFFu;
 }
 
-// Replay the decoder's word requests for lane group j of one chunk and count
-// the words each Huffman candidate stream takes (returned per stream by lane
-// 0 of the wave).
+// Whether a group of gcnt symbols of stream k holds a value other than z.
 template <int B, int G>
-__device__ void count_lane_group(const uint8_t* src, const uint8_t* base, const uint32_t* candmask_p,
-                                 const uint8_t (*lens)[256], uint32_t L, uint32_t j, uint32_t W, uint32_t m,
-                                 uint32_t* words_out)
+__device__ inline bool marked(const uint32_t* wd, int k, uint32_t gcnt, uint32_t z)
+{
+    bool mk = false;
+#pragma unroll
+    for (int i = 0; i < G; i++) mk |= uint32_t(i) < gcnt && sym_of<B>(wd, k, i) != z;
+    return mk;
+}
+
+// Histograms of the ZG candidates (bit k of zc, fill value z[k]) over the
+// groups that hold a value other than z: h[k][s] of this wave, except the
+// count of z itself, which is returned per stream (summed over the wave).
+template <int B, int G>
+__device__ void zg_count(const uint8_t* src, const uint8_t* base, uint32_t zc, const uint32_t* z, uint32_t m,
+                         uint32_t (*h)[256], uint32_t* zcount)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
-    const uint32_t cand = *candmask_p;
+    constexpr uint32_t CB = 4;   // groups in flight per thread
+    const uint32_t Gtot = (m + G - 1) / G;
+    uint32_t nz[B];
+#pragma unroll
+    for (int k = 0; k < B; k++) nz[k] = 0;
+    for (uint32_t q0 = threadIdx.x; q0 < Gtot; q0 += CB * kBlock) {
+        uint32_t wds[CB][NW];
+#pragma unroll
+        for (uint32_t u = 0; u < CB; u++)
+            if (q0 + u * kBlock < Gtot) group_words<B, G>(src, base, q0 + u * kBlock, m, wds[u]);
+#pragma unroll
+        for (uint32_t u = 0; u < CB; u++) {
+            const uint32_t q = q0 + u * kBlock;
+            if (q >= Gtot) continue;
+            const uint32_t gcnt = min(uint32_t(G), m - q * G);
+#pragma unroll
+            for (int k = 0; k < B; k++) {
+                if (!((zc >> k) & 1) || !marked<B, G>(wds[u], k, gcnt, z[k])) continue;
+#pragma unroll
+                for (int i = 0; i < G; i++) {
+                    if (uint32_t(i) >= gcnt) continue;
+                    const uint32_t v = sym_of<B>(wds[u], k, i);
+                    if (v == z[k]) nz[k]++;
+                    else atomicAdd(&h[k][v], 1u);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < B; k++) zcount[k] = wave_sum(nz[k]);
+}
+
+// Replay the decoder's word requests for lane group j of one chunk and count
+// the words each candidate takes: HUF candidates (bit k of hc, lengths
+// lens[k]) over every group, ZG candidates (bit k of zgc, lengths lens2[k],
+// fill value z[k]) over the groups holding another value.  Lane 0 of the
+// wave writes the counts to lgw[0][k][j] and lgw[1][k][j].
+template <int B, int G>
+__device__ void count_lane_group(const uint8_t* src, const uint8_t* base, uint32_t hc, uint32_t zgc,
+                                 const uint8_t (*lens)[256], const uint8_t (*lens2)[256], const uint32_t* z,
+                                 uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t (*lgw)[4][64])
+{
+    constexpr int NB = B * G;
+    constexpr int NW = NB >= 4 ? NB / 4 : 1;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = 64 * j + lane;
     const int twoL = int(2 * L);
     const uint32_t Gtot = (m + G - 1) / G, Gfull = m / G, rem = m - Gfull * G;
     const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;
-    int cnt[B];
-    uint32_t req[B];
+    int cnt[2][B];
+    uint32_t req[2][B];
 #pragma unroll
-    for (int k = 0; k < B; k++) cnt[k] = 0, req[k] = 0;
+    for (int k = 0; k < B; k++) cnt[0][k] = cnt[1][k] = 0, req[0][k] = req[1][k] = 0;
     constexpr uint32_t CB = NW >= 8 ? 4 : 8;   // groups in flight per lane
     for (uint32_t j0 = 0; j0 < ng; j0 += CB) {
         uint32_t wds[CB][NW];
@@ -385,16 +387,21 @@ __device__ void count_lane_group(const uint8_t* src, const uint8_t* base, const 
             const uint32_t* wd = wds[u];
 #pragma unroll
             for (int k = 0; k < B; k++) {
-                if (!((cand >> k) & 1)) continue;
 #pragma unroll
-                for (int pr = 0; pr < G / 2; pr++) {
-                    if (2u * pr < gcnt) {
-                        if (cnt[k] < twoL) {
-                            cnt[k] += 32;
-                            req[k]++;
+                for (int v = 0; v < 2; v++) {
+                    if (!(((v ? zgc : hc) >> k) & 1)) continue;
+                    const uint8_t* ln = v ? lens2[k] : lens[k];
+                    const uint32_t gc = (v && !marked<B, G>(wd, k, gcnt, z[k])) ? 0u : gcnt;
+#pragma unroll
+                    for (int pr = 0; pr < G / 2; pr++) {
+                        if (2u * pr < gc) {
+                            if (cnt[v][k] < twoL) {
+                                cnt[v][k] += 32;
+                                req[v][k]++;
+                            }
+                            cnt[v][k] -= ln[sym_of<B>(wd, k, 2 * pr)];
+                            if (2u * pr + 1 < gc) cnt[v][k] -= ln[sym_of<B>(wd, k, 2 * pr + 1)];
                         }
-                        cnt[k] -= lens[k][sym_of<B>(wd, k, 2 * pr)];
-                        if (2u * pr + 1 < gcnt) cnt[k] -= lens[k][sym_of<B>(wd, k, 2 * pr + 1)];
                     }
                 }
             }
@@ -402,18 +409,39 @@ __device__ void count_lane_group(const uint8_t* src, const uint8_t* base, const 
     }
 #pragma unroll
     for (int k = 0; k < B; k++) {
-        const uint32_t tot = wave_sum(req[k]);
-        if (lane == 0) words_out[k] = tot;
+#pragma unroll
+        for (int v = 0; v < 2; v++) {
+            const uint32_t tot = wave_sum(req[v][k]);
+            if (lane == 0) lgw[v][k][j] = tot;
+        }
     }
 }
 
 struct AnalyzeTail {
-    uint8_t lens[4][256];
-    uint32_t cand;           // bit k: stream k is a Huffman candidate
-    uint32_t words[4];       // words over all lane groups, per stream
-    uint32_t lg_words[kWaves][4];
+    uint8_t lens[4][256];    // HUF code lengths
+    uint8_t lens2[4][256];   // ZG code lengths
+    uint32_t z[4];           // ZG fill value: the most frequent byte (smallest on ties)
+    uint32_t open;           // bit k: mode still to be decided (neither forced RAW nor RLE)
+    uint32_t hc;             // bit k: HUF candidate
+    uint32_t zc;             // bit k: ZG considered (histogram over marked groups needed)
+    uint32_t zgc;            // bit k: ZG candidate
+    uint32_t fin;            // bit k: ZG chosen (else HUF) for a coded stream
+    uint32_t coded;          // bit k: coded (HUF or ZG chosen)
+    uint32_t words[2][4];    // words over all lane groups, per stream: HUF, ZG
 };
 
+// One workgroup per chunk:
+//   1. histogram f of every byte group;
+//   2. wave k classifies group k: forced RAW, RLE (one value), else HUF
+//      lengths of f (unless ZG is forced) and, when ZG is forced or (AUTO)
+//      the most frequent value z fills half the group, a ZG candidate;
+//   3. for ZG candidates: histogram over the groups of g symbols that hold a
+//      value other than z, and ZG lengths of it;
+//   4. the four waves replay the decoder's word requests lane group by lane
+//      group for every candidate, which gives the exact sizes;
+//   5. the mode of each group (AUTO: the smallest of RAW, HUF, ZG, ties to
+//      RAW then HUF), its entry, its lane-group word counts and its canonical
+//      code table.
 template <int BB>
 __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
@@ -423,7 +451,8 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
     __shared__ AnalyzeLds S;
     __shared__ uint32_t hist[4][256];
     __shared__ AnalyzeTail A;
-    const int t = threadIdx.x, wv = t >> 6;
+    __shared__ uint32_t zsum[kWaves][4];
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
     constexpr uint32_t B = BB;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
         const int di = find_desc(chunk_prefix, n_desc, gc);
@@ -434,8 +463,10 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
         const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
         const uint32_t W = (m + p.S - 1) / p.S;
         const uint32_t NG = (W + 63) / 64;
+        const uint32_t head = huf_head(W), head_z = head + zg_bitmap(m, p.g);
         for (uint32_t i = t; i < kWaves * 4 * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
-        if (t < 4) A.words[t] = 0;
+        if (t == 0) A.open = A.hc = A.zc = A.zgc = A.fin = A.coded = 0;
+        if (t < 8) (&A.words[0][0])[t] = 0;
         __syncthreads();
         const uint8_t* src = d.src + e0 * B;
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
@@ -522,30 +553,114 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
             hist[k][s] = S.hist[0][k][s] + S.hist[1][k][s] + S.hist[2][k][s] + S.hist[3][k][s];
         }
         __syncthreads();
+        // 2. classification and HUF lengths, wave k for group k
         if (uint32_t(wv) < B) {
-            const uint64_t ei = uint64_t(gc) * B + wv;
-            build_code(hist[wv], m, W, p.L, p.policy[wv], S.pm[wv], codes + ei * 256, entries + ei);
+            const int k = wv;
+            const int policy = p.policy[k];
+            uint32_t fv[4], d = 0, best = 0, arg = 0;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                fv[r] = hist[k][lane + 64 * r];
+                d += __popcll(__ballot(fv[r] > 0));
+                // most frequent value, smallest on ties: key f << 8 | (255 - s)
+                const uint32_t key = (fv[r] << 8) | uint32_t(255 - (lane + 64 * r));
+                if (key > best) best = key;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) best = max(best, uint32_t(__shfl_xor(best, o, 64)));
+            arg = 255 - (best & 0xFFu);
+            const uint64_t ei = uint64_t(gc) * B + k;
+            if (policy == ZIPNN_RAW || d <= 1) {
+                if (lane == 0) {
+                    EncEntry e;
+                    e.pad = 0;
+                    const bool rle = policy != ZIPNN_RAW && d == 1;
+                    e.mode = rle ? kModeRle : kModeRaw;
+                    e.rle = rle ? uint8_t(arg) : 0;
+                    e.bytes = rle ? 0 : m;
+                    entries[ei] = e;
+                }
+            } else {
+                bool hc = false;
+                if (policy != ZIPNN_ZG) {
+                    hc = build_lengths(fv, m, m, head, p.L, policy == ZIPNN_AUTO, S.pm[k]);
+                    if (hc)
+#pragma unroll
+                        for (int r = 0; r < 4; r++) A.lens[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
+                }
+                const bool zc = policy == ZIPNN_ZG || (policy == ZIPNN_AUTO && 2 * (best >> 8) >= m);
+                if (lane == 0) {
+                    atomicOr(&A.open, 1u << k);
+                    if (hc) atomicOr(&A.hc, 1u << k);
+                    if (zc) atomicOr(&A.zc, 1u << k);
+                    A.z[k] = arg;
+                }
+            }
         }
         __syncthreads();
-        if (t == 0) {
-            uint32_t cm = 0;
-            for (uint32_t k = 0; k < B; k++) cm |= S.pm[k].cand << k;
-            A.cand = cm;
+        // 3. ZG: histogram over the marked groups, then lengths
+        if (A.zc) {
+            for (uint32_t i = t; i < kWaves * 4 * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
+            __syncthreads();
+            uint32_t zn[4] = {0, 0, 0, 0};
+            switch (p.g) {
+            case 2: zg_count<BB, 2>(src, base, A.zc, A.z, m, S.hist[wv], zn); break;
+            case 4: zg_count<BB, 4>(src, base, A.zc, A.z, m, S.hist[wv], zn); break;
+            default: zg_count<BB, 8>(src, base, A.zc, A.z, m, S.hist[wv], zn); break;
+            }
+            if (lane == 0)
+                for (uint32_t k = 0; k < B; k++) zsum[wv][k] = zn[k];
+            __syncthreads();
+            for (uint32_t i = t; i < 4 * 256; i += kBlock) {
+                const uint32_t k = i >> 8, s = i & 255;
+                uint32_t v = S.hist[0][k][s] + S.hist[1][k][s] + S.hist[2][k][s] + S.hist[3][k][s];
+                if (k < B && s == A.z[k]) v += zsum[0][k] + zsum[1][k] + zsum[2][k] + zsum[3][k];
+                S.hist[0][k][s] = v;
+            }
+            __syncthreads();
+            uint32_t fv[4] = {0, 0, 0, 0}, tot = 0, d2 = 0;
+            if (uint32_t(wv) < B) {
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    fv[r] = S.hist[0][wv][lane + 64 * r];
+                    tot += fv[r];
+                    d2 += __popcll(__ballot(fv[r] > 0));
+                }
+                tot = wave_sum(tot);
+            }
+            __syncthreads();   // the sums are read before the workspace is reused
+            if (uint32_t(wv) < B && ((A.zc >> wv) & 1)) {
+                const int k = wv;
+                const int policy = p.policy[k];
+                if (d2 >= 2) {
+                    const bool zgc = build_lengths(fv, tot, m, head_z, p.L, policy == ZIPNN_AUTO, S.pm[k]);
+                    if (zgc) {
+#pragma unroll
+                        for (int r = 0; r < 4; r++) A.lens2[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
+                        if (lane == 0) atomicOr(&A.zgc, 1u << k);
+                    }
+                } else if (policy == ZIPNN_ZG) {
+                    // the marked groups hold a single value: forced ZG falls back to HUF
+                    uint32_t f[4];
+#pragma unroll
+                    for (int r = 0; r < 4; r++) f[r] = hist[k][lane + 64 * r];
+                    build_lengths(f, m, m, head, p.L, false, S.pm[k]);
+#pragma unroll
+                    for (int r = 0; r < 4; r++) A.lens[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
+                    if (lane == 0) atomicOr(&A.hc, 1u << k);
+                }
+            }
+            __syncthreads();
         }
-        for (uint32_t i = t; i < 4 * 256; i += kBlock) {
-            const uint32_t k = i >> 8;
-            A.lens[k][i & 255] = k < B ? S.pm[k].len[i & 255] : 0;
-        }
-        __syncthreads();
-        if (A.cand) {
-            // replay the word requests, one lane group per wave
+        // 4. replay the word requests of every candidate, one lane group per wave
+        if (A.hc | A.zgc) {
             for (uint32_t j0 = 0; j0 < NG; j0 += kWaves) {
                 const uint32_t j = j0 + wv;
                 if (j < NG) {
                     switch (B * 16 + p.g) {
-#define ZIPNN_CASE(BB, GG)                                                                       \
-    case BB * 16 + GG:                                                                          \
-        count_lane_group<BB, GG>(src, base, &A.cand, A.lens, p.L, j, W, m, A.lg_words[wv]);     \
+#define ZIPNN_CASE(BX, GX)                                                                                   \
+    case BX * 16 + GX:                                                                                      \
+        count_lane_group<BX, GX>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw);        \
         break;
                         ZIPNN_CASE(1, 2)
                         ZIPNN_CASE(1, 4)
@@ -560,30 +675,46 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
                     default:
                         break;
                     }
-                    if ((t & 63) == 0) {
+                    if (lane == 0) {
                         for (uint32_t k = 0; k < B; k++) {
-                            if (!((A.cand >> k) & 1)) continue;
-                            nwords[(uint64_t(gc) * B + k) * 64 + j] = A.lg_words[wv][k];
-                            atomicAdd(&A.words[k], A.lg_words[wv][k]);
+                            if ((A.hc >> k) & 1) atomicAdd(&A.words[0][k], S.lgw[0][k][j]);
+                            if ((A.zgc >> k) & 1) atomicAdd(&A.words[1][k], S.lgw[1][k][j]);
                         }
                     }
                 }
             }
         }
         __syncthreads();
-        if (uint32_t(t) < B && ((A.cand >> t) & 1)) {
-            const uint32_t size = huf_head(W) + 4 * A.words[t];
+        // 5. the decision, the entry and the word counts of every open group
+        if (uint32_t(t) < B && ((A.open >> t) & 1)) {
+            const int policy = p.policy[t];
+            const bool hc = (A.hc >> t) & 1, zgc = (A.zgc >> t) & 1;
+            const uint32_t size_h = head + 4 * A.words[0][t], size_z = head_z + 4 * A.words[1][t];
+            int mode = kModeRaw;
+            uint32_t bytes = m;
+            if (policy == ZIPNN_AUTO) {
+                if (hc && size_h < bytes) mode = kModeHuf, bytes = size_h;
+                if (zgc && size_z < bytes) mode = kModeZg, bytes = size_z;
+            } else if (zgc) {
+                mode = kModeZg, bytes = size_z;
+            } else {
+                mode = kModeHuf, bytes = size_h;
+            }
             EncEntry e;
             e.pad = 0;
-            e.rle = 0;
-            if (p.policy[t] == ZIPNN_AUTO && size >= m) {
-                e.mode = kModeRaw;
-                e.bytes = m;
-            } else {
-                e.mode = kModeHuf;
-                e.bytes = size;
-            }
+            e.mode = uint8_t(mode);
+            e.rle = mode == kModeZg ? uint8_t(A.z[t]) : 0;
+            e.bytes = bytes;
             entries[uint64_t(gc) * B + t] = e;
+            if (mode != kModeRaw) atomicOr(&A.coded, 1u << t);
+            if (mode == kModeZg) atomicOr(&A.fin, 1u << t);
+        }
+        __syncthreads();
+        if (uint32_t(wv) < B && ((A.coded >> wv) & 1)) {
+            const uint64_t ei = uint64_t(gc) * B + wv;
+            const int v = (A.fin >> wv) & 1;
+            canonical_codes(v ? A.lens2[wv] : A.lens[wv], p.L, codes + ei * 256);
+            if (uint32_t(lane) < NG) nwords[ei * 64 + lane] = S.lgw[v][wv][lane];
         }
         __syncthreads();
     }
@@ -591,22 +722,24 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
 
 // One workgroup per tensor: offsets of its entries (16-byte aligned, in
 // chunk-major order) and the tensor's container size.
-__global__ __launch_bounds__(kBlock) void k_place(const EncDesc* __restrict__ descs, EncParams p,
+__global__ __launch_bounds__(kBlock) void k_place(EncDesc* __restrict__ descs, EncParams p,
                                                   const EncEntry* __restrict__ entries, uint64_t* __restrict__ offsets,
                                                   uint64_t* __restrict__ totals)
 {
     __shared__ uint64_t red[kWaves];
     __shared__ uint64_t carry;
+    __shared__ uint32_t zg;
     const EncDesc d = descs[blockIdx.x];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t B = p.B;
     const uint64_t ne = uint64_t(d.n_chunks) * B;
     const uint64_t e_first = uint64_t(d.chunk0) * B;
-    if (t == 0) carry = 0;
+    if (t == 0) carry = 0, zg = 0;
     __syncthreads();
     for (uint64_t b0 = 0; b0 < ne; b0 += kBlock) {
         const uint64_t e = b0 + t;
         const uint64_t sz = e < ne ? align_pay(entries[e_first + e].bytes) : 0;
+        if (e < ne && entries[e_first + e].mode == kModeZg) zg = 1;
         uint64_t inc = sz;
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
@@ -622,7 +755,10 @@ __global__ __launch_bounds__(kBlock) void k_place(const EncDesc* __restrict__ de
         if (t == kBlock - 1) carry = pre + inc;
         __syncthreads();
     }
-    if (t == 0) totals[blockIdx.x] = payload_base_of(d.n_chunks, B) + carry;
+    if (t == 0) {
+        totals[blockIdx.x] = payload_base_of(d.n_chunks, B) + carry;
+        descs[blockIdx.x].has_zg = zg;
+    }
 }
 
 // One workgroup: the tensors' containers are laid out back to back in the
@@ -681,7 +817,7 @@ __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, i
         h[3] = uint32_t(d.n >> 32);
         h[4] = p.chunk;
         h[5] = p.S | (p.g << 16) | (p.L << 24);
-        h[6] = d.base ? kFlagDelta : 0u;
+        h[6] = (d.base ? kFlagDelta : 0u) | (d.has_zg ? kFlagZg : 0u);
         h[7] = d.n_chunks;
         h[8] = uint32_t(total);
         h[9] = uint32_t(total >> 32);
@@ -707,6 +843,16 @@ __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, i
 // decoder takes a word it holds fewer than 2L bits, so it asks for at most
 // 2L - 1 + 32 <= 53 bits past what it has consumed; the encoder is at least
 // LG*G + 2 >= 58 symbols (of >= 1 bit) ahead, so the word is always complete.
+//
+// In ZG (template ZG, fill value z) only the groups holding another value are
+// coded and take part; an unmarked group leaves a zero in the length ring.
+// The encoder may then be fewer than 58 coded symbols ahead, so a word the
+// decoder takes may not be finished: the taker records its slot, and the
+// encoder stores the word there when it finishes it (or a zero once the
+// lane's codes are used up).  When the decoder takes a word, the encoder has
+// coded at least the current group, so at most the two words after the
+// finished ones can be waiting (32x < consumed + 2L <= coded + 22 gives
+// x <= finished + 1): one slot per word parity.
 template <int G>
 struct PackShape {
     static constexpr uint32_t LG = (56 + G - 1) / G;                            // lead in groups
@@ -717,8 +863,8 @@ struct PackShape {
 constexpr uint32_t kPackQ = 32;
 constexpr uint32_t kPackLenBytes = 32 * 64;   // per wave: LR * 64 lanes * LB = 32 * 64 bytes for every g
 
-template <int B, int G>
-__device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode,
+template <int B, int G, bool ZG>
+__device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode, uint32_t z,
                                 uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out, uint32_t* qring,
                                 uint8_t* lring)
 {
@@ -736,26 +882,36 @@ __device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, 
     uint64_t eb = 0;   // encoder: bits not yet in a queued word
     uint32_t en = 0;
     uint32_t qt = 0;   // words queued
+    uint32_t qh = 0;   // words taken
+    uint32_t pslot[2] = {0, 0};   // ZG: slots of taken words not yet finished, by word parity
+    bool done = ng == 0;          // ZG: every group of the lane encoded
+    auto finish = [&](uint32_t word) {
+        qring[(qt & (Q - 1)) * 64 + lane] = word;
+        if (ZG && qt < qh) out[pslot[qt & 1]] = word;
+        qt++;
+    };
     auto load = [&](uint32_t e, uint32_t* wd) {
         if (e < ng) group_words<B, G>(src, base, w + e * W, m, wd);
     };
     auto encode = [&](uint32_t e, const uint32_t* wd) {
         if (e >= ng) return;
         const uint32_t ecnt = w + e * W < Gfull ? G : rem;
+        const bool mk = !ZG || marked<B, G>(wd, k, ecnt, z);
         uint32_t lens = 0;
+        if (mk) {
 #pragma unroll
-        for (int i = 0; i < G; i++) {
-            if (uint32_t(i) < ecnt) {
-                const uint32_t cw = rcode[sym_of<B>(wd, k, i)];
-                const uint32_t l = cw >> 16;
-                eb |= uint64_t(cw & 0xFFFFu) << en;
-                en += l;
-                lens |= l << (4 * i);
-                if (en >= 32) {
-                    qring[(qt & (Q - 1)) * 64 + lane] = uint32_t(eb);
-                    qt++;
-                    eb >>= 32;
-                    en -= 32;
+            for (int i = 0; i < G; i++) {
+                if (uint32_t(i) < ecnt) {
+                    const uint32_t cw = rcode[sym_of<B>(wd, k, i)];
+                    const uint32_t l = cw >> 16;
+                    eb |= uint64_t(cw & 0xFFFFu) << en;
+                    en += l;
+                    lens |= l << (4 * i);
+                    if (en >= 32) {
+                        finish(uint32_t(eb));
+                        eb >>= 32;
+                        en -= 32;
+                    }
                 }
             }
         }
@@ -763,11 +919,17 @@ __device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, 
         if constexpr (LB == 1) *lp = uint8_t(lens);
         else if constexpr (LB == 2) *reinterpret_cast<uint16_t*>(lp) = uint16_t(lens);
         else *reinterpret_cast<uint32_t*>(lp) = lens;
-        if (e + 1 == ng && en > 0) {
-            qring[(qt & (Q - 1)) * 64 + lane] = uint32_t(eb);
-            qt++;
-            eb = 0;
-            en = 0;
+        if (e + 1 == ng) {
+            if (en > 0) {
+                finish(uint32_t(eb));
+                eb = 0;
+                en = 0;
+            }
+            if constexpr (ZG) {
+                // taken words past the lane's last code bit are zero
+                for (uint32_t x = qt; x < qh; x++) out[pslot[x & 1]] = 0u;
+                done = true;
+            }
         }
     };
     // prologue: the first LG groups
@@ -783,7 +945,6 @@ __device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, 
     uint32_t pf[kPf][NW];
 #pragma unroll
     for (uint32_t u = 0; u < kPf; u++) load(LG + u, pf[u]);
-    uint32_t qh = 0;   // words taken
     int cnt = 0;       // bits the decoder holds
     uint32_t ptr = 0;  // words of this lane group written
     for (uint32_t j0 = 0; j0 < ng_max; j0 += kPf) {
@@ -793,12 +954,13 @@ __device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, 
             if (jj < ng_max) {
                 encode(jj + LG, pf[u]);
                 load(jj + LG + kPf, pf[u]);
-                const uint32_t gcnt = jj < ng ? (w + jj * W < Gfull ? G : rem) : 0u;
                 const uint8_t* lp = lring + ((jj & (LR - 1)) * 64 + lane) * LB;
                 uint32_t lens;
                 if constexpr (LB == 1) lens = *lp;
                 else if constexpr (LB == 2) lens = *reinterpret_cast<const uint16_t*>(lp);
                 else lens = *reinterpret_cast<const uint32_t*>(lp);
+                // a coded group has a nonzero length for its first symbol
+                const uint32_t gcnt = (jj < ng && (!ZG || lens != 0)) ? (w + jj * W < Gfull ? G : rem) : 0u;
 #pragma unroll
                 for (int pr = 0; pr < G / 2; pr++) {
                     const bool part = 2u * pr < gcnt;
@@ -808,7 +970,9 @@ __device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, 
                                                                    __builtin_amdgcn_mbcnt_lo(uint32_t(msk), ptr));
                     const uint32_t qw = qring[(qh & (Q - 1)) * 64 + lane];
                     if (need) {
-                        out[idx] = qh < qt ? qw : 0u;
+                        if (qh < qt) out[idx] = qw;
+                        else if (!ZG || done) out[idx] = 0u;
+                        else pslot[qh & 1] = idx;
                         qh++;
                         cnt += 32;
                     }
@@ -828,8 +992,33 @@ struct PackLds {
     uint64_t pay[4];            // absolute payload offset of each stream
     uint32_t mode[4];
     uint32_t bytes[4];
+    uint32_t z[4];              // ZG fill value
     uint32_t wpre[4][65];       // lane-group word prefix per stream
 };
+
+// The group bitmap of a ZG stream: wave v writes 64-bit words x = v, v+4, ...
+// of the bm bytes (lane l tests group 64x + l); bits past the last group and
+// the padding are zero.
+template <int B, int G>
+__device__ void pack_bitmap(const uint8_t* src, const uint8_t* base, int k, uint32_t z, uint32_t m, uint32_t bm,
+                            uint8_t* dst)
+{
+    constexpr int NB = B * G;
+    constexpr int NW = NB >= 4 ? NB / 4 : 1;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t Gtot = (m + G - 1) / G;
+    for (uint32_t x = threadIdx.x >> 6; x < bm / 8; x += kWaves) {
+        const uint32_t q = 64 * x + lane;
+        bool mk = false;
+        if (q < Gtot) {
+            uint32_t wd[NW];
+            group_words<B, G>(src, base, q, m, wd);
+            mk = marked<B, G>(wd, k, min(uint32_t(G), m - q * G), z);
+        }
+        const uint64_t bits = __ballot(mk);
+        if (lane == 0) *reinterpret_cast<uint64_t*>(dst + 8 * x) = bits;
+    }
+}
 
 // Raw groups of one chunk: thread t copies elements [16u, 16u+16) of every
 // RAW stream with one 16-byte store each.
@@ -926,7 +1115,8 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
                 ent.w = uint32_t(en.mode) | (uint32_t(en.rle) << 8);
                 *(uint4*)(d.dst + 64 + 16 * (uint64_t(c) * B + k)) = ent;
             }
-            if (en.mode == kModeHuf) {
+            if (t == 0) P.z[k] = en.rle;
+            if (en.mode == kModeHuf || en.mode == kModeZg) {
                 const uint32_t cw = codes[ei * 256 + t];
                 const uint32_t l = cw >> 16;
                 P.rcode[k][t] = l ? ((__brev(cw & 0xFFFFu) >> (32 - l)) | (l << 16)) : 0u;
@@ -949,17 +1139,25 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
         uint8_t* dst = d.dst;
         pack_raw<BB>(src, base, dst, P, m);
         for (uint32_t k = 0; k < B; k++) {
-            if (P.mode[k] != kModeHuf) continue;
+            const bool zg = P.mode[k] == kModeZg;
+            if (P.mode[k] != kModeHuf && !zg) continue;
             uint8_t* pay = dst + P.pay[k];
-            // head: nibble table, word counts, zero pad; zero pad after words
+            // head: nibble table, word counts, zero pad; ZG bitmap; zero pad after words
             if (t < 128) pay[t] = uint8_t((P.rcode[k][2 * t] >> 16) | ((P.rcode[k][2 * t + 1] >> 16) << 4));
             if (uint32_t(t) < NG) ((uint32_t*)(pay + 128))[t] = P.wpre[k][t + 1] - P.wpre[k][t];
             for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
             for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
-            uint32_t* words = (uint32_t*)(pay + head);
-            for (uint32_t j = wv; j < NG; j += kWaves)
-                pack_lane_group<BB, GG>(src, base, int(k), P.rcode[k], p.L, j, W, m, words + P.wpre[k][j], qpool[wv],
-                                        lpool[wv]);
+            const uint32_t bm = zg ? zg_bitmap(m, GG) : 0u;
+            if (zg) pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + head);
+            uint32_t* words = (uint32_t*)(pay + head + bm);
+            for (uint32_t j = wv; j < NG; j += kWaves) {
+                if (zg)
+                    pack_lane_group<BB, GG, true>(src, base, int(k), P.rcode[k], P.z[k], p.L, j, W, m,
+                                                  words + P.wpre[k][j], qpool[wv], lpool[wv]);
+                else
+                    pack_lane_group<BB, GG, false>(src, base, int(k), P.rcode[k], 0u, p.L, j, W, m,
+                                                   words + P.wpre[k][j], qpool[wv], lpool[wv]);
+            }
         }
         __syncthreads();
     }

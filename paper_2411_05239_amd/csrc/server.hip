@@ -222,7 +222,7 @@ bool launch_iteration(zipnn_server s)
         }
     }
     // descriptors by kernel class, in the order taken
-    std::map<std::tuple<uint32_t, uint32_t, bool>, Class> classes;
+    std::map<std::tuple<uint32_t, uint32_t, bool, bool>, Class> classes;
     const double t = now_s();
     for (auto& tk : take) {
         Req& r = s->reqs[tk.first];
@@ -236,8 +236,8 @@ bool launch_iteration(zipnn_server s)
         d.c_begin = r.next;
         d.c_end = r.next + tk.second;
         d.status = nullptr;   // set once the buffer layout is known
-        const bool delta = (e.h.flags & kFlagDelta) != 0;
-        Class& c = classes[std::make_tuple(e.h.B, e.h.g, delta)];
+        const DecClass k = dec_class(e.h);
+        Class& c = classes[std::make_tuple(k.B, k.G, k.delta, k.zg)];
         const uint64_t items = plan_items(e.h, d.c_begin, d.c_end).items;
         if (c.prefix.empty()) c.prefix.push_back(0);
         c.prefix.push_back(c.prefix.back() + items);
@@ -283,8 +283,9 @@ bool launch_iteration(zipnn_server s)
             const Class& c = kv.second;
             const uint64_t items = c.prefix.back();
             const int grid = int(std::min<uint64_t>(uint64_t(s->ctx->dec_grid), std::max<uint64_t>(items, 1)));
-            e = launch_decode_planned(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                                      (const DecDesc*)(it.d_buf + at[ci].first), int(c.descs.size()),
+            const DecClass k{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                             std::get<3>(kv.first)};
+            e = launch_decode_planned(k, (const DecDesc*)(it.d_buf + at[ci].first), int(c.descs.size()),
                                       (const uint64_t*)(it.d_buf + at[ci].second), d_status, grid, s->stream);
             ci++;
         }

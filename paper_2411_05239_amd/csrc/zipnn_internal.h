@@ -22,7 +22,8 @@ constexpr uint32_t kMaxW = 4096;           // sub-streams per chunk and stream
 constexpr uint32_t kMaxBW = 8192;          // sub-streams per chunk over all B streams
 constexpr uint32_t kLutSize = 1u << kMaxL;  // decode table entries per stream
 constexpr uint32_t kFlagDelta = 1;
-constexpr int kModeRaw = 0, kModeHuf = 1, kModeRle = 2;
+constexpr uint32_t kFlagZg = 2;               // the map holds ZG entries
+constexpr int kModeRaw = 0, kModeHuf = 1, kModeRle = 2, kModeZg = 3;
 constexpr int kBlock = 256;                 // threads per workgroup (4 waves)
 
 __host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15u) & ~uint64_t(15); }
@@ -60,6 +61,13 @@ __host__ __device__ inline uint32_t huf_head(uint32_t W)
     return uint32_t(align16(128u + 4u * ((W + kLanes - 1) / kLanes)));
 }
 
+// Size of the group bitmap of a ZG payload (after the head): one bit per
+// group of g symbols, padded to 16 bytes.
+__host__ __device__ inline uint32_t zg_bitmap(uint32_t m, uint32_t g)
+{
+    return uint32_t(align16(((m + g - 1) / g + 7) / 8));
+}
+
 struct Header {
     uint64_t n, total, payload_base;
     uint32_t dtype, B, chunk, S, g, L, flags, n_chunks, E;
@@ -83,7 +91,7 @@ __host__ __device__ inline int parse_header(const uint32_t* w, uint64_t src_len,
     h.total = uint64_t(w[8]) | (uint64_t(w[9]) << 32);
     if (dtype_bytes(int(h.dtype)) != int(h.B) || h.B == 0) return ZIPNN_E_FORMAT;
     if (check_params(int(h.B), h.chunk, h.S, h.g, h.L) != ZIPNN_OK) return ZIPNN_E_FORMAT;
-    if (h.flags & ~kFlagDelta) return ZIPNN_E_FORMAT;
+    if (h.flags & ~(kFlagDelta | kFlagZg)) return ZIPNN_E_FORMAT;
     for (int i = 11; i < 16; i++)
         if (w[i]) return ZIPNN_E_FORMAT;
     h.E = h.chunk / h.B;
@@ -115,6 +123,8 @@ struct EncDesc {
     uint64_t n;
     uint32_t chunk0;       // index of this tensor's first chunk in the scratch arrays
     uint32_t n_chunks;
+    uint32_t has_zg;       // set by the placement kernel: some entry is ZG
+    uint32_t pad;
 };
 
 // Per-(chunk, stream) result of the analysis kernel.
@@ -170,13 +180,22 @@ __host__ __device__ inline ItemPlan plan_items(const Header& h, uint32_t c_begin
 
 // Launchers (decode.hip / encode.hip).  A null descriptor array means "the
 // single tensor passed by value".
-// Decode kernels are specialised on (B, g, delta) taken from the header.
+// Decode kernels are specialised on (B, g, delta, zg) taken from the header
+// (zg: the header's ZG flag; only those kernels carry the ZG decoder).
+struct DecClass {
+    uint32_t B, G;
+    bool delta, zg;
+};
+__host__ __device__ inline DecClass dec_class(const Header& h)
+{
+    return DecClass{h.B, h.g, (h.flags & kFlagDelta) != 0, (h.flags & kFlagZg) != 0};
+}
 hipError_t launch_decode_one(const Header& h, const DecDesc& one, int* d_status, int grid, hipStream_t s);
-hipError_t launch_decode_batch(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
-                               uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s);
+hipError_t launch_decode_batch(const DecClass& k, const DecDesc* d_descs, int n_desc, uint64_t* d_item_prefix,
+                               int* d_status, int grid, hipStream_t s);
 // Batched decode whose item prefix (plan_items per descriptor) was computed
 // on the host and copied beside the descriptors.
-hipError_t launch_decode_planned(uint32_t B, uint32_t G, bool delta, const DecDesc* d_descs, int n_desc,
+hipError_t launch_decode_planned(const DecClass& k, const DecDesc* d_descs, int n_desc,
                                  const uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s);
 hipError_t launch_clear_status(int* d_status, hipStream_t s);
 hipError_t launch_gather_headers(const uint8_t* arena, const uint64_t* d_offs, int n, void* d_out, hipStream_t s);

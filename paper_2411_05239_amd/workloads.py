@@ -12,6 +12,7 @@ Generators:
   fp32_rows       -- FP32 matrix, row r ~ N(0, sigma_r), log10 sigma_r ~ U(-3, -1)
   checkpoint_8b   -- the 291 tensors of an 8B decoder checkpoint (BF16)
   finetune_delta  -- a fine-tuned copy: N(0, 1e-4) noise on a Bernoulli(0.1) mask
+  pruned          -- a copy with a Bernoulli(1 - density) share of its values set to zero
   serving_corpus  -- tensors of log-uniform size, 60% BF16 / 30% FP32 / 10% FP8
 """
 from __future__ import annotations
@@ -96,6 +97,12 @@ def finetune_delta(w: torch.Tensor, seed: int, p: float = 0.1, sigma: float = 1e
     m = torch.rand(w.numel(), generator=g, device=w.device) < p
     z = torch.randn(w.numel(), generator=g, device=w.device) * sigma
     return (w.float().reshape(-1) + m * z).to(torch.bfloat16).reshape(w.shape)
+
+
+def pruned(w: torch.Tensor, density: float, seed: int) -> torch.Tensor:
+    """w with each value kept with probability `density`, else set to +0."""
+    keep = torch.rand(w.numel(), generator=_gen(seed, w.device), device=w.device) < density
+    return torch.where(keep, w.reshape(-1), torch.zeros((), dtype=w.dtype, device=w.device)).reshape(w.shape)
 
 
 FP8_MAX = 448.0

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libzipnn_hip.so")
 ZIPNN_OK, ZIPNN_E_INVAL, ZIPNN_E_FORMAT, ZIPNN_E_CORRUPT = 0, -1, -2, -3
 ZIPNN_E_NOSPACE, ZIPNN_E_NOMEM, ZIPNN_E_HIP, ZIPNN_E_BUSY = -4, -5, -6, -7
 ZIPNN_BF16, ZIPNN_FP16, ZIPNN_FP32, ZIPNN_FP8_E4M3, ZIPNN_U8 = 1, 2, 3, 4, 5
-ZIPNN_AUTO, ZIPNN_HUF, ZIPNN_RAW = 0, 1, 2
+ZIPNN_AUTO, ZIPNN_HUF, ZIPNN_RAW, ZIPNN_ZG = 0, 1, 2, 3
 WIDTH = {ZIPNN_BF16: 2, ZIPNN_FP16: 2, ZIPNN_FP32: 4, ZIPNN_FP8_E4M3: 1, ZIPNN_U8: 1}
 
 # every symbol declared in include/zipnn.h
@@ -53,7 +53,7 @@ class zipnn_info(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("B", ctypes.c_int), ("n_elems", ctypes.c_uint64),
                 ("total_bytes", ctypes.c_uint64), ("n_chunks", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32),
                 ("S", ctypes.c_uint32), ("g", ctypes.c_uint32), ("L", ctypes.c_uint32), ("is_delta", ctypes.c_int),
-                ("bytes_by_mode", ctypes.c_uint64 * 3), ("entries_by_mode", ctypes.c_uint64 * 3)]
+                ("bytes_by_mode", ctypes.c_uint64 * 4), ("entries_by_mode", ctypes.c_uint64 * 4)]
 
 
 class zipnn_tune_entry(ctypes.Structure):

@@ -1,0 +1,170 @@
+"""GPU parity of the ZG mode (zero-aware coding of sparse byte groups, such
+as the XOR delta of a fine-tune, paper §IV-B): containers equal the CPU
+oracle's byte for byte and decode bit-exactly, on deltas (AUTO picks ZG),
+forced ZG over every dtype / group / sub-stream shape (partial lane groups,
+lanes with no marked group, more than 32 steps per lane, ragged tails),
+chunks of mixed modes, batches mixing ZG and plain containers, and damaged
+ZG containers."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_05239_amd import workloads
+from paper_2411_05239_amd import zipnn as Z
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def codec():
+    c = Z.Codec(0)
+    yield c
+    c.close()
+
+
+def _kw(p):
+    return dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy))
+
+
+def _u8(t):
+    return t.contiguous().view(torch.uint8).reshape(-1)
+
+
+def _modes(c_np):
+    h = oracle.header(c_np)
+    B = oracle.WIDTH[h["dtype"]]
+    return [oracle.entry(c_np, ch, k)[2] for ch in range(h["n_chunks"]) for k in range(B)]
+
+
+def roundtrip(codec, x_cpu, p, base_cpu=None):
+    dt = Z.torch_dtype_code(x_cpu.dtype)
+    print(f"case dtype={x_cpu.dtype} n={x_cpu.numel()} {p} delta={base_cpu is not None}", flush=True)
+    x = x_cpu.cuda()
+    base = base_cpu.cuda() if base_cpu is not None else None
+    c_gpu = codec.compress(x, p, base=base)
+    c_orc = oracle.compress(x_cpu, dt, base=base_cpu, nthreads=8, **_kw(p))
+    got = c_gpu.cpu().numpy()
+    assert got.size == c_orc.size, (got.size, c_orc.size)
+    if not np.array_equal(got, c_orc):
+        bad = np.nonzero(got != c_orc)[0]
+        raise AssertionError(f"{bad.size} container bytes differ, first at {bad[:8]}")
+    out = torch.empty_like(x)
+    codec.decompress(c_gpu, out, base=base)
+    assert torch.equal(_u8(out), _u8(x))
+    assert np.array_equal(oracle.decompress(got, base=base_cpu, nthreads=8), oracle.as_bytes(x_cpu))
+    return got
+
+
+@pytest.mark.parametrize("n", [1_000_003, 4 * 131072])
+def test_delta_auto_picks_zg(codec, n):
+    w = workloads.bf16_normal(n, seed=30)
+    ft = workloads.finetune_delta(w, seed=31)
+    c = roundtrip(codec, ft, Z.zipnn_default_params(Z.ZIPNN_BF16), base_cpu=w)
+    modes = _modes(c)
+    assert oracle.MODE_ZG in modes
+    assert oracle.header(c)["flags"] == 3   # delta + ZG entries
+    # smaller than the Huffman-only delta
+    h = oracle.compress(ft, oracle.BF16, base=w, policy=[1, 1], nthreads=8)
+    assert c.size < h.size
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32, torch.uint8])
+@pytest.mark.parametrize("g", [2, 4, 8])
+@pytest.mark.parametrize("S,chunk", [(16, 4096), (512, 262144), (64, 65536)])
+def test_forced_zg_shapes(codec, dtype, g, S, chunk):
+    """Pruned weights (8% kept) with ZG forced on every stream.  S=16 gives
+    partial lane groups and lanes without a marked group; S=512 over 256 KiB
+    chunks gives more than 32 steps per lane (several bitmap batches)."""
+    B = torch.finfo(dtype).bits // 8 if dtype.is_floating_point else 1
+    n = 3 * (chunk // B) + 777
+    if dtype == torch.uint8:
+        x = workloads.pruned(workloads.bf16_normal(n, seed=40 + g), 0.08, seed=41).view(torch.uint8)[:n].clone()
+    else:
+        x = workloads.pruned(workloads.bf16_normal(n, seed=40 + g).to(dtype), 0.08, seed=41)
+    dt = Z.torch_dtype_code(dtype)
+    p = Z.make_params(dt, chunk_bytes=chunk, S=S, g=g, policy=[Z.ZIPNN_ZG] * 4)
+    c = roundtrip(codec, x, p)
+    assert oracle.MODE_ZG in _modes(c)
+
+
+def test_zg_chunks_beside_other_modes(codec):
+    """One tensor whose chunks are dense (HUF/RAW), sparse (ZG) and constant
+    (RLE): the ZG kernel also decodes the other chunks."""
+    E = 131072
+    dense = workloads.bf16_normal(2 * E, seed=50)
+    sparse = workloads.pruned(workloads.bf16_normal(2 * E, seed=51), 0.05, seed=52)
+    zeros = torch.zeros(E + 99, dtype=torch.bfloat16)
+    x = torch.cat([sparse[:E], dense[:E], zeros, sparse[E:], dense[E:]])
+    c = roundtrip(codec, x, Z.zipnn_default_params(Z.ZIPNN_BF16))
+    modes = set(_modes(c))
+    assert {oracle.MODE_ZG, oracle.MODE_HUF, oracle.MODE_RLE} <= modes
+
+
+def test_batch_mixes_zg_and_plain(codec):
+    """A batch holding ZG containers (pruned, delta) and plain ones: every
+    kernel class decodes its own tensors."""
+    a = workloads.pruned(workloads.bf16_normal(300_001, seed=60), 0.1, seed=61).cuda()
+    b = workloads.bf16_normal(200_003, seed=62).cuda()
+    c = workloads.pruned(workloads.bf16_normal(100_000, seed=63), 0.02, seed=64).cuda()
+    xs = [a, b, c]
+    p = Z.zipnn_default_params(Z.ZIPNN_BF16)
+    arena, offs = codec.compress_batch(xs, p)
+    ar = arena.cpu().numpy()
+    flags = [oracle.header(ar[offs[i]:offs[i + 1]])["flags"] for i in range(3)]
+    assert flags == [2, 0, 2]
+    for i, x in enumerate(xs):
+        ref = oracle.compress(x.cpu(), oracle.BF16, **_kw(p))
+        assert np.array_equal(ar[offs[i]: offs[i] + ref.size], ref), i
+    outs = [torch.empty_like(x) for x in xs]
+    bt = codec.prepare_batch(arena, offs, outs)
+    bt.run(check=True)
+    torch.cuda.synchronize()
+    for o, x in zip(outs, xs):
+        assert torch.equal(_u8(o), _u8(x))
+    bt.close()
+
+
+def _status(codec, c_np, n_bytes):
+    c = torch.from_numpy(c_np).cuda()
+    out = torch.zeros(n_bytes + 256, dtype=torch.uint8, device="cuda")
+    try:
+        Z.zipnn_decompress(codec.ctx, c.data_ptr(), c.numel(), None, out.data_ptr(), n_bytes, codec._stream())
+        st = codec.status(clear=True)
+    except Z.ZipnnError as e:
+        st = e.code
+    torch.cuda.synchronize()
+    assert bool((out[n_bytes:] == 0).all())
+    return st
+
+
+def test_damaged_zg_rejected(codec):
+    # m = 1001 symbols per stream, g = 4: 251 groups, so bits 251..255 of the
+    # bitmap's byte 31 lie past the last group
+    x = workloads.pruned(workloads.bf16_normal(1001, seed=70), 0.1, seed=71).view(torch.uint8)[:1001].clone()
+    p = Z.make_params(Z.ZIPNN_U8, chunk_bytes=1024, S=16, g=4, policy=[Z.ZIPNN_ZG])
+    c = oracle.compress(x, oracle.U8, **_kw(p))
+    off, nb, mode, z = oracle.entry(c, 0, 0)
+    assert mode == oracle.MODE_ZG and oracle.header(c)["flags"] == 2
+    W = -(-1001 // 16)
+    H = (128 + 4 * ((W + 63) // 64) + 15) // 16 * 16
+    assert _status(codec, c, 1001) == Z.ZIPNN_OK
+    cases = []
+    d = c.copy(); d[off + H + 31] |= 0x80; cases.append(("bit past the last group", d))
+    d = c.copy(); d[24] = 0; cases.append(("ZG entry without the header flag", d))
+    # marked groups per lane (lane = group mod W): marking a group of a lane
+    # that has none, or unmarking the only one of a lane, changes how many
+    # words the lane takes, so the word counts no longer add up
+    bit = lambda q: (c[off + H + q // 8] >> (q % 8)) & 1
+    per_lane = [sum(bit(q) for q in range(w, 251, W)) for w in range(W)]
+    w0 = per_lane.index(0)
+    d = c.copy(); d[off + H + w0 // 8] |= 1 << (w0 % 8); cases.append(("a lane gains a marked group", d))
+    w1 = per_lane.index(1)
+    q = next(q for q in range(w1, 251, W) if bit(q))
+    d = c.copy(); d[off + H + q // 8] &= 0xFF ^ (1 << (q % 8)); cases.append(("a lane loses its marked group", d))
+    for name, d in cases:
+        print("damage:", name, flush=True)
+        with pytest.raises(oracle.OracleError):
+            oracle.decompress(d)
+        assert _status(codec, d, 1001) == Z.ZIPNN_E_CORRUPT, name
+    assert codec.status() == Z.ZIPNN_OK

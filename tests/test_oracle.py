@@ -507,6 +507,9 @@ def test_zg_matches_closed_form_and_auto_picks_smallest(oracle_lib):
             assert (nb_a, mode_a) == (best[0], best[2])
             picked.add(mode_a)
     assert oracle.MODE_ZG in picked   # the sparse low byte of the delta
+    # header bit 1 says whether the map holds ZG entries
+    assert oracle.header(zg)["flags"] == 2 and oracle.header(auto)["flags"] == 2
+    assert oracle.header(huf)["flags"] == 0
 
 
 def test_zg_needs_half_the_stream(oracle_lib):
@@ -532,7 +535,8 @@ def test_corrupt_zg_rejected(oracle_lib):
     for pos, val in [(272 + 2, 0x01),    # a bitmap bit past the last group
                      (272, 0x42 | 0x01),  # one more marked group: words run short
                      (272, 0x40),         # one fewer marked group: words left over
-                     (64 + 8, 0x20)]:     # payload shorter than head + bitmap
+                     (64 + 8, 0x20),      # payload shorter than head + bitmap
+                     (24, 0x00)]:         # a ZG entry without the header's ZG flag
         d = good.copy()
         d[pos] = val
         with pytest.raises(oracle.OracleError) as ei:
