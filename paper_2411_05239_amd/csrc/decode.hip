@@ -509,11 +509,13 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                 if ((zm >> k) & 1) zload(k, zJ);
         }
     };
-    auto zflag = [&](int k, uint32_t jj) __attribute__((always_inline)) {
+    // the 64 group bits of step jj (uniform; bits of lanes past W belong to
+    // other steps' groups)
+    auto zmask = [&](int k, uint32_t jj) __attribute__((always_inline)) {
         const uint32_t sidx = uni(jj - zJ);
         const uint32_t lo = __builtin_amdgcn_readlane(zwin[k], sidx);
         const uint32_t hi = __builtin_amdgcn_readlane(zwin[k], sidx + 32);
-        return (((lane < 32 ? lo : hi) >> (lane & 31)) & 1u) != 0;
+        return uint64_t(lo) | (uint64_t(hi) << 32);
     };
     uint32_t zm_all = 0;
 #pragma unroll
@@ -542,19 +544,25 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                         for (int x = 0; x < PW; x++) pk[k][x] = slot[k][u * PW + x];
                         buf_load<G>(rr[k], offn, &slot[k][u * PW]);
                     } else if (is_zg) {
-                        const bool on = zflag(k, jj);
+                        const uint64_t zm = zmask(k, jj);
 #pragma unroll
-                        for (int x = 0; x < PW; x++) pk[k][x] = 0;
+                        for (int x = 0; x < PW; x++) pk[k][x] = rlev[k];
+                        if (zm != 0) {   // else no lane of the wave takes part in this step
+                            const bool on = ((zm >> lane) & 1) != 0;
 #pragma unroll
-                        for (int pr = 0; pr < G / 2; pr++) {
-                            huf_take<B>(slot[k], cur[k], on, twoL);
-                            const uint32_t s0 = huf_get_if<B>(slot[k], lut[k], mask, on);
-                            const uint32_t s1 = huf_get_if<B>(slot[k], lut[k], mask, on);
-                            pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
-                            if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1) huf_refill<B>(slot[k], cur[k], lane);
+                            for (int x = 0; x < PW; x++) pk[k][x] = 0;
+#pragma unroll
+                            for (int pr = 0; pr < G / 2; pr++) {
+                                huf_take<B>(slot[k], cur[k], on, twoL);
+                                const uint32_t s0 = huf_get_if<B>(slot[k], lut[k], mask, on);
+                                const uint32_t s1 = huf_get_if<B>(slot[k], lut[k], mask, on);
+                                pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
+                                if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1)
+                                    huf_refill<B>(slot[k], cur[k], lane);
+                            }
+#pragma unroll
+                            for (int x = 0; x < PW; x++) pk[k][x] = on ? pk[k][x] : rlev[k];
                         }
-#pragma unroll
-                        for (int x = 0; x < PW; x++) pk[k][x] = on ? pk[k][x] : rlev[k];
                     } else {
 #pragma unroll
                         for (int x = 0; x < PW; x++) pk[k][x] = 0;
@@ -620,7 +628,7 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                 // reload the window for some lanes only, and v_readlane would
                 // then read a lane that was not loaded).
                 const bool zg = ZGK && mode[k] == kModeZg;
-                const bool flag = zg ? zflag(k, jj) : true;
+                const bool flag = zg ? ((zmask(k, jj) >> lane) & 1) != 0 : true;
                 const bool on = !zg || (has & flag);
                 if (mode[k] == kModeRaw) {
 #pragma unroll

@@ -92,8 +92,9 @@ __device__ inline uint32_t count_le(const uint32_t* a, uint32_t n, uint32_t x)
 // below; leaf i is selected at a level iff i < (leaves among the selected
 // items), so its length is the number of such levels.
 __device__ bool build_lengths(const uint32_t* fv, uint32_t tot, uint32_t raw, uint32_t head, uint32_t L,
-                              bool shortcut, PmWave& P)
+                              bool shortcut, PmWave& P, uint32_t& T_out)
 {
+    T_out = 0;
     const int lane = threadIdx.x & 63;
     uint32_t d = 0;
 #pragma unroll
@@ -193,6 +194,7 @@ __device__ bool build_lengths(const uint32_t* fv, uint32_t tot, uint32_t raw, ui
         }
     }
     T = wave_sum(T);
+    T_out = T;
     __builtin_amdgcn_wave_barrier();
     // the payload holds at least its head and ceil(T/8) bytes
     return !(shortcut && head + (T + 7) / 8 >= raw);
@@ -428,6 +430,7 @@ struct AnalyzeTail {
     uint32_t fin;            // bit k: ZG chosen (else HUF) for a coded stream
     uint32_t coded;          // bit k: coded (HUF or ZG chosen)
     uint32_t words[2][4];    // words over all lane groups, per stream: HUF, ZG
+    uint32_t T[2][4];        // coded bits of the candidates: HUF, ZG
 };
 
 // One workgroup per chunk:
@@ -583,7 +586,9 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
             } else {
                 bool hc = false;
                 if (policy != ZIPNN_ZG) {
-                    hc = build_lengths(fv, m, m, head, p.L, policy == ZIPNN_AUTO, S.pm[k]);
+                    uint32_t T;
+                    hc = build_lengths(fv, m, m, head, p.L, policy == ZIPNN_AUTO, S.pm[k], T);
+                    if (lane == 0) A.T[0][k] = T;
                     if (hc)
 #pragma unroll
                         for (int r = 0; r < 4; r++) A.lens[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
@@ -633,7 +638,9 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
                 const int k = wv;
                 const int policy = p.policy[k];
                 if (d2 >= 2) {
-                    const bool zgc = build_lengths(fv, tot, m, head_z, p.L, policy == ZIPNN_AUTO, S.pm[k]);
+                    uint32_t T;
+                    const bool zgc = build_lengths(fv, tot, m, head_z, p.L, policy == ZIPNN_AUTO, S.pm[k], T);
+                    if (lane == 0) A.T[1][k] = T;
                     if (zgc) {
 #pragma unroll
                         for (int r = 0; r < 4; r++) A.lens2[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
@@ -644,7 +651,8 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
                     uint32_t f[4];
 #pragma unroll
                     for (int r = 0; r < 4; r++) f[r] = hist[k][lane + 64 * r];
-                    build_lengths(f, m, m, head, p.L, false, S.pm[k]);
+                    uint32_t T;
+                    build_lengths(f, m, m, head, p.L, false, S.pm[k], T);
 #pragma unroll
                     for (int r = 0; r < 4; r++) A.lens[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
                     if (lane == 0) atomicOr(&A.hc, 1u << k);
@@ -652,6 +660,16 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
             }
             __syncthreads();
         }
+        // AUTO with both candidates: a candidate that loses even at its best
+        // (head + coded bits) against the other at its worst (plus two words
+        // of padding per sub-stream) needs no replay; ties go to HUF
+        if (uint32_t(t) < B && p.policy[t] == ZIPNN_AUTO && ((A.hc & A.zgc) >> t & 1)) {
+            const uint64_t h_lo = head + (A.T[0][t] + 7) / 8, h_hi = h_lo + 8 * W;
+            const uint64_t z_lo = head_z + (A.T[1][t] + 7) / 8, z_hi = z_lo + 8 * W;
+            if (z_hi < h_lo) atomicAnd(&A.hc, ~(1u << t));
+            else if (h_hi <= z_lo) atomicAnd(&A.zgc, ~(1u << t));
+        }
+        __syncthreads();
         // 4. replay the word requests of every candidate, one lane group per wave
         if (A.hc | A.zgc) {
             for (uint32_t j0 = 0; j0 < NG; j0 += kWaves) {
