@@ -59,7 +59,8 @@ int main(void)
         const uint64_t cap = orc_compress_bound(dtype, n, chunk, S);
         uint8_t* c = (uint8_t*)malloc(cap + 1);
         uint64_t clen = 0;
-        if (orc_compress(x, dtype, n, base, chunk, S, g, L, policy, c, cap, &clen, 2) != ORC_OK) {
+        const uint32_t skip = rnd() % 4;
+        if (orc_compress(x, dtype, n, base, chunk, S, g, L, policy, skip, c, cap, &clen, 2) != ORC_OK) {
             printf("compress failed at %d\n", it);
             return 1;
         }

@@ -13,7 +13,9 @@ Steps (ZipNN, arXiv 2411.05239):
   codes    -- canonical codes by walking the symbols in (length, symbol) order
               (code_{i+1} = (code_i + 1) << (l_{i+1} - l_i)), equivalent to
               RFC 1951 §3.2.2;
-  modes    -- RAW / RLE / HUF / ZG per byte-group (§III-B, §IV-B, §V-A);
+  modes    -- RAW / RLE / HUF / ZG per byte-group (§III-B, §IV-B, §V-A), with
+              probe chunks every K+1 chunks (§III-B, "Identifying
+              compressibility");
   schedule -- the lock-step word order as a sort of (step, pair, lane) events
               rather than nested loops;
   layout   -- 64-byte header, 16-byte map entries, 16-byte aligned payloads
@@ -209,7 +211,7 @@ def encode_stream(sym: np.ndarray, S: int, g: int, L: int, policy: int) -> tuple
 
 
 def compress(words: np.ndarray, dtype: int, *, base: np.ndarray | None = None, chunk_bytes: int = 262144,
-             S: int = 512, g: int = 4, L: int = 11, policy=(AUTO, AUTO, AUTO, AUTO)) -> bytes:
+             S: int = 512, g: int = 4, L: int = 11, policy=(AUTO, AUTO, AUTO, AUTO), skip: int = 0) -> bytes:
     B = WIDTH[dtype]
     raw = np.ascontiguousarray(words).view(np.uint8).reshape(-1)
     if base is not None:
@@ -220,8 +222,12 @@ def compress(words: np.ndarray, dtype: int, *, base: np.ndarray | None = None, c
     entries, payloads = [], []
     for c in range(n_chunks):
         chunk = raw[c * E * B: min(n, (c + 1) * E) * B]
+        probe = c - c % (skip + 1)   # the chunk that probed this one's run (itself if c is a probe)
         for k, s in enumerate(split(chunk, B)):
-            entries.append(encode_stream(s, S, g, L, policy[k]))
+            pol = policy[k]
+            if pol == AUTO and probe != c and entries[probe * B + k][0] == MODE_RAW:
+                pol = RAW   # the probe found this byte group incompressible: no analysis
+            entries.append(encode_stream(s, S, g, L, pol))
     payload_base = _payload_base(n_chunks, B)
     body = bytearray()
     mp = bytearray()
@@ -234,7 +240,7 @@ def compress(words: np.ndarray, dtype: int, *, base: np.ndarray | None = None, c
     pol = bytes(list(policy[:B]) + [0] * (4 - B))
     flags = (1 if base is not None else 0) | (2 if any(e[0] == MODE_ZG for e in entries) else 0)
     hdr = b"ZNN1" + struct.pack("<HBBQIHBBIIQ", 1, dtype, B, n, chunk_bytes, S, g, L,
-                                flags, n_chunks, total) + pol + bytes(20)
+                                flags, n_chunks, total) + pol + bytes([skip]) + bytes(19)
     assert len(hdr) == 64
     return bytes(hdr + mp + bytes(payload_base - 64 - len(mp)) + body)
 

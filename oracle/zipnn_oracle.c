@@ -599,6 +599,8 @@ typedef struct {
     uint32_t S, g;
     int L;
     const uint8_t* policy;
+    uint32_t skip;        /* probe interval K (0: every chunk is analysed) */
+    int phase;            /* 0: probe chunks, 1: the others */
     stream_out* outs;     /* n_chunks * B */
     uint32_t n_chunks;
     uint32_t next;        /* next chunk to take */
@@ -624,8 +626,16 @@ static int encode_chunk(enc_job* J, uint32_t c)
     }
     int rc = ORC_OK;
     for (int k = 0; k < J->B && rc == ORC_OK; k++) {
+        /* compressibility probing (paper §III-B, "Identifying compressibility"):
+         * under AUTO, a chunk that is not a probe chunk is stored raw without
+         * analysis when its run's probe chunk came out raw */
+        int policy = J->policy[k];
+        uint32_t run = J->skip + 1;
+        if (policy == ORC_POLICY_AUTO && c % run != 0 &&
+            J->outs[(uint64_t)(c - c % run) * J->B + k].mode == ORC_MODE_RAW)
+            policy = ORC_POLICY_RAW;
         orc_split_stream(words, m, J->B, k, s);
-        rc = encode_stream(s, m, J->S, J->g, J->L, J->policy[k], &J->outs[(uint64_t)c * J->B + k]);
+        rc = encode_stream(s, m, J->S, J->g, J->L, policy, &J->outs[(uint64_t)c * J->B + k]);
     }
     free(words);
     free(s);
@@ -641,6 +651,7 @@ static void* enc_worker(void* arg)
         int stop = J->rc != ORC_OK;
         pthread_mutex_unlock(&J->mu);
         if (stop || c >= J->n_chunks) break;
+        if ((c % (J->skip + 1) == 0) != (J->phase == 0)) continue;   /* the other phase's chunk */
         int rc = encode_chunk(J, c);
         if (rc != ORC_OK) {
             pthread_mutex_lock(&J->mu);
@@ -685,8 +696,8 @@ uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes, uint32_
 }
 
 int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, uint32_t chunk_bytes,
-                 uint32_t S, uint32_t g, uint32_t L, const uint8_t* policy_in, void* dst_v, uint64_t dst_cap,
-                 uint64_t* dst_len, int nthreads)
+                 uint32_t S, uint32_t g, uint32_t L, const uint8_t* policy_in, uint32_t skip, void* dst_v,
+                 uint64_t dst_cap, uint64_t* dst_len, int nthreads)
 {
     const uint8_t* src = (const uint8_t*)src_v;
     const uint8_t* base = (const uint8_t*)base_v;
@@ -700,6 +711,7 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
         policy[k] = policy_in ? policy_in[k] : ORC_POLICY_AUTO;
         if (policy[k] > ORC_POLICY_ZG) return ORC_E_INVAL;
     }
+    if (skip > 255) return ORC_E_INVAL;
     uint32_t E = chunk_bytes / (uint32_t)B;
     uint64_t nc64 = (n + E - 1) / E;
     if (nc64 > 0xFFFFFFFFu) return ORC_E_INVAL;
@@ -716,11 +728,16 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
     J.g = g;
     J.L = (int)L;
     J.policy = policy;
+    J.skip = skip;
     J.n_chunks = n_chunks;
     J.outs = (stream_out*)calloc((size_t)n_chunks * B + 1, sizeof(stream_out));
     if (!J.outs) return ORC_E_NOMEM;
     pthread_mutex_init(&J.mu, NULL);
-    run_threads(enc_worker, &J, nthreads);
+    /* probe chunks first, then the chunks that follow them */
+    for (J.phase = 0; J.phase < 2 && J.rc == ORC_OK; J.phase++) {
+        J.next = 0;
+        run_threads(enc_worker, &J, nthreads);
+    }
     pthread_mutex_destroy(&J.mu);
     rc = J.rc;
 
@@ -751,6 +768,7 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
         put_u32(dst + 28, n_chunks);
         put_u64(dst + 32, total);
         for (int k = 0; k < 4; k++) dst[40 + k] = policy[k];
+        dst[44] = (uint8_t)skip;
         cur = 0;
         for (uint64_t e = 0; e < (uint64_t)n_chunks * B; e++) {
             uint8_t* ent = dst + 64 + 16 * e;
@@ -787,10 +805,11 @@ int orc_parse_header(const void* src_v, uint64_t src_len, orc_header* h)
     h->n_chunks = get_u32(src + 28);
     h->total = get_u64(src + 32);
     for (int k = 0; k < 4; k++) h->policy[k] = src[40 + k];
+    h->skip = src[44];
     if (dtype_width(h->dtype) == 0 || dtype_width(h->dtype) != h->B) return ORC_E_FORMAT;
     if (orc_check_params(h->B, h->chunk_bytes, h->S, h->g, h->L) != ORC_OK) return ORC_E_FORMAT;
     if (h->flags & ~(uint32_t)(ORC_FLAG_DELTA | ORC_FLAG_ZG)) return ORC_E_FORMAT;
-    for (int i = 44; i < 64; i++)
+    for (int i = 45; i < 64; i++)
         if (src[i]) return ORC_E_FORMAT;
     uint64_t E = h->chunk_bytes / h->B;
     if ((h->n + E - 1) / E != h->n_chunks) return ORC_E_FORMAT;

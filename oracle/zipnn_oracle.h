@@ -7,7 +7,8 @@
  *     0  "ZNN1"            4  u16 version = 1     6  u8 dtype     7  u8 B
  *     8  u64 n_elems       16 u32 chunk_bytes     20 u16 S        22 u8 g
  *     23 u8 L              24 u32 flags                           28 u32 n_chunks
- *     32 u64 total_bytes   40 u8 policy[4]        44..63 zero
+ *     32 u64 total_bytes   40 u8 policy[4]        44 u8 probe interval K
+ *     45..63 zero
  *   flags: bit0 XOR delta; bit1 the map holds ZG entries (written when it
  *     does; a ZG entry without it is corrupt); other bits zero.
  *   map at 64: n_chunks*B entries of 16 bytes, chunk-major (entry c*B+k):
@@ -75,6 +76,7 @@ typedef struct {
     uint32_t chunk_bytes, S, g, L, flags, n_chunks;
     uint64_t total;
     uint8_t policy[4];
+    uint32_t skip;
 } orc_header;
 
 int orc_check_params(int B, uint32_t chunk_bytes, uint32_t S, uint32_t g, uint32_t L);
@@ -82,9 +84,12 @@ void orc_split_stream(const uint8_t* words, uint64_t m, int B, int k, uint8_t* o
 int orc_package_merge(const uint64_t f[256], int L, uint8_t len_out[256]);
 void orc_canonical_codes(const uint8_t len[256], int L, uint32_t code[256]);
 uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes, uint32_t S);
+/* skip: probe interval K (0..255).  Chunk c of the tensor is a probe chunk
+ * when c mod (K+1) = 0; under AUTO the K chunks after a probe chunk are
+ * stored raw without analysis in every byte group the probe stored raw. */
 int orc_compress(const void* src, int dtype, uint64_t n, const void* base, uint32_t chunk_bytes, uint32_t S,
-                 uint32_t g, uint32_t L, const uint8_t* policy, void* dst, uint64_t dst_cap, uint64_t* dst_len,
-                 int nthreads);
+                 uint32_t g, uint32_t L, const uint8_t* policy, uint32_t skip, void* dst, uint64_t dst_cap,
+                 uint64_t* dst_len, int nthreads);
 int orc_parse_header(const void* src, uint64_t src_len, orc_header* h);
 int orc_decompress(const void* src, uint64_t src_len, const void* base, void* dst, uint64_t dst_cap,
                    int nthreads);

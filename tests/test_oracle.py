@@ -198,6 +198,14 @@ def _read_fixture(name):
         elif k == "set":
             data = bytes.fromhex("".join(v[1:]))
             words[int(v[0]):int(v[0]) + len(data)] = np.frombuffer(data, np.uint8)
+        elif k == "set_iota":
+            words[int(v[0]):int(v[0]) + int(v[1])] = np.arange(int(v[1])) & 0xFF
+        elif k == "set_fill":
+            words[int(v[0]):int(v[0]) + int(v[1])] = int(v[2], 16)
+        elif k == "iota":
+            blob[int(v[0]):int(v[0]) + int(v[1])] = bytes(i & 0xFF for i in range(int(v[1])))
+        elif k == "fill":
+            blob[int(v[0]):int(v[0]) + int(v[1])] = bytes([int(v[2], 16)]) * int(v[1])
         elif k == "params":
             for kv in v:
                 a, b = kv.split("=")
@@ -213,10 +221,11 @@ def _read_fixture(name):
     return words, params, bytes(blob)
 
 
-@pytest.mark.parametrize("name", ["tiny_bf16_container.txt", "tiny_u8_rounds.txt", "tiny_u8_zg.txt"])
+@pytest.mark.parametrize("name", ["tiny_bf16_container.txt", "tiny_u8_rounds.txt", "tiny_u8_zg.txt",
+                                  "tiny_u8_probe.txt"])
 def test_tiny_containers_match_hand_derivation(oracle_lib, name):
     words, p, expect = _read_fixture(name)
-    kw = dict(chunk_bytes=p["chunk_bytes"], S=p["S"], g=p["g"], L=p["L"], policy=p["policy"])
+    kw = dict(chunk_bytes=p["chunk_bytes"], S=p["S"], g=p["g"], L=p["L"], policy=p["policy"], skip=p.get("skip", 0))
     c = oracle.compress(words, p["dtype"], **kw)
     assert c.tobytes() == expect
     assert spec.compress(words, p["dtype"], **kw) == expect
@@ -542,3 +551,47 @@ def test_corrupt_zg_rejected(oracle_lib):
         with pytest.raises(oracle.OracleError) as ei:
             oracle.decompress(d)
         assert ei.value.code in (oracle.E_CORRUPT, oracle.E_FORMAT)
+
+
+# ----------------------------------------------------------- compressibility probing
+
+@pytest.mark.parametrize("K", [1, 3, 7])
+def test_probing_follows_its_definition(oracle_lib, K):
+    """Probe interval K (paper §III-B, "Identifying compressibility"): every
+    entry equals the one written without probing, except under AUTO in a
+    chunk that follows a probe chunk (c mod (K+1) != 0) whose entry for that
+    byte group is RAW: there the group is RAW.  Checked on FP32 rows whose
+    low bytes are incompressible and a BF16 tensor mixing raw-like and
+    compressible chunks (random, then normal, then zero), with a ragged
+    tail."""
+    E = 1024
+    rows = workloads.fp32_rows(6, 1024 + 3, seed=2).reshape(-1)
+    mixed = torch.cat([torch.randint(0, 65536, (5 * E,), generator=torch.Generator().manual_seed(4),
+                                     dtype=torch.int32).to(torch.int16).view(torch.bfloat16),
+                       workloads.bf16_normal(3 * E, seed=3),
+                       torch.zeros(2 * E + 17, dtype=torch.bfloat16)])
+    for x, dt in [(rows, oracle.FP32), (mixed, oracle.BF16)]:
+        B = oracle.WIDTH[dt]
+        kw = dict(chunk_bytes=E * B, S=64, g=4)
+        pol = [oracle.AUTO, oracle.AUTO, oracle.HUF, oracle.AUTO][:B]
+        ref = oracle.compress(x, dt, policy=pol, **kw)
+        got = oracle.compress(x, dt, policy=pol, skip=K, **kw)
+        assert oracle.header(got)["skip"] == K and oracle.header(ref)["skip"] == 0
+        assert np.array_equal(oracle.decompress(got), oracle.as_bytes(x))
+        assert spec.compress(oracle.as_bytes(x), dt, policy=pol, skip=K, **kw) == got.tobytes()
+        nc = oracle.header(ref)["n_chunks"]
+        skipped = 0
+        for c in range(nc):
+            for k in range(B):
+                r = oracle.entry(ref, c, k)
+                gmode = oracle.entry(got, c, k)[2:]
+                probe = c - c % (K + 1)
+                if pol[k] == oracle.AUTO and probe != c and oracle.entry(got, probe, k)[2] == oracle.MODE_RAW:
+                    assert gmode == (oracle.MODE_RAW, 0)
+                    skipped += r[2] != oracle.MODE_RAW
+                else:
+                    assert gmode == r[2:]
+                    if r[2] != oracle.MODE_RLE:
+                        assert oracle.entry(got, c, k)[1] == r[1]
+        if dt == oracle.BF16:
+            assert skipped > 0   # compressible chunks after a raw probe stay raw until the next probe
