@@ -25,8 +25,10 @@
  * Container bytes (little-endian; identical to what the CPU reference codec
  * of this project writes):
  *   header (64 B): "ZNN1" | u16 version=1 | u8 dtype | u8 B | u64 n_elems |
- *     u32 chunk_bytes | u16 S | u8 g | u8 L | u32 flags (bit0 = XOR delta) |
- *     u32 n_chunks | u64 total_bytes | u8 policy[4] | 20 zero bytes
+ *     u32 chunk_bytes | u16 S | u8 g | u8 L | u32 flags (bit0 = XOR delta, bit1 = the
+ *     map holds ZG entries) |
+ *     u32 n_chunks | u64 total_bytes | u8 policy[4] | u8 probe interval K |
+ *     19 zero bytes
  *   map: n_chunks*B entries of 16 B, chunk-major: u64 payload offset (from
  *     payload_base = align128(64 + 16*n_chunks*B), or 64 with no chunks; the
  *     gap after the map is zero) | u32 bytes | u8 mode (0 RAW, 1 HUF,
@@ -107,13 +109,23 @@ typedef enum {
  *                   and chunk_bytes/S <= 8192
  *   group           g, 2, 4 or 8
  *   max_code_len    L, 8 .. 11
- *   policy[k]       zipnn_policy of stream k (k < B) */
+ *   policy[k]       zipnn_policy of stream k (k < B)
+ *   probe_skip      K, 0 .. 255: compressibility probing (paper §III-B,
+ *                   "Identifying compressibility").  Chunk c of a tensor
+ *                   with c mod (K+1) = 0 is a probe chunk; under AUTO the K
+ *                   chunks after it store a byte group raw, without
+ *                   analysing it, when the probe chunk stored it raw.  0
+ *                   (the default) analyses every chunk.  Stored in header
+ *                   byte 44.
+ *   reserved        zero */
 typedef struct {
     uint32_t chunk_bytes;
     uint16_t substream_syms;
     uint8_t group;
     uint8_t max_code_len;
     uint8_t policy[4];
+    uint8_t probe_skip;
+    uint8_t reserved[3];
 } zipnn_params;
 
 /* Summary of a container, filled by zipnn_inspect from host bytes. */

@@ -65,6 +65,7 @@ EncParams make_params(int dtype, const zipnn_params& p)
     e.g = p.group;
     e.L = p.max_code_len;
     e.flags = 0;
+    e.skip = p.probe_skip;
     for (int k = 0; k < 4; k++) e.policy[k] = uint32_t(k) < e.B ? p.policy[k] : 0;
     return e;
 }
@@ -163,6 +164,7 @@ int zipnn_check_params(int dtype, const zipnn_params* p)
         return ZIPNN_E_INVAL;
     for (int k = 0; k < B; k++)
         if (p->policy[k] > ZIPNN_ZG) return ZIPNN_E_INVAL;
+    if (p->reserved[0] || p->reserved[1] || p->reserved[2]) return ZIPNN_E_INVAL;
     return ZIPNN_OK;
 }
 

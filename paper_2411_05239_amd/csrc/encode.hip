@@ -91,7 +91,7 @@ __device__ inline uint32_t count_le(const uint32_t* a, uint32_t n, uint32_t x)
 // first m items of a list select the first 2*(their count) items of the list
 // below; leaf i is selected at a level iff i < (leaves among the selected
 // items), so its length is the number of such levels.
-__device__ bool build_lengths(const uint32_t* fv, uint32_t tot, uint32_t raw, uint32_t head, uint32_t L,
+__device__ __attribute__((always_inline)) bool build_lengths(const uint32_t* fv, uint32_t tot, uint32_t raw, uint32_t head, uint32_t L,
                               bool shortcut, PmWave& P, uint32_t& T_out)
 {
     T_out = 0;
@@ -204,7 +204,7 @@ __device__ bool build_lengths(const uint32_t* fv, uint32_t tot, uint32_t raw, ui
 // codes[s] = code | length << 16 (0 for absent symbols).  The first code of
 // each length follows from the counts of the shorter ones; within a length
 // the codes follow the symbol order.
-__device__ void canonical_codes(const uint8_t* len, uint32_t L, CodeWord* codes)
+__device__ __attribute__((always_inline)) void canonical_codes(const uint8_t* len, uint32_t L, CodeWord* codes)
 {
     const int lane = threadIdx.x & 63;
     uint32_t l4[4];
@@ -317,7 +317,7 @@ __device__ inline bool marked(const uint32_t* wd, int k, uint32_t gcnt, uint32_t
 // groups that hold a value other than z: h[k][s] of this wave, except the
 // count of z itself, which is returned per stream (summed over the wave).
 template <int B, int G>
-__device__ void zg_count(const uint8_t* src, const uint8_t* base, uint32_t zc, const uint32_t* z, uint32_t m,
+__device__ __attribute__((always_inline)) void zg_count(const uint8_t* src, const uint8_t* base, uint32_t zc, const uint32_t* z, uint32_t m,
                          uint32_t (*h)[256], uint32_t* zcount)
 {
     constexpr int NB = B * G;
@@ -360,7 +360,7 @@ __device__ void zg_count(const uint8_t* src, const uint8_t* base, uint32_t zc, c
 // fill value z[k]) over the groups holding another value.  Lane 0 of the
 // wave writes the counts to lgw[0][k][j] and lgw[1][k][j].
 template <int B, int G>
-__device__ void count_lane_group(const uint8_t* src, const uint8_t* base, uint32_t hc, uint32_t zgc,
+__device__ __attribute__((always_inline)) void count_lane_group(const uint8_t* src, const uint8_t* base, uint32_t hc, uint32_t zgc,
                                  const uint8_t (*lens)[256], const uint8_t (*lens2)[256], const uint32_t* z,
                                  uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t (*lgw)[4][64])
 {
@@ -375,7 +375,7 @@ __device__ void count_lane_group(const uint8_t* src, const uint8_t* base, uint32
     uint32_t req[2][B];
 #pragma unroll
     for (int k = 0; k < B; k++) cnt[0][k] = cnt[1][k] = 0, req[0][k] = req[1][k] = 0;
-    constexpr uint32_t CB = NW >= 8 ? 4 : 8;   // groups in flight per lane
+    constexpr uint32_t CB = 4;   // groups in flight per lane
     for (uint32_t j0 = 0; j0 < ng; j0 += CB) {
         uint32_t wds[CB][NW];
 #pragma unroll
@@ -431,9 +431,13 @@ struct AnalyzeTail {
     uint32_t coded;          // bit k: coded (HUF or ZG chosen)
     uint32_t words[2][4];    // words over all lane groups, per stream: HUF, ZG
     uint32_t T[2][4];        // coded bits of the candidates: HUF, ZG
+    int pol[4];              // policy of each group in this chunk (RAW where probing skips it)
 };
 
-// One workgroup per chunk:
+// One workgroup per chunk (phase -1: every chunk; with a probe interval K,
+// phase 0: the probe chunks c mod (K+1) = 0 of each tensor, phase 1: the
+// others, where a byte group that the run's probe chunk stored raw is stored
+// raw without analysis under AUTO: compressibility probing, paper §III-B):
 //   1. histogram f of every byte group;
 //   2. wave k classifies group k: forced RAW, RLE (one value), else HUF
 //      lengths of f (unless ZG is forced) and, when ZG is forced or (AUTO)
@@ -446,9 +450,9 @@ struct AnalyzeTail {
 //      RAW then HUF), its entry, its lane-group word counts and its canonical
 //      code table.
 template <int BB>
-__global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
-                                                    EncParams p, EncEntry* __restrict__ entries,
+                                                    EncParams p, int phase, EncEntry* __restrict__ entries,
                                                     CodeWord* __restrict__ codes, uint32_t* __restrict__ nwords)
 {
     __shared__ AnalyzeLds S;
@@ -461,15 +465,36 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
         const int di = find_desc(chunk_prefix, n_desc, gc);
         const EncDesc d = descs[di];
         const uint32_t c = gc - chunk_prefix[di];
+        const uint32_t run = p.skip + 1;
+        const bool probe = c % run == 0;
+        if ((phase == 0 && !probe) || (phase == 1 && probe)) continue;
+        // the groups this chunk analyses (uniform: every thread reads the same entries)
+        uint32_t live = (1u << B) - 1;
+        if (!probe)
+            for (uint32_t k = 0; k < B; k++)
+                if (p.policy[k] == ZIPNN_AUTO && entries[uint64_t(gc - c % run) * B + k].mode == kModeRaw)
+                    live &= ~(1u << k);
         const uint32_t E = p.chunk / B;
         const uint64_t e0 = uint64_t(c) * E;
         const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
         const uint32_t W = (m + p.S - 1) / p.S;
         const uint32_t NG = (W + 63) / 64;
         const uint32_t head = huf_head(W), head_z = head + zg_bitmap(m, p.g);
+        if (live == 0) {
+            if (uint32_t(t) < B) {
+                EncEntry e;
+                e.pad = 0;
+                e.mode = kModeRaw;
+                e.rle = 0;
+                e.bytes = m;
+                entries[uint64_t(gc) * B + t] = e;
+            }
+            continue;
+        }
         for (uint32_t i = t; i < kWaves * 4 * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
         if (t == 0) A.open = A.hc = A.zc = A.zgc = A.fin = A.coded = 0;
         if (t < 8) (&A.words[0][0])[t] = 0;
+        if (t < 4) A.pol[t] = ((live >> t) & 1) ? int(p.policy[t]) : ZIPNN_RAW;
         __syncthreads();
         const uint8_t* src = d.src + e0 * B;
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
@@ -523,6 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
                 for (int jb = 0; jb < 16; jb++) {
                     const uint32_t byte = (wds[jb >> 2] >> (8 * (jb & 3))) & 0xFF;
                     const int k = int(B) - 1 - (jb % int(B));   // byte jb%B of a word -> stream B-1-jb%B
+                    if (!((live >> k) & 1)) continue;
                     const bool sk = SK >= 0 ? ((SK >> k) & 1) != 0 : ((skew >> k) & 1) != 0;
                     if (sk) {
                         const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
@@ -548,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
         }
         for (uint32_t b = nvec * 16 + t; b < nbytes; b += kBlock) {
             uint32_t byte = src[b] ^ (base ? base[b] : 0);
-            atomicAdd(&h[B - 1 - (b % B)][byte], 1u);
+            if ((live >> (B - 1 - (b % B))) & 1) atomicAdd(&h[B - 1 - (b % B)][byte], 1u);
         }
         __syncthreads();
         for (uint32_t i = t; i < 4 * 256; i += kBlock) {
@@ -559,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
         // 2. classification and HUF lengths, wave k for group k
         if (uint32_t(wv) < B) {
             const int k = wv;
-            const int policy = p.policy[k];
+            const int policy = A.pol[k];
             uint32_t fv[4], d = 0, best = 0, arg = 0;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
@@ -636,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
             __syncthreads();   // the sums are read before the workspace is reused
             if (uint32_t(wv) < B && ((A.zc >> wv) & 1)) {
                 const int k = wv;
-                const int policy = p.policy[k];
+                const int policy = A.pol[k];
                 if (d2 >= 2) {
                     uint32_t T;
                     const bool zgc = build_lengths(fv, tot, m, head_z, p.L, policy == ZIPNN_AUTO, S.pm[k], T);
@@ -663,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
         // AUTO with both candidates: a candidate that loses even at its best
         // (head + coded bits) against the other at its worst (plus two words
         // of padding per sub-stream) needs no replay; ties go to HUF
-        if (uint32_t(t) < B && p.policy[t] == ZIPNN_AUTO && ((A.hc & A.zgc) >> t & 1)) {
+        if (uint32_t(t) < B && A.pol[t] == ZIPNN_AUTO && ((A.hc & A.zgc) >> t & 1)) {
             const uint64_t h_lo = head + (A.T[0][t] + 7) / 8, h_hi = h_lo + 8 * W;
             const uint64_t z_lo = head_z + (A.T[1][t] + 7) / 8, z_hi = z_lo + 8 * W;
             if (z_hi < h_lo) atomicAnd(&A.hc, ~(1u << t));
@@ -675,23 +701,10 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
             for (uint32_t j0 = 0; j0 < NG; j0 += kWaves) {
                 const uint32_t j = j0 + wv;
                 if (j < NG) {
-                    switch (B * 16 + p.g) {
-#define ZIPNN_CASE(BX, GX)                                                                                   \
-    case BX * 16 + GX:                                                                                      \
-        count_lane_group<BX, GX>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw);        \
-        break;
-                        ZIPNN_CASE(1, 2)
-                        ZIPNN_CASE(1, 4)
-                        ZIPNN_CASE(1, 8)
-                        ZIPNN_CASE(2, 2)
-                        ZIPNN_CASE(2, 4)
-                        ZIPNN_CASE(2, 8)
-                        ZIPNN_CASE(4, 2)
-                        ZIPNN_CASE(4, 4)
-                        ZIPNN_CASE(4, 8)
-#undef ZIPNN_CASE
-                    default:
-                        break;
+                    switch (p.g) {
+                    case 2: count_lane_group<BB, 2>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw); break;
+                    case 4: count_lane_group<BB, 4>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw); break;
+                    default: count_lane_group<BB, 8>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw); break;
                     }
                     if (lane == 0) {
                         for (uint32_t k = 0; k < B; k++) {
@@ -705,7 +718,7 @@ __global__ __launch_bounds__(kBlock) void k_analyze(const EncDesc* __restrict__ 
         __syncthreads();
         // 5. the decision, the entry and the word counts of every open group
         if (uint32_t(t) < B && ((A.open >> t) & 1)) {
-            const int policy = p.policy[t];
+            const int policy = A.pol[t];
             const bool hc = (A.hc >> t) & 1, zgc = (A.zgc >> t) & 1;
             const uint32_t size_h = head + 4 * A.words[0][t], size_z = head_z + 4 * A.words[1][t];
             int mode = kModeRaw;
@@ -841,7 +854,8 @@ __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, i
         h[9] = uint32_t(total >> 32);
         h[10] = 0;
         for (uint32_t k = 0; k < B; k++) h[10] |= uint32_t(p.policy[k]) << (8 * k);
-        for (int x = 11; x < 16; x++) h[x] = 0;
+        h[11] = p.skip;   // byte 44: the probe interval
+        for (int x = 12; x < 16; x++) h[x] = 0;
         uint4* o = (uint4*)d.dst;
         for (int x = 0; x < 4; x++) o[x] = make_uint4(h[4 * x], h[4 * x + 1], h[4 * x + 2], h[4 * x + 3]);
         // zero padding between the map and the aligned payload area
@@ -882,7 +896,7 @@ constexpr uint32_t kPackQ = 32;
 constexpr uint32_t kPackLenBytes = 32 * 64;   // per wave: LR * 64 lanes * LB = 32 * 64 bytes for every g
 
 template <int B, int G, bool ZG>
-__device__ void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode, uint32_t z,
+__device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode, uint32_t z,
                                 uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out, uint32_t* qring,
                                 uint8_t* lring)
 {
@@ -1189,11 +1203,14 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
 {
     const uint32_t grid = min(max(total_chunks, 1u), 1u << 16);
     if (total_chunks) {
-        if (p.B == 1) k_analyze<1><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
-        else if (p.B == 2) k_analyze<2><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
-        else if (p.B == 4) k_analyze<4><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, nwords);
-        else return hipErrorInvalidValue;
-        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+        // with probing, the probe chunks first: the others read their entries
+        for (int phase = p.skip ? 0 : -1; phase <= (p.skip ? 1 : -1); phase++) {
+            if (p.B == 1) k_analyze<1><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
+            else if (p.B == 2) k_analyze<2><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
+            else if (p.B == 4) k_analyze<4><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
+            else return hipErrorInvalidValue;
+            if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+        }
     }
     k_place<<<n_desc, kBlock, 0, s>>>(d_descs, p, entries, offsets, totals);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;

@@ -92,7 +92,8 @@ __host__ __device__ inline int parse_header(const uint32_t* w, uint64_t src_len,
     if (dtype_bytes(int(h.dtype)) != int(h.B) || h.B == 0) return ZIPNN_E_FORMAT;
     if (check_params(int(h.B), h.chunk, h.S, h.g, h.L) != ZIPNN_OK) return ZIPNN_E_FORMAT;
     if (h.flags & ~(kFlagDelta | kFlagZg)) return ZIPNN_E_FORMAT;
-    for (int i = 11; i < 16; i++)
+    if (w[11] & ~0xFFu) return ZIPNN_E_FORMAT;   // byte 44 is the probe interval
+    for (int i = 12; i < 16; i++)
         if (w[i]) return ZIPNN_E_FORMAT;
     h.E = h.chunk / h.B;
     if ((h.n + h.E - 1) / h.E != h.n_chunks) return ZIPNN_E_FORMAT;
@@ -140,6 +141,7 @@ using CodeWord = uint32_t;
 
 struct EncParams {
     uint32_t dtype, B, chunk, S, g, L, flags;
+    uint32_t skip;         // probe interval K (0: every chunk analysed)
     uint8_t policy[4];
 };
 

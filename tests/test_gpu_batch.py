@@ -20,7 +20,8 @@ def codec():
 
 
 def _kw(p):
-    return dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy))
+    return dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy),
+                skip=p.probe_skip)
 
 
 def _u8(t):

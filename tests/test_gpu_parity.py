@@ -25,7 +25,8 @@ def codec():
 
 
 def _oracle_kw(p):
-    return dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy))
+    return dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy),
+                skip=p.probe_skip)
 
 
 def _u8(t):
@@ -260,3 +261,32 @@ def test_api_argument_errors(codec):
     bad = Z.make_params(Z.ZIPNN_BF16, g=3)
     with pytest.raises(Z.ZipnnError):
         Z.zipnn_compress(codec.ctx, x.data_ptr(), Z.ZIPNN_BF16, 10, None, bad, dst.data_ptr(), 64, codec._stream())
+
+
+@pytest.mark.parametrize("K", [1, 7])
+def test_probe_skip_fp32(codec, K):
+    """Compressibility probing (probe interval K): FP32 rows whose low byte
+    groups are incompressible; the chunks after a probe store them raw
+    without analysis, exactly as the oracle does."""
+    x = workloads.fp32_rows(64, 8192, seed=21).reshape(-1)[: 9 * 65536 + 1001].clone()
+    p = Z.make_params(Z.ZIPNN_FP32, probe_skip=K)
+    c = roundtrip(codec, x, p)
+    assert oracle.header(c.cpu().numpy())["skip"] == K
+
+
+def test_probe_skip_mixed_chunks_and_batch(codec):
+    """Random, then normal, then zero chunks (the normal chunks after a raw
+    probe stay raw until the next probe), alone and in a batch where each
+    tensor counts its chunks from zero."""
+    E = 131072
+    mixed = torch.cat([torch.randint(0, 65536, (3 * E,), generator=torch.Generator().manual_seed(5),
+                                     dtype=torch.int32).to(torch.int16).view(torch.bfloat16),
+                       workloads.bf16_normal(4 * E, seed=6), torch.zeros(2 * E + 7, dtype=torch.bfloat16)])
+    p = Z.make_params(Z.ZIPNN_BF16, probe_skip=3)
+    roundtrip(codec, mixed, p)
+    xs = [mixed[: 5 * E + 3].cuda(), workloads.bf16_normal(3 * E + 11, seed=7).cuda(), mixed[E:].cuda()]
+    arena, offs = codec.compress_batch(xs, p)
+    a = arena.cpu().numpy()
+    for i, x in enumerate(xs):
+        ref = oracle.compress(x.cpu(), oracle.BF16, nthreads=8, **_oracle_kw(p))
+        assert np.array_equal(a[offs[i]: offs[i] + ref.size], ref), i
