@@ -71,7 +71,7 @@ def lib():
             build()
         L = ctypes.CDLL(LIB_PATH)
         u8p, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
-        L.orc_compress.argtypes = [u8p, i32, u64, u8p, u32, u32, u32, u32, u8p, u32, u8p, u64,
+        L.orc_compress.argtypes = [u8p, i32, u64, u8p, u32, u32, u32, u32, u8p, u32, i32, u8p, u64,
                                    ctypes.POINTER(u64), i32]
         L.orc_compress.restype = i32
         L.orc_decompress.argtypes = [u8p, u64, u8p, u8p, u64, i32]
@@ -106,7 +106,7 @@ def as_bytes(x) -> np.ndarray:
 
 
 def compress(x, dtype: int, *, base=None, chunk_bytes: int = 262144, S: int = 512, g: int = 4, L: int = 11,
-             policy=(AUTO, AUTO, AUTO, AUTO), skip: int = 0, nthreads: int = 1) -> np.ndarray:
+             policy=(AUTO, AUTO, AUTO, AUTO), skip: int = 0, exp: bool = False, nthreads: int = 1) -> np.ndarray:
     xb = as_bytes(x)
     B = WIDTH[dtype]
     assert xb.size % B == 0
@@ -119,7 +119,7 @@ def compress(x, dtype: int, *, base=None, chunk_bytes: int = 262144, S: int = 51
     out = np.zeros(max(cap, 64), dtype=np.uint8)
     pol = np.array(list(policy) + [0] * (4 - len(policy)), dtype=np.uint8)
     dlen = ctypes.c_uint64(0)
-    rc = lib().orc_compress(_ptr(xb), dtype, n, _ptr(bb), chunk_bytes, S, g, L, _ptr(pol), skip, _ptr(out), out.size,
+    rc = lib().orc_compress(_ptr(xb), dtype, n, _ptr(bb), chunk_bytes, S, g, L, _ptr(pol), skip, int(exp), _ptr(out), out.size,
                             ctypes.byref(dlen), nthreads)
     if rc != OK:
         raise OracleError(rc, "compress")

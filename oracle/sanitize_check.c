@@ -60,7 +60,8 @@ int main(void)
         uint8_t* c = (uint8_t*)malloc(cap + 1);
         uint64_t clen = 0;
         const uint32_t skip = rnd() % 4;
-        if (orc_compress(x, dtype, n, base, chunk, S, g, L, policy, skip, c, cap, &clen, 2) != ORC_OK) {
+        const int exp = (dtype == ORC_BF16 || dtype == ORC_FP32) ? (int)(rnd() & 1) : 0;
+        if (orc_compress(x, dtype, n, base, chunk, S, g, L, policy, skip, exp, c, cap, &clen, 2) != ORC_OK) {
             printf("compress failed at %d\n", it);
             return 1;
         }

@@ -42,6 +42,21 @@ def split(words: np.ndarray, B: int) -> list[np.ndarray]:
     return [a[:, B - 1 - k].copy() for k in range(B)]
 
 
+def extract_exponent(raw: np.ndarray, B: int, inverse: bool = False) -> np.ndarray:
+    """Exponent extraction (§III-A): sign, exponent, fraction -> exponent,
+    sign, fraction, on little-endian words viewed as unsigned integers."""
+    w = raw.view(np.uint16 if B == 2 else np.uint32).astype(np.uint64)
+    nb = 8 * B
+    frac_mask = (1 << (nb - 9)) - 1
+    if not inverse:
+        sign, exp = w >> (nb - 1), (w >> (nb - 9)) & 0xFF
+        out = (exp << (nb - 8)) + (sign << (nb - 9)) + (w & frac_mask)
+    else:
+        exp, sign = w >> (nb - 8), (w >> (nb - 9)) & 1
+        out = (sign << (nb - 1)) + (exp << (nb - 9)) + (w & frac_mask)
+    return out.astype(np.uint16 if B == 2 else np.uint32).view(np.uint8)
+
+
 def merge(streams: list[np.ndarray], B: int) -> np.ndarray:
     m = len(streams[0])
     a = np.zeros((m, B), dtype=np.uint8)
@@ -211,11 +226,14 @@ def encode_stream(sym: np.ndarray, S: int, g: int, L: int, policy: int) -> tuple
 
 
 def compress(words: np.ndarray, dtype: int, *, base: np.ndarray | None = None, chunk_bytes: int = 262144,
-             S: int = 512, g: int = 4, L: int = 11, policy=(AUTO, AUTO, AUTO, AUTO), skip: int = 0) -> bytes:
+             S: int = 512, g: int = 4, L: int = 11, policy=(AUTO, AUTO, AUTO, AUTO), skip: int = 0,
+             exp: bool = False) -> bytes:
     B = WIDTH[dtype]
     raw = np.ascontiguousarray(words).view(np.uint8).reshape(-1)
     if base is not None:
         raw = raw ^ np.ascontiguousarray(base).view(np.uint8).reshape(-1)
+    if exp:
+        raw = extract_exponent(np.ascontiguousarray(raw), B)
     n = raw.size // B
     E = chunk_bytes // B
     n_chunks = -(-n // E)
@@ -238,7 +256,7 @@ def compress(words: np.ndarray, dtype: int, *, base: np.ndarray | None = None, c
             body += bytes(_apay(len(body)) - len(body))
     total = payload_base + len(body)
     pol = bytes(list(policy[:B]) + [0] * (4 - B))
-    flags = (1 if base is not None else 0) | (2 if any(e[0] == MODE_ZG for e in entries) else 0)
+    flags = (1 if base is not None else 0) | (2 if any(e[0] == MODE_ZG for e in entries) else 0) | (4 if exp else 0)
     hdr = b"ZNN1" + struct.pack("<HBBQIHBBIIQ", 1, dtype, B, n, chunk_bytes, S, g, L,
                                 flags, n_chunks, total) + pol + bytes([skip]) + bytes(19)
     assert len(hdr) == 64
@@ -271,6 +289,8 @@ def decompress(blob: bytes, base: np.ndarray | None = None) -> np.ndarray:
             else:
                 raise SpecError("mode")
         out[c * E * B: (c * E + m) * B] = merge(streams, B)
+    if flags & 4:
+        out = extract_exponent(out, B, inverse=True)
     if base is not None:
         out ^= np.ascontiguousarray(base).view(np.uint8).reshape(-1)
     return out

@@ -102,6 +102,33 @@ void orc_split_stream(const uint8_t* words, uint64_t m, int B, int k, uint8_t* o
     for (uint64_t j = 0; j < m; j++) out[j] = words[j * (uint64_t)B + (uint64_t)(B - 1 - k)];
 }
 
+/* Exponent extraction (paper §III-A, "Exponent Extraction"): in a BF16 or
+ * FP32 word (sign, 8 exponent bits, fraction from the top) the exponent moves
+ * to the top 8 bits and the sign right below it, so that the first byte group
+ * holds exactly the exponent.  The fraction bits keep their places.  The
+ * m little-endian words of B bytes are rewritten in place; `inverse` undoes
+ * it. */
+static void exponent_extract(uint8_t* words, uint64_t m, int B, int inverse)
+{
+    const int nb = 8 * B;
+    for (uint64_t i = 0; i < m; i++) {
+        uint32_t w = 0;
+        for (int b = 0; b < B; b++) w |= (uint32_t)words[i * B + b] << (8 * b);
+        const uint32_t frac = w & ((1u << (nb - 9)) - 1);
+        uint32_t sign, exp, out;
+        if (!inverse) {
+            sign = (w >> (nb - 1)) & 1;
+            exp = (w >> (nb - 9)) & 0xFF;
+            out = (exp << (nb - 8)) | (sign << (nb - 9)) | frac;
+        } else {
+            exp = (w >> (nb - 8)) & 0xFF;
+            sign = (w >> (nb - 9)) & 1;
+            out = (sign << (nb - 1)) | (exp << (nb - 9)) | frac;
+        }
+        for (int b = 0; b < B; b++) words[i * B + b] = (uint8_t)(out >> (8 * b));
+    }
+}
+
 /* Inverse of orc_split_stream for one stream. */
 static void merge_stream(const uint8_t* in, uint64_t m, int B, int k, uint8_t* words)
 {
@@ -600,6 +627,7 @@ typedef struct {
     int L;
     const uint8_t* policy;
     uint32_t skip;        /* probe interval K (0: every chunk is analysed) */
+    int exp;              /* exponent extraction before the split */
     int phase;            /* 0: probe chunks, 1: the others */
     stream_out* outs;     /* n_chunks * B */
     uint32_t n_chunks;
@@ -624,6 +652,7 @@ static int encode_chunk(enc_job* J, uint32_t c)
         uint8_t x = J->src[e0 * J->B + i];
         words[i] = J->base ? (uint8_t)(x ^ J->base[e0 * J->B + i]) : x;
     }
+    if (J->exp) exponent_extract(words, m, J->B, 0);
     int rc = ORC_OK;
     for (int k = 0; k < J->B && rc == ORC_OK; k++) {
         /* compressibility probing (paper §III-B, "Identifying compressibility"):
@@ -696,8 +725,8 @@ uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes, uint32_
 }
 
 int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, uint32_t chunk_bytes,
-                 uint32_t S, uint32_t g, uint32_t L, const uint8_t* policy_in, uint32_t skip, void* dst_v,
-                 uint64_t dst_cap, uint64_t* dst_len, int nthreads)
+                 uint32_t S, uint32_t g, uint32_t L, const uint8_t* policy_in, uint32_t skip, int exp,
+                 void* dst_v, uint64_t dst_cap, uint64_t* dst_len, int nthreads)
 {
     const uint8_t* src = (const uint8_t*)src_v;
     const uint8_t* base = (const uint8_t*)base_v;
@@ -712,6 +741,7 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
         if (policy[k] > ORC_POLICY_ZG) return ORC_E_INVAL;
     }
     if (skip > 255) return ORC_E_INVAL;
+    if (exp && dtype != ORC_BF16 && dtype != ORC_FP32) return ORC_E_INVAL;
     uint32_t E = chunk_bytes / (uint32_t)B;
     uint64_t nc64 = (n + E - 1) / E;
     if (nc64 > 0xFFFFFFFFu) return ORC_E_INVAL;
@@ -729,6 +759,7 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
     J.L = (int)L;
     J.policy = policy;
     J.skip = skip;
+    J.exp = exp != 0;
     J.n_chunks = n_chunks;
     J.outs = (stream_out*)calloc((size_t)n_chunks * B + 1, sizeof(stream_out));
     if (!J.outs) return ORC_E_NOMEM;
@@ -761,7 +792,7 @@ int orc_compress(const void* src_v, int dtype, uint64_t n, const void* base_v, u
         put_u16(dst + 20, (uint16_t)S);
         dst[22] = (uint8_t)g;
         dst[23] = (uint8_t)L;
-        uint32_t fl = base ? ORC_FLAG_DELTA : 0;
+        uint32_t fl = (base ? ORC_FLAG_DELTA : 0) | (exp ? ORC_FLAG_EXP : 0);
         for (uint64_t e = 0; e < (uint64_t)n_chunks * B; e++)
             if (J.outs[e].mode == ORC_MODE_ZG) fl |= ORC_FLAG_ZG;
         put_u32(dst + 24, fl);
@@ -808,7 +839,8 @@ int orc_parse_header(const void* src_v, uint64_t src_len, orc_header* h)
     h->skip = src[44];
     if (dtype_width(h->dtype) == 0 || dtype_width(h->dtype) != h->B) return ORC_E_FORMAT;
     if (orc_check_params(h->B, h->chunk_bytes, h->S, h->g, h->L) != ORC_OK) return ORC_E_FORMAT;
-    if (h->flags & ~(uint32_t)(ORC_FLAG_DELTA | ORC_FLAG_ZG)) return ORC_E_FORMAT;
+    if (h->flags & ~(uint32_t)(ORC_FLAG_DELTA | ORC_FLAG_ZG | ORC_FLAG_EXP)) return ORC_E_FORMAT;
+    if ((h->flags & ORC_FLAG_EXP) && h->dtype != ORC_BF16 && h->dtype != ORC_FP32) return ORC_E_FORMAT;
     for (int i = 45; i < 64; i++)
         if (src[i]) return ORC_E_FORMAT;
     uint64_t E = h->chunk_bytes / h->B;
@@ -859,6 +891,7 @@ static int decode_chunk(dec_job* J, uint32_t c)
         if (rc == ORC_OK) merge_stream(s, m, h->B, k, words);
     }
     if (rc == ORC_OK) {
+        if (h->flags & ORC_FLAG_EXP) exponent_extract(words, m, h->B, 1);
         for (uint64_t i = 0; i < m * h->B; i++) {
             uint8_t y = words[i];
             J->dst[e0 * h->B + i] = J->base ? (uint8_t)(y ^ J->base[e0 * h->B + i]) : y;

@@ -10,7 +10,9 @@
  *     32 u64 total_bytes   40 u8 policy[4]        44 u8 probe interval K
  *     45..63 zero
  *   flags: bit0 XOR delta; bit1 the map holds ZG entries (written when it
- *     does; a ZG entry without it is corrupt); other bits zero.
+ *     does; a ZG entry without it is corrupt); bit2 exponent extraction
+ *     (BF16 / FP32 only: before the split, each word's exponent moves to its
+ *     top 8 bits and the sign right below them); other bits zero.
  *   map at 64: n_chunks*B entries of 16 bytes, chunk-major (entry c*B+k):
  *     u64 offset from payload_base | u32 bytes | u8 mode | u8 value | u16 0
  *     (value: the RLE byte, or the ZG fill byte; zero otherwise)
@@ -56,7 +58,7 @@ enum {
 enum { ORC_BF16 = 1, ORC_FP16 = 2, ORC_FP32 = 3, ORC_FP8_E4M3 = 4, ORC_U8 = 5 };
 enum { ORC_POLICY_AUTO = 0, ORC_POLICY_HUF = 1, ORC_POLICY_RAW = 2, ORC_POLICY_ZG = 3 };
 enum { ORC_MODE_RAW = 0, ORC_MODE_HUF = 1, ORC_MODE_RLE = 2, ORC_MODE_ZG = 3 };
-enum { ORC_FLAG_DELTA = 1, ORC_FLAG_ZG = 2 };
+enum { ORC_FLAG_DELTA = 1, ORC_FLAG_ZG = 2, ORC_FLAG_EXP = 4 };
 
 #define ORC_MIN_CHUNK 256u
 #define ORC_MAX_CHUNK (4u << 20)
@@ -86,9 +88,10 @@ void orc_canonical_codes(const uint8_t len[256], int L, uint32_t code[256]);
 uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes, uint32_t S);
 /* skip: probe interval K (0..255).  Chunk c of the tensor is a probe chunk
  * when c mod (K+1) = 0; under AUTO the K chunks after a probe chunk are
- * stored raw without analysis in every byte group the probe stored raw. */
+ * stored raw without analysis in every byte group the probe stored raw.
+ * exp: exponent extraction (BF16 and FP32 only). */
 int orc_compress(const void* src, int dtype, uint64_t n, const void* base, uint32_t chunk_bytes, uint32_t S,
-                 uint32_t g, uint32_t L, const uint8_t* policy, uint32_t skip, void* dst, uint64_t dst_cap,
+                 uint32_t g, uint32_t L, const uint8_t* policy, uint32_t skip, int exp, void* dst, uint64_t dst_cap,
                  uint64_t* dst_len, int nthreads);
 int orc_parse_header(const void* src, uint64_t src_len, orc_header* h);
 int orc_decompress(const void* src, uint64_t src_len, const void* base, void* dst, uint64_t dst_cap,

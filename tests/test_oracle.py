@@ -222,10 +222,11 @@ def _read_fixture(name):
 
 
 @pytest.mark.parametrize("name", ["tiny_bf16_container.txt", "tiny_u8_rounds.txt", "tiny_u8_zg.txt",
-                                  "tiny_u8_probe.txt"])
+                                  "tiny_u8_probe.txt", "tiny_bf16_exp.txt"])
 def test_tiny_containers_match_hand_derivation(oracle_lib, name):
     words, p, expect = _read_fixture(name)
-    kw = dict(chunk_bytes=p["chunk_bytes"], S=p["S"], g=p["g"], L=p["L"], policy=p["policy"], skip=p.get("skip", 0))
+    kw = dict(chunk_bytes=p["chunk_bytes"], S=p["S"], g=p["g"], L=p["L"], policy=p["policy"], skip=p.get("skip", 0),
+              exp=bool(p.get("exp", 0)))
     c = oracle.compress(words, p["dtype"], **kw)
     assert c.tobytes() == expect
     assert spec.compress(words, p["dtype"], **kw) == expect
@@ -595,3 +596,66 @@ def test_probing_follows_its_definition(oracle_lib, K):
                         assert oracle.entry(got, c, k)[1] == r[1]
         if dt == oracle.BF16:
             assert skipped > 0   # compressible chunks after a raw probe stay raw until the next probe
+
+
+# ----------------------------------------------------------- exponent extraction
+
+def test_exponent_extraction_groups_are_the_fields(oracle_lib):
+    """With exponent extraction the raw byte groups are the IEEE fields,
+    computed here with numpy from the bit layout: BF16 group 0 = exponent,
+    group 1 = sign << 7 | fraction; FP32 group 0 = exponent, group 1 =
+    sign << 7 | fraction[22:16], groups 2, 3 = fraction bytes."""
+    xb = workloads.bf16_normal(3000, seed=8)
+    w = xb.view(torch.int16).numpy().view(np.uint16).astype(np.uint32)
+    c = oracle.compress(xb, oracle.BF16, chunk_bytes=1 << 16, policy=(oracle.RAW,) * 2, exp=True)
+    groups = [(w >> 7) & 0xFF, ((w >> 15) << 7) | (w & 0x7F)]
+    for k in range(2):
+        off, nb, mode, _ = oracle.entry(c, 0, k)
+        assert mode == oracle.MODE_RAW and np.array_equal(c[off:off + nb], groups[k].astype(np.uint8))
+    xf = workloads.fp32_rows(3, 1000, seed=9).reshape(-1)
+    w = xf.numpy().view(np.uint32).astype(np.uint64)
+    c = oracle.compress(xf, oracle.FP32, chunk_bytes=1 << 16, policy=(oracle.RAW,) * 4, exp=True)
+    groups = [(w >> 23) & 0xFF, ((w >> 31) << 7) | ((w >> 16) & 0x7F), (w >> 8) & 0xFF, w & 0xFF]
+    for k in range(4):
+        off, nb, mode, _ = oracle.entry(c, 0, k)
+        assert np.array_equal(c[off:off + nb], groups[k].astype(np.uint8)), k
+    assert np.array_equal(oracle.decompress(c), oracle.as_bytes(xf))
+
+
+def test_exponent_extraction_sizes_follow_the_entropy(oracle_lib):
+    """On N(0, 0.02) BF16 weights the exponent group's empirical entropy is
+    below that of the sign + 7 exponent bits byte; the Huffman payloads of
+    both stay within [entropy bound, entropy + 1 bit + padding], so the
+    extracted container is smaller by about the entropy difference."""
+    x = workloads.bf16_normal(4 * 131072, seed=10)
+    w = x.view(torch.int16).numpy().view(np.uint16)
+
+    def H(b):
+        f = np.bincount(b, minlength=256)
+        p = f[f > 0] / f.sum()
+        return float(-(p * np.log2(p)).sum())
+
+    h_plain, h_exp = H((w >> 8).astype(np.uint8)), H(((w >> 7) & 0xFF).astype(np.uint8))
+    assert h_exp < h_plain - 0.05
+    pol = (oracle.HUF, oracle.RAW)
+    a = oracle.compress(x, oracle.BF16, policy=pol)
+    b = oracle.compress(x, oracle.BF16, policy=pol, exp=True)
+    m = x.numel()
+    saved = sum(oracle.entry(a, c, 0)[1] - oracle.entry(b, c, 0)[1] for c in range(4))
+    assert abs(saved - m * (h_plain - h_exp) / 8) < 0.02 * m
+    assert np.array_equal(oracle.decompress(b), oracle.as_bytes(x))
+    assert spec.compress(oracle.as_bytes(x)[: 2 * 4096], oracle.BF16, chunk_bytes=4096, S=64, exp=True) == \
+        oracle.compress(oracle.as_bytes(x)[: 2 * 4096], oracle.BF16, chunk_bytes=4096, S=64, exp=True).tobytes()
+
+
+def test_exponent_extraction_only_for_bf16_fp32(oracle_lib):
+    with pytest.raises(oracle.OracleError):
+        oracle.compress(np.zeros(16, np.uint8), oracle.FP8_E4M3, exp=True)
+    with pytest.raises(oracle.OracleError):
+        oracle.compress(np.zeros(16, np.uint16), oracle.FP16, exp=True)
+    c = oracle.compress(np.zeros(16, np.uint8), oracle.U8)
+    d = c.copy()
+    d[24] |= 4   # the flag on a U8 container
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.decompress(d)
+    assert ei.value.code == oracle.E_FORMAT

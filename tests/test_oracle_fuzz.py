@@ -30,7 +30,8 @@ def cases(draw):
     with_base = draw(st.booleans())
     seed = draw(st.integers(min_value=0, max_value=2**31 - 1))
     skip = draw(st.sampled_from([0, 0, 1, 2, 5]))
-    return dtype, B, chunk, S, g, L, n, kind, policy, with_base, seed, skip
+    exp = dtype in (oracle.BF16, oracle.FP32) and draw(st.booleans())
+    return dtype, B, chunk, S, g, L, n, kind, policy, with_base, seed, skip, exp
 
 
 def _bytes(kind, n, B, rng):
@@ -56,13 +57,13 @@ def _bytes(kind, n, B, rng):
 @settings(max_examples=120, deadline=None, suppress_health_check=[HealthCheck.too_slow])
 @given(cases())
 def test_oracle_and_spec_agree_and_round_trip(oracle_lib, case):
-    dtype, B, chunk, S, g, L, n, kind, policy, with_base, seed, skip = case
+    dtype, B, chunk, S, g, L, n, kind, policy, with_base, seed, skip, exp = case
     rng = np.random.default_rng(seed)
     x = _bytes(kind, n, B, rng)
     base = rng.integers(0, 256, size=n * B, dtype=np.uint8) if with_base else None
     if with_base:
         x = x ^ base   # the XOR of x with base is then the chosen distribution
-    kw = dict(chunk_bytes=chunk, S=S, g=g, L=L, policy=list(policy), skip=skip)
+    kw = dict(chunk_bytes=chunk, S=S, g=g, L=L, policy=list(policy), skip=skip, exp=exp)
     c = oracle.compress(x, dtype, base=base, **kw)
     assert np.array_equal(oracle.decompress(c, base=base), x)
     ref = spec.compress(x, dtype, base=base, **kw)
