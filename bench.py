@@ -51,7 +51,7 @@ def _traffic(workload: str, alg_bytes: int):
         return None
 
 
-def make_workload(name: str, probe_skip: int = 0):
+def make_workload(name: str, probe_skip: int = 0, exponent: bool = False):
     import torch
 
     from paper_2411_05239_amd import workloads
@@ -59,16 +59,16 @@ def make_workload(name: str, probe_skip: int = 0):
 
     if name == "fp32_256mb":
         x = workloads.fp32_rows(8192, 8192, seed=1)
-        p = Z.make_params(Z.ZIPNN_FP32, probe_skip=probe_skip)
+        p = Z.make_params(Z.ZIPNN_FP32, probe_skip=probe_skip, exponent=exponent)
         desc = {"workload": "fp32_8192x8192_rowsigma_loguniform_1e-3_1e-1", "dtype": "fp32", "elements": x.numel(),
                 "bytes": x.numel() * 4, "chunk_bytes": p.chunk_bytes, "S": p.substream_syms, "g": p.group,
-                "L": p.max_code_len, "policy": "auto", "probe_skip": p.probe_skip}
+                "L": p.max_code_len, "policy": "auto", "probe_skip": p.probe_skip, "exponent": p.exponent}
     elif name == "bf16_8mb":
         x = workloads.bf16_normal(4_194_304, seed=0)
-        p = Z.make_params(Z.ZIPNN_BF16, policy=[Z.ZIPNN_HUF, Z.ZIPNN_RAW], probe_skip=probe_skip)
+        p = Z.make_params(Z.ZIPNN_BF16, policy=[Z.ZIPNN_HUF, Z.ZIPNN_RAW], probe_skip=probe_skip, exponent=exponent)
         desc = {"workload": "bf16_4194304_normal_0.02", "dtype": "bf16", "elements": x.numel(),
                 "bytes": x.numel() * 2, "chunk_bytes": p.chunk_bytes, "S": p.substream_syms, "g": p.group,
-                "L": p.max_code_len, "policy": "huf,raw", "probe_skip": p.probe_skip}
+                "L": p.max_code_len, "policy": "huf,raw", "probe_skip": p.probe_skip, "exponent": p.exponent}
     else:
         raise SystemExit(f"unknown workload {name}")
     return x, p, desc
@@ -86,7 +86,7 @@ def cpu_baseline(x_cpu, p, gpu_container, budget_s: float):
     code = Z.torch_dtype_code(x_cpu.dtype)
     threads = max(1, min(16, os.cpu_count() or 1))
     kw = dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy),
-              skip=p.probe_skip)
+              skip=p.probe_skip, exp=bool(p.exponent))
     t0 = time.perf_counter()
     c = oracle.compress(x_cpu, code, nthreads=threads, **kw)
     t_enc = time.perf_counter() - t0
@@ -111,7 +111,7 @@ def run_single(args):
 
     from paper_2411_05239_amd import zipnn as Z
 
-    x_cpu, p, desc = make_workload(args.workload, args.probe_skip)
+    x_cpu, p, desc = make_workload(args.workload, args.probe_skip, args.exponent)
     dev = torch.device("cuda", 0)
     x = x_cpu.to(dev)
     U = x.numel() * x.element_size()
@@ -231,7 +231,7 @@ def cpu_baseline_sample(xs, bases, p, arena_np, offs, budget_s):
 
     threads = max(1, min(16, os.cpu_count() or 1))
     kw = dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy),
-              skip=p.probe_skip)
+              skip=p.probe_skip, exp=bool(p.exponent))
     idx, tot = [], 0
     for i, x in enumerate(xs):
         if tot >= (512 << 20):
@@ -296,6 +296,7 @@ def run_checkpoint(args, delta: bool):
     best, table = Z.zipnn_autotune(codec.ctx, Z.ZIPNN_BF16, [x.data_ptr() for x in xs], [x.numel() for x in xs],
                                    bptr, 1 << 30, 0.01, policy)
     best.probe_skip = args.probe_skip
+    best.exponent = int(args.exponent)
     arena, offs = codec.compress_batch(xs, best, bases)
     outs = [torch.empty_like(x) for x in xs]
     batch = codec.prepare_batch(arena, offs, outs, bases)
@@ -358,6 +359,7 @@ def run_checkpoint(args, delta: bool):
         "config": {"workload": ("xor_delta_of_" if delta else "") + "bf16_8b_decoder_checkpoint_291_tensors",
                    "tensors": len(xs), "bytes": U, "chunk_bytes": best.chunk_bytes, "S": best.substream_syms,
                    "g": best.group, "L": best.max_code_len, "policy": "auto", "probe_skip": best.probe_skip,
+                   "exponent": best.exponent,
                    "batched": "one launch per kernel + hipGraph replay"},
         "decode_ms": {"mean": round(dec_avg, 4), "median": round(statistics.median(dec_ms), 4)},
         "encode_GBps": round(U / (statistics.mean(enc_ms) * 1e-3) / 1e9, 2),
@@ -533,6 +535,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=4.0)
     ap.add_argument("--decode-only", action="store_true", help="time decode launches only (for profiling)")
+    ap.add_argument("--exponent", action="store_true",
+                    help="exponent extraction (BF16 / FP32): the exponent byte is exactly the 8 exponent bits")
     ap.add_argument("--probe-skip", type=int, default=0,
                     help="compressibility probing interval K for the single-tensor workloads (0: off)")
     args = ap.parse_args()

@@ -26,7 +26,7 @@
  * of this project writes):
  *   header (64 B): "ZNN1" | u16 version=1 | u8 dtype | u8 B | u64 n_elems |
  *     u32 chunk_bytes | u16 S | u8 g | u8 L | u32 flags (bit0 = XOR delta, bit1 = the
- *     map holds ZG entries) |
+ *     map holds ZG entries, bit2 = exponent extraction) |
  *     u32 n_chunks | u64 total_bytes | u8 policy[4] | u8 probe interval K |
  *     19 zero bytes
  *   map: n_chunks*B entries of 16 B, chunk-major: u64 payload offset (from
@@ -117,6 +117,11 @@ typedef enum {
  *                   analysing it, when the probe chunk stored it raw.  0
  *                   (the default) analyses every chunk.  Stored in header
  *                   byte 44.
+ *   exponent        1: exponent extraction (paper §III-A, BF16 and FP32
+ *                   only): before the split each word's 8 exponent bits move
+ *                   to its top byte and the sign right below them, so byte
+ *                   group 0 is exactly the exponent (header flag bit 2).
+ *                   0 (the default): plain byte grouping.
  *   reserved        zero */
 typedef struct {
     uint32_t chunk_bytes;
@@ -125,7 +130,8 @@ typedef struct {
     uint8_t max_code_len;
     uint8_t policy[4];
     uint8_t probe_skip;
-    uint8_t reserved[3];
+    uint8_t exponent;
+    uint8_t reserved[2];
 } zipnn_params;
 
 /* Summary of a container, filled by zipnn_inspect from host bytes. */

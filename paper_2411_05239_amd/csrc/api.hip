@@ -64,7 +64,7 @@ EncParams make_params(int dtype, const zipnn_params& p)
     e.S = p.substream_syms;
     e.g = p.group;
     e.L = p.max_code_len;
-    e.flags = 0;
+    e.flags = p.exponent ? kFlagExp : 0u;
     e.skip = p.probe_skip;
     for (int k = 0; k < 4; k++) e.policy[k] = uint32_t(k) < e.B ? p.policy[k] : 0;
     return e;
@@ -164,7 +164,8 @@ int zipnn_check_params(int dtype, const zipnn_params* p)
         return ZIPNN_E_INVAL;
     for (int k = 0; k < B; k++)
         if (p->policy[k] > ZIPNN_ZG) return ZIPNN_E_INVAL;
-    if (p->reserved[0] || p->reserved[1] || p->reserved[2]) return ZIPNN_E_INVAL;
+    if (p->reserved[0] || p->reserved[1]) return ZIPNN_E_INVAL;
+    if (p->exponent > 1 || (p->exponent && dtype != ZIPNN_BF16 && dtype != ZIPNN_FP32)) return ZIPNN_E_INVAL;
     return ZIPNN_OK;
 }
 

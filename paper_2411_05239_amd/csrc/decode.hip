@@ -417,7 +417,7 @@ template <int B, int G, bool DELTA, bool ZGK>
 __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* __restrict__ src, const ItemState& st, uint32_t* wring,
                                   const uint16_t (*lut)[kLutSize], const uint32_t (*wprefix)[65], uint32_t L,
                                   uint32_t j, uint32_t W, uint32_t m, uint8_t* __restrict__ out,
-                                  const uint8_t* __restrict__ base, int* status)
+                                  const uint8_t* __restrict__ base, int* status, bool xf)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
@@ -578,6 +578,9 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                 }
                 uint32_t ow[NW];
                 merge_words<B, G>(pk, ow);
+                if (xf)
+#pragma unroll
+                    for (int x = 0; x < NW; x++) ow[x] = exp_inv<B>(ow[x]);
                 if constexpr (DELTA) {
 #pragma unroll
                     for (int x = 0; x < NW; x++) ow[x] ^= bring[u][x];
@@ -657,6 +660,9 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
             }
             uint32_t ow[NW];
             merge_words<B, G>(pk, ow);
+            if (xf)
+#pragma unroll
+                for (int x = 0; x < NW; x++) ow[x] = exp_inv<B>(ow[x]);
             if constexpr (DELTA) {
 #pragma unroll
                 for (int x = 0; x < NW; x++) ow[x] ^= bring[u][x];
@@ -665,9 +671,10 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
             if (full) {
                 buf_store<NB>(ro, q * G * B, ow);
             } else if (has) {
-                // the partial last group of a tensor: one byte at a time
+                // the partial last group of a tensor: one element at a time
                 const uint32_t e = q * G;
                 for (uint32_t i = 0; i < gcnt; i++) {
+                    uint32_t word = 0;
 #pragma unroll
                     for (int b = 0; b < B; b++) {
                         const int k = B - 1 - b;
@@ -680,7 +687,13 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                                 if (i >= 4u * x) v = pk[k][x];
                             v = (v >> (8 * (i & 3))) & 0xFFu;
                         }
+                        word |= v << (8 * b);
+                    }
+                    if (xf) word = exp_inv<B>(word);
+#pragma unroll
+                    for (int b = 0; b < B; b++) {
                         const uint64_t o = uint64_t(e + i) * B + b;
+                        const uint32_t v = (word >> (8 * b)) & 0xFFu;
                         out[o] = DELTA ? uint8_t(v ^ base[o]) : uint8_t(v);
                     }
                 }
@@ -822,7 +835,8 @@ __device__ __attribute__((always_inline)) void decode_item(const DecDesc& d, con
     if (j < NG) {
         uint8_t* out = d.dst + uint64_t(c) * h.E * B;
         const uint8_t* base = DELTA ? d.base + uint64_t(c) * h.E * B : nullptr;
-        decode_lane_group<B, G, DELTA, ZGK>(d.src, st, wring, lut, wprefix, h.L, j, W, m, out, base, status);
+        decode_lane_group<B, G, DELTA, ZGK>(d.src, st, wring, lut, wprefix, h.L, j, W, m, out, base, status,
+                                            (h.flags & kFlagExp) != 0);
     }
     __syncthreads();
 }

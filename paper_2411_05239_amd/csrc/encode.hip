@@ -261,10 +261,12 @@ __device__ inline void loadNB(const uint8_t* p, uint32_t* w)
     }
 }
 
-// The words of group q of a chunk (g elements, XORed with the base), or of the
-// partial last group (zero beyond the chunk's m elements).
+// The words of group q of a chunk (g elements, XORed with the base, then with
+// the exponent extracted when xf), or of the partial last group (zero beyond
+// the chunk's m elements).
 template <int B, int G>
-__device__ inline void group_words(const uint8_t* src, const uint8_t* base, uint32_t q, uint32_t m, uint32_t* wd)
+__device__ inline void group_words(const uint8_t* src, const uint8_t* base, uint32_t q, uint32_t m, uint32_t* wd,
+                                   bool xf)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
@@ -293,6 +295,23 @@ __device__ inline void group_words(const uint8_t* src, const uint8_t* base, uint
             }
         }
     }
+    if (xf)
+#pragma unroll
+        for (int x = 0; x < NW; x++) wd[x] = exp_fwd<B>(wd[x]);
+}
+
+// Element e of a chunk as a little-endian word (XORed with the base, exponent
+// extracted when xf), read byte by byte.
+template <int B>
+__device__ inline uint32_t element_word(const uint8_t* src, const uint8_t* base, uint32_t e, bool xf)
+{
+    uint32_t v = 0;
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        const uint64_t o = uint64_t(e) * B + b;
+        v |= uint32_t(src[o] ^ (base ? base[o] : 0u)) << (8 * b);
+    }
+    return xf ? exp_fwd<B>(v) : v;
 }
 
 // byte of stream k of element i of a group's words
@@ -318,7 +337,7 @@ __device__ inline bool marked(const uint32_t* wd, int k, uint32_t gcnt, uint32_t
 // count of z itself, which is returned per stream (summed over the wave).
 template <int B, int G>
 __device__ __attribute__((always_inline)) void zg_count(const uint8_t* src, const uint8_t* base, uint32_t zc, const uint32_t* z, uint32_t m,
-                         uint32_t (*h)[256], uint32_t* zcount)
+                         uint32_t (*h)[256], uint32_t* zcount, bool xf)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
@@ -331,7 +350,7 @@ __device__ __attribute__((always_inline)) void zg_count(const uint8_t* src, cons
         uint32_t wds[CB][NW];
 #pragma unroll
         for (uint32_t u = 0; u < CB; u++)
-            if (q0 + u * kBlock < Gtot) group_words<B, G>(src, base, q0 + u * kBlock, m, wds[u]);
+            if (q0 + u * kBlock < Gtot) group_words<B, G>(src, base, q0 + u * kBlock, m, wds[u], xf);
 #pragma unroll
         for (uint32_t u = 0; u < CB; u++) {
             const uint32_t q = q0 + u * kBlock;
@@ -362,7 +381,7 @@ __device__ __attribute__((always_inline)) void zg_count(const uint8_t* src, cons
 template <int B, int G>
 __device__ __attribute__((always_inline)) void count_lane_group(const uint8_t* src, const uint8_t* base, uint32_t hc, uint32_t zgc,
                                  const uint8_t (*lens)[256], const uint8_t (*lens2)[256], const uint32_t* z,
-                                 uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t (*lgw)[4][64])
+                                 uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t (*lgw)[4][64], bool xf)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
@@ -380,7 +399,7 @@ __device__ __attribute__((always_inline)) void count_lane_group(const uint8_t* s
         uint32_t wds[CB][NW];
 #pragma unroll
         for (uint32_t u = 0; u < CB; u++)
-            if (j0 + u < ng) group_words<B, G>(src, base, w + (j0 + u) * W, m, wds[u]);
+            if (j0 + u < ng) group_words<B, G>(src, base, w + (j0 + u) * W, m, wds[u], xf);
 #pragma unroll
         for (uint32_t u = 0; u < CB; u++) {
             const uint32_t jj = j0 + u;
@@ -499,6 +518,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         const uint8_t* src = d.src + e0 * B;
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
         const uint32_t nbytes = m * B;
+        const bool xf = (p.flags & kFlagExp) != 0;
         uint32_t(*h)[256] = S.hist[wv];
         // 16-byte vectors; the element boundary is aligned since 16 % B == 0
         const uint32_t nvec = nbytes / 16;
@@ -513,6 +533,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 const uint4 y = ((const uint4*)base)[t];
                 x.x ^= y.x;
             }
+            if (xf) x.x = exp_fwd<B>(x.x);
             for (uint32_t k = 0; k < B; k++) {
                 const uint32_t byte = (x.x >> (8 * (B - 1 - k))) & 0xFFu;
                 const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
@@ -537,6 +558,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                           xs[i].y ^= y.y;
                           xs[i].z ^= y.z;
                           xs[i].w ^= y.w;
+                      }
+                      if (xf) {
+                          xs[i].x = exp_fwd<B>(xs[i].x);
+                          xs[i].y = exp_fwd<B>(xs[i].y);
+                          xs[i].z = exp_fwd<B>(xs[i].z);
+                          xs[i].w = exp_fwd<B>(xs[i].w);
                       }
                   }
               }
@@ -572,9 +599,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             else if (B >= 2 && skew == 3) count(integral_constant<int, B >= 2 ? 3 : -1>{});
             else count(integral_constant<int, -1>{});
         }
-        for (uint32_t b = nvec * 16 + t; b < nbytes; b += kBlock) {
-            uint32_t byte = src[b] ^ (base ? base[b] : 0);
-            if ((live >> (B - 1 - (b % B))) & 1) atomicAdd(&h[B - 1 - (b % B)][byte], 1u);
+        // the elements after the last whole vector
+        for (uint32_t e = nvec * 16 / B + t; e < m; e += kBlock) {
+            const uint32_t v = element_word<B>(src, base, e, xf);
+            for (uint32_t b = 0; b < B; b++)
+                if ((live >> (B - 1 - b)) & 1) atomicAdd(&h[B - 1 - b][(v >> (8 * b)) & 0xFFu], 1u);
         }
         __syncthreads();
         for (uint32_t i = t; i < 4 * 256; i += kBlock) {
@@ -635,9 +664,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             __syncthreads();
             uint32_t zn[4] = {0, 0, 0, 0};
             switch (p.g) {
-            case 2: zg_count<BB, 2>(src, base, A.zc, A.z, m, S.hist[wv], zn); break;
-            case 4: zg_count<BB, 4>(src, base, A.zc, A.z, m, S.hist[wv], zn); break;
-            default: zg_count<BB, 8>(src, base, A.zc, A.z, m, S.hist[wv], zn); break;
+            case 2: zg_count<BB, 2>(src, base, A.zc, A.z, m, S.hist[wv], zn, xf); break;
+            case 4: zg_count<BB, 4>(src, base, A.zc, A.z, m, S.hist[wv], zn, xf); break;
+            default: zg_count<BB, 8>(src, base, A.zc, A.z, m, S.hist[wv], zn, xf); break;
             }
             if (lane == 0)
                 for (uint32_t k = 0; k < B; k++) zsum[wv][k] = zn[k];
@@ -702,9 +731,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 const uint32_t j = j0 + wv;
                 if (j < NG) {
                     switch (p.g) {
-                    case 2: count_lane_group<BB, 2>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw); break;
-                    case 4: count_lane_group<BB, 4>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw); break;
-                    default: count_lane_group<BB, 8>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw); break;
+                    case 2: count_lane_group<BB, 2>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw, xf); break;
+                    case 4: count_lane_group<BB, 4>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw, xf); break;
+                    default: count_lane_group<BB, 8>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw, xf); break;
                     }
                     if (lane == 0) {
                         for (uint32_t k = 0; k < B; k++) {
@@ -848,7 +877,7 @@ __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, i
         h[3] = uint32_t(d.n >> 32);
         h[4] = p.chunk;
         h[5] = p.S | (p.g << 16) | (p.L << 24);
-        h[6] = (d.base ? kFlagDelta : 0u) | (d.has_zg ? kFlagZg : 0u);
+        h[6] = (d.base ? kFlagDelta : 0u) | (d.has_zg ? kFlagZg : 0u) | (p.flags & kFlagExp);
         h[7] = d.n_chunks;
         h[8] = uint32_t(total);
         h[9] = uint32_t(total >> 32);
@@ -898,7 +927,7 @@ constexpr uint32_t kPackLenBytes = 32 * 64;   // per wave: LR * 64 lanes * LB = 
 template <int B, int G, bool ZG>
 __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode, uint32_t z,
                                 uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out, uint32_t* qring,
-                                uint8_t* lring)
+                                uint8_t* lring, bool xf)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
@@ -923,7 +952,7 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
         qt++;
     };
     auto load = [&](uint32_t e, uint32_t* wd) {
-        if (e < ng) group_words<B, G>(src, base, w + e * W, m, wd);
+        if (e < ng) group_words<B, G>(src, base, w + e * W, m, wd, xf);
     };
     auto encode = [&](uint32_t e, const uint32_t* wd) {
         if (e >= ng) return;
@@ -1033,7 +1062,7 @@ struct PackLds {
 // the padding are zero.
 template <int B, int G>
 __device__ void pack_bitmap(const uint8_t* src, const uint8_t* base, int k, uint32_t z, uint32_t m, uint32_t bm,
-                            uint8_t* dst)
+                            uint8_t* dst, bool xf)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
@@ -1044,7 +1073,7 @@ __device__ void pack_bitmap(const uint8_t* src, const uint8_t* base, int k, uint
         bool mk = false;
         if (q < Gtot) {
             uint32_t wd[NW];
-            group_words<B, G>(src, base, q, m, wd);
+            group_words<B, G>(src, base, q, m, wd, xf);
             mk = marked<B, G>(wd, k, min(uint32_t(G), m - q * G), z);
         }
         const uint64_t bits = __ballot(mk);
@@ -1055,7 +1084,7 @@ __device__ void pack_bitmap(const uint8_t* src, const uint8_t* base, int k, uint
 // Raw groups of one chunk: thread t copies elements [16u, 16u+16) of every
 // RAW stream with one 16-byte store each.
 template <int B>
-__device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, const PackLds& P, uint32_t m)
+__device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, const PackLds& P, uint32_t m, bool xf)
 {
     uint32_t rawmask = 0;
     for (int k = 0; k < B; k++)
@@ -1076,6 +1105,9 @@ __device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, 
 #pragma unroll
                     for (int x = 0; x < 4 * B; x++) wds[r][x] ^= bw[x];
                 }
+                if (xf)
+#pragma unroll
+                    for (int x = 0; x < 4 * B; x++) wds[r][x] = exp_fwd<B>(wds[r][x]);
             }
         }
 #pragma unroll
@@ -1093,16 +1125,10 @@ __device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, 
     }
     // tail elements, then zero padding to the payload alignment
     for (uint32_t e = units * 16 + threadIdx.x; e < uint32_t(align_pay(m)); e += kBlock) {
+        const uint32_t v = e < m ? element_word<B>(src, base, e, xf) : 0u;
 #pragma unroll
-        for (int k = 0; k < B; k++) {
-            if (!((rawmask >> k) & 1)) continue;
-            uint32_t v = 0;
-            if (e < m) {
-                const uint64_t o = uint64_t(e) * B + (B - 1 - k);
-                v = src[o] ^ (base ? base[o] : 0u);
-            }
-            dst[P.pay[k] + e] = uint8_t(v);
-        }
+        for (int k = 0; k < B; k++)
+            if ((rawmask >> k) & 1) dst[P.pay[k] + e] = uint8_t(v >> (8 * (B - 1 - k)));
     }
 }
 
@@ -1169,7 +1195,8 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
         const uint8_t* src = d.src + e0 * B;
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
         uint8_t* dst = d.dst;
-        pack_raw<BB>(src, base, dst, P, m);
+        const bool xf = (p.flags & kFlagExp) != 0;
+        pack_raw<BB>(src, base, dst, P, m, xf);
         for (uint32_t k = 0; k < B; k++) {
             const bool zg = P.mode[k] == kModeZg;
             if (P.mode[k] != kModeHuf && !zg) continue;
@@ -1180,15 +1207,15 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
             for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
             for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
             const uint32_t bm = zg ? zg_bitmap(m, GG) : 0u;
-            if (zg) pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + head);
+            if (zg) pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + head, xf);
             uint32_t* words = (uint32_t*)(pay + head + bm);
             for (uint32_t j = wv; j < NG; j += kWaves) {
                 if (zg)
                     pack_lane_group<BB, GG, true>(src, base, int(k), P.rcode[k], P.z[k], p.L, j, W, m,
-                                                  words + P.wpre[k][j], qpool[wv], lpool[wv]);
+                                                  words + P.wpre[k][j], qpool[wv], lpool[wv], xf);
                 else
                     pack_lane_group<BB, GG, false>(src, base, int(k), P.rcode[k], 0u, p.L, j, W, m,
-                                                   words + P.wpre[k][j], qpool[wv], lpool[wv]);
+                                                   words + P.wpre[k][j], qpool[wv], lpool[wv], xf);
             }
         }
         __syncthreads();

@@ -23,6 +23,7 @@ constexpr uint32_t kMaxBW = 8192;          // sub-streams per chunk over all B s
 constexpr uint32_t kLutSize = 1u << kMaxL;  // decode table entries per stream
 constexpr uint32_t kFlagDelta = 1;
 constexpr uint32_t kFlagZg = 2;               // the map holds ZG entries
+constexpr uint32_t kFlagExp = 4;              // exponent extraction (BF16 / FP32)
 constexpr int kModeRaw = 0, kModeHuf = 1, kModeRle = 2, kModeZg = 3;
 constexpr int kBlock = 256;                 // threads per workgroup (4 waves)
 
@@ -68,6 +69,26 @@ __host__ __device__ inline uint32_t zg_bitmap(uint32_t m, uint32_t g)
     return uint32_t(align16(((m + g - 1) / g + 7) / 8));
 }
 
+// Exponent extraction (paper §III-A) on a register of little-endian words:
+// BF16 (B = 2, two words) or FP32 (B = 4).  Forward: sign | exponent |
+// fraction becomes exponent | sign | fraction, so the top byte of a word is
+// its exponent; the fraction bits stay.  exp_inv undoes it.  Other widths
+// pass through.
+template <int B>
+__host__ __device__ inline uint32_t exp_fwd(uint32_t x)
+{
+    if constexpr (B == 2) return ((x << 1) & 0xFF00FF00u) | ((x >> 8) & 0x00800080u) | (x & 0x007F007Fu);
+    else if constexpr (B == 4) return ((x << 1) & 0xFF000000u) | ((x >> 8) & 0x00800000u) | (x & 0x007FFFFFu);
+    else return x;
+}
+template <int B>
+__host__ __device__ inline uint32_t exp_inv(uint32_t x)
+{
+    if constexpr (B == 2) return ((x >> 1) & 0x7F807F80u) | ((x << 8) & 0x80008000u) | (x & 0x007F007Fu);
+    else if constexpr (B == 4) return ((x >> 1) & 0x7F800000u) | ((x << 8) & 0x80000000u) | (x & 0x007FFFFFu);
+    else return x;
+}
+
 struct Header {
     uint64_t n, total, payload_base;
     uint32_t dtype, B, chunk, S, g, L, flags, n_chunks, E;
@@ -91,7 +112,8 @@ __host__ __device__ inline int parse_header(const uint32_t* w, uint64_t src_len,
     h.total = uint64_t(w[8]) | (uint64_t(w[9]) << 32);
     if (dtype_bytes(int(h.dtype)) != int(h.B) || h.B == 0) return ZIPNN_E_FORMAT;
     if (check_params(int(h.B), h.chunk, h.S, h.g, h.L) != ZIPNN_OK) return ZIPNN_E_FORMAT;
-    if (h.flags & ~(kFlagDelta | kFlagZg)) return ZIPNN_E_FORMAT;
+    if (h.flags & ~(kFlagDelta | kFlagZg | kFlagExp)) return ZIPNN_E_FORMAT;
+    if ((h.flags & kFlagExp) && h.dtype != ZIPNN_BF16 && h.dtype != ZIPNN_FP32) return ZIPNN_E_FORMAT;
     if (w[11] & ~0xFFu) return ZIPNN_E_FORMAT;   // byte 44 is the probe interval
     for (int i = 12; i < 16; i++)
         if (w[i]) return ZIPNN_E_FORMAT;

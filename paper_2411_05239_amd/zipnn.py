@@ -43,11 +43,11 @@ class ZipnnError(RuntimeError):
 class zipnn_params(ctypes.Structure):
     _fields_ = [("chunk_bytes", ctypes.c_uint32), ("substream_syms", ctypes.c_uint16),
                 ("group", ctypes.c_uint8), ("max_code_len", ctypes.c_uint8), ("policy", ctypes.c_uint8 * 4),
-                ("probe_skip", ctypes.c_uint8), ("reserved", ctypes.c_uint8 * 3)]
+                ("probe_skip", ctypes.c_uint8), ("exponent", ctypes.c_uint8), ("reserved", ctypes.c_uint8 * 2)]
 
     def __repr__(self):
         return (f"zipnn_params(chunk_bytes={self.chunk_bytes}, S={self.substream_syms}, g={self.group}, "
-                f"L={self.max_code_len}, policy={list(self.policy)}, K={self.probe_skip})")
+                f"L={self.max_code_len}, policy={list(self.policy)}, K={self.probe_skip}, exp={self.exponent})")
 
 
 class zipnn_info(ctypes.Structure):
@@ -326,7 +326,8 @@ def torch_dtype_code(dt) -> int:
 
 
 def make_params(dtype: int, chunk_bytes: int | None = None, S: int | None = None, g: int | None = None,
-                L: int | None = None, policy=None, probe_skip: int | None = None) -> zipnn_params:
+                L: int | None = None, policy=None, probe_skip: int | None = None,
+                exponent: bool | None = None) -> zipnn_params:
     p = zipnn_default_params(dtype)
     if chunk_bytes is not None:
         p.chunk_bytes = chunk_bytes
@@ -343,6 +344,8 @@ def make_params(dtype: int, chunk_bytes: int | None = None, S: int | None = None
             p.policy[k] = v
     if probe_skip is not None:
         p.probe_skip = probe_skip
+    if exponent is not None:
+        p.exponent = int(exponent)
     p.substream_syms = max(p.substream_syms, p.group)
     return p
 

@@ -21,7 +21,7 @@ def codec():
 
 def _kw(p):
     return dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy),
-                skip=p.probe_skip)
+                skip=p.probe_skip, exp=bool(p.exponent))
 
 
 def _u8(t):

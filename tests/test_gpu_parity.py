@@ -26,7 +26,7 @@ def codec():
 
 def _oracle_kw(p):
     return dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy),
-                skip=p.probe_skip)
+                skip=p.probe_skip, exp=bool(p.exponent))
 
 
 def _u8(t):
@@ -290,3 +290,33 @@ def test_probe_skip_mixed_chunks_and_batch(codec):
     for i, x in enumerate(xs):
         ref = oracle.compress(x.cpu(), oracle.BF16, nthreads=8, **_oracle_kw(p))
         assert np.array_equal(a[offs[i]: offs[i] + ref.size], ref), i
+
+
+@pytest.mark.parametrize("n", [1, 4 * 131072 + 3, 3 * 131072 + 37])
+def test_exponent_extraction_bf16(codec, n):
+    """Exponent extraction (header flag bit 2) on BF16: AUTO, and forced
+    HUF/RAW with a ragged tail (the partial last group decodes element by
+    element through the inverse transform)."""
+    x = workloads.bf16_normal(n, seed=31)
+    c = roundtrip(codec, x, Z.make_params(Z.ZIPNN_BF16, exponent=True))
+    assert oracle.header(c.cpu().numpy())["flags"] & 4
+    roundtrip(codec, x, Z.make_params(Z.ZIPNN_BF16, policy=[Z.ZIPNN_HUF, Z.ZIPNN_RAW], exponent=True, g=8))
+
+
+def test_exponent_extraction_fp32_delta_zg_probe(codec):
+    """FP32 with exponent extraction, alone, as an XOR delta (where ZG
+    streams appear), and with probing."""
+    x = workloads.fp32_rows(16, 65536 + 5, seed=32).reshape(-1)
+    roundtrip(codec, x, Z.make_params(Z.ZIPNN_FP32, exponent=True))
+    roundtrip(codec, x, Z.make_params(Z.ZIPNN_FP32, exponent=True, probe_skip=3))
+    w = workloads.bf16_normal(2 * 131072 + 9, seed=33)
+    ft = workloads.finetune_delta(w, seed=34)
+    c = roundtrip(codec, ft, Z.make_params(Z.ZIPNN_BF16, exponent=True), base_cpu=w)
+    assert oracle.header(c.cpu().numpy())["flags"] == 1 | 2 | 4
+
+
+def test_exponent_extraction_only_bf16_fp32(codec):
+    x = torch.zeros(1024, dtype=torch.float16, device="cuda")
+    with pytest.raises(Z.ZipnnError) as ei:
+        codec.compress(x, Z.make_params(Z.ZIPNN_FP16, exponent=True))
+    assert ei.value.code == Z.ZIPNN_E_INVAL
