@@ -542,8 +542,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         }
         skew = __builtin_amdgcn_readfirstlane(skew);
         // SK: the skewed streams, known here (or -1: tested per byte)
-        auto count = [&](auto sk_const) {
+        // LV: every group is live (no per-byte test)
+        auto count = [&](auto sk_const, auto lv_const) {
             constexpr int SK = decltype(sk_const)::value;
+            constexpr bool LV = decltype(lv_const)::value;
             constexpr uint32_t HB = 8;   // vectors in flight per lane
             for (uint32_t v0 = t; v0 < nvec; v0 += HB * kBlock) {
               uint4 xs[HB];
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 for (int jb = 0; jb < 16; jb++) {
                     const uint32_t byte = (wds[jb >> 2] >> (8 * (jb & 3))) & 0xFF;
                     const int k = int(B) - 1 - (jb % int(B));   // byte jb%B of a word -> stream B-1-jb%B
-                    if (!((live >> k) & 1)) continue;
+                    if (!LV && !((live >> k) & 1)) continue;
                     const bool sk = SK >= 0 ? ((SK >> k) & 1) != 0 : ((skew >> k) & 1) != 0;
                     if (sk) {
                         const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
@@ -594,10 +596,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         };
         {
             using std::integral_constant;
-            if (skew == 0) count(integral_constant<int, 0>{});
-            else if (skew == 1) count(integral_constant<int, 1>{});
-            else if (B >= 2 && skew == 3) count(integral_constant<int, B >= 2 ? 3 : -1>{});
-            else count(integral_constant<int, -1>{});
+            using T = integral_constant<bool, true>;
+            if (live != (1u << B) - 1) count(integral_constant<int, -1>{}, integral_constant<bool, false>{});
+            else if (skew == 0) count(integral_constant<int, 0>{}, T{});
+            else if (skew == 1) count(integral_constant<int, 1>{}, T{});
+            else if (B >= 2 && skew == 3) count(integral_constant<int, B >= 2 ? 3 : -1>{}, T{});
+            else count(integral_constant<int, -1>{}, T{});
         }
         // the elements after the last whole vector
         for (uint32_t e = nvec * 16 / B + t; e < m; e += kBlock) {
