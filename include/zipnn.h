@@ -259,8 +259,9 @@ typedef struct {
 
 /* Pick format parameters for a set of tensors of `dtype` by measurement on
  * this GPU: a sample (tensors in order, up to sample_bytes) is compressed and
- * batch-decompressed under every candidate chunk size (64 KiB .. 1 MiB) and
- * sub-stream length S (chunk elements / 128 .. / 1024), with `policy` (NULL:
+ * batch-decompressed under every candidate chunk size (64 KiB .. 4 MiB) and
+ * sub-stream length S (chunk elements / 256 .. / 2048, within the limits of
+ * zipnn_check_params), with `policy` (NULL:
  * AUTO).  *best gets the fastest decode among the candidates whose ratio is
  * within (1 + max_ratio_loss) of the best ratio seen; entries[0..max_entries)
  * receive the measurements (*n_entries = how many candidates ran).  Blocking;

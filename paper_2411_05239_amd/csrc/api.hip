@@ -500,11 +500,12 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
         sbytes += t.n_elems * uint64_t(B);
     }
     if (smp.empty()) return ZIPNN_E_INVAL;
-    // candidate formats: chunk size x sub-stream length
+    // candidate formats: chunk size x sub-stream length, with at least 256
+    // sub-streams per chunk (a decode workgroup's four lane groups)
     std::vector<zipnn_params> cands;
-    for (uint32_t chunk = 64u << 10; chunk <= (1u << 20); chunk <<= 1) {
+    for (uint32_t chunk = 64u << 10; chunk <= (4u << 20); chunk <<= 1) {
         const uint32_t E = chunk / uint32_t(B);
-        for (uint32_t div = 128; div <= 1024; div <<= 1) {
+        for (uint32_t div = 256; div <= 2048; div <<= 1) {
             zipnn_params p;
             zipnn_default_params(dtype, &p);
             p.chunk_bytes = chunk;

@@ -197,3 +197,26 @@ def test_checkpoint_8b_delta_full(codec):
         ref = oracle.compress(ft[i].cpu(), oracle.BF16, base=base[i].cpu(), nthreads=16, **_kw(p))
         got = arena[offs[i]: offs[i] + ref.size].cpu().numpy()
         assert np.array_equal(got, ref), i
+
+
+def test_autotune_picks_fastest_within_ratio_loss(codec):
+    """The autotuner measures every candidate (chunk 64 KiB..4 MiB x at least
+    256 sub-streams per chunk) on a sample and returns the fastest decode
+    whose ratio is within (1 + loss) of the best; its pick compresses to the
+    oracle's bytes."""
+    xs = [x.cuda() for x in _small_checkpoint(seed0=300)]
+    loss = 0.01
+    best, table = Z.zipnn_autotune(codec.ctx, Z.ZIPNN_BF16, [x.data_ptr() for x in xs], [x.numel() for x in xs],
+                                   [None] * len(xs), 64 << 20, loss, None)
+    assert len(table) >= 20
+    for e in table:
+        E = e.params.chunk_bytes // 2
+        assert 64 << 10 <= e.params.chunk_bytes <= 4 << 20 and E // e.params.substream_syms >= 256
+    r0 = min(e.ratio for e in table)
+    ok = [e for e in table if e.ratio <= r0 * (1 + loss)]
+    pick = max(ok, key=lambda e: e.decode_gbps)
+    assert (best.chunk_bytes, best.substream_syms) == (pick.params.chunk_bytes, pick.params.substream_syms)
+    x = xs[1]
+    c = codec.compress(x, best)
+    ref = oracle.compress(x.cpu(), oracle.BF16, nthreads=8, **_kw(best))
+    assert np.array_equal(c.cpu().numpy(), ref)
