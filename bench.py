@@ -445,6 +445,62 @@ def _serve_pass(Z, srv, handles, sizes, rate, count, seed):
             "p99_phase_ms": {k: round(_pct(v, 0.99) * 1e3, 4) for k, v in ph.items()}}
 
 
+def run_series(args):
+    """Periodic-base storage of an 11-checkpoint training-like run of a
+    0.7 GB BF16 decoder (paper §IV-B "Periodic Base"): total compressed
+    fraction and the restore time of the checkpoint with the longest chain,
+    for standalone storage and for chain / pairs policies with periods 5 and
+    10."""
+    import torch
+
+    from paper_2411_05239_amd import workloads
+    from paper_2411_05239_amd import zipnn as Z
+    from paper_2411_05239_amd.series import CheckpointSeries
+
+    specs = workloads.checkpoint_8b_specs(layers=4, hidden=2048, kv=512, ffn=7168, vocab=32000, seed0=5000)
+    model = [workloads.make_tensor(sp, device="cuda") for sp in specs]
+    steps = 11
+    traj = workloads.trajectory(model, steps=steps, seed=5100)
+    U = sum(x.numel() * 2 for x in model)
+    codec = Z.Codec(0)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, period, mode in [("standalone", 1, "pairs"), ("chain_p5", 5, "chain"), ("chain_p10", 10, "chain"),
+                               ("pairs_p5", 5, "pairs"), ("pairs_p10", 10, "pairs")]:
+        ser = CheckpointSeries(codec, period, mode)
+        for ck in traj:
+            ser.append(ck)
+        total = sum(st.nbytes for st in ser.stored)
+        worst = max(range(steps), key=lambda t: len(ser.chain(t)))
+        outs = [torch.empty_like(x) for x in traj[worst]]
+        times = []
+        for r in range(args.warmup + max(2, min(args.steps, 5))):
+            a0, a1 = _events()
+            a0.record(stream)
+            n = ser.restore(worst, outs)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            if r >= args.warmup:
+                times.append(a0.elapsed_time(a1))
+        if not all(torch.equal(o.view(torch.uint8), x.view(torch.uint8)) for o, x in zip(outs, traj[worst])):
+            print(json.dumps({"error": f"series restore mismatch ({name})"}))
+            sys.exit(1)
+        res[name] = {"fraction": round(total / (steps * U), 5), "worst_checkpoint": worst, "decodes": n,
+                     "restore_ms": round(statistics.median(times), 3),
+                     "delta_fractions": [round(st.nbytes / U, 4) for st in ser.stored]}
+        del ser
+        torch.cuda.empty_cache()
+    rec = {
+        "metric": "periodic-base checkpoint storage: compressed bytes / raw bytes of the whole run",
+        "value": res["chain_p10"]["fraction"], "unit": "fraction", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "bf16_0.7gb_decoder_training_run_11_checkpoints", "checkpoint_bytes": U,
+                   "trajectory": "p_t = 0.3*0.7^t, sigma_t = 3e-4*0.7^t", "params": "defaults (AUTO, ZG allowed)"},
+        "policies": res,
+    }
+    print(json.dumps(rec))
+
+
 def run_serve(args):
     """Serving loop: a corpus of 128 tensors (64 KiB - 1 GiB log-uniform,
     60/30/10 BF16/FP32/FP8) resident compressed; Poisson request streams at
@@ -530,7 +586,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fp32_256mb",
-                    choices=["bf16_8mb", "fp32_256mb", "ckpt8b", "ckpt8b_delta", "serve"])
+                    choices=["bf16_8mb", "fp32_256mb", "ckpt8b", "ckpt8b_delta", "serve", "series"])
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=4.0)
@@ -547,6 +603,8 @@ def main():
         run_serve(args)
     elif args.workload in ("ckpt8b", "ckpt8b_delta"):
         run_checkpoint(args, delta=args.workload == "ckpt8b_delta")
+    elif args.workload == "series":
+        run_series(args)
     else:
         run_single(args)
 

@@ -13,6 +13,8 @@ Generators:
   checkpoint_8b   -- the 291 tensors of an 8B decoder checkpoint (BF16)
   finetune_delta  -- a fine-tuned copy: N(0, 1e-4) noise on a Bernoulli(0.1) mask
   pruned          -- a copy with a Bernoulli(1 - density) share of its values set to zero
+  trajectory      -- training-like checkpoint sequence: each step updates a Bernoulli(p_t)
+                     share of the values by N(0, sigma_t), with p_t and sigma_t decaying
   serving_corpus  -- tensors of log-uniform size, 60% BF16 / 30% FP32 / 10% FP8
 """
 from __future__ import annotations
@@ -103,6 +105,24 @@ def pruned(w: torch.Tensor, density: float, seed: int) -> torch.Tensor:
     """w with each value kept with probability `density`, else set to +0."""
     keep = torch.rand(w.numel(), generator=_gen(seed, w.device), device=w.device) < density
     return torch.where(keep, w.reshape(-1), torch.zeros((), dtype=w.dtype, device=w.device)).reshape(w.shape)
+
+
+def trajectory(ws: list, steps: int, seed: int, p0: float = 0.3, sigma0: float = 3e-4,
+               decay: float = 0.7) -> list:
+    """Checkpoints 0..steps-1 of a training-like run from the tensors ws:
+    checkpoint t+1 = bf16(fp32(checkpoint t) + M * Z) with M ~ Bernoulli(p0
+    decay^t) and Z ~ N(0, sigma0 decay^t), per tensor, seeded by (seed, t,
+    tensor index).  Changes shrink and thin out as the run converges."""
+    out = [list(ws)]
+    for t in range(steps - 1):
+        cur = []
+        for i, w in enumerate(out[-1]):
+            g = _gen(seed * 1000003 + t * 1009 + i, w.device)
+            m = torch.rand(w.numel(), generator=g, device=w.device) < p0 * decay ** t
+            z = torch.randn(w.numel(), generator=g, device=w.device) * (sigma0 * decay ** t)
+            cur.append((w.float().reshape(-1) + m * z).to(w.dtype).reshape(w.shape))
+        out.append(cur)
+    return out
 
 
 FP8_MAX = 448.0

@@ -29,7 +29,10 @@ def codec():
 @pytest.fixture(scope="module")
 def corpus(codec):
     """Small mixed corpus: BF16 / FP32 / FP8, sizes from 64 KiB to 6 MiB,
-    ragged element counts, two chunk sizes, one XOR delta, one empty."""
+    ragged element counts, two chunk sizes, XOR deltas (Huffman only, and
+    AUTO with ZG streams), a pruned tensor (ZG), exponent extraction,
+    probing, and one empty tensor: several decode kernel classes share the
+    server's iterations."""
     items = workloads.serving_corpus(count=14, seed=3100, min_bytes=64 << 10, max_bytes=6 << 20)
     out = []
     for it in items:
@@ -43,6 +46,17 @@ def corpus(codec):
     ft = workloads.finetune_delta(w, seed=3151)
     c = codec.compress(ft, Z.make_params(Z.ZIPNN_BF16, policy=[1, 1]), base=w).clone()
     out.append(dict(x=ft, c=c, base=w))
+    w2 = workloads.bf16_normal(500_003, seed=3152, device="cuda")
+    ft2 = workloads.finetune_delta(w2, seed=3153)
+    c = codec.compress(ft2, Z.zipnn_default_params(Z.ZIPNN_BF16), base=w2).clone()
+    assert oracle.header(c[:64].cpu().numpy())["flags"] & 2   # ZG entries
+    out.append(dict(x=ft2, c=c, base=w2))
+    pr = workloads.pruned(workloads.bf16_normal(400_001, seed=3154, device="cuda"), 0.05, seed=3155)
+    out.append(dict(x=pr, c=codec.compress(pr).clone(), base=None))
+    ex = workloads.bf16_normal(300_007, seed=3156, device="cuda")
+    out.append(dict(x=ex, c=codec.compress(ex, Z.make_params(Z.ZIPNN_BF16, exponent=True)).clone(), base=None))
+    fp = workloads.fp32_rows(8, 70_001, seed=3157, device="cuda").reshape(-1)
+    out.append(dict(x=fp, c=codec.compress(fp, Z.make_params(Z.ZIPNN_FP32, probe_skip=3)).clone(), base=None))
     e = torch.empty(0, dtype=torch.bfloat16, device="cuda")
     out.append(dict(x=e, c=codec.compress(e).clone(), base=None))
     torch.cuda.synchronize()
@@ -136,7 +150,7 @@ def test_request_larger_than_pool(codec, corpus):
 
 def test_register_rejects(codec, corpus):
     srv = Z.Server(codec, pool_bytes=1 << 20)
-    d = corpus[-2]   # the delta container
+    d = next(d for d in corpus if d["base"] is not None)   # a delta container
     with pytest.raises(Z.ZipnnError):
         srv.register(d["c"])                     # delta without its base
     bad = d["c"].clone()
