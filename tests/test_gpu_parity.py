@@ -320,3 +320,18 @@ def test_exponent_extraction_only_bf16_fp32(codec):
     with pytest.raises(Z.ZipnnError) as ei:
         codec.compress(x, Z.make_params(Z.ZIPNN_FP16, exponent=True))
     assert ei.value.code == Z.ZIPNN_E_INVAL
+
+
+def test_exponent_extraction_special_values_and_norms(codec):
+    """Exponent extraction keeps NaN payloads, infinities, signed zeros and
+    denormals bit-exact; norm-like BF16 weights (1 + N(0, 0.05)) and the
+    maximal probe interval round-trip too."""
+    raw = (torch.randn(200_003, generator=torch.Generator().manual_seed(35)) * 0.05).numpy().view(np.uint32).copy()
+    special = np.array([0x7F800000, 0xFF800000, 0x7FC00001, 0xFFFFFFFF, 0x80000000, 1, 0x007FFFFF, 0, 0x80000001],
+                       dtype=np.uint32)
+    raw[1000: 1000 + 64 * len(special)] = np.repeat(special, 64)
+    x = torch.from_numpy(raw.view(np.float32))
+    roundtrip(codec, x, Z.make_params(Z.ZIPNN_FP32, exponent=True, probe_skip=255))
+    norms = (1 + 0.05 * torch.randn(300_001, generator=torch.Generator().manual_seed(36))).to(torch.bfloat16)
+    roundtrip(codec, norms, Z.make_params(Z.ZIPNN_BF16, exponent=True))
+    roundtrip(codec, norms, Z.make_params(Z.ZIPNN_BF16, exponent=True, policy=[Z.ZIPNN_ZG, Z.ZIPNN_HUF]))

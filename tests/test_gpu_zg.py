@@ -169,3 +169,20 @@ def test_damaged_zg_rejected(codec):
             oracle.decompress(d)
         assert _status(codec, d, 1001) == Z.ZIPNN_E_CORRUPT, name
     assert codec.status() == Z.ZIPNN_OK
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 257])
+@pytest.mark.parametrize("dtype", [torch.uint8, torch.bfloat16, torch.float32])
+def test_forced_zg_tiny(codec, n, dtype):
+    """Forced ZG on tensors of a few elements (one partial group, partial lane
+    groups, a single sub-stream), g = 2 and code lengths limited to 8."""
+    base = workloads.pruned(workloads.bf16_normal(n, seed=80 + n), 0.3, seed=81)
+    x = base.view(torch.uint8)[:n].clone() if dtype == torch.uint8 else base.to(dtype)
+    dt = Z.torch_dtype_code(dtype)
+    roundtrip(codec, x, Z.make_params(dt, chunk_bytes=256, S=4, g=2, L=8, policy=[Z.ZIPNN_ZG] * 4))
+
+
+def test_zg_policy_mix_per_stream(codec):
+    """Per-stream policies mixing ZG, HUF, RAW and AUTO in one FP32 tensor."""
+    x = workloads.pruned(workloads.fp32_rows(4, 40_000, seed=82).reshape(-1), 0.2, seed=83)
+    roundtrip(codec, x, Z.make_params(Z.ZIPNN_FP32, policy=[Z.ZIPNN_ZG, Z.ZIPNN_HUF, Z.ZIPNN_RAW, Z.ZIPNN_AUTO]))
