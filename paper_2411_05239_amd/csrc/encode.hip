@@ -931,7 +931,7 @@ constexpr uint32_t kPackLenBytes = 32 * 64;   // per wave: LR * 64 lanes * LB = 
 template <int B, int G, bool ZG>
 __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode, uint32_t z,
                                 uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out, uint32_t* qring,
-                                uint8_t* lring, bool xf)
+                                uint8_t* lring, bool xf, uint64_t* bitmap)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
@@ -959,9 +959,16 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
         if (e < ng) group_words<B, G>(src, base, w + e * W, m, wd, xf);
     };
     auto encode = [&](uint32_t e, const uint32_t* wd) {
-        if (e >= ng) return;
         const uint32_t ecnt = w + e * W < Gfull ? G : rem;
-        const bool mk = !ZG || marked<B, G>(wd, k, ecnt, z);
+        const bool mk = !ZG || (e < ng && marked<B, G>(wd, k, ecnt, z));
+        if (ZG && bitmap) {
+            // ZG with W a multiple of 64: the 64 bits of this lane group's
+            // step e are one aligned word of the bitmap (the wave is uniform
+            // here: every lane calls encode with the same e)
+            const uint64_t bits = __ballot(mk);
+            if (lane == 0 && e < ng_max) bitmap[j + e * (W / 64)] = bits;
+        }
+        if (e >= ng) return;
         uint32_t lens = 0;
         if (mk) {
 #pragma unroll
@@ -1211,15 +1218,23 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
             for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
             for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
             const uint32_t bm = zg ? zg_bitmap(m, GG) : 0u;
-            if (zg) pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + head, xf);
+            // with W a multiple of 64 the packer writes the bitmap's words as it
+            // marks the groups; here only the words past the last group are zeroed
+            uint64_t* fused = (zg && W % 64 == 0) ? reinterpret_cast<uint64_t*>(pay + head) : nullptr;
+            if (fused) {
+                const uint32_t Gtot = (m + GG - 1) / GG;
+                for (uint32_t x = (Gtot + 63) / 64 + t; x < bm / 8; x += kBlock) fused[x] = 0;
+            } else if (zg) {
+                pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + head, xf);
+            }
             uint32_t* words = (uint32_t*)(pay + head + bm);
             for (uint32_t j = wv; j < NG; j += kWaves) {
                 if (zg)
                     pack_lane_group<BB, GG, true>(src, base, int(k), P.rcode[k], P.z[k], p.L, j, W, m,
-                                                  words + P.wpre[k][j], qpool[wv], lpool[wv], xf);
+                                                  words + P.wpre[k][j], qpool[wv], lpool[wv], xf, fused);
                 else
                     pack_lane_group<BB, GG, false>(src, base, int(k), P.rcode[k], 0u, p.L, j, W, m,
-                                                   words + P.wpre[k][j], qpool[wv], lpool[wv], xf);
+                                                   words + P.wpre[k][j], qpool[wv], lpool[wv], xf, nullptr);
             }
         }
         __syncthreads();
