@@ -451,6 +451,7 @@ struct AnalyzeTail {
     uint32_t words[2][4];    // words over all lane groups, per stream: HUF, ZG
     uint32_t T[2][4];        // coded bits of the candidates: HUF, ZG
     int pol[4];              // policy of each group in this chunk (RAW where probing skips it)
+    uint32_t specok;         // bit k: the main pass's count of zeros in marked groups holds (z = 0)
 };
 
 // One workgroup per chunk (phase -1: every chunk; with a probe interval K,
@@ -478,6 +479,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     __shared__ uint32_t hist[4][256];
     __shared__ AnalyzeTail A;
     __shared__ uint32_t zsum[kWaves][4];
+    __shared__ uint32_t zspec[kWaves][4];
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
     constexpr uint32_t B = BB;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
@@ -511,7 +513,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             continue;
         }
         for (uint32_t i = t; i < kWaves * 4 * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
-        if (t == 0) A.open = A.hc = A.zc = A.zgc = A.fin = A.coded = 0;
+        if (t == 0) A.open = A.hc = A.zc = A.zgc = A.fin = A.coded = A.specok = 0;
         if (t < 8) (&A.words[0][0])[t] = 0;
         if (t < 4) A.pol[t] = ((live >> t) & 1) ? int(p.policy[t]) : ZIPNN_RAW;
         __syncthreads();
@@ -541,11 +543,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             }
         }
         skew = __builtin_amdgcn_readfirstlane(skew);
+        // Delta-like groups (zero bytes in at least half of the first 64
+        // vectors; the same vectors in every wave, so the choice is uniform)
+        // also count, in this pass, the zero bytes that lie in groups of g
+        // holding a nonzero byte.  Every nonzero byte lies in such a group, so
+        // if 0 turns out to be the most frequent value, the ZG histogram is
+        // this pass's histogram with that count in place of the count of 0,
+        // and the ZG pass over the data is not needed.
+        uint32_t spec = 0;
+        if (nbytes % 16 == 0 && p.g * B <= 16) {
+            uint32_t x0 = 0;
+            if (uint32_t(lane) < nvec) {
+                x0 = ((const uint32_t*)src)[4 * lane];
+                if (base) x0 ^= ((const uint32_t*)base)[4 * lane];
+                if (xf) x0 = exp_fwd<B>(x0);
+            }
+            for (uint32_t k = 0; k < B; k++) {
+                const uint32_t byte = (x0 >> (8 * (B - 1 - k))) & 0xFFu;
+                const bool zg_policy = A.pol[k] == ZIPNN_AUTO || A.pol[k] == ZIPNN_ZG;
+                if (zg_policy && __popcll(__ballot(uint32_t(lane) < nvec && byte == 0)) >= 32) spec |= 1u << k;
+            }
+        }
+        spec = __builtin_amdgcn_readfirstlane(spec);
+        uint32_t zin[4] = {0, 0, 0, 0};   // zero bytes in marked groups, per group of bytes
+        const uint32_t G = p.g;
         // SK: the skewed streams, known here (or -1: tested per byte)
         // LV: every group is live (no per-byte test)
-        auto count = [&](auto sk_const, auto lv_const) {
+        // SP: count the zeros in marked groups of the streams in `spec`
+        auto count = [&](auto sk_const, auto lv_const, auto sp_const) {
             constexpr int SK = decltype(sk_const)::value;
             constexpr bool LV = decltype(lv_const)::value;
+            constexpr bool SP = decltype(sp_const)::value;
             constexpr uint32_t HB = 8;   // vectors in flight per lane
             for (uint32_t v0 = t; v0 < nvec; v0 += HB * kBlock) {
               uint4 xs[HB];
@@ -590,6 +618,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                         atomicAdd(&h[k][byte], 1u);
                     }
                 }
+                if constexpr (SP) {
+#pragma unroll
+                    for (int k = 0; k < int(B); k++) {
+                        if (!((spec >> k) & 1)) continue;
+                        uint32_t nz = 0;   // bit e: element e's byte of group k is nonzero
+#pragma unroll
+                        for (int e = 0; e < 16 / int(B); e++) {
+                            const int jb = e * int(B) + (int(B) - 1 - k);
+                            nz |= uint32_t(((wds[jb >> 2] >> (8 * (jb & 3))) & 0xFFu) != 0) << e;
+                        }
+                        uint32_t mk = 0;   // bit e: element e's group of g holds a nonzero byte
+                        for (uint32_t g0 = 0; g0 < 16 / B; g0 += G) {
+                            const uint32_t gm = ((1u << G) - 1) << g0;
+                            if (nz & gm) mk |= gm;
+                        }
+                        zin[k] += __popc(mk & ~nz);
+                    }
+                }
                 }
               }
             }
@@ -597,12 +643,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         {
             using std::integral_constant;
             using T = integral_constant<bool, true>;
-            if (live != (1u << B) - 1) count(integral_constant<int, -1>{}, integral_constant<bool, false>{});
-            else if (skew == 0) count(integral_constant<int, 0>{}, T{});
-            else if (skew == 1) count(integral_constant<int, 1>{}, T{});
-            else if (B >= 2 && skew == 3) count(integral_constant<int, B >= 2 ? 3 : -1>{}, T{});
-            else count(integral_constant<int, -1>{}, T{});
+            using F = integral_constant<bool, false>;
+            if (live != (1u << B) - 1) count(integral_constant<int, -1>{}, F{}, F{});
+            else if (spec) count(integral_constant<int, -1>{}, T{}, T{});
+            else if (skew == 0) count(integral_constant<int, 0>{}, T{}, F{});
+            else if (skew == 1) count(integral_constant<int, 1>{}, T{}, F{});
+            else if (B >= 2 && skew == 3) count(integral_constant<int, B >= 2 ? 3 : -1>{}, T{}, F{});
+            else count(integral_constant<int, -1>{}, T{}, F{});
         }
+        if (spec)
+            for (uint32_t k = 0; k < B; k++) {
+                const uint32_t zs = wave_sum(zin[k]);
+                if (lane == 0) zspec[wv][k] = zs;
+            }
         // the elements after the last whole vector
         for (uint32_t e = nvec * 16 / B + t; e < m; e += kBlock) {
             const uint32_t v = element_word<B>(src, base, e, xf);
@@ -657,6 +710,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                     atomicOr(&A.open, 1u << k);
                     if (hc) atomicOr(&A.hc, 1u << k);
                     if (zc) atomicOr(&A.zc, 1u << k);
+                    if (zc && ((spec >> k) & 1) && arg == 0) atomicOr(&A.specok, 1u << k);
                     A.z[k] = arg;
                 }
             }
@@ -664,29 +718,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         __syncthreads();
         // 3. ZG: histogram over the marked groups, then lengths
         if (A.zc) {
-            for (uint32_t i = t; i < kWaves * 4 * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
-            __syncthreads();
-            uint32_t zn[4] = {0, 0, 0, 0};
-            switch (p.g) {
-            case 2: zg_count<BB, 2>(src, base, A.zc, A.z, m, S.hist[wv], zn, xf); break;
-            case 4: zg_count<BB, 4>(src, base, A.zc, A.z, m, S.hist[wv], zn, xf); break;
-            default: zg_count<BB, 8>(src, base, A.zc, A.z, m, S.hist[wv], zn, xf); break;
+            // groups whose ZG histogram the main pass could not give: one more
+            // pass over the data
+            const uint32_t need = A.zc & ~A.specok;
+            if (need) {
+                for (uint32_t i = t; i < kWaves * 4 * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
+                __syncthreads();
+                uint32_t zn[4] = {0, 0, 0, 0};
+                switch (p.g) {
+                case 2: zg_count<BB, 2>(src, base, need, A.z, m, S.hist[wv], zn, xf); break;
+                case 4: zg_count<BB, 4>(src, base, need, A.z, m, S.hist[wv], zn, xf); break;
+                default: zg_count<BB, 8>(src, base, need, A.z, m, S.hist[wv], zn, xf); break;
+                }
+                if (lane == 0)
+                    for (uint32_t k = 0; k < B; k++) zsum[wv][k] = zn[k];
+                __syncthreads();
+                for (uint32_t i = t; i < 4 * 256; i += kBlock) {
+                    const uint32_t k = i >> 8, s = i & 255;
+                    uint32_t v = S.hist[0][k][s] + S.hist[1][k][s] + S.hist[2][k][s] + S.hist[3][k][s];
+                    if (k < B && s == A.z[k]) v += zsum[0][k] + zsum[1][k] + zsum[2][k] + zsum[3][k];
+                    S.hist[0][k][s] = v;
+                }
+                __syncthreads();
             }
-            if (lane == 0)
-                for (uint32_t k = 0; k < B; k++) zsum[wv][k] = zn[k];
-            __syncthreads();
-            for (uint32_t i = t; i < 4 * 256; i += kBlock) {
-                const uint32_t k = i >> 8, s = i & 255;
-                uint32_t v = S.hist[0][k][s] + S.hist[1][k][s] + S.hist[2][k][s] + S.hist[3][k][s];
-                if (k < B && s == A.z[k]) v += zsum[0][k] + zsum[1][k] + zsum[2][k] + zsum[3][k];
-                S.hist[0][k][s] = v;
-            }
-            __syncthreads();
             uint32_t fv[4] = {0, 0, 0, 0}, tot = 0, d2 = 0;
             if (uint32_t(wv) < B) {
+                const bool fromspec = (A.specok >> wv) & 1;
+                const uint32_t z0 = zspec[0][wv] + zspec[1][wv] + zspec[2][wv] + zspec[3][wv];
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    fv[r] = S.hist[0][wv][lane + 64 * r];
+                    const uint32_t sym = lane + 64 * r;
+                    fv[r] = fromspec ? (sym == 0 ? z0 : hist[wv][sym]) : S.hist[0][wv][sym];
                     tot += fv[r];
                     d2 += __popcll(__ballot(fv[r] > 0));
                 }
