@@ -194,9 +194,9 @@ def test_zero_speculation_falls_back(codec):
     value (norm-like weights near 1.0): the ZG histogram comes from the
     second pass, and the bytes still equal the oracle's."""
     E = 131072
-    norms = (1 + 0.01 * torch.randn(3 * E + 1000, generator=torch.Generator().manual_seed(90))).to(torch.bfloat16)
-    for c in range(4):
-        norms[c * E: c * E + 2048] = 0   # the first 4 KiB of every chunk
+    norms = (1 + 0.3 * torch.randn(3 * E + 1000, generator=torch.Generator().manual_seed(90))).to(torch.bfloat16)
+    for c in range(3):
+        norms[c * E: c * E + 2048] = 0   # the first 4 KiB of every full chunk
     p = Z.make_params(Z.ZIPNN_BF16, policy=[Z.ZIPNN_ZG, Z.ZIPNN_AUTO])
     got = roundtrip(codec, norms, p)
     h = oracle.header(got)
