@@ -520,10 +520,10 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
     uint32_t zm_all = 0;
 #pragma unroll
     for (int k = 0; k < B; k++) zm_all |= uint32_t((ZGK && mode[k] == kModeZg)) << k;
-    // fast path: all 64 lanes have full groups j0 .. j0+kDepth-1 and every
-    // stream is Huffman, ZG or raw.  HM is the set of Huffman and ZG streams
-    // and ZM that of the ZG ones, or -1 for sets without their own copy of
-    // the loop, tested per stream at run time.
+    // fast path: all 64 lanes have full groups j0 .. j0+kDepth-1.  HM is the
+    // set of Huffman and ZG streams and ZM that of the ZG ones, or -1 for sets
+    // without their own copy of the loop, tested per stream at run time; the
+    // other streams are raw or single-valued (a uniform test per step).
     auto fast = [&](auto hm_const, auto zm_const) __attribute__((always_inline)) {
         constexpr int HM = decltype(hm_const)::value;
         constexpr int ZM = decltype(zm_const)::value;
@@ -540,8 +540,11 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                     const bool is_huf = HM >= 0 ? ((HM >> k) & 1) != 0 : (mode[k] == kModeHuf || (ZGK && mode[k] == kModeZg));
                     const bool is_zg = ZM >= 0 ? ((ZM >> k) & 1) != 0 : (ZGK && mode[k] == kModeZg);
                     if (!is_huf) {
+                        // raw, or a single value filled from a register (its
+                        // buffer has no bytes, so its loads read nothing)
+                        const bool rle = mode[k] == kModeRle;
 #pragma unroll
-                        for (int x = 0; x < PW; x++) pk[k][x] = slot[k][u * PW + x];
+                        for (int x = 0; x < PW; x++) pk[k][x] = rle ? rlev[k] : slot[k][u * PW + x];
                         buf_load<G>(rr[k], offn, &slot[k][u * PW]);
                     } else if (is_zg) {
                         const uint64_t zm = zmask(k, jj);
@@ -592,23 +595,46 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
     };
     {
         uint32_t hm = 0;
-        bool other = false;
 #pragma unroll
-        for (int k = 0; k < B; k++) {
-            hm |= uint32_t(mode[k] == kModeHuf || (ZGK && mode[k] == kModeZg)) << k;
-            other |= mode[k] == kModeRle;
-        }
+        for (int k = 0; k < B; k++) hm |= uint32_t(mode[k] == kModeHuf || (ZGK && mode[k] == kModeZg)) << k;
         const uint32_t zm = zm_all;
         using std::integral_constant;
         using I = int;
-        if (other) n_fast = 0;   // chunks with a single-valued stream take the general path
-        else if (zm == 0 && hm == 1) fast(integral_constant<I, 1>{}, integral_constant<I, 0>{});
-        else if (zm == 0 && hm == 0) fast(integral_constant<I, 0>{}, integral_constant<I, 0>{});
-        else if (zm == 0 && B >= 2 && hm == 3) fast(integral_constant<I, B >= 2 ? 3 : -1>{}, integral_constant<I, 0>{});
-        else if (zm == 1 && hm == 1) fast(integral_constant<I, 1>{}, integral_constant<I, 1>{});
-        else if (B >= 2 && zm == 3 && hm == 3)
-            fast(integral_constant<I, B >= 2 ? 3 : -1>{}, integral_constant<I, B >= 2 ? 3 : -1>{});
-        else fast(integral_constant<I, -1>{}, integral_constant<I, -1>{});
+        // a copy of the loop for every set of a BF16/FP8 chunk and for the
+        // common FP32 sets (ZM != 0 only in the kernels with the ZG decoder)
+        auto spec = [&](auto h, auto z) {
+            constexpr int H = decltype(h)::value, Z = decltype(z)::value;
+            if constexpr (Z != 0 && !ZGK) return false;
+            else {
+                if (hm != uint32_t(H) || zm != uint32_t(Z)) return false;
+                fast(h, z);
+                return true;
+            }
+        };
+        bool done = false;
+        if constexpr (B == 1) {
+            done = spec(integral_constant<I, 0>{}, integral_constant<I, 0>{}) ||
+                   spec(integral_constant<I, 1>{}, integral_constant<I, 0>{}) ||
+                   spec(integral_constant<I, 1>{}, integral_constant<I, 1>{});
+        } else if constexpr (B == 2) {
+            done = spec(integral_constant<I, 0>{}, integral_constant<I, 0>{}) ||
+                   spec(integral_constant<I, 1>{}, integral_constant<I, 0>{}) ||
+                   spec(integral_constant<I, 2>{}, integral_constant<I, 0>{}) ||
+                   spec(integral_constant<I, 3>{}, integral_constant<I, 0>{}) ||
+                   spec(integral_constant<I, 1>{}, integral_constant<I, 1>{}) ||
+                   spec(integral_constant<I, 2>{}, integral_constant<I, 2>{}) ||
+                   spec(integral_constant<I, 3>{}, integral_constant<I, 1>{}) ||
+                   spec(integral_constant<I, 3>{}, integral_constant<I, 2>{}) ||
+                   spec(integral_constant<I, 3>{}, integral_constant<I, 3>{});
+        } else {
+            done = spec(integral_constant<I, 0>{}, integral_constant<I, 0>{}) ||
+                   spec(integral_constant<I, 1>{}, integral_constant<I, 0>{}) ||
+                   spec(integral_constant<I, 3>{}, integral_constant<I, 0>{}) ||
+                   spec(integral_constant<I, 1>{}, integral_constant<I, 1>{}) ||
+                   spec(integral_constant<I, 3>{}, integral_constant<I, 3>{}) ||
+                   spec(integral_constant<I, 15>{}, integral_constant<I, 15>{});
+        }
+        if (!done) fast(integral_constant<I, -1>{}, integral_constant<I, -1>{});
     }
     // general path: the remaining groups, with per-lane conditions
     for (uint32_t j0 = n_fast; j0 < ng_max; j0 += kDepth) {

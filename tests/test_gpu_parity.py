@@ -335,3 +335,17 @@ def test_exponent_extraction_special_values_and_norms(codec):
     norms = (1 + 0.05 * torch.randn(300_001, generator=torch.Generator().manual_seed(36))).to(torch.bfloat16)
     roundtrip(codec, norms, Z.make_params(Z.ZIPNN_BF16, exponent=True))
     roundtrip(codec, norms, Z.make_params(Z.ZIPNN_BF16, exponent=True, policy=[Z.ZIPNN_ZG, Z.ZIPNN_HUF]))
+
+
+@pytest.mark.parametrize("n", [8 * 65536, 5 * 65536 + 4099])
+def test_clean_fp32_single_valued_groups(codec, n):
+    """'Clean' FP32 weights (paper §III-B: values that came from BF16, so the
+    two low fraction bytes are zero): those byte groups are RLE in every
+    chunk, beside a Huffman exponent group and a raw group; the decoder's
+    fast loop fills them from a register."""
+    x = workloads.bf16_normal(n, seed=37).to(torch.float32)
+    c = roundtrip(codec, x, Z.zipnn_default_params(Z.ZIPNN_FP32)).cpu().numpy()
+    assert [oracle.entry(c, 0, k)[2] for k in range(4)] == [oracle.MODE_HUF, oracle.MODE_RAW, oracle.MODE_RLE,
+                                                             oracle.MODE_RLE]
+    d = workloads.finetune_delta(workloads.bf16_normal(n, seed=38), seed=39).to(torch.float32)
+    roundtrip(codec, d, Z.zipnn_default_params(Z.ZIPNN_FP32), base_cpu=workloads.bf16_normal(n, seed=38).to(torch.float32))
