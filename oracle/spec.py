@@ -18,7 +18,7 @@ Steps (ZipNN, arXiv 2411.05239):
               compressibility");
   schedule -- the lock-step word order as a sort of (step, pair, lane) events
               rather than nested loops;
-  layout   -- 64-byte header, 16-byte map entries, 16-byte aligned payloads
+  layout   -- 64-byte header, 16-byte map entries, 128-byte aligned payloads
               (the container described in ``zipnn_oracle.h``).
 """
 from __future__ import annotations

@@ -1,27 +1,31 @@
 // Encode kernels of the gfx950 ZipNN codec.
 //
 //   k_analyze  one workgroup per chunk: reads the chunk (16-byte loads, XOR
-//              with the base for a delta, paper §IV-B), splits every word into
-//              its B byte groups (paper §III-A/§III-B) and histograms each
-//              group in LDS; wave k then builds the code of group k: optimal
-//              lengths <= L by package-merge (Larmore & Hirschberg, computed
-//              with parallel ranks, see build_code) and canonical codes (RFC
-//              1951 §3.2.2).  A group with one value becomes RLE (paper §III-B);
-//              for a Huffman candidate the four waves replay the decoder's
-//              lock-step word requests lane group by lane group, which gives
-//              the exact payload size, so AUTO keeps Huffman only when it is
-//              strictly smaller than raw (paper §III-B, §V-A).
+//              with the base for a delta, paper §IV-B, exponent extraction
+//              when asked, §III-A), splits every word into its B byte groups
+//              (paper §III-A/§III-B) and histograms each group in LDS; wave k
+//              then builds the code of group k: optimal lengths <= L by
+//              package-merge (Larmore & Hirschberg, computed with parallel
+//              ranks, see build_lengths) and canonical codes (RFC 1951
+//              §3.2.2).  A group with one value becomes RLE (paper §III-B);
+//              a group whose most frequent byte fills half of it is also a ZG
+//              candidate (zero-aware coding, §IV-B).  For every candidate the
+//              four waves replay the decoder's lock-step word requests lane
+//              group by lane group, which gives the exact payload sizes, so
+//              AUTO keeps the smallest of RAW, HUF and ZG (paper §III-B, §V-A).
+//              With a probe interval the probe chunks run first
+//              (compressibility probing, §III-B).
 //   k_place    one workgroup per tensor: exclusive scan of the 128-byte aligned
 //              payload sizes in chunk-major order -> map entries and header
 //              (the map that enables parallel decode, paper §V-A), and whether
 //              the map holds ZG entries (a header flag).
 //   k_pack     one workgroup per chunk: raw groups are copied with 16-byte
-//              stores; for a Huffman group, wave v writes lane groups v, v+4,
-//              ...: its lanes replay the same rounds, and in every round the
-//              lanes that the decoder will serve write their next word to
+//              stores; for a Huffman or ZG group, wave v writes lane groups v,
+//              v+4, ...: its lanes replay the same steps, and in every round
+//              the lanes that the decoder will serve write their next word to
 //              consecutive slots (ballot + prefix popcount), encoding codes
-//              ahead just far enough to fill that word.  Every byte of the
-//              payload extent, padding included, is written; no atomics.
+//              ahead of the decoder model.  Every byte of the payload extent,
+//              padding included, is written; no atomics.
 #include <type_traits>
 
 #include "zipnn_internal.h"
@@ -846,7 +850,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     }
 }
 
-// One workgroup per tensor: offsets of its entries (16-byte aligned, in
+// One workgroup per tensor: offsets of its entries (128-byte aligned, in
 // chunk-major order) and the tensor's container size.
 __global__ __launch_bounds__(kBlock) void k_place(EncDesc* __restrict__ descs, EncParams p,
                                                   const EncEntry* __restrict__ entries, uint64_t* __restrict__ offsets,
