@@ -377,6 +377,30 @@ __device__ __attribute__((always_inline)) void zg_count(const uint8_t* src, cons
     for (int k = 0; k < B; k++) zcount[k] = wave_sum(nz[k]);
 }
 
+// Bytes of stream k of the g elements of a group's words, packed little-endian
+// into one register (groups of at most 4 bytes per stream): v_perm_b32 picks
+// byte B-1-k of each word (selector 0-3: the second operand, 4-7: the first,
+// 0x0C: zero).
+template <int B, int G>
+__device__ inline uint32_t gather_stream(const uint32_t* wd, int k)
+{
+    if constexpr (B == 2) {
+        const uint32_t b = uint32_t(1 - k);   // byte of the 16-bit element
+        if constexpr (G == 2) return __builtin_amdgcn_perm(0u, wd[0], 0x0C0C0000u | ((b + 2) << 8) | b);
+        else return __builtin_amdgcn_perm(wd[1], wd[0], ((b + 6) << 24) | ((b + 4) << 16) | ((b + 2) << 8) | b);
+    } else if constexpr (B == 4) {
+        const uint32_t b = uint32_t(3 - k);
+        const uint32_t lo = __builtin_amdgcn_perm(wd[1], wd[0], 0x0C0C0000u | ((b + 4) << 8) | b);
+        if constexpr (G == 2) return lo;
+        else return lo | __builtin_amdgcn_perm(wd[3], wd[2], ((b + 4) << 24) | (b << 16) | 0x0C0Cu);
+    } else {
+        uint32_t v = 0;
+#pragma unroll
+        for (int i = 0; i < G; i++) v |= sym_of<B>(wd, k, i) << (8 * i);
+        return v;
+    }
+}
+
 // Replay the decoder's word requests for lane group j of one chunk and count
 // the words each candidate takes: HUF candidates (bit k of hc, lengths
 // lens[k]) over every group, ZG candidates (bit k of zgc, lengths lens2[k],
@@ -997,7 +1021,8 @@ constexpr uint32_t kPackLenBytes = 32 * 64;   // per wave: LR * 64 lanes * LB = 
 template <int B, int G, bool ZG>
 __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode, uint32_t z,
                                 uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out, uint32_t* qring,
-                                uint8_t* lring, bool xf, uint64_t* bitmap)
+                                uint8_t* lring, bool xf, uint64_t* bitmap, uint32_t rawmask, uint8_t* dst,
+                                const uint64_t* rawpay)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
@@ -1010,6 +1035,24 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
     const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;
     const uint32_t ng_max = __builtin_amdgcn_readfirstlane(ng);   // lane 0 has the most
 
+    // raw byte groups copied here (Huffman packer, groups of at most 4 bytes:
+    // b16 / b32 stores through a buffer resource on the chunk's payloads)
+    constexpr bool kFuseRaw = !ZG && G <= 4 && B * G <= 16;
+    // one resource over the chunk's payloads (they are consecutive) and a
+    // scalar offset per raw group
+    __amdgpu_buffer_rsrc_t rr;
+    uint32_t roff[B];
+    {
+        const uint64_t a = uint64_t(dst + rawpay[0]);
+        // (the builtin returns int: widen through uint32_t, not by sign)
+        const uint64_t au = uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(a)))) |
+                            (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(a >> 32)))) << 32);
+        const uint32_t span = uint32_t(rawpay[B - 1] - rawpay[0]) + m;
+        rr = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(au), (short)0,
+                                               int(__builtin_amdgcn_readfirstlane(rawmask ? span : 0u)), 0x00020000);
+#pragma unroll
+        for (int r = 0; r < B; r++) roff[r] = __builtin_amdgcn_readfirstlane(uint32_t(rawpay[r] - rawpay[0]));
+    }
     uint64_t eb = 0;   // encoder: bits not yet in a queued word
     uint32_t en = 0;
     uint32_t qt = 0;   // words queued
@@ -1035,6 +1078,25 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
             if (lane == 0 && e < ng_max) bitmap[j + e * (W / 64)] = bits;
         }
         if (e >= ng) return;
+        // the raw byte groups of this group of g elements, copied on this pass
+        // (the first coded group's) instead of in a pass of their own
+        if constexpr (kFuseRaw) {
+            if (rawmask) {
+                const uint32_t q0 = (w + e * W) * G;
+#pragma unroll
+                for (int r = 0; r < B; r++) {
+                    if (!((rawmask >> r) & 1)) continue;
+                    if (ecnt == G) {
+                        const uint32_t v = gather_stream<B, G>(wd, r);
+                        if constexpr (G == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(v), rr, q0, roff[r], 0);
+                        else __builtin_amdgcn_raw_buffer_store_b32(v, rr, q0, roff[r], 0);
+                    } else {
+                        for (uint32_t i = 0; i < ecnt; i++)
+                            __builtin_amdgcn_raw_buffer_store_b8(uint8_t(sym_of<B>(wd, r, int(i))), rr, q0 + i, roff[r], 0);
+                    }
+                }
+            }
+        }
         uint32_t lens = 0;
         if (mk) {
 #pragma unroll
@@ -1159,14 +1221,24 @@ __device__ void pack_bitmap(const uint8_t* src, const uint8_t* base, int k, uint
 }
 
 // Raw groups of one chunk: thread t copies elements [16u, 16u+16) of every
-// RAW stream with one 16-byte store each.
+// RAW stream with one 16-byte store each, then the zero padding.  With
+// pad_only the packer of a coded group copies the elements, and only the
+// padding is written here.
 template <int B>
-__device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, const PackLds& P, uint32_t m, bool xf)
+__device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, const PackLds& P, uint32_t m, bool xf,
+                         bool pad_only)
 {
     uint32_t rawmask = 0;
     for (int k = 0; k < B; k++)
         if (P.mode[k] == kModeRaw) rawmask |= 1u << k;
     if (!rawmask) return;
+    if (pad_only) {
+        for (uint32_t e = m + threadIdx.x; e < uint32_t(align_pay(m)); e += kBlock)
+#pragma unroll
+            for (int k = 0; k < B; k++)
+                if ((rawmask >> k) & 1) dst[P.pay[k] + e] = 0;
+        return;
+    }
     const uint32_t units = m / 16;
     constexpr uint32_t RB = B == 4 ? 2 : (B == 2 ? 4 : 8);   // units in flight per thread
     for (uint32_t u0 = threadIdx.x; u0 < units; u0 += RB * kBlock) {
@@ -1210,7 +1282,7 @@ __device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, 
 }
 
 template <int BB, int GG>
-__global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ descs, int n_desc,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pack(const EncDesc* __restrict__ descs, int n_desc,
                                                  const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                  EncParams p, const EncEntry* __restrict__ entries,
                                                  const CodeWord* __restrict__ codes,
@@ -1273,7 +1345,14 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
         uint8_t* dst = d.dst;
         const bool xf = (p.flags & kFlagExp) != 0;
-        pack_raw<BB>(src, base, dst, P, m, xf);
+        // the first Huffman group's packer also copies the raw groups (groups
+        // of at most 4 bytes)
+        uint32_t rawmask = 0, k0 = B;
+        for (uint32_t k = 0; k < B; k++) {
+            if (P.mode[k] == kModeRaw) rawmask |= 1u << k;
+            if (GG <= 4 && BB * GG <= 16 && k0 == B && P.mode[k] == kModeHuf) k0 = k;
+        }
+        pack_raw<BB>(src, base, dst, P, m, xf, k0 < B);
         for (uint32_t k = 0; k < B; k++) {
             const bool zg = P.mode[k] == kModeZg;
             if (P.mode[k] != kModeHuf && !zg) continue;
@@ -1297,10 +1376,12 @@ __global__ __launch_bounds__(kBlock) void k_pack(const EncDesc* __restrict__ des
             for (uint32_t j = wv; j < NG; j += kWaves) {
                 if (zg)
                     pack_lane_group<BB, GG, true>(src, base, int(k), P.rcode[k], P.z[k], p.L, j, W, m,
-                                                  words + P.wpre[k][j], qpool[wv], lpool[wv], xf, fused);
+                                                  words + P.wpre[k][j], qpool[wv], lpool[wv], xf, fused,
+                                                  k == k0 ? rawmask : 0u, dst, P.pay);
                 else
                     pack_lane_group<BB, GG, false>(src, base, int(k), P.rcode[k], 0u, p.L, j, W, m,
-                                                   words + P.wpre[k][j], qpool[wv], lpool[wv], xf, nullptr);
+                                                   words + P.wpre[k][j], qpool[wv], lpool[wv], xf, nullptr,
+                                                   k == k0 ? rawmask : 0u, dst, P.pay);
             }
         }
         __syncthreads();
