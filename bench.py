@@ -272,10 +272,12 @@ def _modes(arena_np, offs):
     return dict(zip(["raw", "huf", "rle", "zg"], tot))
 
 
-def run_checkpoint(args, delta: bool):
+def run_checkpoint(args, delta: bool, zg: bool = False):
     """Synthetic 8B decoder checkpoint (291 BF16 tensors, ~16 GB), batched:
     every kernel runs once for all tensors; decode replays a hipGraph.  With
-    delta: the fine-tuned copy is stored as the XOR against the base."""
+    delta: the fine-tuned copy is stored as the XOR against the base, every
+    byte group Huffman-coded (paper §IV-B); with zg as well, AUTO chooses per
+    byte group among RAW, RLE, HUF and the zero-aware ZG mode."""
     import torch
 
     from paper_2411_05239_amd import workloads
@@ -291,7 +293,10 @@ def run_checkpoint(args, delta: bool):
     U = sum(x.numel() * 2 for x in xs)
     codec = Z.Codec(0)
     stream = torch.cuda.current_stream()
-    policy = None   # AUTO: RAW / RLE / HUF / ZG per byte group and chunk
+    if delta and not zg:
+        policy = [Z.ZIPNN_HUF, Z.ZIPNN_HUF]   # Huffman on both byte groups (RLE if single-valued)
+    else:
+        policy = None   # AUTO: RAW / RLE / HUF / ZG per byte group and chunk
     bptr = [b.data_ptr() for b in bases] if delta else [None] * len(xs)
     best, table = Z.zipnn_autotune(codec.ctx, Z.ZIPNN_BF16, [x.data_ptr() for x in xs], [x.numel() for x in xs],
                                    bptr, 1 << 30, 0.01, policy)
@@ -349,16 +354,18 @@ def run_checkpoint(args, delta: bool):
     dec_avg = statistics.mean(dec_ms)
     alg = C + U + (U if delta else 0)
     achieved = alg / (dec_avg * 1e-3) / 1e9
-    name = "ckpt8b_delta" if delta else "ckpt8b"
+    name = ("ckpt8b_delta_zg" if zg else "ckpt8b_delta") if delta else "ckpt8b"
     rec = {
         "metric": "decode GB/s at bit-exact roundtrip (uncompressed bytes / decode time); encode GB/s beside it",
         "value": round(U / (dec_avg * 1e-3) / 1e9, 2),
         "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": ("xor_delta_of_" if delta else "") + "bf16_8b_decoder_checkpoint_291_tensors",
+        "config": {"workload": ("xor_delta_of_" if delta else "") + "bf16_8b_decoder_checkpoint_291_tensors"
+                               + ("_zg" if zg else ""),
                    "tensors": len(xs), "bytes": U, "chunk_bytes": best.chunk_bytes, "S": best.substream_syms,
-                   "g": best.group, "L": best.max_code_len, "policy": "auto", "probe_skip": best.probe_skip,
+                   "g": best.group, "L": best.max_code_len, "policy": "huf,huf" if delta and not zg else "auto",
+                   "probe_skip": best.probe_skip,
                    "exponent": best.exponent,
                    "batched": "one launch per kernel + hipGraph replay"},
         "decode_ms": {"mean": round(dec_avg, 4), "median": round(statistics.median(dec_ms), 4)},
@@ -586,7 +593,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fp32_256mb",
-                    choices=["bf16_8mb", "fp32_256mb", "ckpt8b", "ckpt8b_delta", "serve", "series"])
+                    choices=["bf16_8mb", "fp32_256mb", "ckpt8b", "ckpt8b_delta", "ckpt8b_delta_zg", "serve",
+                             "series"])
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=4.0)
@@ -601,8 +609,8 @@ def main():
         sys.exit(2)
     if args.workload == "serve":
         run_serve(args)
-    elif args.workload in ("ckpt8b", "ckpt8b_delta"):
-        run_checkpoint(args, delta=args.workload == "ckpt8b_delta")
+    elif args.workload in ("ckpt8b", "ckpt8b_delta", "ckpt8b_delta_zg"):
+        run_checkpoint(args, delta=args.workload != "ckpt8b", zg=args.workload == "ckpt8b_delta_zg")
     elif args.workload == "series":
         run_series(args)
     else:
