@@ -149,12 +149,13 @@ def _sample_indices(n):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("chunk,S", [(262144, 512), (1048576, 2048)])
+@pytest.mark.parametrize("chunk,S", [(262144, 512), (1048576, 2048), (2097152, 2048)])
 def test_checkpoint_8b_full(codec, chunk, S):
     """The full 8B-shaped BF16 checkpoint (291 tensors, 16.06 GB) in the
-    batched configuration the benchmark times: one encode launch chain, one
-    prepared (graph) decode.  Every tensor round-trips bit-exactly; sampled
-    containers equal the oracle's bytes."""
+    batched configuration the benchmark times (2 MiB chunks, S = 2048 is the
+    autotuner's pick there): one encode launch chain, one prepared (graph)
+    decode.  Every tensor round-trips bit-exactly; sampled containers equal
+    the oracle's bytes."""
     specs = workloads.checkpoint_8b_specs()
     xs = [workloads.make_tensor(sp, device="cuda") for sp in specs]
     p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=chunk, S=S)
@@ -175,14 +176,18 @@ def test_checkpoint_8b_full(codec, chunk, S):
 
 
 @pytest.mark.slow
-def test_checkpoint_8b_delta_full(codec):
+@pytest.mark.parametrize("policy,chunk,S", [("huf", 262144, 512), ("huf", 2097152, 2048), ("auto", 2097152, 4096)])
+def test_checkpoint_8b_delta_full(codec, policy, chunk, S):
     """The full XOR-delta checkpoint: fine-tuned copy against the base, both
-    streams Huffman; every tensor reconstructs bit-exactly; sampled containers
-    equal the oracle's."""
+    streams Huffman (or AUTO, where ZG takes almost every stream), in the
+    default shape and in the shapes the autotuner picks for the benchmark;
+    every tensor reconstructs bit-exactly; sampled containers equal the
+    oracle's."""
     specs = workloads.checkpoint_8b_specs()
     base = [workloads.make_tensor(sp, device="cuda") for sp in specs]
     ft = [workloads.finetune_delta(w, seed=2000 + i) for i, w in enumerate(base)]
-    p = Z.make_params(Z.ZIPNN_BF16, policy=[Z.ZIPNN_HUF, Z.ZIPNN_HUF])
+    pol = [Z.ZIPNN_HUF, Z.ZIPNN_HUF] if policy == "huf" else [Z.ZIPNN_AUTO, Z.ZIPNN_AUTO]
+    p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=chunk, S=S, policy=pol)
     arena, offs = codec.compress_batch(ft, p, base)
     outs = [torch.empty_like(x) for x in ft]
     b = codec.prepare_batch(arena, offs, outs, base)
