@@ -231,9 +231,11 @@ typedef struct zipnn_batch_s* zipnn_batch;
  * host, n+1 entries as returned by zipnn_compress_batch) into dst[i] (host
  * array of device pointers, dst_cap[i] bytes each), XORing with base[i] for
  * delta containers (base may be NULL when no container is a delta).  Reads
- * and checks every header (blocking), uploads the descriptor tables and
- * records the launches (one per kernel class of (B, g, delta)) in a hipGraph.
- * The arena and outputs must stay valid while the batch is used. */
+ * and checks every header (blocking, on the null stream: work of another
+ * stream that writes the arena must be complete; the compress calls are
+ * blocking), uploads the descriptor tables and records the launches (one per
+ * kernel class of (B, g, delta, ZG entries present)) in a hipGraph.  The
+ * arena and outputs must stay valid while the batch is used. */
 int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets, int n, void* const* dst,
                        const uint64_t* dst_cap, const void* const* base, zipnn_batch* out);
 

@@ -515,6 +515,7 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
             if (zipnn_check_params(dtype, &p) == ZIPNN_OK) cands.push_back(p);
         }
     }
+    if (cands.empty()) return ZIPNN_E_INVAL;   // e.g. a policy value out of range
     DeviceGuard g(ctx->device);
     uint64_t cap = 0;
     for (const auto& p : cands) {

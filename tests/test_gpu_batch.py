@@ -225,3 +225,7 @@ def test_autotune_picks_fastest_within_ratio_loss(codec):
     c = codec.compress(x, best)
     ref = oracle.compress(x.cpu(), oracle.BF16, nthreads=8, **_kw(best))
     assert np.array_equal(c.cpu().numpy(), ref)
+    # a policy value out of range leaves no candidate: rejected, nothing measured
+    with pytest.raises(Z.ZipnnError) as ei:
+        Z.zipnn_autotune(codec.ctx, Z.ZIPNN_BF16, [x.data_ptr()], [x.numel()], [None], 1 << 20, loss, [9, 9])
+    assert ei.value.code == Z.ZIPNN_E_INVAL
