@@ -535,11 +535,17 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                 const uint32_t offn = raw_off(jj + kDepth);
                 if (ZM != 0 && u == 0) zstep(jj, ZM >= 0 ? uint32_t(ZM) : zm_all);
                 uint32_t pk[B][PW];
+                bool zon[B];   // ZG streams decoded side by side: this lane's group is marked
 #pragma unroll
                 for (int k = 0; k < B; k++) {
                     const bool is_huf = HM >= 0 ? ((HM >> k) & 1) != 0 : (mode[k] == kModeHuf || (ZGK && mode[k] == kModeZg));
                     const bool is_zg = ZM >= 0 ? ((ZM >> k) & 1) != 0 : (ZGK && mode[k] == kModeZg);
-                    if (!is_huf) {
+                    zon[k] = false;
+                    if (HM >= 0 && B <= 2 && !DELTA && is_zg) {
+                        zon[k] = ((zmask(k, jj) >> lane) & 1) != 0;
+#pragma unroll
+                        for (int x = 0; x < PW; x++) pk[k][x] = 0;
+                    } else if (!is_huf) {
                         // raw, or a single value filled from a register (its
                         // buffer has no bytes, so its loads read nothing)
                         const bool rle = mode[k] == kModeRle;
@@ -586,32 +592,43 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                     }
                 }
                 if constexpr (HM >= 0 && B <= 2) {
-                    // the plain Huffman streams (a set fixed at compile time)
-                    // pair by pair, every stream's step of a pair next to the
-                    // others': the chains of table reads of the streams overlap
-                    // (BF16 chunks with both groups coded: -7%)
-                    constexpr int PM = HM & ~(ZM >= 0 ? ZM : 0);
+                    // the coded streams (a set fixed at compile time) pair by
+                    // pair, every stream's step of a pair next to the others':
+                    // the chains of table reads of the streams overlap (BF16
+                    // chunks with both groups coded: -7%).  In a ZG stream the
+                    // lanes whose group is z alone take no part.
+                    constexpr int ZS = (ZM >= 0 && !DELTA) ? ZM : 0;
+                    constexpr int CM = HM & ~((ZM >= 0 ? ZM : 0) & ~ZS);
 #pragma unroll
                     for (int pr = 0; pr < G / 2; pr++) {
                         uint32_t s0[B];
 #pragma unroll
                         for (int k = 0; k < B; k++)
-                            if ((PM >> k) & 1) huf_take<B>(slot[k], cur[k], true, twoL);
-#pragma unroll
-                        for (int k = 0; k < B; k++)
-                            if ((PM >> k) & 1) s0[k] = huf_get<B>(slot[k], lut[k], mask);
+                            if ((CM >> k) & 1) huf_take<B>(slot[k], cur[k], ((ZS >> k) & 1) ? zon[k] : true, twoL);
 #pragma unroll
                         for (int k = 0; k < B; k++) {
-                            if ((PM >> k) & 1) {
-                                const uint32_t s1 = huf_get<B>(slot[k], lut[k], mask);
+                            if ((CM >> k) & 1)
+                                s0[k] = ((ZS >> k) & 1) ? huf_get_if<B>(slot[k], lut[k], mask, zon[k])
+                                                        : huf_get<B>(slot[k], lut[k], mask);
+                        }
+#pragma unroll
+                        for (int k = 0; k < B; k++) {
+                            if ((CM >> k) & 1) {
+                                const uint32_t s1 = ((ZS >> k) & 1) ? huf_get_if<B>(slot[k], lut[k], mask, zon[k])
+                                                                    : huf_get<B>(slot[k], lut[k], mask);
                                 pk[k][(2 * pr) >> 2] |= (s0[k] | (s1 << 8)) << (8 * ((2 * pr) & 3));
                             }
                         }
 #pragma unroll
                         for (int k = 0; k < B; k++)
-                            if (((PM >> k) & 1) && ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1))
+                            if (((CM >> k) & 1) && ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1))
                                 huf_refill<B>(slot[k], cur[k], lane);
                     }
+#pragma unroll
+                    for (int k = 0; k < B; k++)
+                        if ((ZS >> k) & 1)
+#pragma unroll
+                            for (int x = 0; x < PW; x++) pk[k][x] = zon[k] ? pk[k][x] : rlev[k];
                 }
                 uint32_t ow[NW];
                 merge_words<B, G>(pk, ow);
@@ -909,7 +926,9 @@ __device__ __attribute__((always_inline)) void decode_item(const DecDesc& d, con
 // Four waves per SIMD (at most 128 VGPRs) keep enough lanes in flight to
 // hide LDS and memory latency; the widest words with the largest groups get
 // the registers of two waves instead of spilling (16-byte groups with an
-// XOR base count as wide).
+// XOR base count as wide).  (The BF16 ZG delta kernel spills 8 bytes at 128
+// VGPRs; at 130 VGPRs and three waves it decoded the ZG delta checkpoint 28%
+// slower.)
 template <int B, int G, bool DELTA, bool ZGK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B * G >= (DELTA ? 16 : 32) ? 2 : 4, 8))) void k_decode(DecDesc one, const DecDesc* __restrict__ descs, int n_desc,
                                                    const uint64_t* __restrict__ item_prefix, int* status)
