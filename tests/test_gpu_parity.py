@@ -141,6 +141,38 @@ def test_code_length_limits(codec):
         roundtrip(codec, geo, Z.make_params(Z.ZIPNN_U8, L=L, policy=[1]))
 
 
+@pytest.mark.parametrize("dtype,g", [(torch.uint8, 2), (torch.uint8, 4), (torch.uint8, 8), (torch.bfloat16, 8),
+                                     (torch.float32, 4)])
+def test_longest_codes_fill_the_packer_queue(codec, dtype, g):
+    """A few sub-streams hold only rare bytes among zeros: with Huffman forced
+    their codes all reach the L = 11 limit, so the packer's per-lane queue of
+    finished words reaches its largest fill, (LG + 1) g L / 32 words."""
+    gen = torch.Generator().manual_seed(40 + g)
+    bsz = torch.tensor([], dtype=dtype).element_size()
+    chunk, S = 65536, 512
+    E = chunk // bsz
+    W = (E + S - 1) // S
+    n = 4 * E - 1000                      # four chunks, the last one partial
+    x = torch.zeros(n * bsz, dtype=torch.uint8)
+    e = torch.arange(n)
+    lane = (e // g) % W
+    hot = (lane == 5) | (lane == W // 2 + 3) | (lane == W - 1)
+    idx = e[hot]
+    for b in range(bsz):
+        x[idx * bsz + b] = torch.randint(1, 256, (idx.numel(),), generator=gen, dtype=torch.uint8)
+    xt = x.view(dtype)
+    p = Z.make_params(Z.torch_dtype_code(dtype), chunk_bytes=chunk, S=S, g=g, policy=[Z.ZIPNN_HUF] * bsz)
+    c = roundtrip(codec, xt, p).cpu().numpy()
+    # every entry is Huffman-coded and the rare bytes' codes are at the limit
+    for ch in range(4):
+        for k in range(bsz):
+            off, nbytes, mode, _ = oracle.entry(c, ch, k)
+            assert mode == oracle.MODE_HUF
+            nib = c[off: off + 128]
+            lens = np.stack([nib & 15, nib >> 4], axis=1).reshape(-1)
+            assert lens.max() == 11, (ch, k, lens.max())
+
+
 def test_xor_delta(codec):
     w = workloads.bf16_normal(1_000_003, seed=10)
     ft = workloads.finetune_delta(w, seed=11)
