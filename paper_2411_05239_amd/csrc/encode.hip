@@ -1026,6 +1026,12 @@ struct PackShape {
     static constexpr uint32_t LB = G / 2;   // bytes of one group's lengths (4 bits each)
 };
 constexpr uint32_t kPackQ = 24;
+// the bound on waiting words, for every group size the format allows
+static_assert(kMinG == 2 && kMaxG == 8, "group sizes checked below");
+static_assert((PackShape<2>::LG + 1) * 2 * kMaxL / 32 < PackShape<2>::Q, "packer queue too short for g = 2");
+static_assert((PackShape<4>::LG + 1) * 4 * kMaxL / 32 < PackShape<4>::Q, "packer queue too short for g = 4");
+static_assert((PackShape<8>::LG + 1) * 8 * kMaxL / 32 < PackShape<8>::Q, "packer queue too short for g = 8");
+static_assert(PackShape<2>::Q == kPackQ && PackShape<4>::Q == kPackQ && PackShape<8>::Q == kPackQ, "queue size");
 constexpr uint32_t kPackLenBytes = 32 * 64;   // per wave: LR * 64 lanes * LB = 32 * 64 bytes for every g
 
 template <int B, int G, bool ZG>
