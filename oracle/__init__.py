@@ -82,6 +82,8 @@ def lib():
         L.orc_package_merge.restype = i32
         L.orc_canonical_codes.argtypes = [u8p, i32, u8p]
         L.orc_canonical_codes.restype = None
+        L.orc_substream_bits.argtypes = [u8p, u64, u32, u32, i32, u8p, u8p, u64, u8p, u64, ctypes.POINTER(u64)]
+        L.orc_substream_bits.restype = i32
         L.orc_entry.argtypes = [u8p, u64, u32, i32, ctypes.POINTER(u64), ctypes.POINTER(u64),
                                 ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.orc_entry.restype = i32
@@ -167,6 +169,24 @@ def canonical_codes(lengths, L: int) -> np.ndarray:
     out = np.zeros(256, dtype=np.uint32)
     lib().orc_canonical_codes(_ptr(ln), L, _ptr(out))
     return out
+
+
+def substream_bits(sym: np.ndarray, S: int, g: int, L: int, lengths, w: int, flags=None) -> tuple[bytes, int]:
+    """Bit string of sub-stream w (the coding without the word layout): the
+    packed bytes (LSB-first) and the bit count."""
+    s = np.ascontiguousarray(sym, dtype=np.uint8)
+    m = s.size
+    ln = np.zeros(256, dtype=np.uint8)
+    ln[: len(lengths)] = np.asarray(lengths, dtype=np.uint8)
+    fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
+    W, G = -(-m // S), -(-m // g)
+    cap = (-(-G // max(W, 1)) * g * L + 7) // 8 + 8   # the longest sub-stream at L bits a symbol
+    out = np.zeros(cap, dtype=np.uint8)
+    nb = ctypes.c_uint64(0)
+    rc = lib().orc_substream_bits(_ptr(s), m, S, g, L, _ptr(ln), _ptr(fl), w, _ptr(out), out.size, ctypes.byref(nb))
+    if rc != OK:
+        raise OracleError(rc, "substream_bits")
+    return out[: (nb.value + 7) // 8].tobytes(), nb.value
 
 
 def entry(c: np.ndarray, chunk: int, k: int) -> tuple[int, int, int, int]:

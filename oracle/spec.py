@@ -16,9 +16,10 @@ Steps (ZipNN, arXiv 2411.05239):
   modes    -- RAW / RLE / HUF / ZG per byte-group (§III-B, §IV-B, §V-A), with
               probe chunks every K+1 chunks (§III-B, "Identifying
               compressibility");
-  schedule -- the lock-step word order as a sort of (step, pair, lane) events
-              rather than nested loops;
-  layout   -- 64-byte header, 16-byte map entries, 128-byte aligned payloads
+  coding   -- one bit string per sub-stream (``substream_bits``);
+  layout   -- the lock-step word order of a lane group as a sort of (step,
+              pair, lane) events rather than nested loops (``layout``);
+  container -- 64-byte header, 16-byte map entries, 128-byte aligned payloads
               (the container described in ``zipnn_oracle.h``).
 """
 from __future__ import annotations
@@ -152,6 +153,36 @@ def _events(m: int, S: int, g: int, coded) -> list[list[tuple[int, list[int]]]]:
     return [[(key[2], idx) for key, idx in sorted(ev)] for ev in per_group]
 
 
+def substream_bits(sym: np.ndarray, S: int, g: int, codes: dict[int, tuple[int, int]], coded, w: int) -> tuple[int, int]:
+    """The coding of sub-stream w: the codes of the symbols of its coded groups
+    w, w+W, ... as (bits, count), bit i of the integer = i-th stream bit."""
+    m = len(sym)
+    W, G = -(-m // S), -(-m // g)
+    acc, n = 0, 0
+    for q in range(w, G, W):
+        if not coded(q):
+            continue
+        for e in range(q * g, min(q * g + g, m)):
+            c, l = codes[int(sym[e])]
+            for b in range(l):
+                acc |= ((c >> (l - 1 - b)) & 1) << n
+                n += 1
+    return acc, n
+
+
+def layout(events: list[tuple[int, list[int]]], lane_bits: dict[int, int], pair_bits, L: int) -> list[int]:
+    """The word layout of one lane group: walking its sorted events, a lane
+    holding fewer than 2L bits takes its next 32-bit word first."""
+    buffered, nxt, out = {}, {}, []
+    for lane, idx in events:
+        if buffered.get(lane, 0) < 2 * L:
+            out.append((lane_bits.get(lane, 0) >> (32 * nxt.get(lane, 0))) & 0xFFFFFFFF)
+            nxt[lane] = nxt.get(lane, 0) + 1
+            buffered[lane] = buffered.get(lane, 0) + 32
+        buffered[lane] -= pair_bits(idx)
+    return out
+
+
 def _huf_payload(sym: np.ndarray, S: int, g: int, L: int, lengths: dict[int, int], bitmap: bytes | None) -> bytes:
     m = len(sym)
     codes = canonical(lengths)
@@ -159,26 +190,15 @@ def _huf_payload(sym: np.ndarray, S: int, g: int, L: int, lengths: dict[int, int
         coded = lambda q: True
     else:
         coded = lambda q: (bitmap[q // 8] >> (q % 8)) & 1
+    W = -(-m // S)
     counts_out, words_out = [], []
-    for events in _events(m, S, g, coded):
-        # each lane's bit string (a Python int, bit i = i-th stream bit)
-        acc, nbits = {}, {}
-        for lane, idx in events:
-            for e in idx:
-                c, l = codes[int(sym[e])]
-                for b in range(l):
-                    acc[lane] = acc.get(lane, 0) | (((c >> (l - 1 - b)) & 1) << nbits.get(lane, 0))
-                    nbits[lane] = nbits.get(lane, 0) + 1
-        buffered, nxt, stream = {}, {}, []
-        for lane, idx in events:
-            if buffered.get(lane, 0) < 2 * L:
-                stream.append((acc.get(lane, 0) >> (32 * nxt.get(lane, 0))) & 0xFFFFFFFF)
-                nxt[lane] = nxt.get(lane, 0) + 1
-                buffered[lane] = buffered.get(lane, 0) + 32
-            buffered[lane] -= sum(lengths[int(sym[e])] for e in idx)
+    for j, events in enumerate(_events(m, S, g, coded)):
+        lane_bits = {l: substream_bits(sym, S, g, codes, coded, LANES * j + l)[0]
+                     for l in range(min(LANES, W - LANES * j))}
+        stream = layout(events, lane_bits, lambda idx: sum(lengths[int(sym[e])] for e in idx), L)
         counts_out.append(len(stream))
         words_out.extend(stream)
-    NG = -(-(-(-m // S)) // LANES)
+    NG = -(-W // LANES)
     H = _a16(128 + 4 * NG)
     table = bytes(lengths.get(2 * i, 0) | (lengths.get(2 * i + 1, 0) << 4) for i in range(128))
     head = table + struct.pack(f"<{NG}I", *counts_out)

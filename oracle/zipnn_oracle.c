@@ -268,6 +268,147 @@ static void put_code(uint8_t* buf, uint64_t* pos, uint32_t code, int len)
     }
 }
 
+/* ------------------------------------------------------- the coding */
+
+/* The bit string of one sub-stream -- the Huffman coding proper (paper
+ * §III-A: every byte group is coded with Huffman only).  A stream of m
+ * symbols is cut into groups of g consecutive symbols (group q = symbols
+ * qg .. min(qg+g, m)-1); with W = ceil(m/S) sub-streams, group q belongs to
+ * sub-stream q mod W, so sub-stream w holds the groups w, w+W, w+2W, ... in
+ * that order (this spreading of a chunk over W independent sub-streams is
+ * the format's own; the paper parallelises over chunks and byte groups only,
+ * §V-A).  With flags != NULL (ZG) the groups whose flag is 0 are left out.
+ * The bit string is the concatenation of the canonical codes of the symbols,
+ * each code most significant bit first; stream bit i is bit i%8 of byte i/8
+ * of out (out_bytes bytes, zeroed here).  *nbits receives its length.
+ * Returns ORC_OK, ORC_E_INVAL for w >= W or a symbol without a code, or
+ * ORC_E_NOSPACE when out is too small. */
+int orc_substream_bits(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g, int L, const uint8_t len[256],
+                       const uint8_t* flags, uint64_t w, uint8_t* out, uint64_t out_bytes, uint64_t* nbits)
+{
+    uint32_t code[256];
+    uint64_t W = (m + S - 1) / S;
+    uint64_t G = (m + g - 1) / g;
+    uint64_t pos = 0;
+    if (S == 0 || g == 0 || w >= W) return ORC_E_INVAL;
+    orc_canonical_codes(len, L, code);
+    memset(out, 0, out_bytes);
+    for (uint64_t q = w; q < G; q += W) {
+        if (flags && !flags[q]) continue;
+        uint64_t end = (q + 1) * g < m ? (q + 1) * g : m;
+        for (uint64_t e = q * g; e < end; e++) {
+            if (len[sym[e]] == 0) return ORC_E_INVAL;
+            if (pos + len[sym[e]] > 8 * out_bytes) return ORC_E_NOSPACE;
+            put_code(out, &pos, code[sym[e]], len[sym[e]]);
+        }
+    }
+    *nbits = pos;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------- the layout */
+
+/* The word layout of a HUF / ZG payload is the format's choice, not part of
+ * the method: the sub-strings are stored so that a decoder that runs 64
+ * sub-streams in lock-step (one per lane of a 64-wide wavefront) reads the
+ * words it needs next from consecutive addresses.  Sub-streams are taken 64
+ * at a time: sub-stream 64j+l is lane l of lane group j.  The layout is
+ * defined by the decode events of a lane group:
+ *   - the groups of lane l are its steps: the group at step s is
+ *     q = 64j + l + s*W; a coded group (every group for HUF, the marked ones
+ *     for ZG) gives one event per pair of symbols p = 0, 1, ..., covering
+ *     symbols 2p and 2p+1 of the group (the last pair of a short last group
+ *     may hold one symbol);
+ *   - the events are ordered by (step, pair, lane);
+ *   - walking them in that order, a lane whose buffer holds fewer than 2L
+ *     bits takes its next 32-bit word (word k = bits 32k .. 32k+31 of its bit
+ *     string, zero past the end) before its event, which adds 32 bits to the
+ *     buffer; the event's code bits then leave the buffer.
+ * The words of a lane group are stored in the order they are taken, and the
+ * lane groups one after another.  2L bits cover the two codes of a pair, so a
+ * decoder always holds the bits it is about to read; near the end a lane may
+ * take one word that lies wholly past its last code bit (all zero). */
+
+typedef struct {
+    uint64_t step;
+    uint32_t pair;
+    uint32_t lane;
+    uint32_t bits;   /* code bits of the pair's symbols (0 when not known yet) */
+} lg_event;
+
+static int event_order(const void* a, const void* b)
+{
+    const lg_event* x = (const lg_event*)a;
+    const lg_event* y = (const lg_event*)b;
+    if (x->step != y->step) return x->step < y->step ? -1 : 1;
+    if (x->pair != y->pair) return x->pair < y->pair ? -1 : 1;
+    if (x->lane != y->lane) return x->lane < y->lane ? -1 : 1;
+    return 0;
+}
+
+/* The events of lane group j, sorted.  flags: NULL (every group coded) or
+ * one byte per group.  With len != NULL each event carries the length of its
+ * codes (sym is then read); else 0.  *n_ev receives their number; NULL on an
+ * allocation failure. */
+static lg_event* lane_group_events(const uint8_t* sym, const uint8_t* len, uint64_t m, uint32_t S, uint32_t g,
+                                   const uint8_t* flags, uint64_t j, uint64_t* n_ev)
+{
+    uint64_t W = (m + S - 1) / S;
+    uint64_t G = (m + g - 1) / g;
+    uint64_t lanes = W - ORC_LANES * j < ORC_LANES ? W - ORC_LANES * j : ORC_LANES;
+    uint64_t steps = (G + W - 1) / W;
+    uint64_t cap = lanes * steps * ((g + 1) / 2) + 1;
+    lg_event* ev = (lg_event*)malloc(sizeof(lg_event) * cap);
+    uint64_t n = 0;
+    if (!ev) return NULL;
+    for (uint64_t l = 0; l < lanes; l++) {
+        for (uint64_t s = 0; s < steps; s++) {
+            uint64_t q = ORC_LANES * j + l + s * W;
+            if (q >= G || (flags && !flags[q])) continue;
+            uint64_t cnt = (q + 1) * g <= m ? g : m - q * g;
+            for (uint64_t p = 0; 2 * p < cnt; p++) {
+                uint32_t bits = 0;
+                if (len) {
+                    bits = len[sym[q * g + 2 * p]];
+                    if (2 * p + 1 < cnt) bits += len[sym[q * g + 2 * p + 1]];
+                }
+                ev[n].step = s;
+                ev[n].pair = (uint32_t)p;
+                ev[n].lane = (uint32_t)l;
+                ev[n].bits = bits;
+                n++;
+            }
+        }
+    }
+    qsort(ev, n, sizeof(lg_event), event_order);
+    *n_ev = n;
+    return ev;
+}
+
+/* Lay out one lane group: the lanes' bit strings (lane l at bits +
+ * l*lane_bytes, each long enough for the word taken past its end) become the
+ * word sequence defined above, written to words; returns the word count. */
+static uint64_t interleave(const lg_event* ev, uint64_t n_ev, const uint8_t* bits, uint64_t lane_bytes, int L,
+                           uint8_t* words)
+{
+    int64_t buffered[ORC_LANES];
+    uint64_t taken[ORC_LANES];
+    uint64_t n = 0;
+    memset(buffered, 0, sizeof(buffered));
+    memset(taken, 0, sizeof(taken));
+    for (uint64_t i = 0; i < n_ev; i++) {
+        uint32_t l = ev[i].lane;
+        if (buffered[l] < 2 * L) {
+            put_u32(words + 4 * n, get_u32(bits + l * lane_bytes + 4 * taken[l]));
+            n++;
+            taken[l]++;
+            buffered[l] += 32;
+        }
+        buffered[l] -= ev[i].bits;
+    }
+    return n;
+}
+
 /* ------------------------------------------------------- per-stream coding */
 
 typedef struct {
@@ -291,36 +432,23 @@ static uint64_t zg_bitmap_bytes(uint64_t m, uint32_t g)
     return align16(((m + g - 1) / g + 7) / 8);
 }
 
-/* Build the Huffman payload of m symbols with the given code lengths.  With
- * flags == NULL (HUF) every group of g symbols is coded; otherwise (ZG) only
- * the groups q with flags[q] set, and the group bitmap follows the head.
- *
- * Sub-stream w holds the codes of its coded symbols back to back; its bit
- * sequence is cut into 32-bit words (word k = bits 32k..32k+31, zero past
- * the end).  The sub-streams are taken 64 at a time (a lane group:
- * sub-stream 64j+l is lane l of group j) and the words of one lane group are
- * stored in the order in which a decoder that runs its 64 lanes in lock-step
- * asks for them: at step s every lane decodes its s-th group (group
- * w + s*W), pair by pair; for pair p, every lane whose group exists, is
- * coded and has a symbol 2p first takes its next word if its bit buffer holds
- * fewer than 2L bits (lanes in order), then decodes symbols 2p and 2p+1 of
- * the group.  A lane may take one word past its last code bit (all zero).
- * For HUF this is the order of rounds r = s*g/2 + p over every lane's own
- * symbols, since only a chunk's last group can be short. */
+/* The Huffman payload of m symbols with the given code lengths: the 4-bit
+ * length table, the word count of each lane group, (ZG: the group bitmap,)
+ * then each lane group's sub-stream bit strings laid out as described above.
+ * flags == NULL: HUF, every group coded; else ZG, the groups q with flags[q]
+ * set are coded and marked in the bitmap. */
 static int huf_payload(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g, int L, const uint8_t len[256],
                        const uint8_t* flags, stream_out* out)
 {
-    uint32_t code[256];
-    orc_canonical_codes(len, L, code);
     uint64_t W = (m + S - 1) / S;
     uint64_t NG = (W + ORC_LANES - 1) / ORC_LANES;
     uint64_t H = huf_head_bytes(W);
     uint64_t G = (m + g - 1) / g;
     uint64_t BM = flags ? zg_bitmap_bytes(m, g) : 0;
-    uint64_t steps = (G + W - 1) / W;                         /* groups of the longest sub-stream */
-    uint64_t nmax = steps * g;                                /* symbols of the longest sub-stream */
-    uint64_t lane_bytes = (nmax * (uint64_t)L + 7) / 8 + 8;   /* room for one extra zero word */
-    uint64_t max_words = W * ((nmax * (uint64_t)L + 31) / 32 + 2);
+    uint64_t steps = (G + W - 1) / W;                          /* groups of the longest sub-stream */
+    uint64_t nmax = steps * g;                                 /* symbols of the longest sub-stream */
+    uint64_t lane_bytes = ((nmax * (uint64_t)L + 31) / 32 + 1) * 4;   /* its words + the one past the end */
+    uint64_t max_words = W * (lane_bytes / 4);
     uint8_t* p = (uint8_t*)calloc(H + BM + 4 * max_words, 1);
     uint8_t* bits = (uint8_t*)malloc(ORC_LANES * lane_bytes);
     if (!p || !bits) {
@@ -334,43 +462,29 @@ static int huf_payload(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g, i
             if (flags[q]) p[H + q / 8] |= (uint8_t)(1u << (q % 8));
     uint8_t* words = p + H + BM;
     uint64_t wpos = 0;
-    for (uint64_t j = 0; j < NG; j++) {
+    int rc = ORC_OK;
+    for (uint64_t j = 0; j < NG && rc == ORC_OK; j++) {
         uint64_t lanes = W - ORC_LANES * j < ORC_LANES ? W - ORC_LANES * j : ORC_LANES;
-        uint64_t taken[ORC_LANES];
-        int cnt[ORC_LANES];
-        memset(bits, 0, ORC_LANES * lane_bytes);
-        for (uint64_t l = 0; l < lanes; l++) {
-            uint64_t pos = 0;
-            for (uint64_t q = ORC_LANES * j + l; q < G; q += W) {
-                if (flags && !flags[q]) continue;
-                uint64_t end = (q + 1) * g < m ? (q + 1) * g : m;
-                for (uint64_t e = q * g; e < end; e++) put_code(bits + l * lane_bytes, &pos, code[sym[e]], len[sym[e]]);
-            }
-            taken[l] = 0;
-            cnt[l] = 0;
+        uint64_t nbits, n_ev;
+        for (uint64_t l = 0; l < lanes && rc == ORC_OK; l++)
+            rc = orc_substream_bits(sym, m, S, g, L, len, flags, ORC_LANES * j + l, bits + l * lane_bytes, lane_bytes,
+                                    &nbits);
+        if (rc != ORC_OK) break;
+        lg_event* ev = lane_group_events(sym, len, m, S, g, flags, j, &n_ev);
+        if (!ev) {
+            rc = ORC_E_NOMEM;
+            break;
         }
-        uint64_t start = wpos;
-        for (uint64_t st = 0; st < steps; st++) {
-            for (uint32_t pr = 0; 2 * pr < g; pr++) {
-                for (uint64_t l = 0; l < lanes; l++) {
-                    uint64_t q = ORC_LANES * j + l + st * W;
-                    if (q >= G || (flags && !flags[q])) continue;
-                    uint64_t gcnt = (q + 1) * g <= m ? g : m - q * g;
-                    if (2 * pr >= gcnt) continue;
-                    if (cnt[l] < 2 * L) {
-                        put_u32(words + 4 * wpos, get_u32(bits + l * lane_bytes + 4 * taken[l]));
-                        wpos++;
-                        taken[l]++;
-                        cnt[l] += 32;
-                    }
-                    cnt[l] -= len[sym[q * g + 2 * pr]];
-                    if (2 * pr + 1 < gcnt) cnt[l] -= len[sym[q * g + 2 * pr + 1]];
-                }
-            }
-        }
-        put_u32(p + 128 + 4 * j, (uint32_t)(wpos - start));
+        uint64_t nw = interleave(ev, n_ev, bits, lane_bytes, L, words + 4 * wpos);
+        free(ev);
+        put_u32(p + 128 + 4 * j, (uint32_t)nw);
+        wpos += nw;
     }
     free(bits);
+    if (rc != ORC_OK) {
+        free(p);
+        return rc;
+    }
     out->mode = flags ? ORC_MODE_ZG : ORC_MODE_HUF;
     out->bytes = H + BM + 4 * wpos;
     out->payload = p;
@@ -495,10 +609,12 @@ raw:
 }
 
 /* Decode a Huffman (zg = 0) or ZG (zg = 1, fill value z) payload of m
- * symbols by replaying the lock-step steps and pairs described at
- * huf_payload: each lane collects the words it takes, and reads its codes
- * one bit at a time from them; the groups a ZG bitmap leaves unmarked are
- * filled with z.  Returns ORC_OK or ORC_E_CORRUPT. */
+ * symbols.  The groups a ZG bitmap leaves unmarked are filled with z.  Each
+ * lane group is read back by walking its sorted decode events (see "the
+ * layout" above): before an event, a lane holding fewer than 2L unread bits
+ * takes the next word of the lane group's sequence; then the event's one or
+ * two symbols are read from the lane's bits one bit at a time, each code
+ * being recognised by canonical decoding.  Returns ORC_OK or ORC_E_CORRUPT. */
 static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, uint32_t g, int L, int zg,
                       uint8_t z, uint8_t* sym)
 {
@@ -534,6 +650,20 @@ static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, 
     if (bytes != H + BM + 4 * total) return ORC_E_CORRUPT;
     const uint8_t* words = p + H + BM;
 
+    /* ZG: the coded groups are the marked ones; the others hold z */
+    uint8_t* flags = NULL;
+    if (zg) {
+        flags = (uint8_t*)malloc(G ? G : 1);
+        if (!flags) return ORC_E_NOMEM;
+        for (uint64_t q = 0; q < G; q++) {
+            flags[q] = (uint8_t)((p[H + q / 8] >> (q % 8)) & 1);
+            if (!flags[q]) {
+                uint64_t end = (q + 1) * g < m ? (q + 1) * g : m;
+                memset(sym + q * g, z, end - q * g);
+            }
+        }
+    }
+
     /* canonical decoding tables: symbols sorted by (length, symbol) and the
      * count of codes of each length */
     int count[32] = {0};
@@ -549,69 +679,69 @@ static int decode_huf(const uint8_t* p, uint64_t bytes, uint64_t m, uint32_t S, 
     uint64_t nmax = steps * g;
     uint64_t max_take = (nmax * (uint64_t)L + 2 * L) / 32 + 2;   /* words a lane can take */
     uint32_t* got = (uint32_t*)malloc(sizeof(uint32_t) * ORC_LANES * max_take);
-    if (!got) return ORC_E_NOMEM;
+    if (!got) {
+        free(flags);
+        return ORC_E_NOMEM;
+    }
     int rc = ORC_OK;
     uint64_t wpos = 0;
     for (uint64_t j = 0; j < NG && rc == ORC_OK; j++) {
-        uint64_t lanes = W - ORC_LANES * j < ORC_LANES ? W - ORC_LANES * j : ORC_LANES;
         uint64_t taken[ORC_LANES], bitpos[ORC_LANES];
-        int cnt[ORC_LANES];
-        for (uint64_t l = 0; l < lanes; l++) {
-            taken[l] = bitpos[l] = 0;
-            cnt[l] = 0;
-        }
+        int64_t buffered[ORC_LANES];
+        memset(taken, 0, sizeof(taken));
+        memset(bitpos, 0, sizeof(bitpos));
+        memset(buffered, 0, sizeof(buffered));
         uint64_t end = wpos + get_u32(p + 128 + 4 * j);
-        for (uint64_t st = 0; st < steps && rc == ORC_OK; st++) {
-            for (uint32_t pr = 0; 2 * pr < g && rc == ORC_OK; pr++) {
-                for (uint64_t l = 0; l < lanes && rc == ORC_OK; l++) {
-                    uint64_t q = ORC_LANES * j + l + st * W;
-                    if (q >= G) continue;
-                    uint64_t gcnt = (q + 1) * g <= m ? g : m - q * g;
-                    if (zg && !((p[H + q / 8] >> (q % 8)) & 1)) {
-                        if (pr == 0) memset(sym + q * g, z, gcnt);   /* an unmarked group */
-                        continue;
-                    }
-                    if (2 * pr >= gcnt) continue;
-                    if (cnt[l] < 2 * L) {
-                        if (wpos >= end || taken[l] >= max_take) {
-                            rc = ORC_E_CORRUPT;
-                            break;
-                        }
-                        got[l * max_take + taken[l]++] = get_u32(words + 4 * wpos++);
-                        cnt[l] += 32;
-                    }
-                    for (uint64_t t = 2 * pr; t < 2 * pr + 2 && t < gcnt; t++) {
-                        /* read code bits one at a time; after l bits, the code
-                         * value minus the first code of length l is the index
-                         * among the symbols of length l if below their count */
-                        int codev = 0, first = 0, index = 0, found = -1;
-                        for (int b = 1; b <= L; b++) {
-                            if (bitpos[l] >= 32 * taken[l]) break;
-                            uint32_t wd = got[l * max_take + bitpos[l] / 32];
-                            codev |= (int)((wd >> (bitpos[l] % 32)) & 1u);
-                            bitpos[l]++;
-                            cnt[l]--;
-                            if (codev - first < count[b]) {
-                                found = sorted[index + codev - first];
-                                break;
-                            }
-                            index += count[b];
-                            first += count[b];
-                            first <<= 1;
-                            codev <<= 1;
-                        }
-                        if (found < 0) {
-                            rc = ORC_E_CORRUPT;
-                            break;
-                        }
-                        sym[q * g + t] = (uint8_t)found;
-                    }
+        uint64_t n_ev;
+        lg_event* ev = lane_group_events(NULL, NULL, m, S, g, flags, j, &n_ev);
+        if (!ev) {
+            rc = ORC_E_NOMEM;
+            break;
+        }
+        for (uint64_t i = 0; i < n_ev && rc == ORC_OK; i++) {
+            uint32_t l = ev[i].lane;
+            uint64_t q = ORC_LANES * j + l + ev[i].step * W;
+            uint64_t cnt = (q + 1) * g <= m ? g : m - q * g;
+            if (buffered[l] < 2 * L) {
+                if (wpos >= end || taken[l] >= max_take) {
+                    rc = ORC_E_CORRUPT;
+                    break;
                 }
+                got[l * max_take + taken[l]++] = get_u32(words + 4 * wpos++);
+                buffered[l] += 32;
+            }
+            for (uint64_t t = 2 * (uint64_t)ev[i].pair; t < 2 * (uint64_t)ev[i].pair + 2 && t < cnt; t++) {
+                /* read code bits one at a time; after b bits, the code value
+                 * minus the first code of length b is the index among the
+                 * symbols of length b if below their count */
+                int codev = 0, first = 0, index = 0, found = -1;
+                for (int b = 1; b <= L; b++) {
+                    if (bitpos[l] >= 32 * taken[l]) break;
+                    uint32_t wd = got[l * max_take + bitpos[l] / 32];
+                    codev |= (int)((wd >> (bitpos[l] % 32)) & 1u);
+                    bitpos[l]++;
+                    buffered[l]--;
+                    if (codev - first < count[b]) {
+                        found = sorted[index + codev - first];
+                        break;
+                    }
+                    index += count[b];
+                    first += count[b];
+                    first <<= 1;
+                    codev <<= 1;
+                }
+                if (found < 0) {
+                    rc = ORC_E_CORRUPT;
+                    break;
+                }
+                sym[q * g + t] = (uint8_t)found;
             }
         }
+        free(ev);
         if (rc == ORC_OK && wpos != end) rc = ORC_E_CORRUPT;   /* every word taken exactly */
     }
     free(got);
+    free(flags);
     return rc;
 }
 

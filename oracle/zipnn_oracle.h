@@ -24,19 +24,24 @@
  *   HUF payload: 128 bytes of 4-bit code lengths (byte i = l[2i] | l[2i+1]<<4)
  *     | u32 word count of each of the NG = ceil(W/64) lane groups | zero pad
  *     to align16(128 + 4*NG) | the word streams of lane groups 0..NG-1.
- *     W = ceil(m/S) sub-streams; group q of g consecutive symbols belongs to
- *     sub-stream q mod W; sub-stream 64j+l is lane l of lane group j.  A
- *     sub-stream's codes (most significant bit first, LSB-first packing) are
- *     cut into 32-bit words; a lane group's words are stored in the order a
- *     lock-step decoder of its 64 lanes takes them: at step s each lane
- *     decodes its group w + s*W pair by pair; for each pair, every lane whose
- *     group exists and has that pair takes its next word if it holds fewer
- *     than 2L bits (lanes in order), then decodes the pair.
+ *     The coding: W = ceil(m/S) sub-streams; group q of g consecutive symbols
+ *     belongs to sub-stream q mod W; a sub-stream's bit string is the
+ *     canonical codes of its symbols, most significant bit first, packed
+ *     LSB-first (orc_substream_bits).
+ *     The layout (the format's choice, made for a decoder that runs 64
+ *     sub-streams in lock-step, one per lane of a wavefront): sub-stream
+ *     64j+l is lane l of lane group j; each bit string is cut into 32-bit
+ *     words; the decode events of a lane group -- (step s, pair p, lane l)
+ *     for every pair of symbols of every coded group 64j+l+s*W -- are sorted
+ *     by (s, p, l); walking them, a lane holding fewer than 2L bits takes its
+ *     next word before its event, and the event's code bits then leave its
+ *     buffer.  The words are stored in the order taken (a lane may take one
+ *     all-zero word past its last code bit).
  *   ZG payload (fill value z in the map): the HUF head | a bitmap of the
  *     G = ceil(m/g) groups, bit q (byte q/8, bit q%8) set when group q holds
  *     a symbol other than z, zero padded to align16(ceil(G/8)) | the word
- *     streams as for HUF, where only marked groups are coded and take part in
- *     the steps; unmarked groups decode to z.
+ *     streams as for HUF, where only marked groups are coded and give
+ *     events; unmarked groups decode to z.
  */
 #ifndef ZIPNN_ORACLE_H
 #define ZIPNN_ORACLE_H
@@ -85,6 +90,12 @@ int orc_check_params(int B, uint32_t chunk_bytes, uint32_t S, uint32_t g, uint32
 void orc_split_stream(const uint8_t* words, uint64_t m, int B, int k, uint8_t* out);
 int orc_package_merge(const uint64_t f[256], int L, uint8_t len_out[256]);
 void orc_canonical_codes(const uint8_t len[256], int L, uint32_t code[256]);
+/* Bit string of sub-stream w of a stream of m symbols (the coding without the
+ * word layout): the canonical codes of the symbols of its groups w, w+W, ...
+ * (W = ceil(m/S); flags != NULL: only groups with flags[q] != 0), most
+ * significant code bit first, packed LSB-first into out (zeroed first). */
+int orc_substream_bits(const uint8_t* sym, uint64_t m, uint32_t S, uint32_t g, int L, const uint8_t len[256],
+                       const uint8_t* flags, uint64_t w, uint8_t* out, uint64_t out_bytes, uint64_t* nbits);
 uint64_t orc_compress_bound(int dtype, uint64_t n, uint32_t chunk_bytes, uint32_t S);
 /* skip: probe interval K (0..255).  Chunk c of the tensor is a probe chunk
  * when c mod (K+1) = 0; under AUTO the K chunks after a probe chunk are

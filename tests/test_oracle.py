@@ -198,6 +198,15 @@ def _read_fixture(name):
         elif k == "set":
             data = bytes.fromhex("".join(v[1:]))
             words[int(v[0]):int(v[0]) + len(data)] = np.frombuffer(data, np.uint8)
+        elif k == "set_groups":
+            # set_groups W g wmod wrem steps HEX: every group q of g symbols with
+            # (q mod W) mod wmod == wrem and q div W in steps holds HEX
+            W, gg, wmod, wrem = (int(x) for x in v[:4])
+            steps = {int(x) for x in v[4].split(",")}
+            data = np.frombuffer(bytes.fromhex("".join(v[5:])), np.uint8)
+            for q in range(-(-len(words) // gg)):
+                if (q % W) % wmod == wrem and q // W in steps:
+                    words[q * gg:q * gg + gg] = data
         elif k == "set_iota":
             words[int(v[0]):int(v[0]) + int(v[1])] = np.arange(int(v[1])) & 0xFF
         elif k == "set_fill":
@@ -212,6 +221,11 @@ def _read_fixture(name):
                 params[a] = tuple(int(x) for x in b.split(",")) if "," in b else int(b)
         elif k == "size":
             blob = bytearray(int(v[0]))
+        elif k == "rep":
+            # rep OFF COUNT HEX: HEX written COUNT times from OFF
+            off, count = int(v[0]), int(v[1])
+            data = bytes.fromhex("".join(v[2:])) * count
+            blob[off:off + len(data)] = data
         elif k == "at":
             off = int(v[0])
             data = bytes.fromhex("".join(v[1:]))
@@ -222,7 +236,8 @@ def _read_fixture(name):
 
 
 @pytest.mark.parametrize("name", ["tiny_bf16_container.txt", "tiny_u8_rounds.txt", "tiny_u8_zg.txt",
-                                  "tiny_u8_probe.txt", "tiny_bf16_exp.txt"])
+                                  "tiny_u8_probe.txt", "tiny_bf16_exp.txt", "tiny_u8_lanegroups.txt",
+                                  "tiny_u8_zg_lanegroups.txt"])
 def test_tiny_containers_match_hand_derivation(oracle_lib, name):
     words, p, expect = _read_fixture(name)
     kw = dict(chunk_bytes=p["chunk_bytes"], S=p["S"], g=p["g"], L=p["L"], policy=p["policy"], skip=p.get("skip", 0),
