@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the gfx950 ZipNN codec (byte grouping + chunked Huffman).
 
-Default workload: one FP32 tensor of 8192 x 8192 elements (256 MiB), row r
-drawn from N(0, sigma_r) with log10(sigma_r) ~ U(-3, -1), 256 KiB chunks,
-every byte group Huffman-coded only where that beats raw (AUTO).
+Default workload: the synthetic 8B-parameter decoder checkpoint (291 BF16
+tensors, 16.06 GB: embedding and head N(0, 0.01), projections N(0, 0.02),
+RMSNorm vectors 1 + N(0, 0.05)), batched: every kernel runs once for all
+tensors and the decode replays a hipGraph; chunk size and sub-stream length
+are picked by the autotuner in 64 KiB .. 1 MiB.
 
-One step = the whole hot path on that tensor, input resident in HBM:
-compress (split + histogram + code build + placement + bit packing) and
-decompress (table build + Huffman decode + merge + store).  The headline
-`value` is decode throughput in GB/s of uncompressed bytes (the paper's
-convention), from HIP events around every decode launch of the timed steps
-(on the stream the kernel runs on); `encode_GBps` is the same for compress.
+One step = the whole hot path on the checkpoint, inputs resident in HBM:
+batched compress (split + histogram + code build + placement + bit packing)
+then batched decompress (table build + Huffman decode + merge + store).  The
+headline `value` is decode throughput in GB/s of uncompressed bytes (the
+paper's convention), from HIP events around every decode launch of the timed
+steps (on the stream the graph runs on); `encode_GBps` is the same for
+compress.  The same line carries the plain per-tensor decode, the roofline of
+the decode kernel, the oracle timed on the host cores (1 thread and the
+box's 16), and a serving block: the continuous-batching server against plain
+per-request launches at 100, 1000 and 5000 requests/s plus a closed loop.
 
 Prints ONE JSON line.  `--gpus N` with N > 1 is refused: this build runs on
 one GPU.
@@ -74,36 +80,65 @@ def make_workload(name: str, probe_skip: int = 0, exponent: bool = False):
     return x, p, desc
 
 
-def cpu_baseline(x_cpu, p, gpu_container, budget_s: float):
-    """The oracle (plain C, test infrastructure) on the host cores: one full
-    compress and repeated full decompressions of the same tensor."""
+BOX_THREADS = 16   # host threads the benchmark boxes give one GPU
+
+
+def host_info() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def oracle_legs(tensors, bases, p, gpu_containers, budget_s: float, sample: str) -> dict:
+    """The oracle (plain C, test infrastructure) on the host cores, at 1
+    thread and at the box's share of threads: every sample tensor is
+    compressed once (its container compared with the GPU's) and the sample is
+    decompressed repeatedly until `budget_s` seconds of decode have passed."""
     import numpy as np
 
     import oracle
 
     from paper_2411_05239_amd import zipnn as Z
 
-    code = Z.torch_dtype_code(x_cpu.dtype)
-    threads = max(1, min(16, os.cpu_count() or 1))
+    many = max(1, min(BOX_THREADS, os.cpu_count() or 1))
     kw = dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy),
               skip=p.probe_skip, exp=bool(p.exponent))
-    t0 = time.perf_counter()
-    c = oracle.compress(x_cpu, code, nthreads=threads, **kw)
-    t_enc = time.perf_counter() - t0
-    matches = bool(np.array_equal(c, gpu_container))
-    reps, t_dec = 0, 0.0
-    while reps == 0 or t_dec < budget_s:
-        t0 = time.perf_counter()
-        out = oracle.decompress(c, nthreads=threads)
-        t_dec += time.perf_counter() - t0
-        reps += 1
-    ok = bool(np.array_equal(out, oracle.as_bytes(x_cpu)))
-    U = x_cpu.numel() * x_cpu.element_size()
-    return {
-        "value": round(U * reps / t_dec / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
-        "sample": f"full tensor ({U} bytes): 1 compress + {reps} decompress passes, {threads} threads",
-        "encode_GBps": round(U / t_enc / 1e9, 4), "roundtrip_ok": ok, "container_matches_gpu": matches,
-    }
+    U = sum(x.numel() * x.element_size() for x in tensors)
+    legs, matches, ok = {}, True, True
+    for th in (many, 1):
+        t_enc, cs = 0.0, []
+        for i, x in enumerate(tensors):
+            t0 = time.perf_counter()
+            c = oracle.compress(x, Z.torch_dtype_code(x.dtype), base=bases[i] if bases else None, nthreads=th, **kw)
+            t_enc += time.perf_counter() - t0
+            if th == many:
+                matches &= bool(np.array_equal(c, gpu_containers[i]))
+            cs.append(c)
+        reps, t_dec = 0, 0.0
+        while reps == 0 or t_dec < budget_s:
+            for i, c in enumerate(cs):
+                t0 = time.perf_counter()
+                d = oracle.decompress(c, base=bases[i] if bases else None, nthreads=th)
+                t_dec += time.perf_counter() - t0
+                if reps == 0:
+                    ok &= bool(np.array_equal(d, oracle.as_bytes(tensors[i])))
+            reps += 1
+        legs[th] = {"decode_GBps": round(U * reps / t_dec / 1e9, 4), "encode_GBps": round(U / t_enc / 1e9, 4),
+                    "threads": th, "decode_passes": reps}
+    return {"value": legs[many]["decode_GBps"], "unit": "GB/s", "cores": many, "kind": "oracle",
+            "sample": f"{sample} ({U} bytes): 1 compress + {legs[many]['decode_passes']} decompress passes at "
+                      f"{many} threads; 1 compress + {legs[1]['decode_passes']} decompress passes at 1 thread",
+            "encode_GBps": legs[many]["encode_GBps"], "single_thread": legs[1],
+            "host": {**host_info(), "threads_used": many,
+                     "note": f"the all-cores leg uses the {BOX_THREADS} host threads a one-GPU box is given"},
+            "roundtrip_ok": ok, "containers_match_gpu": matches}
 
 
 def run_single(args):
@@ -211,7 +246,7 @@ def run_single(args):
         "paper_context": "ZipNN CPU: up to 80 GB/s decompression, 13 GB/s compression (Xeon 8480+, 16 workers)",
     }
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(x_cpu, p, c.cpu().numpy(), args.cpu_budget)
+        rec["cpu_baseline"] = oracle_legs([x_cpu], None, p, [c.cpu().numpy()], args.cpu_budget, "the whole tensor")
     print(json.dumps(rec))
 
 
@@ -219,45 +254,6 @@ def _events():
     import torch
 
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-
-def cpu_baseline_sample(xs, bases, p, arena_np, offs, budget_s):
-    """The oracle (plain C, test infrastructure) on the host cores, on a
-    bounded sample: the first tensors of the checkpoint up to ~512 MB; their
-    oracle containers are compared with the GPU's."""
-    import numpy as np
-
-    import oracle
-
-    threads = max(1, min(16, os.cpu_count() or 1))
-    kw = dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy),
-              skip=p.probe_skip, exp=bool(p.exponent))
-    idx, tot = [], 0
-    for i, x in enumerate(xs):
-        if tot >= (512 << 20):
-            break
-        if x.numel():
-            idx.append(i)
-            tot += x.numel() * 2
-    t_enc = t_dec = 0.0
-    matches = ok = True
-    for i in idx:
-        xc = xs[i].cpu()
-        bc = bases[i].cpu() if bases is not None else None
-        t0 = time.perf_counter()
-        c = oracle.compress(xc, oracle.BF16, base=bc, nthreads=threads, **kw)
-        t_enc += time.perf_counter() - t0
-        matches &= bool(np.array_equal(c, arena_np[offs[i]: offs[i] + c.size]))
-        t0 = time.perf_counter()
-        d = oracle.decompress(c, base=bc, nthreads=threads)
-        t_dec += time.perf_counter() - t0
-        ok &= bool(np.array_equal(d, oracle.as_bytes(xc)))
-        if t_enc + t_dec > budget_s * 4:
-            break
-    return {"value": round(tot / t_dec / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {len(idx)} tensors of the checkpoint ({tot} bytes), 1 compress + 1 decompress each, "
-                      f"{threads} threads",
-            "encode_GBps": round(tot / t_enc / 1e9, 4), "roundtrip_ok": ok, "containers_match_gpu": matches}
 
 
 def _modes(arena_np, offs):
@@ -270,6 +266,16 @@ def _modes(arena_np, offs):
         for m in range(4):
             tot[m] += info.entries_by_mode[m]
     return dict(zip(["raw", "huf", "rle", "zg"], tot))
+
+
+def _container(arena_np, off: int):
+    """The container at `off` of a host copy of an arena, by its header's size."""
+    total = int.from_bytes(arena_np[off + 32: off + 40].tobytes(), "little")
+    return arena_np[off: off + total]
+
+
+def _kind(name: str) -> str:
+    return name.split(".")[-1]
 
 
 def run_checkpoint(args, delta: bool, zg: bool = False):
@@ -298,10 +304,22 @@ def run_checkpoint(args, delta: bool, zg: bool = False):
     else:
         policy = None   # AUTO: RAW / RLE / HUF / ZG per byte group and chunk
     bptr = [b.data_ptr() for b in bases] if delta else [None] * len(xs)
-    best, table = Z.zipnn_autotune(codec.ctx, Z.ZIPNN_BF16, [x.data_ptr() for x in xs], [x.numel() for x in xs],
-                                   bptr, 1 << 30, 0.01, policy)
+    # chunk size and sub-stream length: the autotuner, over the paper's range
+    # around its 256 KB default (64 KiB .. 1 MiB), on a share of every tensor
+    if args.chunk_bytes:
+        # a fixed shape (profiling runs): no autotuning
+        best, table = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=args.chunk_bytes, S=args.substream_syms,
+                                    policy=policy), []
+    else:
+        best, table = Z.tune_checkpoint(codec, xs, bases, policy)
     best.probe_skip = args.probe_skip
     best.exponent = int(args.exponent)
+    smp = Z.autotune_sample([x.numel() for x in xs], 2, Z.TUNE_SAMPLE_BYTES, Z.TUNE_MAX_CHUNK)
+    comp = {}
+    for sp, k in zip(specs, smp):
+        c = comp.setdefault(_kind(sp.name), {"tensors": 0, "bytes": 0})
+        c["tensors"] += 1
+        c["bytes"] += 2 * k
     arena, offs = codec.compress_batch(xs, best, bases)
     outs = [torch.empty_like(x) for x in xs]
     batch = codec.prepare_batch(arena, offs, outs, bases)
@@ -313,22 +331,25 @@ def run_checkpoint(args, delta: bool, zg: bool = False):
     C = offs[-1]
     enc, dec = [], []
     for i in range(args.warmup + args.steps):
-        a0, a1 = _events()
-        a0.record(stream)
-        _, offs2 = codec.compress_batch(xs, best, bases, arena=arena)
-        a1.record(stream)
+        if i == args.warmup:
+            torch.cuda.synchronize()
+            t_wall = time.perf_counter()
+        if not args.decode_only:
+            a0, a1 = _events()
+            a0.record(stream)
+            _, offs2 = codec.compress_batch(xs, best, bases, arena=arena)
+            a1.record(stream)
+            assert offs2 == offs
         b0, b1 = _events()
         b0.record(stream)
         batch.run()
         b1.record(stream)
         if i >= args.warmup:
-            enc.append((a0, a1))
+            if not args.decode_only:
+                enc.append((a0, a1))
             dec.append((b0, b1))
-        if i == args.warmup:
-            t_wall = time.perf_counter()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
-    assert offs2 == offs
     st = codec.status()
     if st != Z.ZIPNN_OK or not all(torch.equal(o.view(torch.uint8), x.view(torch.uint8)) for o, x in zip(outs, xs)):
         print(json.dumps({"error": f"status {st} or mismatch after timing"}))
@@ -348,42 +369,78 @@ def run_checkpoint(args, delta: bool, zg: bool = False):
         p1.record(stream)
         per.append((p0, p1))
     torch.cuda.synchronize()
+    # plain device copy of 1 GiB: the achievable streaming rate beside the
+    # 8 TB/s peak, and the calibration kernel for the HBM counters
+    cin = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    cin.fill_(7)
+    cout = torch.empty_like(cin)
+    cp = []
+    for i in range(5):
+        c0, c1 = _events()
+        c0.record(stream)
+        cout.copy_(cin)
+        c1.record(stream)
+        cp.append((c0, c1))
+    torch.cuda.synchronize()
+    copy_ms = statistics.median(a.elapsed_time(b) for a, b in cp)
+    del cin, cout
     dec_ms = [a.elapsed_time(b) for a, b in dec]
     enc_ms = [a.elapsed_time(b) for a, b in enc]
     per_ms = min(a.elapsed_time(b) for a, b in per[1:])
     dec_avg = statistics.mean(dec_ms)
     alg = C + U + (U if delta else 0)
     achieved = alg / (dec_avg * 1e-3) / 1e9
+    enc_alg = U + (U if delta else 0) + C
     name = ("ckpt8b_delta_zg" if zg else "ckpt8b_delta") if delta else "ckpt8b"
     rec = {
-        "metric": "decode GB/s at bit-exact roundtrip (uncompressed bytes / decode time); encode GB/s beside it",
+        "metric": "decode/encode GB/s at bit-exact roundtrip; batched-serving vs plain p99 latency",
         "value": round(U / (dec_avg * 1e-3) / 1e9, 2),
         "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": ("xor_delta_of_" if delta else "") + "bf16_8b_decoder_checkpoint_291_tensors"
                                + ("_zg" if zg else ""),
-                   "tensors": len(xs), "bytes": U, "chunk_bytes": best.chunk_bytes, "S": best.substream_syms,
-                   "g": best.group, "L": best.max_code_len, "policy": "huf,huf" if delta and not zg else "auto",
-                   "probe_skip": best.probe_skip,
-                   "exponent": best.exponent,
-                   "batched": "one launch per kernel + hipGraph replay"},
-        "decode_ms": {"mean": round(dec_avg, 4), "median": round(statistics.median(dec_ms), 4)},
-        "encode_GBps": round(U / (statistics.mean(enc_ms) * 1e-3) / 1e9, 2),
-        "encode_ms": {"mean": round(statistics.mean(enc_ms), 4)},
+                   "tensor_dtype": "bf16", "tensors": len(xs), "bytes": U, "chunk_bytes": best.chunk_bytes,
+                   "S": best.substream_syms, "g": best.group, "L": best.max_code_len,
+                   "policy": "huf,huf" if delta and not zg else "auto", "probe_skip": best.probe_skip,
+                   "exponent": best.exponent, "batched": "one launch per kernel + hipGraph replay",
+                   "step": "batched encode + batched decode" if not args.decode_only else "batched decode"},
+        "decode_ms": {"mean": round(dec_avg, 4), "median": round(statistics.median(dec_ms), 4),
+                      "p10": round(sorted(dec_ms)[len(dec_ms) // 10], 4),
+                      "p90": round(sorted(dec_ms)[(len(dec_ms) * 9) // 10], 4)},
+        "encode_GBps": round(U / (statistics.mean(enc_ms) * 1e-3) / 1e9, 2) if enc_ms else None,
+        "encode_ms": {"mean": round(statistics.mean(enc_ms), 4)} if enc_ms else None,
+        "encode_roofline_frac": round(enc_alg / (statistics.mean(enc_ms) * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+        if enc_ms else None,
         "per_tensor_decode": {"launches": sum(1 for x in xs if x.numel()), "ms": round(per_ms, 4),
                               "GBps": round(U / (per_ms * 1e-3) / 1e9, 2)},
         "compressed_bytes": C, "ratio": round(C / U, 5), "entries_by_mode": _modes(a_np, offs),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": _traffic(name, alg),
                      "kernel": "k_decode", "algorithmic_bytes_per_launch": alg},
-        "autotune": [{"chunk_bytes": e.params.chunk_bytes, "S": e.params.substream_syms, "ratio": round(e.ratio, 5),
-                      "decode_GBps": round(e.decode_gbps, 1), "encode_GBps": round(e.encode_gbps, 1)} for e in table],
+        "copy_probe_GBps": round(2 * (1 << 30) / (copy_ms * 1e-3) / 1e9, 1),
+        "autotune": {"pick": {"chunk_bytes": best.chunk_bytes, "S": best.substream_syms},
+                     "rule": "64 KiB..1 MiB chunks x 256..2048 sub-streams on the whole checkpoint; median of 7 "
+                             "decodes; ratio within 1%; rates within 2% of the fastest tie; smallest chunk, then "
+                             "best ratio",
+                     "sample": {"bytes": 2 * sum(smp), "by_kind": comp},
+                     "candidates": [{"chunk_bytes": e.params.chunk_bytes, "S": e.params.substream_syms,
+                                     "ratio": round(e.ratio, 5), "decode_GBps": round(e.decode_gbps, 1),
+                                     "encode_GBps": round(e.encode_gbps, 1)} for e in table]},
         "paper_context": "ZipNN CPU: up to 80 GB/s decompression, 13 GB/s compression (Xeon 8480+, 16 workers)",
     }
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline_sample(xs, bases, best, a_np, offs, args.cpu_budget)
+        # a bounded sample: layer 0's nine tensors (every projection kind and both norms) and the final norm
+        idx = [i for i, sp in enumerate(specs) if sp.name.startswith("layers.0.") or sp.name == "final_norm"]
+        rec["cpu_baseline"] = oracle_legs([xs[i].cpu() for i in idx], [bases[i].cpu() for i in idx] if delta else None,
+                                          best, [_container(a_np, offs[i]) for i in idx], args.cpu_budget,
+                                          "layer 0 (q, k, v, o, gate, up, down, 2 norms) and the final norm")
     batch.close()
+    del outs, arena, batch, xs, bases
+    codec.close()
+    torch.cuda.empty_cache()
+    if not delta and not args.no_serve and not args.decode_only:
+        rec["serving"] = serve_block(args, [int(r) for r in args.serve_rates.split(",")])
     print(json.dumps(rec))
 
 
@@ -508,13 +565,13 @@ def run_series(args):
     print(json.dumps(rec))
 
 
-def run_serve(args):
+def serve_block(args, rates) -> dict:
     """Serving loop: a corpus of 128 tensors (64 KiB - 1 GiB log-uniform,
     60/30/10 BF16/FP32/FP8) resident compressed; Poisson request streams at
-    rates 100 - 5000/s decoded by the continuous-batching server and by the
-    same server launching one decode per request; then a closed-loop pass
-    (every item requested at once) whose results are checked byte for byte
-    against the original tensors."""
+    `rates` decoded by the continuous-batching server and by the same server
+    launching one decode per request; first a closed-loop pass (every item
+    requested at once) whose results are checked byte for byte against the
+    original tensors."""
     import torch
 
     from paper_2411_05239_amd import workloads
@@ -532,9 +589,7 @@ def run_serve(args):
     torch.cuda.synchronize()
     sizes = [x.numel() * x.element_size() for x in xs]
     U, C = sum(sizes), sum(c.numel() for c in cs)
-    rates = [100, 200, 500, 1000, 2000, 5000]
-    res = {}
-    closed = {}
+    res, closed = {}, {}
     for mode, name in [(Z.ZIPNN_SERVE_CONTINUOUS, "continuous"), (Z.ZIPNN_SERVE_PER_REQUEST, "per_request")]:
         srv = Z.Server(codec, pool_bytes=16 << 30, max_inflight=256, mode=mode)
         handles = [srv.register(c) for c in cs]
@@ -567,23 +622,36 @@ def run_serve(args):
         st = Z.zipnn_server_stats(srv.h)
         closed[name]["iterations"] = st.iterations
         srv.close()
-    alg = C + U
-    cl = closed["continuous"]
+    codec.close()
+    del xs, cs
+    torch.cuda.empty_cache()
+    cmp = [{"rate": a["rate"], "p99_continuous_ms": a["p99_ms"], "p99_per_request_ms": b["p99_ms"],
+            "continuous_p99_le_per_request": a["p99_ms"] <= b["p99_ms"],
+            "GBps_continuous": a["GBps"], "GBps_per_request": b["GBps"]}
+           for a, b in zip(res["continuous"], res["per_request"])]
+    return {"workload": "serving_corpus_128_tensors_64KiB_1GiB_bf16_fp32_fp8", "bytes": U, "compressed_bytes": C,
+            "pool_bytes": 16 << 30, "rates": rates, "closed_loop": closed, "open_loop": res, "comparison": cmp}
+
+
+def run_serve(args):
+    """The serving loop alone, over the full rate sweep (100 - 5000/s)."""
+    rates = [100, 200, 500, 1000, 2000, 5000]
+    blk = serve_block(args, rates)
+    cl = blk["closed_loop"]["continuous"]
+    alg = blk["compressed_bytes"] + blk["bytes"]
     rec = {
-        "metric": "decode GB/s at bit-exact roundtrip; batched-serving vs plain p99 latency",
+        "metric": "decode/encode GB/s at bit-exact roundtrip; batched-serving vs plain p99 latency",
         "value": cl["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(cl["seconds"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": "serving_corpus_128_tensors_64KiB_1GiB_bf16_fp32_fp8", "bytes": U,
-                   "compressed_bytes": C, "pool_bytes": 16 << 30, "chunks_per_iter": 2048, "rates": rates},
-        "closed_loop": closed,
-        "open_loop": res,
+        "config": {"workload": blk["workload"], "bytes": blk["bytes"], "compressed_bytes": blk["compressed_bytes"],
+                   "pool_bytes": blk["pool_bytes"], "chunks_per_iter": 2048, "rates": rates},
+        "closed_loop": blk["closed_loop"], "open_loop": blk["open_loop"], "comparison": blk["comparison"],
         "roofline": {"bound": "hbm", "achieved": round(alg / cl["seconds"] / 1e9, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(alg / cl["seconds"] / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None,
                      "kernel": "k_decode (server iterations; wall clock of the closed-loop pass)",
                      "algorithmic_bytes_per_launch": alg},
     }
-    codec.close()
     print(json.dumps(rec))
 
 
@@ -592,17 +660,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fp32_256mb",
+    ap.add_argument("--workload", default="ckpt8b",
                     choices=["bf16_8mb", "fp32_256mb", "ckpt8b", "ckpt8b_delta", "ckpt8b_delta_zg", "serve",
                              "series"])
-    ap.add_argument("--serve-seconds", type=float, default=1.0, help="serve: seconds of arrivals per rate")
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="seconds of arrivals per rate")
+    ap.add_argument("--serve-rates", default="100,1000,5000", help="ckpt8b: rates of the serving block")
+    ap.add_argument("--no-serve", action="store_true", help="ckpt8b: leave out the serving block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=4.0)
+    ap.add_argument("--cpu-budget", type=float, default=4.0, help="seconds of oracle decode per thread count")
     ap.add_argument("--decode-only", action="store_true", help="time decode launches only (for profiling)")
     ap.add_argument("--exponent", action="store_true",
                     help="exponent extraction (BF16 / FP32): the exponent byte is exactly the 8 exponent bits")
+    ap.add_argument("--chunk-bytes", type=int, default=0,
+                    help="checkpoint workloads: use this chunk size (with --substream-syms) instead of autotuning")
+    ap.add_argument("--substream-syms", type=int, default=None, help="S with --chunk-bytes")
     ap.add_argument("--probe-skip", type=int, default=0,
-                    help="compressibility probing interval K for the single-tensor workloads (0: off)")
+                    help="compressibility probing interval K (0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this codec build runs on one GPU; --gpus must be 1"}))

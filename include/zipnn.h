@@ -198,8 +198,11 @@ int zipnn_decompress(zipnn_ctx ctx, const void* src, uint64_t src_len, const voi
 
 /* As zipnn_decompress, for a caller that already holds a host copy of the
  * container's 64-byte header (`header_host`): nothing waits, the call only
- * queues the decode on `stream`.  The device checks its own header against
- * the one given and reports a mismatch as ZIPNN_E_FORMAT in the status. */
+ * queues the decode on `stream`.  The host copy picks the kernel class (B,
+ * g, delta, ZG flag); the device parses and checks the header in device
+ * memory itself and decodes by it.  If that header is invalid, or its kernel
+ * class differs from the host copy's, nothing is decoded and ZIPNN_E_FORMAT
+ * is recorded in the status. */
 int zipnn_decompress_async(zipnn_ctx ctx, const void* header_host, const void* src, uint64_t src_len,
                            const void* base, void* dst, uint64_t dst_cap, void* stream);
 
@@ -219,7 +222,7 @@ typedef struct {
 
 /* Compress tensors[0..n) (all of `dtype`, host array of device pointers) into
  * the device arena (arena_cap bytes; enough is the sum over tensors of
- * zipnn_compress_bound + 15).  offsets (host, n+1 entries) receives the
+ * zipnn_compress_bound + 127, since containers start at 128-byte offsets).  offsets (host, n+1 entries) receives the
  * offset of each container and, last, the arena bytes used.  Blocking; the
  * containers are byte-identical to per-tensor zipnn_compress calls. */
 int zipnn_compress_batch(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, const zipnn_params* p,
@@ -259,18 +262,39 @@ typedef struct {
     double encode_gbps;    /* uncompressed GB/s of the batched encode */
 } zipnn_tune_entry;
 
+/* How zipnn_autotune samples and decides.  Zero fields take the defaults. */
+typedef struct {
+    uint64_t sample_bytes;   /* about this many input bytes are compressed per candidate (0: 1 GiB) */
+    uint32_t min_chunk;      /* candidate chunk sizes: the powers of two in [min_chunk, max_chunk] */
+    uint32_t max_chunk;      /*   (0, 0: 64 KiB .. 1 MiB, the range of the paper's 256 KB default) */
+    int repeats;             /* timed decode replays per candidate; the median counts (0: 7) */
+    double max_ratio_loss;   /* candidates whose ratio exceeds (1 + loss) x the best ratio are out */
+    double tie;              /* decode rates within this fraction of the fastest are ties (0: 0.02) */
+    uint8_t policy[4];       /* per-stream zipnn_policy of every candidate (AUTO = 0) */
+} zipnn_tune_config;
+
 /* Pick format parameters for a set of tensors of `dtype` by measurement on
- * this GPU: a sample (tensors in order, up to sample_bytes) is compressed and
- * batch-decompressed under every candidate chunk size (64 KiB .. 4 MiB) and
- * sub-stream length S (chunk elements / 256 .. / 2048, within the limits of
- * zipnn_check_params), with `policy` (NULL:
- * AUTO).  *best gets the fastest decode among the candidates whose ratio is
- * within (1 + max_ratio_loss) of the best ratio seen; entries[0..max_entries)
- * receive the measurements (*n_entries = how many candidates ran).  Blocking;
- * allocates and frees its own sample buffers. */
-int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, uint64_t sample_bytes,
-                   double max_ratio_loss, const uint8_t* policy, zipnn_params* best, zipnn_tune_entry* entries,
-                   int max_entries, int* n_entries);
+ * this GPU (the chunk size is the paper's main parameter, §V-A; S is this
+ * format's sub-stream length).
+ *   Sample (when the tensors hold more than sample_bytes): stratified by
+ *   size class (tensors of equal length, in order of first appearance).  A
+ *   class holding c of the total bytes gets ceil(c * sample_bytes / total)
+ *   bytes, filled with its tensors in order, whole, the last one cut to
+ *   what is left (at least max_chunk bytes, or the whole tensor).  Every kind
+ *   of tensor of a checkpoint (embedding, projections, norms) is then in it
+ *   in its proportion, at its real length.
+ *   Candidates: every chunk size in the range x S = chunk elements / 256 ..
+ *   / 2048 (256 to 2048 sub-streams per chunk), within zipnn_check_params.
+ *   Each candidate's sample is compressed (timed once) and batch-decompressed
+ *   (graph replay: one warm-up, then `repeats` timed runs, median).
+ *   Pick: among candidates within the ratio loss, those whose decode rate is
+ *   within `tie` of the fastest tie; of those, the smallest chunk, then the
+ *   best ratio (exact, so the pick does not follow timing noise).
+ * *best gets the pick; entries[0..max_entries) the measurements; *n_entries
+ * how many candidates ran.  Blocking; allocates and frees its own sample
+ * buffers.  ZIPNN_E_INVAL for an empty candidate set. */
+int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, const zipnn_tune_config* cfg,
+                   zipnn_params* best, zipnn_tune_entry* entries, int max_entries, int* n_entries);
 
 /* ------------------------------------------------------------------ serving
  *
@@ -280,10 +304,11 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
  * Requests are admitted in arrival order while the pool has room for the
  * output (and fewer than max_inflight are admitted).  A scheduler thread
  * runs decode iterations on a private stream, keeping two in flight: in
- * ZIPNN_SERVE_CONTINUOUS mode an iteration takes the not yet decoded chunks
- * of every admitted request (fewest remaining first) up to chunks_per_iter,
- * so a request that arrives while others decode joins the next iteration and
- * a large one spans several; ZIPNN_SERVE_PER_REQUEST runs one iteration per
+ * ZIPNN_SERVE_CONTINUOUS mode an iteration takes admitted requests whole
+ * while their chunks fit under chunks_per_iter (the first one always) --
+ * requests admitted more than 2 ms ago first (oldest first), then the others
+ * with the fewest chunks first -- so requests that arrive while others
+ * decode join the next iteration, many to a launch; ZIPNN_SERVE_PER_REQUEST runs one iteration per
  * request holding all of its chunks (the plain per-request launch).  Chunks
  * decode independently given the map (paper §V-A), so the bytes of a result
  * do not depend on what else was in its iterations.  Every call is
@@ -296,7 +321,7 @@ typedef enum { ZIPNN_SERVE_CONTINUOUS = 0, ZIPNN_SERVE_PER_REQUEST = 1 } zipnn_s
 typedef struct {
     uint64_t pool_bytes;        /* output pool (device memory allocated at create) */
     int max_inflight;           /* admitted requests not yet released, at most */
-    uint32_t chunks_per_iter;   /* CONTINUOUS: chunk cap of one iteration (0: 2048) */
+    uint32_t chunks_per_iter;   /* CONTINUOUS: chunk cap of one iteration beyond its first request (0: 2048) */
     int mode;                   /* zipnn_serve_mode */
 } zipnn_server_config;
 

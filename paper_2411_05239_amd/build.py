@@ -23,10 +23,12 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     """Compile every HIP source and link the shared library (always rebuilds)."""
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
+
     tmpdir = os.path.join(HERE, "_build")
     os.makedirs(tmpdir, exist_ok=True)
-    for src in SOURCES:
+
+    def compile_one(src):
         obj = os.path.join(tmpdir, src.replace(".hip", ".o"))
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
@@ -35,7 +37,11 @@ def build(verbose: bool = False) -> str:
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError(f"hipcc failed on {src}")
-        objs.append(obj)
+        return obj
+
+    # the sources compile independently (at most 4 hipcc processes)
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

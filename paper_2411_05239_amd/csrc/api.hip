@@ -111,7 +111,13 @@ int zipnn_ctx_create(int hip_device, zipnn_ctx* out)
         zipnn_ctx_destroy(ctx);
         return ZIPNN_E_HIP;
     }
-    ctx->dec_grid = decode_grid_size(hip_device);
+    for (uint32_t B : {1u, 2u, 4u})
+        for (uint32_t G : {2u, 4u, 8u})
+            for (int d = 0; d < 2; d++)
+                for (int z = 0; z < 2; z++) {
+                    const DecClass k{B, G, d != 0, z != 0};
+                    ctx->dec_grid[dec_class_index(k)] = decode_grid_size(hip_device, k);
+                }
     *out = ctx;
     return ZIPNN_OK;
 }
@@ -204,17 +210,8 @@ static int encode_tensors(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, in
     if (map_bytes > cap) return ZIPNN_E_NOSPACE;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
-    const size_t ne = size_t(total_chunks) * B;
-    const size_t off_entries = 0;
-    const size_t off_codes = align256(off_entries + ne * sizeof(EncEntry));
-    const size_t off_offsets = align256(off_codes + ne * 256 * sizeof(CodeWord));
-    const size_t off_nwords = align256(off_offsets + ne * sizeof(uint64_t));
-    const size_t off_totals = align256(off_nwords + ne * 64 * sizeof(uint32_t));
-    const size_t off_aoff = align256(off_totals + size_t(n) * sizeof(uint64_t));
-    const size_t off_descs = align256(off_aoff + size_t(n + 1) * sizeof(uint64_t));
-    const size_t off_prefix = align256(off_descs + size_t(n) * sizeof(EncDesc));
-    const size_t need = off_prefix + size_t(n + 1) * sizeof(uint32_t) + 256;
-    int rc = grow_scratch(ctx, need);
+    const EncScratch lay = enc_scratch_layout(size_t(total_chunks) * B, size_t(n));
+    int rc = grow_scratch(ctx, lay.need);
     if (rc) return rc;
     // host staging (pinned): descriptors, chunk prefix, then the arena offsets
     const size_t stage_bytes = size_t(n) * sizeof(EncDesc) + size_t(n + 1) * sizeof(uint32_t) +
@@ -241,15 +238,15 @@ static int encode_tensors(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, in
     }
     hp[n] = run;
     uint8_t* sc = (uint8_t*)ctx->d_scratch;
-    EncDesc* d_descs = (EncDesc*)(sc + off_descs);
-    uint32_t* d_prefix = (uint32_t*)(sc + off_prefix);
-    uint64_t* d_aoff = (uint64_t*)(sc + off_aoff);
+    EncDesc* d_descs = (EncDesc*)(sc + lay.descs);
+    uint32_t* d_prefix = (uint32_t*)(sc + lay.prefix);
+    uint64_t* d_aoff = (uint64_t*)(sc + lay.aoff);
     EncParams ep = make_params(dtype, *p);
     if (hipMemcpyAsync(d_descs, hd, size_t(n) * sizeof(EncDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(d_prefix, hp, size_t(n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
         launch_encode(d_descs, n, d_prefix, uint32_t(total_chunks), ep, (uint8_t*)arena, cap,
-                      (EncEntry*)(sc + off_entries), (CodeWord*)(sc + off_codes), (uint32_t*)(sc + off_nwords),
-                      (uint64_t*)(sc + off_offsets), (uint64_t*)(sc + off_totals), d_aoff, s) != hipSuccess ||
+                      (EncEntry*)(sc + lay.entries), (CodeWord*)(sc + lay.codes), (uint32_t*)(sc + lay.nwords),
+                      (uint64_t*)(sc + lay.offsets), (uint64_t*)(sc + lay.totals), d_aoff, s) != hipSuccess ||
         hipMemcpyAsync(ho, d_aoff, size_t(n + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return ZIPNN_E_HIP;
@@ -299,7 +296,8 @@ static int decompress_common(zipnn_ctx ctx, const uint32_t* hdr_words, const voi
     one.c_begin = 0;
     one.c_end = kAllChunks;
     one.status = nullptr;
-    if (launch_decode_one(h, one, ctx->d_status, ctx->dec_grid, s) != hipSuccess) return ZIPNN_E_HIP;
+    if (launch_decode_one(h, one, ctx->d_status, ctx->dec_grid[dec_class_index(dec_class(h))], s) != hipSuccess)
+        return ZIPNN_E_HIP;
     return ZIPNN_OK;
 }
 
@@ -353,7 +351,8 @@ struct zipnn_batch_s {
 static hipError_t batch_launch(zipnn_batch b, hipStream_t s)
 {
     for (auto& c : b->classes) {
-        hipError_t e = launch_decode_batch(c.k, c.d_descs, c.n, c.d_prefix, b->ctx->d_status, b->ctx->dec_grid, s);
+        hipError_t e = launch_decode_batch(c.k, c.d_descs, c.n, c.d_prefix, b->ctx->d_status,
+                                           b->ctx->dec_grid[dec_class_index(c.k)], s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -482,36 +481,74 @@ int zipnn_decompress_batch(zipnn_ctx ctx, const void* arena, const uint64_t* off
 
 // ------------------------------------------------------------ autotuner
 
-int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, uint64_t sample_bytes,
-                   double max_ratio_loss, const uint8_t* policy, zipnn_params* best, zipnn_tune_entry* entries,
-                   int max_entries, int* n_entries)
+int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, const zipnn_tune_config* cfg,
+                   zipnn_params* best, zipnn_tune_entry* entries, int max_entries, int* n_entries)
 {
     const int B = dtype_bytes(dtype);
-    if (!ctx || !tensors || n < 1 || !best || !B || max_ratio_loss < 0) return ZIPNN_E_INVAL;
-    // the sample: tensors in order, the last one cut, up to sample_bytes
+    if (!ctx || !tensors || n < 1 || !best || !B) return ZIPNN_E_INVAL;
+    zipnn_tune_config c = {};
+    if (cfg) c = *cfg;
+    if (c.max_ratio_loss < 0 || c.tie < 0 || c.repeats < 0) return ZIPNN_E_INVAL;
+    if (!c.sample_bytes) c.sample_bytes = 1ull << 30;
+    if (!c.min_chunk && !c.max_chunk) {
+        c.min_chunk = 64u << 10;
+        c.max_chunk = 1u << 20;
+    }
+    if (!pow2(c.min_chunk) || !pow2(c.max_chunk) || c.min_chunk > c.max_chunk || c.min_chunk < kMinChunk ||
+        c.max_chunk > kMaxChunk)
+        return ZIPNN_E_INVAL;
+    if (!c.repeats) c.repeats = 7;
+    if (c.tie == 0) c.tie = 0.02;
+    // the sample, stratified by size class (tensors of equal length, e.g. the
+    // q projections of every layer): each class gets its share of
+    // sample_bytes, filled with its tensors in order, whole, the last one cut
+    // to the remaining share (at least one largest chunk); every class is in
+    // it, and the tensors keep their real lengths, so the chunk and work-item
+    // counts per tensor are the checkpoint's own
+    uint64_t total = 0;
+    for (int i = 0; i < n; i++) total += tensors[i].n_elems * uint64_t(B);
+    if (!total) return ZIPNN_E_INVAL;
+    std::vector<uint64_t> take(size_t(n), 0);
+    if (total <= c.sample_bytes) {
+        for (int i = 0; i < n; i++) take[size_t(i)] = tensors[i].n_elems;
+    } else {
+        std::vector<uint64_t> sizes;   // the classes in order of first appearance
+        for (int i = 0; i < n; i++)
+            if (tensors[i].n_elems && std::find(sizes.begin(), sizes.end(), tensors[i].n_elems) == sizes.end())
+                sizes.push_back(tensors[i].n_elems);
+        for (const uint64_t len : sizes) {
+            uint64_t cls = 0;
+            for (int i = 0; i < n; i++)
+                if (tensors[i].n_elems == len) cls += len;
+            uint64_t left = uint64_t(((unsigned __int128)cls * c.sample_bytes + total - 1) / total) / uint64_t(B);
+            for (int i = 0; i < n && left; i++) {
+                if (tensors[i].n_elems != len) continue;
+                const uint64_t k = std::min<uint64_t>(len, std::max<uint64_t>(left, c.max_chunk / uint32_t(B)));
+                take[size_t(i)] = k;
+                left -= std::min(left, k);
+            }
+        }
+    }
     std::vector<zipnn_tensor_in> smp;
     uint64_t sbytes = 0;
-    for (int i = 0; i < n && sbytes < sample_bytes; i++) {
+    for (int i = 0; i < n; i++) {
+        if (!take[size_t(i)]) continue;
         zipnn_tensor_in t = tensors[i];
-        const uint64_t room = (sample_bytes - sbytes) / uint64_t(B);
-        if (t.n_elems > room) t.n_elems = room;
-        if (!t.n_elems) continue;
+        t.n_elems = take[size_t(i)];
         smp.push_back(t);
         sbytes += t.n_elems * uint64_t(B);
     }
-    if (smp.empty()) return ZIPNN_E_INVAL;
-    // candidate formats: chunk size x sub-stream length, with at least 256
-    // sub-streams per chunk (a decode workgroup's four lane groups)
+    // candidate formats: chunk size x sub-stream length, with 256 to 2048
+    // sub-streams per chunk (at least a decode workgroup's four lane groups)
     std::vector<zipnn_params> cands;
-    for (uint32_t chunk = 64u << 10; chunk <= (4u << 20); chunk <<= 1) {
+    for (uint32_t chunk = c.min_chunk; chunk <= c.max_chunk; chunk <<= 1) {
         const uint32_t E = chunk / uint32_t(B);
         for (uint32_t div = 256; div <= 2048; div <<= 1) {
             zipnn_params p;
             zipnn_default_params(dtype, &p);
             p.chunk_bytes = chunk;
             p.substream_syms = uint16_t(std::max<uint32_t>(4, E / div));
-            if (policy)
-                for (int k = 0; k < 4; k++) p.policy[k] = policy[k];
+            for (int k = 0; k < 4; k++) p.policy[k] = c.policy[k];
             if (zipnn_check_params(dtype, &p) == ZIPNN_OK) cands.push_back(p);
         }
     }
@@ -519,9 +556,9 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
     DeviceGuard g(ctx->device);
     uint64_t cap = 0;
     for (const auto& p : cands) {
-        uint64_t c = 0;
-        for (const auto& t : smp) c += zipnn_compress_bound(dtype, t.n_elems, &p) + kPayAlign;
-        cap = std::max(cap, c);
+        uint64_t cb = 0;
+        for (const auto& t : smp) cb += zipnn_compress_bound(dtype, t.n_elems, &p) + kPayAlign;
+        cap = std::max(cap, cb);
     }
     void* arena = nullptr;
     void* outs = nullptr;
@@ -551,6 +588,7 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
     std::vector<zipnn_tune_entry> res;
     int rc = ZIPNN_OK;
     std::vector<uint64_t> offs(smp.size() + 1);
+    std::vector<float> times(size_t(c.repeats));
     for (const auto& p : cands) {
         (void)hipEventRecord(e0, s);
         rc = zipnn_compress_batch(ctx, dtype, smp.data(), int(smp.size()), &p, arena, cap, offs.data(), s);
@@ -563,21 +601,21 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
         rc = zipnn_batch_create(ctx, arena, offs.data(), int(smp.size()), dst.data(), caps.data(),
                                 any_base ? bases.data() : nullptr, &b);
         if (rc) break;
-        float best_ms = 1e30f;
-        for (int r = 0; r < 4; r++) {
+        (void)zipnn_batch_decompress(b, s);   // warm-up
+        for (int r = 0; r < c.repeats; r++) {
             (void)hipEventRecord(e0, s);
             (void)zipnn_batch_decompress(b, s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (r > 0) best_ms = std::min(best_ms, ms);   // first run warms up
+            (void)hipEventElapsedTime(&times[size_t(r)], e0, e1);
         }
         zipnn_batch_destroy(b);
+        std::sort(times.begin(), times.end());
+        const float med = times[times.size() / 2];
         zipnn_tune_entry te;
         te.params = p;
         te.ratio = double(offs.back()) / double(sbytes);
-        te.decode_gbps = double(sbytes) / (double(best_ms) * 1e6);
+        te.decode_gbps = double(sbytes) / (double(med) * 1e6);
         te.encode_gbps = double(sbytes) / (double(enc_ms) * 1e6);
         res.push_back(te);
     }
@@ -587,17 +625,25 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
     (void)hipFree(outs);
     if (rc) return rc;
     if (zipnn_ctx_status(ctx, nullptr, 1) != ZIPNN_OK) return ZIPNN_E_CORRUPT;
-    // fastest decode among the candidates within the allowed ratio loss
+    // within the ratio loss: the fastest decode sets the bar; every candidate
+    // within `tie` of it ties; the smallest chunk wins, then the best ratio
     double best_ratio = 1e30;
     for (const auto& r : res) best_ratio = std::min(best_ratio, r.ratio);
+    double fastest = 0;
+    for (const auto& r : res)
+        if (r.ratio <= best_ratio * (1.0 + c.max_ratio_loss)) fastest = std::max(fastest, r.decode_gbps);
     int pick = -1;
-    for (size_t i = 0; i < res.size(); i++)
-        if (res[i].ratio <= best_ratio * (1.0 + max_ratio_loss) && (pick < 0 || res[i].decode_gbps > res[pick].decode_gbps))
+    for (size_t i = 0; i < res.size(); i++) {
+        const auto& r = res[i];
+        if (r.ratio > best_ratio * (1.0 + c.max_ratio_loss) || r.decode_gbps < fastest * (1.0 - c.tie)) continue;
+        if (pick < 0 || r.params.chunk_bytes < res[pick].params.chunk_bytes ||
+            (r.params.chunk_bytes == res[pick].params.chunk_bytes && r.ratio < res[pick].ratio))
             pick = int(i);
-    *best = res[pick].params;
+    }
+    *best = res[size_t(pick)].params;
     if (n_entries) *n_entries = int(res.size());
     if (entries)
-        for (int i = 0; i < std::min(max_entries, int(res.size())); i++) entries[i] = res[i];
+        for (int i = 0; i < std::min(max_entries, int(res.size())); i++) entries[i] = res[size_t(i)];
     return ZIPNN_OK;
 }
 

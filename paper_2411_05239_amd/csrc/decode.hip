@@ -974,9 +974,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B * G >=
                     if (item_prefix[mid] <= item) lo = mid;
                     else hi = mid - 1;
                 }
-                if (lo != ts.desc) load_tensor(descs[lo], lo, ts, status, false);
+                if (lo != ts.desc) {
+                    // the plan gave this tensor items, so its header was valid
+                    // when planned; a container changed since then is
+                    // reported and its items are skipped
+                    const DecDesc& dl = descs[lo];
+                    if (load_tensor(dl, lo, ts, status, false) && !matches(ts)) ts.valid = 0;
+                    if (!ts.valid) set_status(dl.status ? dl.status : status, ZIPNN_E_FORMAT);
+                }
             }
             __syncthreads();
+            if (!ts.valid) continue;
         }
         const uint64_t local = item - (item_prefix ? item_prefix[ts.desc] : 0);
         const uint64_t full_items = uint64_t(ts.p.full_chunks) * ts.p.slices_full;
@@ -1066,14 +1074,33 @@ hipError_t dispatch(const DecClass& k, const DecDesc& one, const DecDesc* descs,
 
 }  // namespace
 
-int decode_grid_size(int device)
+namespace {
+template <int B, int G, bool D, bool Z>
+int blocks_per_cu()
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode<B, G, D, Z>, kBlock, 0) != hipSuccess)
+        return 0;
+    return per_cu;
+}
+}  // namespace
+
+// The persistent grid of a kernel class: as many workgroups as fit on the
+// device at once for that instantiation (its own registers and LDS).
+int decode_grid_size(int device, const DecClass& k)
 {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 1024;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode<2, 4, false, false>, kBlock, 0) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 4;
+#define ZIPNN_OCC(BB, GG)                                                                                     \
+    if (k.B == BB && k.G == GG)                                                                              \
+        per_cu = k.zg ? (k.delta ? blocks_per_cu<BB, GG, true, true>() : blocks_per_cu<BB, GG, false, true>()) \
+                      : (k.delta ? blocks_per_cu<BB, GG, true, false>() : blocks_per_cu<BB, GG, false, false>());
+    ZIPNN_OCC(1, 2) ZIPNN_OCC(1, 4) ZIPNN_OCC(1, 8)
+    ZIPNN_OCC(2, 2) ZIPNN_OCC(2, 4) ZIPNN_OCC(2, 8)
+    ZIPNN_OCC(4, 2) ZIPNN_OCC(4, 4) ZIPNN_OCC(4, 8)
+#undef ZIPNN_OCC
+    if (per_cu < 1) per_cu = 2;
     return prop.multiProcessorCount * per_cu;
 }
 

@@ -3,8 +3,8 @@
 // allocation, admission in arrival order by free pool bytes, and a scheduler
 // thread that packs chunk ranges of the admitted requests into decode
 // iterations (continuous batching).  Chunks are independent given the map
-// (paper §V-A), so any split of a request over iterations decodes the same
-// bytes; iterations go to one stream, two in flight.
+// (paper §V-A), so the bytes of a request do not depend on what it was
+// batched with; iterations go to one stream, two in flight.
 #include <string.h>
 #include <time.h>
 
@@ -29,7 +29,13 @@ namespace {
 constexpr int kIterDepth = 2;            // iterations in flight
 constexpr uint64_t kPoolAlign = 256;
 constexpr uint32_t kDefaultChunksPerIter = 2048;
-constexpr double kIdleSpinSeconds = 2e-3;  // the scheduler polls this long before it sleeps
+// The scheduler polls this long before it sleeps: a sleeping scheduler costs
+// each arrival a thread wake-up (tens of microseconds); at 100 requests/s
+// only gaps longer than this (e^-5 of them) pay it.
+constexpr double kIdleSpinSeconds = 50e-3;
+// A request admitted this long ago goes before the others (oldest first), so
+// that a large one is not held back by a steady stream of smaller ones.
+constexpr double kAgeSeconds = 2e-3;
 
 double now_s()
 {
@@ -207,18 +213,28 @@ bool launch_iteration(zipnn_server s)
         const Req& r = s->reqs[ticket];
         take.push_back({ticket, r.n_chunks - r.next});
     } else {
-        std::vector<std::tuple<uint32_t, uint64_t>> order;   // remaining, ticket (fewest first, then oldest)
+        // order: requests waiting longer than kAgeSeconds first (oldest
+        // first), then the others with the fewest chunks left first
+        const double now = now_s();
+        std::vector<std::tuple<int, double, uint64_t>> order;   // aged?, key, ticket
         for (uint64_t ticket : s->active) {
             const Req& r = s->reqs[ticket];
-            order.push_back({r.n_chunks - r.next, ticket});
+            const bool aged = now - r.t.t_admit > kAgeSeconds;
+            order.push_back({aged ? 0 : 1, aged ? r.t.t_admit : double(r.n_chunks - r.next), ticket});
         }
         std::sort(order.begin(), order.end());
-        uint32_t left = s->cfg.chunks_per_iter;
+        // whole requests, in that order, while they fit under the chunk cap
+        // (the first one always): a request is never split, since the
+        // largest requests set the tail latency and a split only adds a
+        // launch to theirs, while the requests batched with it would wait
+        // for the whole iteration anyway
+        uint64_t used = 0;
         for (auto& o : order) {
-            if (left == 0) break;
-            const uint32_t n = std::min(std::get<0>(o), left);
-            take.push_back({std::get<1>(o), n});
-            left -= n;
+            const Req& r = s->reqs[std::get<2>(o)];
+            const uint32_t n = r.n_chunks - r.next;
+            if (!take.empty() && used + n > s->cfg.chunks_per_iter) continue;
+            take.push_back({std::get<2>(o), n});
+            used += n;
         }
     }
     // descriptors by kernel class, in the order taken
@@ -282,9 +298,10 @@ bool launch_iteration(zipnn_server s)
             if (e != hipSuccess) break;
             const Class& c = kv.second;
             const uint64_t items = c.prefix.back();
-            const int grid = int(std::min<uint64_t>(uint64_t(s->ctx->dec_grid), std::max<uint64_t>(items, 1)));
             const DecClass k{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
                              std::get<3>(kv.first)};
+            const int grid = int(std::min<uint64_t>(uint64_t(s->ctx->dec_grid[dec_class_index(k)]),
+                                                    std::max<uint64_t>(items, 1)));
             e = launch_decode_planned(k, (const DecDesc*)(it.d_buf + at[ci].first), int(c.descs.size()),
                                       (const uint64_t*)(it.d_buf + at[ci].second), d_status, grid, s->stream);
             ci++;

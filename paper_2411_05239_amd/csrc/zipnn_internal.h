@@ -223,7 +223,15 @@ hipError_t launch_decode_planned(const DecClass& k, const DecDesc* d_descs, int 
                                  const uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s);
 hipError_t launch_clear_status(int* d_status, hipStream_t s);
 hipError_t launch_gather_headers(const uint8_t* arena, const uint64_t* d_offs, int n, void* d_out, hipStream_t s);
-int decode_grid_size(int device);
+int decode_grid_size(int device, const DecClass& k);
+// Index of a kernel class in per-class tables (B in {1,2,4}, G in {2,4,8}).
+constexpr int kDecClasses = 36;
+__host__ __device__ inline int dec_class_index(const DecClass& k)
+{
+    const int bi = k.B == 1 ? 0 : k.B == 2 ? 1 : 2;
+    const int gi = k.G == 2 ? 0 : k.G == 4 ? 1 : 2;
+    return ((bi * 3 + gi) * 2 + (k.delta ? 1 : 0)) * 2 + (k.zg ? 1 : 0);
+}
 
 // Compress n_desc tensors (descriptors and chunk prefix in device memory)
 // into `arena`: analyze -> place -> arena layout (dst of every descriptor,
@@ -232,13 +240,34 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
                          const EncParams& p, uint8_t* arena, uint64_t cap, EncEntry* entries, CodeWord* codes,
                          uint32_t* nwords, uint64_t* offsets, uint64_t* totals, uint64_t* arena_off, hipStream_t s);
 
+// Offsets of the encoder's device scratch for ne = chunks * B entries of n
+// tensors (every array 256-byte aligned); `need` is the total.
+struct EncScratch {
+    size_t entries, codes, offsets, nwords, totals, aoff, descs, prefix, need;
+};
+inline EncScratch enc_scratch_layout(size_t ne, size_t n)
+{
+    auto a256 = [](size_t v) { return (v + 255) & ~size_t(255); };
+    EncScratch L;
+    L.entries = 0;
+    L.codes = a256(L.entries + ne * sizeof(EncEntry));
+    L.offsets = a256(L.codes + ne * 256 * sizeof(CodeWord));
+    L.nwords = a256(L.offsets + ne * sizeof(uint64_t));
+    L.totals = a256(L.nwords + ne * 64 * sizeof(uint32_t));
+    L.aoff = a256(L.totals + n * sizeof(uint64_t));
+    L.descs = a256(L.aoff + (n + 1) * sizeof(uint64_t));
+    L.prefix = a256(L.descs + n * sizeof(EncDesc));
+    L.need = L.prefix + (n + 1) * sizeof(uint32_t) + 256;
+    return L;
+}
+
 }  // namespace zipnn
 
 // A codec context: the device it runs on, the sticky device-side status and
 // the encoder's scratch (grown on demand, serialised by `mu`).
 struct zipnn_ctx_s {
     int device = 0;
-    int dec_grid = 1024;
+    int dec_grid[zipnn::kDecClasses] = {};   // persistent decode grid of each kernel class
     int* d_status = nullptr;      // sticky device-side status
     int* h_status = nullptr;      // pinned
     uint64_t* h_total = nullptr;  // pinned, encode sizes

@@ -62,6 +62,12 @@ class zipnn_tune_entry(ctypes.Structure):
                 ("encode_gbps", ctypes.c_double)]
 
 
+class zipnn_tune_config(ctypes.Structure):
+    _fields_ = [("sample_bytes", ctypes.c_uint64), ("min_chunk", ctypes.c_uint32), ("max_chunk", ctypes.c_uint32),
+                ("repeats", ctypes.c_int), ("max_ratio_loss", ctypes.c_double), ("tie", ctypes.c_double),
+                ("policy", ctypes.c_uint8 * 4)]
+
+
 class zipnn_tensor_in(ctypes.Structure):
     _fields_ = [("src", ctypes.c_void_p), ("n_elems", ctypes.c_uint64), ("base", ctypes.c_void_p)]
 
@@ -115,7 +121,7 @@ def lib():
         L.zipnn_batch_destroy.argtypes, L.zipnn_batch_destroy.restype = [vp], None
         L.zipnn_decompress_batch.argtypes = [vp, vp, P(u64), i32, P(vp), P(u64), P(vp), vp]
         L.zipnn_decompress_batch.restype = i32
-        L.zipnn_autotune.argtypes = [vp, i32, P(zipnn_tensor_in), i32, u64, ctypes.c_double, vp, P(zipnn_params),
+        L.zipnn_autotune.argtypes = [vp, i32, P(zipnn_tensor_in), i32, P(zipnn_tune_config), P(zipnn_params),
                                      P(zipnn_tune_entry), i32, P(i32)]
         L.zipnn_autotune.restype = i32
         L.zipnn_clock.argtypes, L.zipnn_clock.restype = [], ctypes.c_double
@@ -240,17 +246,59 @@ def zipnn_decompress_batch(ctx, arena, offsets, dsts, caps, bases, stream) -> No
            "zipnn_decompress_batch")
 
 
-def zipnn_autotune(ctx, dtype, srcs, ns, bases, sample_bytes, max_ratio_loss, policy=None):
+def zipnn_autotune(ctx, dtype, srcs, ns, bases, sample_bytes=1 << 30, max_ratio_loss=0.01, policy=None,
+                   min_chunk=0, max_chunk=0, repeats=0, tie=0.0):
     """-> (best zipnn_params, list of zipnn_tune_entry)"""
     n = len(srcs)
     ts = (zipnn_tensor_in * n)(*[zipnn_tensor_in(s_, n_, b_) for s_, n_, b_ in zip(srcs, ns, bases)])
+    cfg = zipnn_tune_config(sample_bytes, min_chunk, max_chunk, repeats, max_ratio_loss, tie,
+                            (ctypes.c_uint8 * 4)(*(list(policy) + [0] * (4 - len(policy)) if policy else [0] * 4)))
     best = zipnn_params()
     ents = (zipnn_tune_entry * 64)()
     cnt = ctypes.c_int(0)
-    pol = (ctypes.c_uint8 * 4)(*policy) if policy is not None else None
-    _check(lib().zipnn_autotune(ctx, dtype, ts, n, sample_bytes, max_ratio_loss, pol, ctypes.byref(best), ents, 64,
-                                ctypes.byref(cnt)), "zipnn_autotune")
+    _check(lib().zipnn_autotune(ctx, dtype, ts, n, ctypes.byref(cfg), ctypes.byref(best), ents, 64, ctypes.byref(cnt)),
+           "zipnn_autotune")
     return best, [ents[i] for i in range(cnt.value)]
+
+
+TUNE_SAMPLE_BYTES = 16 << 30   # a whole 8B checkpoint: steady-state rates need many items per workgroup
+TUNE_MIN_CHUNK, TUNE_MAX_CHUNK = 64 << 10, 1 << 20
+
+
+def tune_checkpoint(codec, xs, bases=None, policy=None):
+    """zipnn_autotune over a checkpoint's BF16 tensors with the settings the
+    benchmark uses: up to 16 GiB of sample (an 8B checkpoint whole: a smaller
+    sample gives each workgroup too few items to show steady-state rates),
+    chunks of 64 KiB .. 1 MiB, ratio within 1% of the best.  -> (params, table)"""
+    bptr = [b.data_ptr() for b in bases] if bases is not None else [None] * len(xs)
+    return zipnn_autotune(codec.ctx, ZIPNN_BF16, [x.data_ptr() for x in xs], [x.numel() for x in xs], bptr,
+                          TUNE_SAMPLE_BYTES, 0.01, policy, min_chunk=TUNE_MIN_CHUNK, max_chunk=TUNE_MAX_CHUNK)
+
+
+def autotune_sample(ns, B: int, sample_bytes: int = 1 << 30, max_chunk: int = 1 << 20) -> list[int]:
+    """Elements of each tensor that zipnn_autotune puts in its sample (the
+    rule documented with zipnn_autotune), for reporting its composition."""
+    ns = [int(n) for n in ns]
+    total = sum(n * B for n in ns)
+    if total <= sample_bytes:
+        return list(ns)
+    take = [0] * len(ns)
+    sizes = []
+    for n in ns:
+        if n and n not in sizes:
+            sizes.append(n)
+    for ln in sizes:
+        cls = sum(n for n in ns if n == ln)
+        left = -(-cls * B * sample_bytes // total) // B
+        for i, n in enumerate(ns):
+            if not left:
+                break
+            if n != ln:
+                continue
+            k = min(ln, max(left, max_chunk // B))
+            take[i] = k
+            left -= min(left, k)
+    return take
 
 
 def zipnn_clock() -> float:

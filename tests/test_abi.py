@@ -106,3 +106,23 @@ def test_inspect_rejects_corrupt_maps(hiplib, oracle_lib):
 def test_strerror(hiplib):
     assert Z.zipnn_strerror(0) == "ok"
     assert "corrupt" in Z.zipnn_strerror(Z.ZIPNN_E_CORRUPT)
+
+
+def test_autotune_sample_holds_every_tensor():
+    """The documented sample rule: every size class in proportion to its
+    bytes, whole tensors in order, the last one cut (at least one largest
+    chunk); the whole set when it fits."""
+    ns = [1 << 26, 4096, 1 << 22, 1 << 22, 1 << 22, 4096, 1 << 26, 12]
+    B, sample = 2, 64 << 20
+    got = Z.autotune_sample(ns, B, sample_bytes=sample, max_chunk=1 << 20)
+    total = B * sum(ns)
+    assert all(0 <= g <= n for g, n in zip(got, ns))
+    for ln in set(ns):
+        share = -(-sum(n for n in ns if n == ln) * B * sample // total) // B
+        took = [g for g, n in zip(got, ns) if n == ln]
+        assert took[0] > 0                                   # every class is in the sample
+        assert sum(took) == min(sum(n for n in ns if n == ln), max(share, min(ln, (1 << 20) // B)))
+        nz = [t for t in took if t]
+        assert all(t == ln for t in nz[:-1]) and took[:len(nz)] == nz   # whole tensors in order, the last cut
+    assert got[1] == 4096 and got[7] == 12                  # small classes whole
+    assert Z.autotune_sample(ns[1:2], B, sample_bytes=1 << 30) == [4096]

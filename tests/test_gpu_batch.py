@@ -149,16 +149,20 @@ def _sample_indices(n):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("chunk,S", [(262144, 512), (1048576, 2048), (2097152, 2048)])
+@pytest.mark.parametrize("chunk,S", [(262144, 512), (1048576, 2048), ("tuned", None)])
 def test_checkpoint_8b_full(codec, chunk, S):
-    """The full 8B-shaped BF16 checkpoint (291 tensors, 16.06 GB) in the
-    batched configuration the benchmark times (2 MiB chunks, S = 2048 is the
-    autotuner's pick there): one encode launch chain, one prepared (graph)
-    decode.  Every tensor round-trips bit-exactly; sampled containers equal
-    the oracle's bytes."""
+    """The full 8B-shaped BF16 checkpoint (291 tensors, 16.06 GB) batched:
+    one encode launch chain, one prepared (graph) decode, at the paper's
+    default chunk, at 1 MiB, and at the autotuner's pick with the benchmark's
+    settings (the configuration the benchmark times).  Every tensor
+    round-trips bit-exactly; sampled containers equal the oracle's bytes."""
     specs = workloads.checkpoint_8b_specs()
     xs = [workloads.make_tensor(sp, device="cuda") for sp in specs]
-    p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=chunk, S=S)
+    if chunk == "tuned":
+        p, _ = Z.tune_checkpoint(codec, xs)
+        print("autotuned:", p, flush=True)
+    else:
+        p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=chunk, S=S)
     arena, offs = codec.compress_batch(xs, p)
     outs = [torch.empty_like(x) for x in xs]
     b = codec.prepare_batch(arena, offs, outs)
@@ -176,18 +180,22 @@ def test_checkpoint_8b_full(codec, chunk, S):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("policy,chunk,S", [("huf", 262144, 512), ("huf", 2097152, 2048), ("auto", 2097152, 4096)])
+@pytest.mark.parametrize("policy,chunk,S", [("huf", 262144, 512), ("huf", "tuned", None), ("auto", "tuned", None)])
 def test_checkpoint_8b_delta_full(codec, policy, chunk, S):
     """The full XOR-delta checkpoint: fine-tuned copy against the base, both
     streams Huffman (or AUTO, where ZG takes almost every stream), in the
-    default shape and in the shapes the autotuner picks for the benchmark;
+    default shape and at the autotuner's pick with the benchmark's settings;
     every tensor reconstructs bit-exactly; sampled containers equal the
     oracle's."""
     specs = workloads.checkpoint_8b_specs()
     base = [workloads.make_tensor(sp, device="cuda") for sp in specs]
     ft = [workloads.finetune_delta(w, seed=2000 + i) for i, w in enumerate(base)]
     pol = [Z.ZIPNN_HUF, Z.ZIPNN_HUF] if policy == "huf" else [Z.ZIPNN_AUTO, Z.ZIPNN_AUTO]
-    p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=chunk, S=S, policy=pol)
+    if chunk == "tuned":
+        p, _ = Z.tune_checkpoint(codec, ft, base, pol if policy == "huf" else None)
+        print("autotuned:", p, flush=True)
+    else:
+        p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=chunk, S=S, policy=pol)
     arena, offs = codec.compress_batch(ft, p, base)
     outs = [torch.empty_like(x) for x in ft]
     b = codec.prepare_batch(arena, offs, outs, base)
@@ -205,27 +213,40 @@ def test_checkpoint_8b_delta_full(codec, policy, chunk, S):
 
 
 def test_autotune_picks_fastest_within_ratio_loss(codec):
-    """The autotuner measures every candidate (chunk 64 KiB..4 MiB x at least
-    256 sub-streams per chunk) on a sample and returns the fastest decode
-    whose ratio is within (1 + loss) of the best; its pick compresses to the
-    oracle's bytes."""
+    """The autotuner measures every candidate (chunk 64 KiB..1 MiB by default
+    x 256 to 2048 sub-streams per chunk) on a sample holding a share of every
+    tensor; among candidates within the ratio loss, decode rates within `tie`
+    of the fastest tie and the smallest chunk, then the best ratio, wins.  Its
+    pick compresses to the oracle's bytes."""
     xs = [x.cuda() for x in _small_checkpoint(seed0=300)]
-    loss = 0.01
+    loss, tie = 0.01, 0.02
     best, table = Z.zipnn_autotune(codec.ctx, Z.ZIPNN_BF16, [x.data_ptr() for x in xs], [x.numel() for x in xs],
-                                   [None] * len(xs), 64 << 20, loss, None)
-    assert len(table) >= 20
+                                   [None] * len(xs), 64 << 20, loss, None, tie=tie)
+    assert len(table) == 5 * 4
     for e in table:
         E = e.params.chunk_bytes // 2
-        assert 64 << 10 <= e.params.chunk_bytes <= 4 << 20 and E // e.params.substream_syms >= 256
+        assert 64 << 10 <= e.params.chunk_bytes <= 1 << 20 and 256 <= E // e.params.substream_syms <= 2048
     r0 = min(e.ratio for e in table)
     ok = [e for e in table if e.ratio <= r0 * (1 + loss)]
-    pick = max(ok, key=lambda e: e.decode_gbps)
+    fastest = max(e.decode_gbps for e in ok)
+    ties = [e for e in ok if e.decode_gbps >= fastest * (1 - tie)]
+    pick = min(ties, key=lambda e: (e.params.chunk_bytes, e.ratio))
     assert (best.chunk_bytes, best.substream_syms) == (pick.params.chunk_bytes, pick.params.substream_syms)
     x = xs[1]
     c = codec.compress(x, best)
     ref = oracle.compress(x.cpu(), oracle.BF16, nthreads=8, **_kw(best))
     assert np.array_equal(c.cpu().numpy(), ref)
+    # another chunk range: only those chunk sizes are measured
+    _, t2 = Z.zipnn_autotune(codec.ctx, Z.ZIPNN_BF16, [x.data_ptr()], [x.numel()], [None], 8 << 20, loss, None,
+                             min_chunk=2 << 20, max_chunk=4 << 20, repeats=3)
+    assert {e.params.chunk_bytes for e in t2} == {2 << 20, 4 << 20}
     # a policy value out of range leaves no candidate: rejected, nothing measured
     with pytest.raises(Z.ZipnnError) as ei:
         Z.zipnn_autotune(codec.ctx, Z.ZIPNN_BF16, [x.data_ptr()], [x.numel()], [None], 1 << 20, loss, [9, 9])
     assert ei.value.code == Z.ZIPNN_E_INVAL
+    # an empty or inverted chunk range is rejected
+    with pytest.raises(Z.ZipnnError) as ei:
+        Z.zipnn_autotune(codec.ctx, Z.ZIPNN_BF16, [x.data_ptr()], [x.numel()], [None], 1 << 20, loss, None,
+                         min_chunk=1 << 20, max_chunk=64 << 10)
+    assert ei.value.code == Z.ZIPNN_E_INVAL
+

@@ -381,3 +381,42 @@ def test_clean_fp32_single_valued_groups(codec, n):
                                                              oracle.MODE_RLE]
     d = workloads.finetune_delta(workloads.bf16_normal(n, seed=38), seed=39).to(torch.float32)
     roundtrip(codec, d, Z.zipnn_default_params(Z.ZIPNN_FP32), base_cpu=workloads.bf16_normal(n, seed=38).to(torch.float32))
+
+
+# ----------------------------------------------------------- 4 MiB chunks (the largest the format allows)
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32, torch.uint8])
+@pytest.mark.parametrize("div", [256, 2048])
+def test_4mib_chunks(codec, dtype, div):
+    """Chunks of 4 MiB with S = chunk elements / 256 (capped at the largest S,
+    4096: W = 512 / 256 / 1024 sub-streams for BF16 / FP32 / U8) and / 2048
+    (W = 2048), two full chunks and a ragged third, byte-compared with the
+    oracle."""
+    B = torch.empty(0, dtype=dtype).element_size()
+    E = (4 << 20) // B
+    n = 2 * E + 12345
+    if dtype == torch.bfloat16:
+        x = workloads.bf16_normal(n, seed=41)
+    elif dtype == torch.float32:
+        x = workloads.fp32_rows(n // 8192 + 1, 8192, seed=42).reshape(-1)[:n].contiguous()
+    else:
+        g = torch.Generator().manual_seed(43)
+        x = (torch.randn(n, generator=g) * 12).round().clamp(-128, 127).to(torch.int16).to(torch.uint8)
+    p = Z.make_params(Z.torch_dtype_code(dtype), chunk_bytes=4 << 20, S=min(4096, E // div))
+    assert Z.zipnn_check_params(Z.torch_dtype_code(dtype), p) == Z.ZIPNN_OK
+    roundtrip(codec, x, p, nthreads=16)
+
+
+@pytest.mark.parametrize("policy", ["huf", "auto"])
+def test_4mib_chunks_delta(codec, policy):
+    """A BF16 XOR delta in 4 MiB chunks (S = 2048), both byte groups Huffman,
+    or AUTO where ZG takes the mostly-zero groups."""
+    E = (4 << 20) // 2
+    base = workloads.bf16_normal(2 * E + 777, seed=44)
+    ft = workloads.finetune_delta(base, seed=45)
+    pol = [Z.ZIPNN_HUF, Z.ZIPNN_HUF] if policy == "huf" else [Z.ZIPNN_AUTO, Z.ZIPNN_AUTO]
+    p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=4 << 20, S=2048, policy=pol)
+    c = roundtrip(codec, ft, p, base_cpu=base, nthreads=16)
+    if policy == "auto":
+        info = Z.zipnn_inspect(c[:64 + 16 * 2 * 3].cpu().numpy().tobytes())
+        assert info.entries_by_mode[3] > 0   # ZG entries present

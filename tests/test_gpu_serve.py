@@ -106,12 +106,20 @@ def test_mix_equals_solo(codec, corpus, mode, cap):
     for i in range(len(corpus)):
         tk = srv.submit(handles[i])
         _drain(srv, [(tk, i)], corpus, handles)
+        tickets.append((tk, i))
+    with_chunks = sum(1 for _, j in tickets if corpus[j]["x"].numel() > 0)
     st = srv.stats()
     assert st.submitted == st.completed == st.released == 4 * len(corpus)
     assert st.pool_in_use == 0
     if mode == Z.ZIPNN_SERVE_CONTINUOUS and cap == 7:
-        # small chunk cap: iterations mixed requests and large ones spanned several
+        # small chunk cap: few requests to an iteration
         assert st.iterations > len(corpus)
+    if mode == Z.ZIPNN_SERVE_CONTINUOUS and cap == 0:
+        # the burst was batched: fewer iterations than requests
+        assert st.iterations < st.submitted
+    if mode == Z.ZIPNN_SERVE_PER_REQUEST:
+        # one iteration per request that has chunks (an empty tensor needs none)
+        assert st.iterations == with_chunks
     srv.close()
 
 
