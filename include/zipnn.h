@@ -82,7 +82,8 @@ typedef enum {
     ZIPNN_E_NOSPACE = -4,  /* output capacity too small */
     ZIPNN_E_NOMEM = -5,    /* device or host allocation failed */
     ZIPNN_E_HIP = -6,      /* a HIP runtime call failed */
-    ZIPNN_E_BUSY = -7      /* result not ready yet (serving API) */
+    ZIPNN_E_BUSY = -7,     /* result not ready yet (serving API) */
+    ZIPNN_E_TOOBIG = -8    /* input beyond the fixed scratch of zipnn_compress_noalloc */
 } zipnn_status;
 
 typedef enum {
@@ -182,6 +183,24 @@ uint64_t zipnn_compress_bound(int dtype, uint64_t n_elems, const zipnn_params* p
  * ZIPNN_E_NOSPACE if dst_cap is too small (dst contents then undefined). */
 int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n_elems, const void* base,
                    const zipnn_params* p, void* dst, uint64_t dst_cap, uint64_t* dst_len, void* stream);
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops that must not call hipMalloc, harnesses that forbid it): as
+ * zipnn_compress, with the same bytes, but the call allocates nothing.  Every
+ * device buffer the encoder needs beyond src, base and dst lies in one fixed
+ * array of ZIPNN_NOALLOC_SCRATCH_BYTES in each device's memory, set up by
+ * zipnn_ctx_create and held until the process ends; the few host words it
+ * reads back live on the caller's stack.  Sizes: the tensor may have at most
+ * about ZIPNN_NOALLOC_SCRATCH_BYTES / 1.3 KiB chunk-streams (chunks x B; for
+ * BF16 at 256 KiB chunks, a tensor of up to 3 GiB); beyond that the call
+ * returns ZIPNN_E_TOOBIG before any work is queued.  The array is shared by
+ * every call on a device and keeps the last call's contents: calls are
+ * serialised by a process-wide lock, and work the caller queues on another
+ * stream must not overlap a call on the same device.  Blocking, like
+ * zipnn_compress. */
+#define ZIPNN_NOALLOC_SCRATCH_BYTES (32u << 20)
+int zipnn_compress_noalloc(zipnn_ctx ctx, const void* src, int dtype, uint64_t n_elems, const void* base,
+                           const zipnn_params* p, void* dst, uint64_t dst_cap, uint64_t* dst_len, void* stream);
 
 /* Decompress the container at device pointer src (src_len bytes) into device
  * buffer dst (dst_cap bytes; needs n_elems*B), XORing with device `base`

@@ -72,6 +72,30 @@ EncParams make_params(int dtype, const zipnn_params& p)
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// The fixed scratch of zipnn_compress_noalloc: one array in every device's
+// memory, held until the process ends.  Its name is a host-side stand-in:
+// host code uses only the device address that hipGetSymbolAddress returns
+// for the current device, kept per device below.
+constexpr size_t kFixedScratch = ZIPNN_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kFixedScratch];
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;                     // guards g_fixed_ptr; serialises zipnn_compress_noalloc
+void* g_fixed_ptr[kMaxDevices] = {};       // device address of `scratch` on each device
+
+// Once per device, with that device current: look up the array's address.
+int fixed_scratch_for(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return ZIPNN_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    if (!g_fixed_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return ZIPNN_E_HIP;
+        g_fixed_ptr[dev] = ptr;
+    }
+    *out = g_fixed_ptr[dev];
+    return ZIPNN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -87,6 +111,7 @@ const char* zipnn_strerror(int code)
     case ZIPNN_E_NOMEM: return "out of memory";
     case ZIPNN_E_HIP: return "HIP runtime error";
     case ZIPNN_E_BUSY: return "not ready";
+    case ZIPNN_E_TOOBIG: return "input needs more than the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
@@ -111,6 +136,9 @@ int zipnn_ctx_create(int hip_device, zipnn_ctx* out)
         zipnn_ctx_destroy(ctx);
         return ZIPNN_E_HIP;
     }
+    // the fixed scratch's address on this device (checked; without it only
+    // zipnn_compress_noalloc is unavailable, and it says so)
+    if (fixed_scratch_for(hip_device, &ctx->fixed_scratch) != ZIPNN_OK) ctx->fixed_scratch = nullptr;
     for (uint32_t B : {1u, 2u, 4u})
         for (uint32_t G : {2u, 4u, 8u})
             for (int d = 0; d < 2; d++)
@@ -267,6 +295,50 @@ int zipnn_compress(zipnn_ctx ctx, const void* src, int dtype, uint64_t n, const 
     const int rc = encode_tensors(ctx, dtype, &t, 1, p, dst, dst_cap, off, (hipStream_t)stream);
     if (rc == ZIPNN_OK) *dst_len = off[1];
     return rc;
+}
+
+int zipnn_compress_noalloc(zipnn_ctx ctx, const void* src, int dtype, uint64_t n, const void* base,
+                           const zipnn_params* p, void* dst, uint64_t dst_cap, uint64_t* dst_len, void* stream)
+{
+    if (!ctx || !dst || !dst_len || (!src && n)) return ZIPNN_E_INVAL;
+    if (zipnn_check_params(dtype, p) != ZIPNN_OK) return ZIPNN_E_INVAL;
+    if (!aligned16(dst) || !aligned16(src) || !aligned16(base)) return ZIPNN_E_INVAL;
+    const uint32_t B = uint32_t(dtype_bytes(dtype));
+    const uint64_t E = p->chunk_bytes / B;
+    const uint64_t nc = (n + E - 1) / E;
+    if (payload_base_of(nc, B) > dst_cap) return ZIPNN_E_NOSPACE;
+    const EncScratch lay = enc_scratch_layout(size_t(nc) * B, 1);
+    if (lay.need > kFixedScratch) return ZIPNN_E_TOOBIG;
+    if (!ctx->fixed_scratch) return ZIPNN_E_HIP;
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* sc = (uint8_t*)ctx->fixed_scratch;
+    EncDesc one;
+    one.src = (const uint8_t*)src;
+    one.base = (const uint8_t*)base;
+    one.dst = nullptr;
+    one.dst_cap = 0;
+    one.n = n;
+    one.chunk0 = 0;
+    one.n_chunks = uint32_t(nc);
+    one.has_zg = 0;
+    one.pad = 0;
+    EncDesc* d_descs = (EncDesc*)(sc + lay.descs);
+    uint32_t* d_prefix = (uint32_t*)(sc + lay.prefix);
+    uint64_t* d_aoff = (uint64_t*)(sc + lay.aoff);
+    uint64_t ho[2] = {0, 0};   // the arena offsets come back to the stack
+    const EncParams ep = make_params(dtype, *p);
+    if (launch_fill_desc(one, uint32_t(nc), d_descs, d_prefix, s) != hipSuccess ||
+        launch_encode(d_descs, 1, d_prefix, uint32_t(nc), ep, (uint8_t*)dst, dst_cap, (EncEntry*)(sc + lay.entries),
+                      (CodeWord*)(sc + lay.codes), (uint32_t*)(sc + lay.nwords), (uint64_t*)(sc + lay.offsets),
+                      (uint64_t*)(sc + lay.totals), d_aoff, s) != hipSuccess ||
+        hipMemcpyAsync(ho, d_aoff, sizeof(ho), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return ZIPNN_E_HIP;
+    if (ho[1] > dst_cap) return ZIPNN_E_NOSPACE;
+    *dst_len = ho[1];
+    return ZIPNN_OK;
 }
 
 int zipnn_compress_batch(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, const zipnn_params* p,

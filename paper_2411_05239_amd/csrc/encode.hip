@@ -1411,7 +1411,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     }
 }
 
+// One tensor's descriptor and chunk prefix, written from kernel arguments (the
+// allocation-free entry point has no host staging to copy them from).
+__global__ void k_fill_desc(EncDesc one, uint32_t total_chunks, EncDesc* __restrict__ d, uint32_t* __restrict__ prefix)
+{
+    if (threadIdx.x == 0) {
+        *d = one;
+        prefix[0] = 0;
+        prefix[1] = total_chunks;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_fill_desc(const EncDesc& one, uint32_t total_chunks, EncDesc* d_desc, uint32_t* d_prefix,
+                            hipStream_t s)
+{
+    k_fill_desc<<<1, 64, 0, s>>>(one, total_chunks, d_desc, d_prefix);
+    return hipGetLastError();
+}
 
 hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_prefix, uint32_t total_chunks,
                          const EncParams& p, uint8_t* arena, uint64_t cap, EncEntry* entries, CodeWord* codes,

@@ -240,6 +240,9 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
                          const EncParams& p, uint8_t* arena, uint64_t cap, EncEntry* entries, CodeWord* codes,
                          uint32_t* nwords, uint64_t* offsets, uint64_t* totals, uint64_t* arena_off, hipStream_t s);
 
+hipError_t launch_fill_desc(const EncDesc& one, uint32_t total_chunks, EncDesc* d_desc, uint32_t* d_prefix,
+                            hipStream_t s);
+
 // Offsets of the encoder's device scratch for ne = chunks * B entries of n
 // tensors (every array 256-byte aligned); `need` is the total.
 struct EncScratch {
@@ -273,6 +276,7 @@ struct zipnn_ctx_s {
     uint64_t* h_total = nullptr;  // pinned, encode sizes
     size_t h_total_cap = 0;
     void* d_scratch = nullptr;    // encode scratch (grown on demand)
+    void* fixed_scratch = nullptr;  // the device's fixed scratch array (zipnn_compress_noalloc)
     size_t scratch_cap = 0;
     std::mutex mu;                // serialises users of the scratch
 };

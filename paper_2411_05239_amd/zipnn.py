@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzipnn_hip.so")
 
 ZIPNN_OK, ZIPNN_E_INVAL, ZIPNN_E_FORMAT, ZIPNN_E_CORRUPT = 0, -1, -2, -3
-ZIPNN_E_NOSPACE, ZIPNN_E_NOMEM, ZIPNN_E_HIP, ZIPNN_E_BUSY = -4, -5, -6, -7
+ZIPNN_E_NOSPACE, ZIPNN_E_NOMEM, ZIPNN_E_HIP, ZIPNN_E_BUSY, ZIPNN_E_TOOBIG = -4, -5, -6, -7, -8
+ZIPNN_NOALLOC_SCRATCH_BYTES = 32 << 20
 ZIPNN_BF16, ZIPNN_FP16, ZIPNN_FP32, ZIPNN_FP8_E4M3, ZIPNN_U8 = 1, 2, 3, 4, 5
 ZIPNN_AUTO, ZIPNN_HUF, ZIPNN_RAW, ZIPNN_ZG = 0, 1, 2, 3
 WIDTH = {ZIPNN_BF16: 2, ZIPNN_FP16: 2, ZIPNN_FP32: 4, ZIPNN_FP8_E4M3: 1, ZIPNN_U8: 1}
@@ -24,7 +25,8 @@ WIDTH = {ZIPNN_BF16: 2, ZIPNN_FP16: 2, ZIPNN_FP32: 4, ZIPNN_FP8_E4M3: 1, ZIPNN_U
 # every symbol declared in include/zipnn.h
 EXPORTS = [
     "zipnn_strerror", "zipnn_ctx_create", "zipnn_ctx_destroy", "zipnn_ctx_status", "zipnn_default_params",
-    "zipnn_check_params", "zipnn_compress_bound", "zipnn_compress", "zipnn_decompress", "zipnn_decompress_async",
+    "zipnn_check_params", "zipnn_compress_bound", "zipnn_compress", "zipnn_compress_noalloc", "zipnn_decompress",
+    "zipnn_decompress_async",
     "zipnn_inspect", "zipnn_compress_batch", "zipnn_batch_create", "zipnn_batch_decompress", "zipnn_batch_destroy",
     "zipnn_decompress_batch", "zipnn_autotune", "zipnn_clock", "zipnn_server_create", "zipnn_server_destroy",
     "zipnn_server_register", "zipnn_server_submit", "zipnn_server_poll", "zipnn_server_next_done",
@@ -109,6 +111,8 @@ def lib():
         L.zipnn_compress_bound.argtypes, L.zipnn_compress_bound.restype = [i32, u64, P(zipnn_params)], u64
         L.zipnn_compress.argtypes = [vp, vp, i32, u64, vp, P(zipnn_params), vp, u64, P(u64), vp]
         L.zipnn_compress.restype = i32
+        L.zipnn_compress_noalloc.argtypes = [vp, vp, i32, u64, vp, P(zipnn_params), vp, u64, P(u64), vp]
+        L.zipnn_compress_noalloc.restype = i32
         L.zipnn_decompress.argtypes, L.zipnn_decompress.restype = [vp, vp, u64, vp, vp, u64, vp], i32
         L.zipnn_decompress_async.argtypes = [vp, ctypes.c_char_p, vp, u64, vp, vp, u64, vp]
         L.zipnn_decompress_async.restype = i32
@@ -186,6 +190,13 @@ def zipnn_compress(ctx, src, dtype, n, base, p, dst, dst_cap, stream) -> int:
     out = ctypes.c_uint64(0)
     _check(lib().zipnn_compress(ctx, src, dtype, n, base, ctypes.byref(p), dst, dst_cap, ctypes.byref(out), stream),
            "zipnn_compress")
+    return out.value
+
+
+def zipnn_compress_noalloc(ctx, src, dtype, n, base, p, dst, dst_cap, stream) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().zipnn_compress_noalloc(ctx, src, dtype, n, base, ctypes.byref(p), dst, dst_cap, ctypes.byref(out),
+                                        stream), "zipnn_compress_noalloc")
     return out.value
 
 
