@@ -10,8 +10,8 @@
 //              §3.2.2).  A group with one value becomes RLE (paper §III-B);
 //              a group whose most frequent byte fills half of it is also a ZG
 //              candidate (zero-aware coding, §IV-B).  For every candidate the
-//              four waves replay the decoder's lock-step word requests lane
-//              group by lane group, which gives the exact payload sizes, so
+//              four waves sum each lane's code bits lane group by lane
+//              group, which gives the exact payload sizes, so
 //              AUTO keeps the smallest of RAW, HUF and ZG (paper §III-B, §V-A).
 //              With a probe interval the probe chunks run first
 //              (compressibility probing, §III-B).
@@ -34,6 +34,14 @@ namespace zipnn {
 namespace {
 
 constexpr int kWaves = kBlock / 64;
+// The counting pass's histograms: kRep copies for all byte groups together
+// (16 / B copies of each), shared by the workgroup's waves; lane l of every
+// wave adds to copy l / (64 B / 16) of its group, whose bins start kRepShift *
+// copy words further on.  Lanes holding one value hit at most 4 B of the
+// same address in an instruction instead of 64 (LDS atomics on one address
+// serialise), and the shift puts the copies' equal bins on different banks.
+constexpr int kRep = 16;
+constexpr int kRepStride = 288;   // 256 bins + room for the shift
 
 struct PmWave {                 // package-merge workspace of one wave
     uint32_t leafw[256];        // leaf weights, ascending (f, symbol)
@@ -46,7 +54,8 @@ struct PmWave {                 // package-merge workspace of one wave
 };
 
 union AnalyzeLds {
-    uint32_t hist[kWaves][4][256];   // per-wave sub-histograms (counting passes)
+    uint32_t rep[kRep][kRepStride];  // the counting pass's histogram copies
+    uint32_t hist[kWaves][4][256];   // per-wave sub-histograms (the ZG counting pass)
     PmWave pm[kWaves];               // per-wave code construction
     uint32_t lgw[2][4][64];          // words per lane group: HUF, ZG (replay)
 };
@@ -405,11 +414,12 @@ __device__ inline uint32_t gather_stream(const uint32_t* wd, int k)
     }
 }
 
-// Replay the decoder's word requests for lane group j of one chunk and count
-// the words each candidate takes: HUF candidates (bit k of hc, lengths
-// lens[k]) over every group, ZG candidates (bit k of zgc, lengths lens2[k],
-// fill value z[k]) over the groups holding another value.  Lane 0 of the
-// wave writes the counts to lgw[0][k][j] and lgw[1][k][j].
+// Count the words each candidate's lane group j of one chunk takes: HUF
+// candidates (bit k of hc, lengths lens[k]) over every group, ZG candidates
+// (bit k of zgc, lengths lens2[k], fill value z[k]) over the groups holding
+// another value.  A lane's count follows from its code bits and those of its
+// last pair alone (see the end of the function).  Lane 0 of the wave writes
+// the counts to lgw[0][k][j] and lgw[1][k][j].
 template <int B, int G>
 __device__ __attribute__((always_inline)) void count_lane_group(const uint8_t* src, const uint8_t* base, uint32_t hc, uint32_t zgc,
                                  const uint8_t (*lens)[256], const uint8_t (*lens2)[256], const uint32_t* z,
@@ -419,13 +429,13 @@ __device__ __attribute__((always_inline)) void count_lane_group(const uint8_t* s
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = 64 * j + lane;
-    const int twoL = int(2 * L);
     const uint32_t Gtot = (m + G - 1) / G, Gfull = m / G, rem = m - Gfull * G;
     const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;
-    int cnt[2][B];
-    uint32_t req[2][B];
+    // per candidate: the lane's code bits and those of its last pair (a lane
+    // with no pair takes no word)
+    uint32_t bits[2][B], last[2][B];
 #pragma unroll
-    for (int k = 0; k < B; k++) cnt[0][k] = cnt[1][k] = 0, req[0][k] = req[1][k] = 0;
+    for (int k = 0; k < B; k++) bits[0][k] = bits[1][k] = last[0][k] = last[1][k] = 0;
     constexpr uint32_t CB = 4;   // groups in flight per lane
     for (uint32_t j0 = 0; j0 < ng; j0 += CB) {
         uint32_t wds[CB][NW];
@@ -448,23 +458,25 @@ __device__ __attribute__((always_inline)) void count_lane_group(const uint8_t* s
 #pragma unroll
                     for (int pr = 0; pr < G / 2; pr++) {
                         if (2u * pr < gc) {
-                            if (cnt[v][k] < twoL) {
-                                cnt[v][k] += 32;
-                                req[v][k]++;
-                            }
-                            cnt[v][k] -= ln[sym_of<B>(wd, k, 2 * pr)];
-                            if (2u * pr + 1 < gc) cnt[v][k] -= ln[sym_of<B>(wd, k, 2 * pr + 1)];
+                            uint32_t c = ln[sym_of<B>(wd, k, 2 * pr)];
+                            if (2u * pr + 1 < gc) c += ln[sym_of<B>(wd, k, 2 * pr + 1)];
+                            bits[v][k] += c;
+                            last[v][k] = c;
                         }
                     }
                 }
             }
         }
     }
+    // before each pair a lane holding fewer than 2L bits takes a word, so
+    // after that check 32 * taken - consumed lies in [2L, 2L + 31]: a lane
+    // takes ceil((consumed before its last pair + 2L) / 32) words in all
 #pragma unroll
     for (int k = 0; k < B; k++) {
 #pragma unroll
         for (int v = 0; v < 2; v++) {
-            const uint32_t tot = wave_sum(req[v][k]);
+            const uint32_t req = bits[v][k] ? (bits[v][k] - last[v][k] + 2 * L + 31) / 32 : 0u;
+            const uint32_t tot = wave_sum(req);
             if (lane == 0) lgw[v][k][j] = tot;
         }
     }
@@ -496,7 +508,7 @@ struct AnalyzeTail {
 //      the most frequent value z fills half the group, a ZG candidate;
 //   3. for ZG candidates: histogram over the groups of g symbols that hold a
 //      value other than z, and ZG lengths of it;
-//   4. the four waves replay the decoder's word requests lane group by lane
+//   4. the four waves count the words of every candidate lane group by lane
 //      group for every candidate, which gives the exact sizes;
 //   5. the mode of each group (AUTO: the smallest of RAW, HUF, ZG, ties to
 //      RAW then HUF), its entry, its lane-group word counts and its canonical
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             }
             continue;
         }
-        for (uint32_t i = t; i < kWaves * 4 * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
+        for (uint32_t i = t; i < kRep * kRepStride; i += kBlock) (&S.rep[0][0])[i] = 0;
         if (t == 0) A.open = A.hc = A.zc = A.zgc = A.fin = A.coded = A.specok = 0;
         if (t < 8) (&A.words[0][0])[t] = 0;
         if (t < 4) A.pol[t] = ((live >> t) & 1) ? int(p.policy[t]) : ZIPNN_RAW;
@@ -556,7 +568,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
         const uint32_t nbytes = m * B;
         const bool xf = (p.flags & kFlagExp) != 0;
-        uint32_t(*h)[256] = S.hist[wv];
+        // this lane's copy of every byte group's histogram
+        constexpr uint32_t R = kRep / B;
+        const uint32_t rc = uint32_t(lane) / (64 / R);
+        const uint32_t rshift = rc * (32 / R);
+        auto bin = [&](uint32_t k, uint32_t v) { return &S.rep[k * R + rc][v + rshift]; };
         // 16-byte vectors; the element boundary is aligned since 16 % B == 0
         const uint32_t nvec = nbytes / 16;
         // a stream whose bytes agree across an eighth of the wave's lanes in
@@ -645,12 +661,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                     if (sk) {
                         const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
                         const uint64_t msk = __ballot(byte == hot);
-                        if (byte != hot) atomicAdd(&h[k][byte], 1u);
+                        if (byte != hot) atomicAdd(bin(k, byte), 1u);
                         else if (__builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32),
                                                            __builtin_amdgcn_mbcnt_lo(uint32_t(msk), 0u)) == 0)
-                            atomicAdd(&h[k][hot], uint32_t(__popcll(msk)));
+                            atomicAdd(bin(k, hot), uint32_t(__popcll(msk)));
                     } else {
-                        atomicAdd(&h[k][byte], 1u);
+                        atomicAdd(bin(k, byte), 1u);
                     }
                 }
                 if constexpr (SP) {
@@ -695,12 +711,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         for (uint32_t e = nvec * 16 / B + t; e < m; e += kBlock) {
             const uint32_t v = element_word<B>(src, base, e, xf);
             for (uint32_t b = 0; b < B; b++)
-                if ((live >> (B - 1 - b)) & 1) atomicAdd(&h[B - 1 - b][(v >> (8 * b)) & 0xFFu], 1u);
+                if ((live >> (B - 1 - b)) & 1) atomicAdd(bin(B - 1 - b, (v >> (8 * b)) & 0xFFu), 1u);
         }
         __syncthreads();
         for (uint32_t i = t; i < 4 * 256; i += kBlock) {
             const uint32_t k = i >> 8, s = i & 255;
-            hist[k][s] = S.hist[0][k][s] + S.hist[1][k][s] + S.hist[2][k][s] + S.hist[3][k][s];
+            uint32_t v = 0;
+            if (k < B)
+                for (uint32_t r = 0; r < R; r++) v += S.rep[k * R + r][s + r * (32 / R)];
+            hist[k][s] = v;
         }
         __syncthreads();
         // 2. classification and HUF lengths, wave k for group k
@@ -826,7 +845,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             else if (h_hi <= z_lo) atomicAnd(&A.zgc, ~(1u << t));
         }
         __syncthreads();
-        // 4. replay the word requests of every candidate, one lane group per wave
+        // 4. the words of every candidate, one lane group per wave
         if (A.hc | A.zgc) {
             for (uint32_t j0 = 0; j0 < NG; j0 += kWaves) {
                 const uint32_t j = j0 + wv;
@@ -994,57 +1013,25 @@ __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, i
     }
 }
 
-// Write the words of lane group j of one Huffman stream k, in lock-step.  An
-// encoder runs LG groups ahead of a model of the decoder: every step it
-// encodes the lane's group jj + LG into a per-lane queue of finished words in
-// LDS (after the lane's last group the partial word is flushed) and keeps
-// that group's code lengths in a per-lane ring.  The decoder model then plays
-// step jj's rounds from the lengths: a lane that the decoder serves in a
-// round pops its next queued word (zero once the lane's codes are used up)
-// and stores it at the cursor + its rank among the round's takers.  When the
-// decoder takes a word it holds fewer than 2L bits, so it asks for at most
-// 2L - 1 + 32 <= 53 bits past what it has consumed; the encoder is at least
-// LG*G + 2 >= 58 symbols (of >= 1 bit) ahead, so the word is always complete.
-//
-// In ZG (template ZG, fill value z) only the groups holding another value are
-// coded and take part; an unmarked group leaves a zero in the length ring.
-// The encoder may then be fewer than 58 coded symbols ahead, so a word the
-// decoder takes may not be finished: the taker records its slot, and the
-// encoder stores the word there when it finishes it (or a zero once the
-// lane's codes are used up).  When the decoder takes a word, the encoder has
-// coded at least the current group, so at most the two words after the
-// finished ones can be waiting (32x < consumed + 2L <= coded + 22 gives
-// x <= finished + 1): one slot per word parity.
-template <int G>
-struct PackShape {
-    static constexpr uint32_t LG = (56 + G - 1) / G;                            // lead in groups
-    static constexpr uint32_t LR = LG + 1 <= 8 ? 8 : (LG + 1 <= 16 ? 16 : 32);  // ring of lengths
-    // queued words per lane: when the encoder has coded groups up to jj + LG
-    // the decoder has consumed every group before jj, so at most
-    // (LG + 1) g L / 32 <= 22 finished words wait (L <= 11, g <= 8)
-    static constexpr uint32_t Q = 24;
-    static constexpr uint32_t LB = G / 2;   // bytes of one group's lengths (4 bits each)
-};
-constexpr uint32_t kPackQ = 24;
-// the bound on waiting words, for every group size the format allows
-static_assert(kMinG == 2 && kMaxG == 8, "group sizes checked below");
-static_assert((PackShape<2>::LG + 1) * 2 * kMaxL / 32 < PackShape<2>::Q, "packer queue too short for g = 2");
-static_assert((PackShape<4>::LG + 1) * 4 * kMaxL / 32 < PackShape<4>::Q, "packer queue too short for g = 4");
-static_assert((PackShape<8>::LG + 1) * 8 * kMaxL / 32 < PackShape<8>::Q, "packer queue too short for g = 8");
-static_assert(PackShape<2>::Q == kPackQ && PackShape<4>::Q == kPackQ && PackShape<8>::Q == kPackQ, "queue size");
-constexpr uint32_t kPackLenBytes = 32 * 64;   // per wave: LR * 64 lanes * LB = 32 * 64 bytes for every g
-
+// Write the words of lane group j of one Huffman stream k (template ZG: a ZG
+// stream with fill value z, whose unmarked groups are not coded), in
+// lock-step over the steps and pairs of the layout.  At every pair of its
+// coded groups a lane first takes a word if it holds fewer than 2L bits: the
+// word's place is the lane group's cursor plus the lane's rank among the
+// pair's takers.  Then the pair's codes join the lane's bits, and a word that
+// is complete is stored at the oldest place taken for it.  A taken word is
+// wholly past what the lane has consumed, so it is finished later; and since
+// after each take 32 * taken - consumed lies in [2L, 2L + 31], at most two
+// taken words are ever unfinished.  After the lane's last pair the unfinished
+// words are stored: the partial one, then zero.
 template <int B, int G, bool ZG>
 __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode, uint32_t z,
-                                uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out, uint32_t* qring,
-                                uint8_t* lring, bool xf, uint64_t* bitmap, uint32_t rawmask, uint8_t* dst,
-                                const uint64_t* rawpay)
+                                uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out, uint32_t nw, bool xf,
+                                uint64_t* bitmap, uint32_t rawmask, uint8_t* dst, const uint64_t* rawpay)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
-    constexpr uint32_t LG = PackShape<G>::LG, LR = PackShape<G>::LR, Q = PackShape<G>::Q, LB = PackShape<G>::LB;
-    // groups of input prefetched ahead of the encoder (two for 4-byte words:
-    // fewer spills at 128 VGPRs, FP32 encode 5% faster)
+    // groups of input prefetched ahead (two for 4-byte words: fewer registers)
     constexpr uint32_t kPf = B == 4 ? 2 : 4;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = 64 * j + lane;
@@ -1071,37 +1058,28 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
 #pragma unroll
         for (int r = 0; r < B; r++) roff[r] = __builtin_amdgcn_readfirstlane(uint32_t(rawpay[r] - rawpay[0]));
     }
-    uint64_t eb = 0;   // encoder: bits not yet in a queued word
-    uint32_t en = 0;
-    uint32_t qt = 0;   // words queued
-    uint32_t qh = 0;   // words taken
-    uint32_t qti = 0, qhi = 0;   // their ring slots (qt mod Q, qh mod Q)
-    uint32_t pslot[2] = {0, 0};   // ZG: slots of taken words not yet finished, by word parity
-    bool done = ng == 0;          // ZG: every group of the lane encoded
-    auto finish = [&](uint32_t word) {
-        qring[qti * 64 + lane] = word;
-        if (ZG && qt < qh) out[pslot[qt & 1]] = word;
-        qt++;
-        qti = qti + 1 == Q ? 0u : qti + 1;
-    };
+    uint64_t acc = 0;       // coded bits not yet stored (fewer than 32 between pairs)
+    uint32_t nacc = 0;
+    int held = 0;           // bits the decoder holds: 32 * taken - consumed
+    uint32_t cur = 0;       // words of the lane group taken so far (uniform)
+    uint32_t slot0 = 0, slot1 = 0;   // places of the taken, unfinished words, oldest first
+    uint32_t npend = 0;
     auto load = [&](uint32_t e, uint32_t* wd) {
         if (e < ng) group_words<B, G>(src, base, w + e * W, m, wd, xf);
     };
-    auto encode = [&](uint32_t e, const uint32_t* wd) {
-        const uint32_t ecnt = w + e * W < Gfull ? G : rem;
+    auto step = [&](uint32_t e, const uint32_t* wd) {
+        const uint32_t ecnt = e < ng ? (w + e * W < Gfull ? G : rem) : 0u;
         const bool mk = !ZG || (e < ng && marked<B, G>(wd, k, ecnt, z));
         if (ZG && bitmap) {
             // ZG with W a multiple of 64: the 64 bits of this lane group's
-            // step e are one aligned word of the bitmap (the wave is uniform
-            // here: every lane calls encode with the same e)
+            // step e are one aligned word of the bitmap
             const uint64_t bits = __ballot(mk);
-            if (lane == 0 && e < ng_max) bitmap[j + e * (W / 64)] = bits;
+            if (lane == 0) bitmap[j + e * (W / 64)] = bits;
         }
-        if (e >= ng) return;
         // the raw byte groups of this group of g elements, copied on this pass
         // (the first coded group's) instead of in a pass of their own
         if constexpr (kFuseRaw) {
-            if (rawmask) {
+            if (rawmask && e < ng) {
                 const uint32_t q0 = (w + e * W) * G;
 #pragma unroll
                 for (int r = 0; r < B; r++) {
@@ -1117,95 +1095,62 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
                 }
             }
         }
-        uint32_t lens = 0;
-        if (mk) {
+        const uint32_t gcnt = mk ? ecnt : 0u;
 #pragma unroll
-            for (int i = 0; i < G; i++) {
-                if (uint32_t(i) < ecnt) {
-                    const uint32_t cw = rcode[sym_of<B>(wd, k, i)];
-                    const uint32_t l = cw >> 16;
-                    eb |= uint64_t(cw & 0xFFFFu) << en;
-                    en += l;
-                    lens |= l << (4 * i);
-                    if (en >= 32) {
-                        finish(uint32_t(eb));
-                        eb >>= 32;
-                        en -= 32;
-                    }
+        for (int pr = 0; pr < G / 2; pr++) {
+            const bool part = 2u * pr < gcnt;
+            const bool need = part && held < twoL;
+            const uint64_t msk = __ballot(need);
+            if (need) {
+                const uint32_t idx = __builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo(uint32_t(msk), cur));
+                if (npend == 0) slot0 = idx;
+                else slot1 = idx;
+                npend++;
+                held += 32;
+            }
+            cur += uint32_t(__popcll(msk));
+            if (part) {
+                const uint32_t c0 = rcode[sym_of<B>(wd, k, 2 * pr)];
+                uint32_t l = c0 >> 16;
+                acc |= uint64_t(c0 & 0xFFFFu) << nacc;
+                nacc += l;
+                if (2u * pr + 1 < gcnt) {
+                    const uint32_t c1 = rcode[sym_of<B>(wd, k, 2 * pr + 1)];
+                    acc |= uint64_t(c1 & 0xFFFFu) << nacc;
+                    nacc += c1 >> 16;
+                    l += c1 >> 16;
+                }
+                held -= int(l);
+                if (nacc >= 32) {   // at most one word completes per pair (nacc < 32 + 2L)
+                    if (slot0 < nw) out[slot0] = uint32_t(acc);   // (always: nw counts these takes)
+                    acc >>= 32;
+                    nacc -= 32;
+                    slot0 = slot1;
+                    npend--;
                 }
             }
         }
-        uint8_t* lp = lring + ((e & (LR - 1)) * 64 + lane) * LB;
-        if constexpr (LB == 1) *lp = uint8_t(lens);
-        else if constexpr (LB == 2) *reinterpret_cast<uint16_t*>(lp) = uint16_t(lens);
-        else *reinterpret_cast<uint32_t*>(lp) = lens;
-        if (e + 1 == ng) {
-            if (en > 0) {
-                finish(uint32_t(eb));
-                eb = 0;
-                en = 0;
-            }
-            if constexpr (ZG) {
-                // taken words past the lane's last code bit are zero
-                for (uint32_t x = qt; x < qh; x++) out[pslot[x & 1]] = 0u;
-                done = true;
-            }
-        }
     };
-    // prologue: the first LG groups
-    for (uint32_t e0 = 0; e0 < LG; e0 += kPf) {
-        uint32_t wd[kPf][NW];
-#pragma unroll
-        for (uint32_t u = 0; u < kPf; u++)
-            if (e0 + u < LG) load(e0 + u, wd[u]);
-#pragma unroll
-        for (uint32_t u = 0; u < kPf; u++)
-            if (e0 + u < LG) encode(e0 + u, wd[u]);
-    }
     uint32_t pf[kPf][NW];
 #pragma unroll
-    for (uint32_t u = 0; u < kPf; u++) load(LG + u, pf[u]);
-    int cnt = 0;       // bits the decoder holds
-    uint32_t ptr = 0;  // words of this lane group written
+    for (uint32_t u = 0; u < kPf; u++) load(u, pf[u]);
     for (uint32_t j0 = 0; j0 < ng_max; j0 += kPf) {
 #pragma unroll
         for (uint32_t u = 0; u < kPf; u++) {
             const uint32_t jj = j0 + u;
             if (jj < ng_max) {
-                encode(jj + LG, pf[u]);
-                load(jj + LG + kPf, pf[u]);
-                const uint8_t* lp = lring + ((jj & (LR - 1)) * 64 + lane) * LB;
-                uint32_t lens;
-                if constexpr (LB == 1) lens = *lp;
-                else if constexpr (LB == 2) lens = *reinterpret_cast<const uint16_t*>(lp);
-                else lens = *reinterpret_cast<const uint32_t*>(lp);
-                // a coded group has a nonzero length for its first symbol
-                const uint32_t gcnt = (jj < ng && (!ZG || lens != 0)) ? (w + jj * W < Gfull ? G : rem) : 0u;
+                uint32_t cw[NW];
 #pragma unroll
-                for (int pr = 0; pr < G / 2; pr++) {
-                    const bool part = 2u * pr < gcnt;
-                    const bool need = part && cnt < twoL;
-                    const uint64_t msk = __ballot(need);
-                    const uint32_t idx = __builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32),
-                                                                   __builtin_amdgcn_mbcnt_lo(uint32_t(msk), ptr));
-                    const uint32_t qw = qring[qhi * 64 + lane];
-                    if (need) {
-                        if (qh < qt) out[idx] = qw;
-                        else if (!ZG || done) out[idx] = 0u;
-                        else pslot[qh & 1] = idx;
-                        qh++;
-                        qhi = qhi + 1 == Q ? 0u : qhi + 1;
-                        cnt += 32;
-                    }
-                    ptr += uint32_t(__popcll(msk));
-                    if (part) {
-                        cnt -= int((lens >> (8 * pr)) & 15u);
-                        if (2u * pr + 1 < gcnt) cnt -= int((lens >> (8 * pr + 4)) & 15u);
-                    }
-                }
+                for (int x = 0; x < NW; x++) cw[x] = pf[u][x];
+                load(jj + kPf, pf[u]);
+                step(jj, cw);
             }
         }
     }
+    // the lane's unfinished words: the partial one (zero bits if none), then zero
+    if (npend > 0 && slot0 < nw) out[slot0] = uint32_t(acc);
+    if (npend > 1 && slot1 < nw) out[slot1] = 0u;
 }
 
 struct PackLds {
@@ -1314,8 +1259,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                                                  const uint32_t* __restrict__ nwords)
 {
     __shared__ PackLds P;
-    __shared__ uint32_t qpool[kWaves][kPackQ * 64];
-    __shared__ __align__(16) uint8_t lpool[kWaves][kPackLenBytes];
     const int t = threadIdx.x, wv = t >> 6;
     constexpr uint32_t B = BB;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
@@ -1399,11 +1342,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             for (uint32_t j = wv; j < NG; j += kWaves) {
                 if (zg)
                     pack_lane_group<BB, GG, true>(src, base, int(k), P.rcode[k], P.z[k], p.L, j, W, m,
-                                                  words + P.wpre[k][j], qpool[wv], lpool[wv], xf, fused,
+                                                  words + P.wpre[k][j], P.wpre[k][j + 1] - P.wpre[k][j], xf, fused,
                                                   k == k0 ? rawmask : 0u, dst, P.pay);
                 else
                     pack_lane_group<BB, GG, false>(src, base, int(k), P.rcode[k], 0u, p.L, j, W, m,
-                                                   words + P.wpre[k][j], qpool[wv], lpool[wv], xf, nullptr,
+                                                   words + P.wpre[k][j], P.wpre[k][j + 1] - P.wpre[k][j], xf, nullptr,
                                                    k == k0 ? rawmask : 0u, dst, P.pay);
             }
         }
