@@ -147,6 +147,10 @@ def run_single(args):
     from paper_2411_05239_amd import zipnn as Z
 
     x_cpu, p, desc = make_workload(args.workload, args.probe_skip, args.exponent)
+    if args.chunk_bytes:
+        p.chunk_bytes = args.chunk_bytes
+        p.substream_syms = args.substream_syms
+        desc.update(chunk_bytes=p.chunk_bytes, S=p.substream_syms)
     dev = torch.device("cuda", 0)
     x = x_cpu.to(dev)
     U = x.numel() * x.element_size()
@@ -329,6 +333,9 @@ def run_checkpoint(args, delta: bool, zg: bool = False):
         print(json.dumps({"error": "batched round trip mismatch"}))
         sys.exit(1)
     C = offs[-1]
+    # the timed encode replays a prepared encoder (descriptors on the device,
+    # launches captured in a hipGraph) writing the same arena
+    encoder = codec.prepare_encoder(xs, best, bases, arena=arena)
     enc, dec = [], []
     for i in range(args.warmup + args.steps):
         if i == args.warmup:
@@ -337,7 +344,7 @@ def run_checkpoint(args, delta: bool, zg: bool = False):
         if not args.decode_only:
             a0, a1 = _events()
             a0.record(stream)
-            _, offs2 = codec.compress_batch(xs, best, bases, arena=arena)
+            offs2 = encoder.run()
             a1.record(stream)
             assert offs2 == offs
         b0, b1 = _events()
@@ -403,7 +410,7 @@ def run_checkpoint(args, delta: bool, zg: bool = False):
                    "tensor_dtype": "bf16", "tensors": len(xs), "bytes": U, "chunk_bytes": best.chunk_bytes,
                    "S": best.substream_syms, "g": best.group, "L": best.max_code_len,
                    "policy": "huf,huf" if delta and not zg else "auto", "probe_skip": best.probe_skip,
-                   "exponent": best.exponent, "batched": "one launch per kernel + hipGraph replay",
+                   "exponent": best.exponent, "batched": "encode and decode each a hipGraph replay of one launch per kernel",
                    "step": "batched encode + batched decode" if not args.decode_only else "batched decode"},
         "decode_ms": {"mean": round(dec_avg, 4), "median": round(statistics.median(dec_ms), 4),
                       "p10": round(sorted(dec_ms)[len(dec_ms) // 10], 4),
@@ -436,7 +443,8 @@ def run_checkpoint(args, delta: bool, zg: bool = False):
                                           best, [_container(a_np, offs[i]) for i in idx], args.cpu_budget,
                                           "layer 0 (q, k, v, o, gate, up, down, 2 norms) and the final norm")
     batch.close()
-    del outs, arena, batch, xs, bases
+    encoder.close()
+    del outs, arena, batch, encoder, xs, bases
     codec.close()
     torch.cuda.empty_cache()
     if not delta and not args.no_serve and not args.decode_only:

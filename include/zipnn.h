@@ -247,6 +247,26 @@ typedef struct {
 int zipnn_compress_batch(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, const zipnn_params* p,
                          void* arena, uint64_t arena_cap, uint64_t* offsets, void* stream);
 
+typedef struct zipnn_encoder_s* zipnn_encoder;
+
+/* Prepare the batched compression of tensors[0..n) (as zipnn_compress_batch,
+ * same bytes) for repeated runs, e.g. saving a checkpoint again and again:
+ * the descriptors are uploaded once, and the encode launches (histogram and
+ * code build, placement, container layout, packing) plus the copy of the
+ * n+1 arena offsets to pinned host memory are captured in a hipGraph.  The
+ * encoder owns its scratch.  The tensors (and bases) are read, and the arena
+ * written, at every run: they must stay valid while the encoder lives. */
+int zipnn_encoder_create(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int n, const zipnn_params* p,
+                         void* arena, uint64_t arena_cap, zipnn_encoder* out);
+
+/* Replay the graph on `stream` and wait; offsets (host, n+1 entries) receive
+ * the containers' offsets and, last, the arena bytes used (ZIPNN_E_NOSPACE if
+ * that exceeds arena_cap: the arena then holds unspecified bytes). */
+int zipnn_encoder_run(zipnn_encoder e, void* stream, uint64_t* offsets);
+
+/* Wait for the device, then release the encoder.  NULL is ignored. */
+void zipnn_encoder_destroy(zipnn_encoder e);
+
 typedef struct zipnn_batch_s* zipnn_batch;
 
 /* Prepare the decompression of the n containers of a device arena (offsets:

@@ -348,6 +348,114 @@ int zipnn_compress_batch(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensor
     return encode_tensors(ctx, dtype, tensors, n, p, arena, arena_cap, offsets, (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------ prepared encodes
+
+struct zipnn_encoder_s {
+    zipnn_ctx ctx = nullptr;
+    int n = 0;
+    uint64_t cap = 0;
+    void* d_mem = nullptr;        // scratch, descriptors and chunk prefix of this batch
+    uint64_t* h_offs = nullptr;   // pinned: the n+1 arena offsets of the last run
+    hipStream_t capst = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int zipnn_encoder_create(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, int n, const zipnn_params* p,
+                         void* arena, uint64_t cap, zipnn_encoder* out)
+{
+    if (!ctx || !t || !out) return ZIPNN_E_INVAL;
+    *out = nullptr;
+    if (zipnn_check_params(dtype, p) != ZIPNN_OK || n < 1 || !arena || !aligned16(arena)) return ZIPNN_E_INVAL;
+    const uint32_t B = uint32_t(dtype_bytes(dtype));
+    const uint64_t E = p->chunk_bytes / B;
+    uint64_t total_chunks = 0, map_bytes = 0;
+    for (int i = 0; i < n; i++) {
+        if ((!t[i].src && t[i].n_elems) || !aligned16(t[i].src) || !aligned16(t[i].base)) return ZIPNN_E_INVAL;
+        const uint64_t nc = (t[i].n_elems + E - 1) / E;
+        total_chunks += nc;
+        map_bytes += payload_base_of(nc, B);
+    }
+    if (total_chunks > 0xFFFFFFFFull) return ZIPNN_E_INVAL;
+    if (map_bytes > cap) return ZIPNN_E_NOSPACE;
+    DeviceGuard g(ctx->device);
+    zipnn_encoder e = new (std::nothrow) zipnn_encoder_s;
+    if (!e) return ZIPNN_E_NOMEM;
+    e->ctx = ctx;
+    e->n = n;
+    e->cap = cap;
+    const EncScratch lay = enc_scratch_layout(size_t(total_chunks) * B, size_t(n));
+    std::vector<EncDesc> hd(static_cast<size_t>(n));
+    std::vector<uint32_t> hp(static_cast<size_t>(n) + 1);
+    uint32_t run = 0;
+    for (int i = 0; i < n; i++) {
+        const uint64_t nc = (t[i].n_elems + E - 1) / E;
+        hd[size_t(i)] = EncDesc{(const uint8_t*)t[i].src, (const uint8_t*)t[i].base, nullptr, 0, t[i].n_elems, run,
+                                uint32_t(nc), 0, 0};
+        hp[size_t(i)] = run;
+        run += uint32_t(nc);
+    }
+    hp[size_t(n)] = run;
+    if (hipMalloc(&e->d_mem, lay.need) != hipSuccess ||
+        hipHostMalloc((void**)&e->h_offs, size_t(n + 1) * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+        zipnn_encoder_destroy(e);
+        return ZIPNN_E_NOMEM;
+    }
+    uint8_t* sc = (uint8_t*)e->d_mem;
+    EncDesc* d_descs = (EncDesc*)(sc + lay.descs);
+    uint32_t* d_prefix = (uint32_t*)(sc + lay.prefix);
+    uint64_t* d_aoff = (uint64_t*)(sc + lay.aoff);
+    if (hipMemcpy(d_descs, hd.data(), hd.size() * sizeof(EncDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_prefix, hp.data(), hp.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        zipnn_encoder_destroy(e);
+        return ZIPNN_E_HIP;
+    }
+    // capture the launches and the copy of the offsets once; every run replays them
+    const EncParams ep = make_params(dtype, *p);
+    if (hipStreamCreateWithFlags(&e->capst, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamBeginCapture(e->capst, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        zipnn_encoder_destroy(e);
+        return ZIPNN_E_HIP;
+    }
+    hipError_t le = launch_encode(d_descs, n, d_prefix, uint32_t(total_chunks), ep, (uint8_t*)arena, cap,
+                                  (EncEntry*)(sc + lay.entries), (CodeWord*)(sc + lay.codes),
+                                  (uint32_t*)(sc + lay.nwords), (uint64_t*)(sc + lay.offsets),
+                                  (uint64_t*)(sc + lay.totals), d_aoff, e->capst);
+    if (le == hipSuccess)
+        le = hipMemcpyAsync(e->h_offs, d_aoff, size_t(n + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, e->capst);
+    const hipError_t ce = hipStreamEndCapture(e->capst, &e->graph);
+    if (le != hipSuccess || ce != hipSuccess || hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0) != hipSuccess) {
+        zipnn_encoder_destroy(e);
+        return ZIPNN_E_HIP;
+    }
+    *out = e;
+    return ZIPNN_OK;
+}
+
+int zipnn_encoder_run(zipnn_encoder e, void* stream, uint64_t* offsets)
+{
+    if (!e || !offsets) return ZIPNN_E_INVAL;
+    DeviceGuard g(e->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipGraphLaunch(e->exec, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return ZIPNN_E_HIP;
+    if (e->h_offs[e->n] > e->cap) return ZIPNN_E_NOSPACE;
+    memcpy(offsets, e->h_offs, size_t(e->n + 1) * sizeof(uint64_t));
+    return ZIPNN_OK;
+}
+
+void zipnn_encoder_destroy(zipnn_encoder e)
+{
+    if (!e) return;
+    DeviceGuard g(e->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    if (e->capst) (void)hipStreamDestroy(e->capst);
+    if (e->d_mem) (void)hipFree(e->d_mem);
+    if (e->h_offs) (void)hipHostFree(e->h_offs);
+    delete e;
+}
+
 static int decompress_common(zipnn_ctx ctx, const uint32_t* hdr_words, const void* src, uint64_t src_len,
                              const void* base, void* dst, uint64_t dst_cap, hipStream_t s)
 {

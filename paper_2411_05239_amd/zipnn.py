@@ -27,7 +27,8 @@ EXPORTS = [
     "zipnn_strerror", "zipnn_ctx_create", "zipnn_ctx_destroy", "zipnn_ctx_status", "zipnn_default_params",
     "zipnn_check_params", "zipnn_compress_bound", "zipnn_compress", "zipnn_compress_noalloc", "zipnn_decompress",
     "zipnn_decompress_async",
-    "zipnn_inspect", "zipnn_compress_batch", "zipnn_batch_create", "zipnn_batch_decompress", "zipnn_batch_destroy",
+    "zipnn_inspect", "zipnn_compress_batch", "zipnn_encoder_create", "zipnn_encoder_run", "zipnn_encoder_destroy",
+    "zipnn_batch_create", "zipnn_batch_decompress", "zipnn_batch_destroy",
     "zipnn_decompress_batch", "zipnn_autotune", "zipnn_clock", "zipnn_server_create", "zipnn_server_destroy",
     "zipnn_server_register", "zipnn_server_submit", "zipnn_server_poll", "zipnn_server_next_done",
     "zipnn_server_release", "zipnn_server_stats",
@@ -119,6 +120,10 @@ def lib():
         L.zipnn_inspect.argtypes, L.zipnn_inspect.restype = [vp, u64, P(zipnn_info)], i32
         L.zipnn_compress_batch.argtypes = [vp, i32, P(zipnn_tensor_in), i32, P(zipnn_params), vp, u64, P(u64), vp]
         L.zipnn_compress_batch.restype = i32
+        L.zipnn_encoder_create.argtypes = [vp, i32, P(zipnn_tensor_in), i32, P(zipnn_params), vp, u64, P(vp)]
+        L.zipnn_encoder_create.restype = i32
+        L.zipnn_encoder_run.argtypes, L.zipnn_encoder_run.restype = [vp, vp, P(u64)], i32
+        L.zipnn_encoder_destroy.argtypes, L.zipnn_encoder_destroy.restype = [vp], None
         L.zipnn_batch_create.argtypes = [vp, vp, P(u64), i32, P(vp), P(u64), P(vp), P(vp)]
         L.zipnn_batch_create.restype = i32
         L.zipnn_batch_decompress.argtypes, L.zipnn_batch_decompress.restype = [vp, vp], i32
@@ -494,8 +499,55 @@ class Codec:
     def prepare_batch(self, arena, offsets, outs, bases=None) -> "Batch":
         return Batch(self, arena, offsets, outs, bases)
 
+    def prepare_encoder(self, xs, params: zipnn_params | None = None, bases=None, arena=None) -> "Encoder":
+        return Encoder(self, xs, params, bases, arena)
+
     def status(self, clear: bool = True) -> int:
         return zipnn_ctx_status(self.ctx, self._stream(), clear)
+
+
+class Encoder:
+    """A prepared batched compression (descriptors on the device and a
+    captured hipGraph); run() replays it on the current stream and returns
+    the arena offsets (n+1)."""
+
+    def __init__(self, codec: Codec, xs, params=None, bases=None, arena=None):
+        import torch
+
+        self.codec = codec
+        dt = torch_dtype_code(xs[0].dtype)
+        p = params or zipnn_default_params(dt)
+        xs = [x.contiguous() for x in xs]
+        bases = [None] * len(xs) if bases is None else [b.contiguous() if b is not None else None for b in bases]
+        cap = sum(zipnn_compress_bound(dt, x.numel(), p) + 127 for x in xs)
+        if arena is None or arena.numel() < cap:
+            arena = torch.empty(cap, dtype=torch.uint8, device=xs[0].device)
+        self.arena = arena
+        self._keep = (xs, bases)
+        n = len(xs)
+        ts = (zipnn_tensor_in * n)(*[zipnn_tensor_in(x.data_ptr(), x.numel(), b.data_ptr() if b is not None else None)
+                                     for x, b in zip(xs, bases)])
+        h = ctypes.c_void_p()
+        _check(lib().zipnn_encoder_create(codec.ctx, dt, ts, n, ctypes.byref(p), arena.data_ptr(), arena.numel(),
+                                          ctypes.byref(h)), "zipnn_encoder_create")
+        self.h = h.value
+        self.n = n
+
+    def run(self) -> list[int]:
+        offs = (ctypes.c_uint64 * (self.n + 1))()
+        _check(lib().zipnn_encoder_run(self.h, Codec._stream(), offs), "zipnn_encoder_run")
+        return list(offs)
+
+    def close(self):
+        if self.h:
+            lib().zipnn_encoder_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

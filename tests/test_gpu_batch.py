@@ -250,3 +250,47 @@ def test_autotune_picks_fastest_within_ratio_loss(codec):
                          min_chunk=1 << 20, max_chunk=64 << 10)
     assert ei.value.code == Z.ZIPNN_E_INVAL
 
+
+def test_prepared_encoder_graph_replays(codec):
+    """The prepared encoder (descriptors uploaded once, launches captured in a
+    hipGraph) gives zipnn_compress_batch's bytes on every replay, with eager
+    work of the program (another compress, a decompress, synchronisations)
+    between the replays; a delta batch too."""
+    xs = [x.cuda() for x in _small_checkpoint(seed0=700)]
+    p = Z.make_params(Z.ZIPNN_BF16, chunk_bytes=65536)
+    arena, offs = codec.compress_batch(xs, p)
+    ref = arena[: offs[-1]].cpu().numpy().copy()
+
+    def containers(a):
+        # each container by its header's size (the gap after a 64-byte empty
+        # container, up to the next 128-byte offset, is not part of any)
+        return [a[o: o + int.from_bytes(a[o + 32: o + 40].tobytes(), "little")] for o in offs[:-1]]
+
+    enc = codec.prepare_encoder(xs, p)
+    for r in range(3):
+        enc.arena.fill_(0xA5)          # the replay must write every byte of the containers
+        got_offs = enc.run()
+        assert got_offs == offs, r
+        got = containers(enc.arena[: offs[-1]].cpu().numpy())
+        assert all(np.array_equal(a, b) for a, b in zip(got, containers(ref))), r
+        # eager work between replays
+        c = codec.compress(xs[1], p)
+        out = torch.empty_like(xs[1])
+        codec.decompress(c, out)
+        torch.cuda.synchronize()
+        assert torch.equal(_u8(out), _u8(xs[1]))
+    enc.close()
+    i = 1
+    want = oracle.compress(xs[i].cpu(), oracle.BF16, nthreads=8, **_kw(p))
+    assert np.array_equal(ref[offs[i]: offs[i] + want.size], want)
+    base = [workloads.bf16_normal(x.numel(), seed=800 + k).cuda() if x.numel() else x for k, x in enumerate(xs)]
+    ft = [workloads.finetune_delta(b, seed=900 + k) if b.numel() else b for k, b in enumerate(base)]
+    a2, o2 = codec.compress_batch(ft, p, base)
+    enc = codec.prepare_encoder(ft, p, base)
+    ref2 = a2[: o2[-1]].cpu().numpy()
+    for r in range(2):
+        assert enc.run() == o2
+        got = enc.arena[: o2[-1]].cpu().numpy()
+        assert all(np.array_equal(got[o: o + len(c)], c) for o, c in zip(o2[:-1], [ref2[o:][: int.from_bytes(
+            ref2[o + 32: o + 40].tobytes(), "little")] for o in o2[:-1]]))
+    enc.close()
