@@ -476,8 +476,12 @@ static int decompress_common(zipnn_ctx ctx, const uint32_t* hdr_words, const voi
     one.c_begin = 0;
     one.c_end = kAllChunks;
     one.status = nullptr;
-    if (launch_decode_one(h, one, ctx->d_status, ctx->dec_grid[dec_class_index(dec_class(h))], s) != hipSuccess)
-        return ZIPNN_E_HIP;
+    // no more workgroups than items: a small tensor does not dispatch the
+    // whole persistent grid
+    const uint64_t items = plan_items(h, 0, kAllChunks).items;
+    const int grid = int(std::min<uint64_t>(uint64_t(ctx->dec_grid[dec_class_index(dec_class(h))]),
+                                            std::max<uint64_t>(items, 1)));
+    if (launch_decode_one(h, one, ctx->d_status, grid, s) != hipSuccess) return ZIPNN_E_HIP;
     return ZIPNN_OK;
 }
 
