@@ -77,8 +77,9 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v)
 }
 
 // Expand a 128-byte nibble table into the LSB-first lookup table `lut`
-// (entry = symbol | length << 8 for every L-bit window).  Returns false (in
-// every thread) when the lengths are not a complete prefix code.
+// (entry = length | symbol << 8 for every L-bit window: bits 5..7 are zero, so
+// a shift by the entry shifts by the length).  Returns false (in every
+// thread) when the lengths are not a complete prefix code.
 __device__ bool build_lut(const uint8_t* table, uint32_t L, uint16_t* lut, LutTmp& T)
 {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -122,7 +123,7 @@ __device__ bool build_lut(const uint8_t* table, uint32_t L, uint16_t* lut, LutTm
         uint32_t pos = T.offs[l] + pre + rank;
         uint32_t code = T.first[l] + pre + rank;
         T.start[pos] = uint16_t(code << (L - l));
-        T.entry[pos] = uint16_t(t | (l << 8));
+        T.entry[pos] = uint16_t(l | (t << 8));
     }
     __syncthreads();
     // every L-bit value v (most significant code bit first) lies in the range
@@ -236,14 +237,20 @@ struct SlotSize {
 struct WordCursor {
     __amdgpu_buffer_rsrc_t rs;   // this lane group's words
     uint32_t* ring;              // this wave's ring for the stream (LDS)
+    uint8_t* rings;              // the workgroup's rings, aligned to RW*4 bytes
+    uint32_t roff;               // byte offset of `ring` in `rings` (a multiple of RW*4)
     uint32_t ptr;                // words taken so far
     uint32_t rb;                 // stream index of the ring's oldest word (multiple of RW/2)
 };
 
 // A stream's register slot holds, for a Huffman stream: the pending block
-// r[0..PN), the buffered bit count r[PN] and the 64-bit bit buffer
-// r[PN+1] | r[PN+2] << 32; for a raw stream: the ring of prefetched groups
-// (r[u*PW + x]).  The mode of a stream is fixed for a chunk, so one set of
+// r[0..PN), the count r[PN] and the 64-bit bit buffer r[PN+1] | r[PN+2] << 32
+// whose bit 0 is a placeholder: with c = r[PN] & 0xFF, the buffered code bits
+// are bits 1 .. c-1, next code first, so that r[PN+1] & (table mask << 1) is
+// the byte offset of the next code's table entry.  Decoding subtracts whole
+// table entries from r[PN]: c loses the length, and the symbol bits only
+// reach bits 8 and up (c stays within 1..55 and never borrows); for a raw
+// stream: the ring of prefetched groups (r[u*PW + x]).  The mode of a stream is fixed for a chunk, so one set of
 // registers serves both.
 
 template <int B>
@@ -255,11 +262,14 @@ __device__ inline void pend_load(uint32_t* r, const WordCursor& c, uint32_t firs
 
 template <int B>
 __device__ inline void huf_init(uint32_t* r, WordCursor& c, const uint32_t* words, uint32_t nwords, uint32_t lane,
-                                uint32_t* ring)
+                                uint32_t* rings, uint32_t ring_index)
 {
     constexpr int RW = Ring<B>::RW, PN = Ring<B>::PN;
+    uint32_t* ring = rings + ring_index * RW;
     c.rs = rsrc(words, nwords * 4);
     c.ring = ring;
+    c.rings = reinterpret_cast<uint8_t*>(rings);
+    c.roff = ring_index * RW * 4;
     c.ptr = 0;
     c.rb = 0;
     // fill the ring with words [0, RW), then fetch [RW, RW + RW/2)
@@ -268,24 +278,26 @@ __device__ inline void huf_init(uint32_t* r, WordCursor& c, const uint32_t* word
 #pragma unroll
     for (int x = 0; x < 2 * PN; x++) ring[2 * PN * lane + x] = v[x];
     pend_load<B>(r, c, RW, lane);
-    r[PN] = 0;
+    r[PN] = 1;   // no code bits yet, only the placeholder bit
     r[PN + 1] = 0;
     r[PN + 2] = 0;
 }
 
 // One round's word requests: lanes taking part with fewer than 2L buffered
-// bits take the next words of the stream, in lane order (a ballot and a
-// prefix popcount give each lane its word).
+// bits (r[PN] <= 2L) take the next words of the stream, in lane order (a
+// ballot and a prefix popcount give each lane its word).
 template <int B>
 __device__ inline void huf_take(uint32_t* r, WordCursor& c, bool part, uint32_t twoL)
 {
     constexpr int RW = Ring<B>::RW, PN = Ring<B>::PN;
-    const bool need = part && r[PN] < twoL;
+    const bool need = part && (r[PN] & 0xFFu) <= twoL;
     const uint64_t m = __ballot(need);
-    // ring index of this lane's word: the cursor plus the needing lanes below
-    const uint32_t idx = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), c.ptr));
-    const uint32_t word = c.ring[idx & (RW - 1)];   // every lane reads; only the needing ones keep it
-    const uint64_t x = uint64_t(need ? word : 0u) << r[PN];
+    // this lane's word: the cursor plus the needing lanes below, modulo the
+    // ring; the ring's byte offset is a multiple of its size, so OR places it
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    const uint32_t off = ((c.ptr * 4u + below * 4u) & (RW * 4u - 4u)) | c.roff;
+    const uint32_t word = *(const uint32_t*)(c.rings + off);   // every lane reads; only the needing ones keep it
+    const uint64_t x = uint64_t(need ? word : 0u) << (r[PN] & 63u);
     r[PN + 1] |= uint32_t(x);
     r[PN + 2] |= uint32_t(x >> 32);
     r[PN] += need ? 32u : 0u;
@@ -308,30 +320,41 @@ __device__ inline void huf_refill(uint32_t* r, WordCursor& c, uint32_t lane)
     }
 }
 
+// Decode one symbol: returns its table entry (length | symbol << 8) and
+// drops its code bits.  mask2 = (2^L - 1) << 1 picks the byte offset of the
+// entry of the L bits after the placeholder; the funnel shifts use the low
+// five bits of the entry, which are the length.
 template <int B>
-__device__ inline uint32_t huf_get(uint32_t* r, const uint16_t* lut, uint32_t mask)
+__device__ inline uint32_t huf_get(uint32_t* r, const uint16_t* lut, uint32_t mask2)
 {
     constexpr int PN = Ring<B>::PN;
-    const uint32_t e = lut[r[PN + 1] & mask];
-    const uint32_t l = e >> 8;
-    r[PN + 1] = __builtin_amdgcn_alignbit(r[PN + 2], r[PN + 1], l);
-    r[PN + 2] >>= l;
-    r[PN] -= l;
-    return e & 0xFFu;
+    const uint32_t e = *(const uint16_t*)((const uint8_t*)lut + (r[PN + 1] & mask2));
+    r[PN + 1] = __builtin_amdgcn_alignbit(r[PN + 2], r[PN + 1], e);
+    r[PN + 2] = __builtin_amdgcn_alignbit(0u, r[PN + 2], e);
+    r[PN] -= e;
+    return e;
 }
 
 // huf_get for a lane that may not take part (a ZG group made of z alone):
 // the table is read, but the bits are consumed only when `on`.
 template <int B>
-__device__ inline uint32_t huf_get_if(uint32_t* r, const uint16_t* lut, uint32_t mask, bool on)
+__device__ inline uint32_t huf_get_if(uint32_t* r, const uint16_t* lut, uint32_t mask2, bool on)
 {
     constexpr int PN = Ring<B>::PN;
-    const uint32_t e = lut[r[PN + 1] & mask];
-    const uint32_t l = on ? e >> 8 : 0u;
-    r[PN + 1] = __builtin_amdgcn_alignbit(r[PN + 2], r[PN + 1], l);
-    r[PN + 2] >>= l;
-    r[PN] -= l;
-    return e & 0xFFu;
+    const uint32_t e = *(const uint16_t*)((const uint8_t*)lut + (r[PN + 1] & mask2));
+    const uint32_t s = on ? e : 0u;
+    r[PN + 1] = __builtin_amdgcn_alignbit(r[PN + 2], r[PN + 1], s);
+    r[PN + 2] = __builtin_amdgcn_alignbit(0u, r[PN + 2], s);
+    r[PN] -= s;
+    return e;
+}
+
+// The symbols of two table entries as bytes `pos` and pos+1 of a word whose
+// other bytes are zero (v_perm_b32: selector 1 is byte 1 of the second
+// operand, 5 byte 1 of the first, 0x0c a zero byte).
+__device__ inline uint32_t sym_pair(uint32_t e0, uint32_t e1, uint32_t pos)
+{
+    return __builtin_amdgcn_perm(e1, e0, pos == 0 ? 0x0c0c0501u : 0x05010c0cu);
 }
 
 template <int G>
@@ -433,7 +456,7 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
     L = uni(L);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = 64 * j + lane;
-    const uint32_t mask = (1u << L) - 1, twoL = 2 * L;
+    const uint32_t mask2 = ((1u << L) - 1) << 1, twoL = 2 * L;
     const uint32_t Gtot = (m + G - 1) / G, Gfull = m / G, rem = m - Gfull * G;
     const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;     // groups of this lane
     const uint32_t nfull = (w < W && w < Gfull) ? (Gfull - 1 - w) / W + 1 : 0; // full ones
@@ -456,6 +479,8 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
     const __amdgpu_buffer_rsrc_t rb = rsrc(DELTA ? base : out, m * B);
     // byte offset of this lane's group jj in a raw payload: (w + jj*W)*G
     auto raw_off = [&](uint32_t jj) { return jj < nfull ? (w + jj * W) * G : kOff; };
+    // the same for the XOR base, in bytes
+    auto base_off = [&](uint32_t jj) { return jj < nfull ? (w + jj * W) * (G * B) : kOff; };
     // ZG: lane l loads bits 32(l/32) .. +31 of step J + l%32 of this lane
     // group, i.e. bits 64j + (J + l%32)W + 32(l/32) onwards of the bitmap
     auto zload = [&](int k, uint32_t J) __attribute__((always_inline)) {
@@ -485,7 +510,7 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
             const uint32_t s0 = __builtin_amdgcn_readfirstlane(wprefix[k][j]);
             const uint32_t s1 = __builtin_amdgcn_readfirstlane(wprefix[k][j + 1]);
             nw[k] = s1 - s0;
-            huf_init<B>(slot[k], cur[k], words + s0, s1 - s0, lane, wring + (k * 4 + (threadIdx.x >> 6)) * Ring<B>::RW);
+            huf_init<B>(slot[k], cur[k], words + s0, s1 - s0, lane, wring, k * 4 + (threadIdx.x >> 6));
         } else if (mode[k] == kModeRaw) {
 #pragma unroll
             for (int u = 0; u < kDepth; u++) buf_load<G>(rr[k], raw_off(u), &slot[k][u * PW]);
@@ -494,8 +519,7 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
     if constexpr (DELTA) {
 #pragma unroll
         for (int u = 0; u < kDepth; u++) {
-            const uint32_t o = raw_off(u);
-            buf_load<NB>(rb, o == kOff ? kOff : o * B, bring[u]);
+            buf_load<NB>(rb, base_off(u), bring[u]);
         }
     }
     // ZG: at step jj (the steps are visited in order, kDepth at a time),
@@ -563,9 +587,9 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
 #pragma unroll
                             for (int pr = 0; pr < G / 2; pr++) {
                                 huf_take<B>(slot[k], cur[k], on, twoL);
-                                const uint32_t s0 = huf_get_if<B>(slot[k], lut[k], mask, on);
-                                const uint32_t s1 = huf_get_if<B>(slot[k], lut[k], mask, on);
-                                pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
+                                const uint32_t e0 = huf_get_if<B>(slot[k], lut[k], mask2, on);
+                                const uint32_t e1 = huf_get_if<B>(slot[k], lut[k], mask2, on);
+                                pk[k][(2 * pr) >> 2] |= sym_pair(e0, e1, (2 * pr) & 3);
                                 if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1)
                                     huf_refill<B>(slot[k], cur[k], lane);
                             }
@@ -582,9 +606,9 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
 #pragma unroll
                             for (int pr = 0; pr < G / 2; pr++) {
                                 huf_take<B>(slot[k], cur[k], true, twoL);
-                                const uint32_t s0 = huf_get<B>(slot[k], lut[k], mask);
-                                const uint32_t s1 = huf_get<B>(slot[k], lut[k], mask);
-                                pk[k][(2 * pr) >> 2] |= (s0 | (s1 << 8)) << (8 * ((2 * pr) & 3));
+                                const uint32_t e0 = huf_get<B>(slot[k], lut[k], mask2);
+                                const uint32_t e1 = huf_get<B>(slot[k], lut[k], mask2);
+                                pk[k][(2 * pr) >> 2] |= sym_pair(e0, e1, (2 * pr) & 3);
                                 if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1)
                                     huf_refill<B>(slot[k], cur[k], lane);
                             }
@@ -601,22 +625,22 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                     constexpr int CM = HM & ~((ZM >= 0 ? ZM : 0) & ~ZS);
 #pragma unroll
                     for (int pr = 0; pr < G / 2; pr++) {
-                        uint32_t s0[B];
+                        uint32_t e0[B];
 #pragma unroll
                         for (int k = 0; k < B; k++)
                             if ((CM >> k) & 1) huf_take<B>(slot[k], cur[k], ((ZS >> k) & 1) ? zon[k] : true, twoL);
 #pragma unroll
                         for (int k = 0; k < B; k++) {
                             if ((CM >> k) & 1)
-                                s0[k] = ((ZS >> k) & 1) ? huf_get_if<B>(slot[k], lut[k], mask, zon[k])
-                                                        : huf_get<B>(slot[k], lut[k], mask);
+                                e0[k] = ((ZS >> k) & 1) ? huf_get_if<B>(slot[k], lut[k], mask2, zon[k])
+                                                        : huf_get<B>(slot[k], lut[k], mask2);
                         }
 #pragma unroll
                         for (int k = 0; k < B; k++) {
                             if ((CM >> k) & 1) {
-                                const uint32_t s1 = ((ZS >> k) & 1) ? huf_get_if<B>(slot[k], lut[k], mask, zon[k])
-                                                                    : huf_get<B>(slot[k], lut[k], mask);
-                                pk[k][(2 * pr) >> 2] |= (s0[k] | (s1 << 8)) << (8 * ((2 * pr) & 3));
+                                const uint32_t e1 = ((ZS >> k) & 1) ? huf_get_if<B>(slot[k], lut[k], mask2, zon[k])
+                                                                    : huf_get<B>(slot[k], lut[k], mask2);
+                                pk[k][(2 * pr) >> 2] |= sym_pair(e0[k], e1, (2 * pr) & 3);
                             }
                         }
 #pragma unroll
@@ -638,7 +662,7 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                 if constexpr (DELTA) {
 #pragma unroll
                     for (int x = 0; x < NW; x++) ow[x] ^= bring[u][x];
-                    buf_load<NB>(rb, offn == kOff ? kOff : offn * B, bring[u]);
+                    buf_load<NB>(rb, base_off(jj + kDepth), bring[u]);
                 }
                 buf_store<NB>(ro, off * B, ow);
             }
@@ -723,9 +747,10 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                         const bool part = on && 2u * pr < gcnt;
                         huf_take<B>(slot[k], cur[k], part, twoL);
                         if (part) {
-                            pk[k][(2 * pr) >> 2] |= huf_get<B>(slot[k], lut[k], mask) << (8 * ((2 * pr) & 3));
+                            pk[k][(2 * pr) >> 2] |= (huf_get<B>(slot[k], lut[k], mask2) >> 8) << (8 * ((2 * pr) & 3));
                             if (2u * pr + 1 < gcnt)
-                                pk[k][(2 * pr + 1) >> 2] |= huf_get<B>(slot[k], lut[k], mask) << (8 * ((2 * pr + 1) & 3));
+                                pk[k][(2 * pr + 1) >> 2] |= (huf_get<B>(slot[k], lut[k], mask2) >> 8)
+                                                            << (8 * ((2 * pr + 1) & 3));
                         }
                         if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1) huf_refill<B>(slot[k], cur[k], lane);
                     }
@@ -743,7 +768,7 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
             if constexpr (DELTA) {
 #pragma unroll
                 for (int x = 0; x < NW; x++) ow[x] ^= bring[u][x];
-                buf_load<NB>(rb, offn == kOff ? kOff : offn * B, bring[u]);
+                buf_load<NB>(rb, base_off(jj + kDepth), bring[u]);
             }
             if (full) {
                 buf_store<NB>(ro, q * G * B, ow);
@@ -935,7 +960,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B * G >=
 {
     __shared__ uint16_t lut[B][kLutSize];
     __shared__ uint32_t wprefix[B][65];
-    __shared__ uint32_t wring[B * 4 * Ring<B>::RW];
+    // aligned to one ring's size: a ring's words are addressed by OR (huf_take)
+    __shared__ __attribute__((aligned(Ring<B>::RW * 4))) uint32_t wring[B * 4 * Ring<B>::RW];
     __shared__ LutTmp T;
     __shared__ ItemState st;
     __shared__ TensorState ts;
