@@ -349,6 +349,32 @@ __device__ inline uint32_t huf_get_if(uint32_t* r, const uint16_t* lut, uint32_t
     return e;
 }
 
+// A pair of symbols in two halves.  huf_pair0 reads the first symbol's entry
+// and returns it with `lo1`, the buffer's low word past its code; huf_pair1
+// reads the second entry from lo1 and drops both codes at once (the sum of
+// two entries carries the sum of the lengths, at most 2L < 32, in its low
+// five bits).  With `on` false the lane consumes nothing.
+template <int B>
+__device__ inline uint32_t huf_pair0(const uint32_t* r, const uint16_t* lut, uint32_t mask2, uint32_t& lo1)
+{
+    constexpr int PN = Ring<B>::PN;
+    const uint32_t e = *(const uint16_t*)((const uint8_t*)lut + (r[PN + 1] & mask2));
+    lo1 = __builtin_amdgcn_alignbit(r[PN + 2], r[PN + 1], e);
+    return e;
+}
+template <int B>
+__device__ inline uint32_t huf_pair1(uint32_t* r, const uint16_t* lut, uint32_t mask2, uint32_t e0, uint32_t lo1,
+                                     bool on = true)
+{
+    constexpr int PN = Ring<B>::PN;
+    const uint32_t e1 = *(const uint16_t*)((const uint8_t*)lut + (lo1 & mask2));
+    const uint32_t s = on ? e0 + e1 : 0u;
+    r[PN + 1] = __builtin_amdgcn_alignbit(r[PN + 2], r[PN + 1], s);
+    r[PN + 2] = __builtin_amdgcn_alignbit(0u, r[PN + 2], s);
+    r[PN] -= s;
+    return e1;
+}
+
 // The symbols of two table entries as bytes `pos` and pos+1 of a word whose
 // other bytes are zero (v_perm_b32: selector 1 is byte 1 of the second
 // operand, 5 byte 1 of the first, 0x0c a zero byte).
@@ -551,6 +577,13 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
     auto fast = [&](auto hm_const, auto zm_const) __attribute__((always_inline)) {
         constexpr int HM = decltype(hm_const)::value;
         constexpr int ZM = decltype(zm_const)::value;
+        // the interleaved form below (HM >= 0, B <= 2): ZS, the ZG streams
+        // decoded there; CM, all the streams it decodes
+        constexpr int ZS = (ZM >= 0 && !DELTA) ? ZM : 0;
+        constexpr int CM = HM & ~((ZM >= 0 ? ZM : 0) & ~ZS);
+        // both byte groups of a BF16/FP16 word coded: the words are built
+        // from the table entries directly
+        constexpr bool DIRECT = HM >= 0 && B == 2 && CM == 3 && ZS == 0;
         for (uint32_t j0 = 0; j0 < n_fast; j0 += kDepth) {
 #pragma unroll
             for (int u = 0; u < kDepth; u++) {
@@ -559,6 +592,7 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                 const uint32_t offn = raw_off(jj + kDepth);
                 if (ZM != 0 && u == 0) zstep(jj, ZM >= 0 ? uint32_t(ZM) : zm_all);
                 uint32_t pk[B][PW];
+                uint32_t ow[NW];
                 bool zon[B];   // ZG streams decoded side by side: this lane's group is marked
 #pragma unroll
                 for (int k = 0; k < B; k++) {
@@ -587,8 +621,9 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
 #pragma unroll
                             for (int pr = 0; pr < G / 2; pr++) {
                                 huf_take<B>(slot[k], cur[k], on, twoL);
-                                const uint32_t e0 = huf_get_if<B>(slot[k], lut[k], mask2, on);
-                                const uint32_t e1 = huf_get_if<B>(slot[k], lut[k], mask2, on);
+                                uint32_t lo1;
+                                const uint32_t e0 = huf_pair0<B>(slot[k], lut[k], mask2, lo1);
+                                const uint32_t e1 = huf_pair1<B>(slot[k], lut[k], mask2, e0, lo1, on);
                                 pk[k][(2 * pr) >> 2] |= sym_pair(e0, e1, (2 * pr) & 3);
                                 if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1)
                                     huf_refill<B>(slot[k], cur[k], lane);
@@ -606,8 +641,9 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
 #pragma unroll
                             for (int pr = 0; pr < G / 2; pr++) {
                                 huf_take<B>(slot[k], cur[k], true, twoL);
-                                const uint32_t e0 = huf_get<B>(slot[k], lut[k], mask2);
-                                const uint32_t e1 = huf_get<B>(slot[k], lut[k], mask2);
+                                uint32_t lo1;
+                                const uint32_t e0 = huf_pair0<B>(slot[k], lut[k], mask2, lo1);
+                                const uint32_t e1 = huf_pair1<B>(slot[k], lut[k], mask2, e0, lo1);
                                 pk[k][(2 * pr) >> 2] |= sym_pair(e0, e1, (2 * pr) & 3);
                                 if ((pr + 1) % Ring<B>::CHECK == 0 || pr == G / 2 - 1)
                                     huf_refill<B>(slot[k], cur[k], lane);
@@ -621,26 +657,25 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                     // the chains of table reads of the streams overlap (BF16
                     // chunks with both groups coded: -7%).  In a ZG stream the
                     // lanes whose group is z alone take no part.
-                    constexpr int ZS = (ZM >= 0 && !DELTA) ? ZM : 0;
-                    constexpr int CM = HM & ~((ZM >= 0 ? ZM : 0) & ~ZS);
+                    uint32_t ent[B][G];
 #pragma unroll
                     for (int pr = 0; pr < G / 2; pr++) {
-                        uint32_t e0[B];
+                        uint32_t e0[B], lo1[B];
 #pragma unroll
                         for (int k = 0; k < B; k++)
                             if ((CM >> k) & 1) huf_take<B>(slot[k], cur[k], ((ZS >> k) & 1) ? zon[k] : true, twoL);
 #pragma unroll
                         for (int k = 0; k < B; k++) {
-                            if ((CM >> k) & 1)
-                                e0[k] = ((ZS >> k) & 1) ? huf_get_if<B>(slot[k], lut[k], mask2, zon[k])
-                                                        : huf_get<B>(slot[k], lut[k], mask2);
+                            if ((CM >> k) & 1) e0[k] = huf_pair0<B>(slot[k], lut[k], mask2, lo1[k]);
                         }
 #pragma unroll
                         for (int k = 0; k < B; k++) {
                             if ((CM >> k) & 1) {
-                                const uint32_t e1 = ((ZS >> k) & 1) ? huf_get_if<B>(slot[k], lut[k], mask2, zon[k])
-                                                                    : huf_get<B>(slot[k], lut[k], mask2);
-                                pk[k][(2 * pr) >> 2] |= sym_pair(e0[k], e1, (2 * pr) & 3);
+                                const uint32_t e1 = huf_pair1<B>(slot[k], lut[k], mask2, e0[k], lo1[k],
+                                                                 ((ZS >> k) & 1) ? zon[k] : true);
+                                ent[k][2 * pr] = e0[k];
+                                ent[k][2 * pr + 1] = e1;
+                                if (!DIRECT) pk[k][(2 * pr) >> 2] |= sym_pair(e0[k], e1, (2 * pr) & 3);
                             }
                         }
 #pragma unroll
@@ -653,9 +688,16 @@ __device__ __attribute__((always_inline)) void decode_lane_group(const uint8_t* 
                         if ((ZS >> k) & 1)
 #pragma unroll
                             for (int x = 0; x < PW; x++) pk[k][x] = zon[k] ? pk[k][x] : rlev[k];
+                    if constexpr (DIRECT) {
+                        // word x holds elements 2x (bytes 0, 1) and 2x+1: the
+                        // low byte from group 1, the high byte from group 0
+#pragma unroll
+                        for (int x = 0; x < G / 2; x++)
+                            ow[x] = __builtin_amdgcn_perm(ent[0][2 * x], ent[1][2 * x], 0x0c0c0501u) |
+                                    __builtin_amdgcn_perm(ent[0][2 * x + 1], ent[1][2 * x + 1], 0x05010c0cu);
+                    }
                 }
-                uint32_t ow[NW];
-                merge_words<B, G>(pk, ow);
+                if constexpr (!DIRECT) merge_words<B, G>(pk, ow);
                 if (xf)
 #pragma unroll
                     for (int x = 0; x < NW; x++) ow[x] = exp_inv<B>(ow[x]);
