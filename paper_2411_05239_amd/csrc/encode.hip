@@ -1013,129 +1013,211 @@ __global__ __launch_bounds__(kBlock) void k_arena(EncDesc* __restrict__ descs, i
     }
 }
 
-// Write the words of lane group j of one Huffman stream k (template ZG: a ZG
-// stream with fill value z, whose unmarked groups are not coded), in
-// lock-step over the steps and pairs of the layout.  At every pair of its
+struct PackLds {
+    uint32_t rcode[4][256];     // reversed code | length << 27 (0 for absent symbols)
+    uint64_t pay[4];            // absolute payload offset of each stream
+    uint32_t mode[4];
+    uint32_t bytes[4];
+    uint32_t z[4];              // ZG fill value
+    uint32_t wpre[4][65];       // lane-group word prefix per stream
+};
+
+constexpr uint32_t kLenShift = 27;              // code length's place in a packer code entry
+
+// f(integral_constant<int, k>) for k = 0 .. N-1: per-stream state is then
+// picked at compile time and stays in registers
+template <int N, class F>
+__device__ __attribute__((always_inline)) inline void for_streams(F&& f)
+{
+    if constexpr (N > 0) {
+        for_streams<N - 1>(f);
+        f(std::integral_constant<int, N - 1>{});
+    }
+}
+constexpr uint32_t kNoStore = 0x80000000u;      // buffer offset past every resource: the store is dropped
+
+// Write the words of lane group j of every coded stream of one chunk (bit k
+// of cm; with bit k of zm a ZG stream with fill value P.z[k], whose unmarked
+// groups are not coded) in one pass over the chunk's groups, in lock-step
+// over the steps and pairs of the layout.  Per stream, at every pair of its
 // coded groups a lane first takes a word if it holds fewer than 2L bits: the
 // word's place is the lane group's cursor plus the lane's rank among the
 // pair's takers.  Then the pair's codes join the lane's bits, and a word that
-// is complete is stored at the oldest place taken for it.  A taken word is
-// wholly past what the lane has consumed, so it is finished later; and since
-// after each take 32 * taken - consumed lies in [2L, 2L + 31], at most two
-// taken words are ever unfinished.  After the lane's last pair the unfinished
-// words are stored: the partial one, then zero.
-template <int B, int G, bool ZG>
-__device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* src, const uint8_t* base, int k, const uint32_t* rcode, uint32_t z,
-                                uint32_t L, uint32_t j, uint32_t W, uint32_t m, uint32_t* out, uint32_t nw, bool xf,
-                                uint64_t* bitmap, uint32_t rawmask, uint8_t* dst, const uint64_t* rawpay)
+// is complete is stored at the oldest place taken for it.  With held =
+// 32 * taken - consumed and nacc the coded bits not yet stored, held + nacc is
+// 32 times the words taken and not yet stored: a taken word lies wholly past
+// what the lane has consumed, so it is finished later, and at most two are
+// ever unfinished (after each take held lies in [2L, 2L + 31]).  After the
+// lane's last pair the unfinished words are stored: the partial one, then
+// zero.  The stores go through a buffer resource over the lane group's words,
+// so a place past them (which the analysis's counts never give) is dropped.
+// Steps in which every lane has a full group run without per-lane group
+// counts; the raw byte groups of small groups are copied on the same pass.
+template <int B, int G>
+__device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* src, const uint8_t* base, uint32_t cm,
+                                                               uint32_t zm, const PackLds& P, uint32_t L, uint32_t j,
+                                                               uint32_t W, uint32_t m, bool xf, bool fuse_bitmap,
+                                                               uint32_t rawmask, uint8_t* dst)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
     // groups of input prefetched ahead (two for 4-byte words: fewer registers)
     constexpr uint32_t kPf = B == 4 ? 2 : 4;
+    cm = __builtin_amdgcn_readfirstlane(cm);
+    zm = __builtin_amdgcn_readfirstlane(zm);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = 64 * j + lane;
     const int twoL = int(2 * L);
     const uint32_t Gtot = (m + G - 1) / G, Gfull = m / G, rem = m - Gfull * G;
     const uint32_t ng = (w < W && w < Gtot) ? (Gtot - 1 - w) / W + 1 : 0;
     const uint32_t ng_max = __builtin_amdgcn_readfirstlane(ng);   // lane 0 has the most
-
-    // raw byte groups copied here (Huffman packer, groups of at most 4 bytes:
-    // b16 / b32 stores through a buffer resource on the chunk's payloads)
-    constexpr bool kFuseRaw = !ZG && G <= 4 && B * G <= 16;
-    // one resource over the chunk's payloads (they are consecutive) and a
-    // scalar offset per raw group
-    __amdgpu_buffer_rsrc_t rr;
-    uint32_t roff[B];
-    {
-        const uint64_t a = uint64_t(dst + rawpay[0]);
-        // (the builtin returns int: widen through uint32_t, not by sign)
-        const uint64_t au = uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(a)))) |
-                            (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(a >> 32)))) << 32);
-        const uint32_t span = uint32_t(rawpay[B - 1] - rawpay[0]) + m;
-        rr = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(au), (short)0,
-                                               int(__builtin_amdgcn_readfirstlane(rawmask ? span : 0u)), 0x00020000);
-#pragma unroll
-        for (int r = 0; r < B; r++) roff[r] = __builtin_amdgcn_readfirstlane(uint32_t(rawpay[r] - rawpay[0]));
-    }
-    uint64_t acc = 0;       // coded bits not yet stored (fewer than 32 between pairs)
-    uint32_t nacc = 0;
-    int held = 0;           // bits the decoder holds: 32 * taken - consumed
-    uint32_t cur = 0;       // words of the lane group taken so far (uniform)
-    uint32_t slot0 = 0, slot1 = 0;   // places of the taken, unfinished words, oldest first
-    uint32_t npend = 0;
-    auto load = [&](uint32_t e, uint32_t* wd) {
-        if (e < ng) group_words<B, G>(src, base, w + e * W, m, wd, xf);
+    // full groups of the lane group's last lane: every lane has at least these
+    const uint32_t w_last = min(W, 64 * j + 64) - 1;
+    const uint32_t nfull_all = w_last < Gfull ? (Gfull - 1 - w_last) / W + 1 : 0;
+    const uint32_t n_fast = (64 * j + 64 <= W) ? nfull_all / kPf * kPf : 0;
+    const uint32_t head = huf_head(W), bm = zg_bitmap(m, G);
+    auto uni64 = [](uint64_t v) {
+        return uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(v)))) |
+               (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(v >> 32)))) << 32);
     };
-    auto step = [&](uint32_t e, const uint32_t* wd) {
-        const uint32_t ecnt = e < ng ? (w + e * W < Gfull ? G : rem) : 0u;
-        const bool mk = !ZG || (e < ng && marked<B, G>(wd, k, ecnt, z));
-        if (ZG && bitmap) {
-            // ZG with W a multiple of 64: the 64 bits of this lane group's
-            // step e are one aligned word of the bitmap
-            const uint64_t bits = __ballot(mk);
-            if (lane == 0) bitmap[j + e * (W / 64)] = bits;
-        }
-        // the raw byte groups of this group of g elements, copied on this pass
-        // (the first coded group's) instead of in a pass of their own
+    // per coded stream: its words of this lane group (a buffer resource), the
+    // fused bitmap, and the lock-step state
+    struct Stream {
+        __amdgpu_buffer_rsrc_t out;
+        uint64_t* bmw;
+        uint32_t cur, alo, ahi, nacc, s0, s1;
+        int held;
+    };
+    Stream st0, st1, st2, st3;
+    auto S = [&](auto kc) __attribute__((always_inline)) -> Stream& {
+        constexpr int k = decltype(kc)::value;
+        if constexpr (k == 0) return st0;
+        else if constexpr (k == 1) return st1;
+        else if constexpr (k == 2) return st2;
+        else return st3;
+    };
+    for_streams<B>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        Stream& x = S(kc);
+        const uint32_t zb = (zm >> k) & 1;
+        const uint64_t pk = uni64(P.pay[k]);
+        const uint32_t w0 = __builtin_amdgcn_readfirstlane(P.wpre[k][j]);
+        const uint32_t nw = __builtin_amdgcn_readfirstlane(P.wpre[k][j + 1]) - w0;
+        const uint64_t wa = uni64(uint64_t(dst + pk + head + (zb ? bm : 0u)) + 4ull * w0);
+        x.out = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(wa), (short)0,
+                                                  int(((cm >> k) & 1) ? 4 * nw : 0u), 0x00020000);
+        x.bmw = (zb && fuse_bitmap) ? reinterpret_cast<uint64_t*>(dst + pk + head) : nullptr;
+        x.cur = x.alo = x.ahi = x.nacc = x.s0 = x.s1 = 0;
+        x.held = 0;
+    });
+    // raw byte groups copied here (groups of at most 4 bytes: b16 / b32
+    // stores through one resource over the chunk's payloads, which are
+    // consecutive, and a scalar offset per raw group)
+    constexpr bool kFuseRaw = G <= 4 && B * G <= 16;
+    const uint64_t raw0 = uni64(uint64_t(dst + P.pay[0]));
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<void*>(raw0), (short)0,
+        int(__builtin_amdgcn_readfirstlane(rawmask ? uint32_t(P.pay[B - 1] - P.pay[0]) + m : 0u)), 0x00020000);
+    // one pair of stream k: entries c0, c1 (zero for a symbol that is not
+    // coded), p0 whether the lane takes part
+    auto pair = [&](auto kc, uint32_t c0, uint32_t c1, bool p0) __attribute__((always_inline)) {
+        Stream& x = S(kc);
+        const bool need = p0 && x.held < twoL;
+        const uint64_t msk = __ballot(need);
+        const uint32_t rank =
+            __builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(msk), 0u));
+        const uint32_t place = (x.cur + rank) * 4u;
+        // nothing pending: held + nacc = 0, i.e. held = 0 (nacc < 32)
+        const bool empty = x.held == 0;
+        x.s0 = (need && empty) ? place : x.s0;
+        x.s1 = need ? place : x.s1;
+        x.held += need ? 32 : 0;
+        x.cur += uint32_t(__popcll(msk));
+        // the two codes side by side (the lengths sit in bits 27..31 of an
+        // entry, so the entries' sum carries the sum of the lengths, <= 2L)
+        const uint32_t l0 = c0 >> kLenShift, l = (c0 + c1) >> kLenShift;
+        const uint32_t pc = (c0 | (c1 << l0)) & ((1u << kLenShift) - 1);
+        const uint64_t v = uint64_t(pc) << x.nacc;
+        x.alo |= uint32_t(v);
+        x.ahi |= uint32_t(v >> 32);
+        x.nacc += l;
+        x.held -= int(l);
+        // at most one word completes per pair (nacc < 32 + 2L)
+        const bool full = x.nacc >= 32;
+        __builtin_amdgcn_raw_buffer_store_b32(x.alo, x.out, full ? x.s0 : kNoStore, 0, 0);
+        x.alo = full ? x.ahi : x.alo;
+        x.ahi = 0;   // fewer than 32 bits left: none above the low word
+        x.nacc &= 31u;
+        x.s0 = full ? x.s1 : x.s0;
+    };
+    // one step (group e of every lane); FAST: every lane has a full group
+    auto step = [&](uint32_t e, const uint32_t* wd, auto fast_c) __attribute__((always_inline)) {
+        constexpr bool FAST = decltype(fast_c)::value;
+        const bool has = FAST || e < ng;
+        const uint32_t ecnt = FAST ? uint32_t(G) : (has ? (w + e * W < Gfull ? G : rem) : 0u);
         if constexpr (kFuseRaw) {
-            if (rawmask && e < ng) {
+            if (rawmask && has) {
                 const uint32_t q0 = (w + e * W) * G;
-#pragma unroll
-                for (int r = 0; r < B; r++) {
-                    if (!((rawmask >> r) & 1)) continue;
-                    if (ecnt == G) {
+                for_streams<B>([&](auto rc) __attribute__((always_inline)) {
+                    constexpr int r = decltype(rc)::value;
+                    if (!((rawmask >> r) & 1)) return;
+                    const uint32_t roff = __builtin_amdgcn_readfirstlane(uint32_t(P.pay[r] - P.pay[0]));
+                    if (FAST || ecnt == G) {
                         const uint32_t v = gather_stream<B, G>(wd, r);
-                        if constexpr (G == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(v), rr, q0, roff[r], 0);
-                        else __builtin_amdgcn_raw_buffer_store_b32(v, rr, q0, roff[r], 0);
+                        if constexpr (G == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(v), rr, q0, roff, 0);
+                        else __builtin_amdgcn_raw_buffer_store_b32(v, rr, q0, roff, 0);
                     } else {
                         for (uint32_t i = 0; i < ecnt; i++)
-                            __builtin_amdgcn_raw_buffer_store_b8(uint8_t(sym_of<B>(wd, r, int(i))), rr, q0 + i, roff[r], 0);
+                            __builtin_amdgcn_raw_buffer_store_b8(uint8_t(sym_of<B>(wd, r, int(i))), rr, q0 + i, roff,
+                                                                 0);
                     }
-                }
+                });
             }
         }
-        const uint32_t gcnt = mk ? ecnt : 0u;
+        for_streams<B>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value;
+            if (!((cm >> k) & 1)) return;
+            // the pairs of a group of gcnt coded symbols
+            auto pairs = [&](uint32_t gcnt) __attribute__((always_inline)) {
 #pragma unroll
-        for (int pr = 0; pr < G / 2; pr++) {
-            const bool part = 2u * pr < gcnt;
-            const bool need = part && held < twoL;
-            const uint64_t msk = __ballot(need);
-            if (need) {
-                const uint32_t idx = __builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo(uint32_t(msk), cur));
-                if (npend == 0) slot0 = idx;
-                else slot1 = idx;
-                npend++;
-                held += 32;
-            }
-            cur += uint32_t(__popcll(msk));
-            if (part) {
-                const uint32_t c0 = rcode[sym_of<B>(wd, k, 2 * pr)];
-                uint32_t l = c0 >> 16;
-                acc |= uint64_t(c0 & 0xFFFFu) << nacc;
-                nacc += l;
-                if (2u * pr + 1 < gcnt) {
-                    const uint32_t c1 = rcode[sym_of<B>(wd, k, 2 * pr + 1)];
-                    acc |= uint64_t(c1 & 0xFFFFu) << nacc;
-                    nacc += c1 >> 16;
-                    l += c1 >> 16;
+                for (int pr = 0; pr < G / 2; pr++) {
+                    const bool p0 = 2u * pr < gcnt, p1 = 2u * pr + 1 < gcnt;
+                    const uint32_t c0 = P.rcode[k][sym_of<B>(wd, k, 2 * pr)];
+                    const uint32_t c1 = P.rcode[k][sym_of<B>(wd, k, 2 * pr + 1)];
+                    pair(kc, p0 ? c0 : 0u, p1 ? c1 : 0u, p0);
                 }
-                held -= int(l);
-                if (nacc >= 32) {   // at most one word completes per pair (nacc < 32 + 2L)
-                    if (slot0 < nw) out[slot0] = uint32_t(acc);   // (always: nw counts these takes)
-                    acc >>= 32;
-                    nacc -= 32;
-                    slot0 = slot1;
-                    npend--;
+            };
+            if ((zm >> k) & 1) {
+                const bool mk = has && marked<B, G>(wd, k, ecnt, P.z[k]);
+                if (fuse_bitmap) {
+                    // ZG with W a multiple of 64: the 64 bits of this lane
+                    // group's step e are one aligned word of the bitmap
+                    const uint64_t bits = __ballot(mk);
+                    if (lane == 0) S(kc).bmw[j + e * (W / 64)] = bits;
                 }
+                pairs(mk ? ecnt : 0u);
+            } else {
+                pairs(ecnt);   // in a fast step, G: no per-lane conditions
             }
-        }
+        });
+    };
+    auto load = [&](uint32_t e, uint32_t* wd) {
+        if (e < ng) group_words<B, G>(src, base, w + e * W, m, wd, xf);
     };
     uint32_t pf[kPf][NW];
 #pragma unroll
     for (uint32_t u = 0; u < kPf; u++) load(u, pf[u]);
-    for (uint32_t j0 = 0; j0 < ng_max; j0 += kPf) {
+    for (uint32_t j0 = 0; j0 < n_fast; j0 += kPf) {
+#pragma unroll
+        for (uint32_t u = 0; u < kPf; u++) {
+            uint32_t cw[NW];
+#pragma unroll
+            for (int x = 0; x < NW; x++) cw[x] = pf[u][x];
+            load(j0 + u + kPf, pf[u]);
+            step(j0 + u, cw, std::integral_constant<bool, true>{});
+        }
+    }
+    for (uint32_t j0 = n_fast; j0 < ng_max; j0 += kPf) {
 #pragma unroll
         for (uint32_t u = 0; u < kPf; u++) {
             const uint32_t jj = j0 + u;
@@ -1144,23 +1226,20 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
 #pragma unroll
                 for (int x = 0; x < NW; x++) cw[x] = pf[u][x];
                 load(jj + kPf, pf[u]);
-                step(jj, cw);
+                step(jj, cw, std::integral_constant<bool, false>{});
             }
         }
     }
     // the lane's unfinished words: the partial one (zero bits if none), then zero
-    if (npend > 0 && slot0 < nw) out[slot0] = uint32_t(acc);
-    if (npend > 1 && slot1 < nw) out[slot1] = 0u;
+    for_streams<B>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        if (!((cm >> k) & 1)) return;
+        const Stream& x = S(kc);
+        const int pend = (x.held + int(x.nacc)) >> 5;
+        __builtin_amdgcn_raw_buffer_store_b32(x.alo, x.out, pend > 0 ? x.s0 : kNoStore, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(0u, x.out, pend > 1 ? x.s1 : kNoStore, 0, 0);
+    });
 }
-
-struct PackLds {
-    uint32_t rcode[4][256];     // reversed code | length << 16
-    uint64_t pay[4];            // absolute payload offset of each stream
-    uint32_t mode[4];
-    uint32_t bytes[4];
-    uint32_t z[4];              // ZG fill value
-    uint32_t wpre[4][65];       // lane-group word prefix per stream
-};
 
 // The group bitmap of a ZG stream: wave v writes 64-bit words x = v, v+4, ...
 // of the bm bytes (lane l tests group 64x + l); bits past the last group and
@@ -1292,7 +1371,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             if (en.mode == kModeHuf || en.mode == kModeZg) {
                 const uint32_t cw = codes[ei * 256 + t];
                 const uint32_t l = cw >> 16;
-                P.rcode[k][t] = l ? ((__brev(cw & 0xFFFFu) >> (32 - l)) | (l << 16)) : 0u;
+                P.rcode[k][t] = l ? ((__brev(cw & 0xFFFFu) >> (32 - l)) | (l << kLenShift)) : 0u;
                 if (t < 64) {
                     const uint32_t nw = uint32_t(t) < NG ? nwords[ei * 64 + t] : 0u;
                     uint32_t inc = nw;
@@ -1311,45 +1390,44 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
         uint8_t* dst = d.dst;
         const bool xf = (p.flags & kFlagExp) != 0;
-        // the first Huffman group's packer also copies the raw groups (groups
-        // of at most 4 bytes)
-        uint32_t rawmask = 0, k0 = B;
+        // the coded groups (HUF and ZG) are packed in one pass, which also
+        // copies the raw groups when groups are small (at most 4 bytes)
+        uint32_t rawmask = 0, cm = 0, zm = 0;
         for (uint32_t k = 0; k < B; k++) {
             if (P.mode[k] == kModeRaw) rawmask |= 1u << k;
-            if (GG <= 4 && BB * GG <= 16 && k0 == B && P.mode[k] == kModeHuf) k0 = k;
+            if (P.mode[k] == kModeHuf || P.mode[k] == kModeZg) cm |= 1u << k;
+            if (P.mode[k] == kModeZg) zm |= 1u << k;
         }
-        pack_raw<BB>(src, base, dst, P, m, xf, k0 < B);
+        const bool fuse_raw = GG <= 4 && BB * GG <= 16 && cm != 0;
+        pack_raw<BB>(src, base, dst, P, m, xf, fuse_raw);
+        // with W a multiple of 64 the packer writes a ZG bitmap's words as it
+        // marks the groups
+        const bool fuse_bitmap = W % 64 == 0;
         for (uint32_t k = 0; k < B; k++) {
             const bool zg = P.mode[k] == kModeZg;
             if (P.mode[k] != kModeHuf && !zg) continue;
             uint8_t* pay = dst + P.pay[k];
             // head: nibble table, word counts, zero pad; ZG bitmap; zero pad after words
-            if (t < 128) pay[t] = uint8_t((P.rcode[k][2 * t] >> 16) | ((P.rcode[k][2 * t + 1] >> 16) << 4));
+            if (t < 128)
+                pay[t] = uint8_t((P.rcode[k][2 * t] >> kLenShift) | ((P.rcode[k][2 * t + 1] >> kLenShift) << 4));
             if (uint32_t(t) < NG) ((uint32_t*)(pay + 128))[t] = P.wpre[k][t + 1] - P.wpre[k][t];
             for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
             for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
-            const uint32_t bm = zg ? zg_bitmap(m, GG) : 0u;
-            // with W a multiple of 64 the packer writes the bitmap's words as it
-            // marks the groups; here only the words past the last group are zeroed
-            uint64_t* fused = (zg && W % 64 == 0) ? reinterpret_cast<uint64_t*>(pay + head) : nullptr;
-            if (fused) {
-                const uint32_t Gtot = (m + GG - 1) / GG;
-                for (uint32_t x = (Gtot + 63) / 64 + t; x < bm / 8; x += kBlock) fused[x] = 0;
-            } else if (zg) {
-                pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + head, xf);
-            }
-            uint32_t* words = (uint32_t*)(pay + head + bm);
-            for (uint32_t j = wv; j < NG; j += kWaves) {
-                if (zg)
-                    pack_lane_group<BB, GG, true>(src, base, int(k), P.rcode[k], P.z[k], p.L, j, W, m,
-                                                  words + P.wpre[k][j], P.wpre[k][j + 1] - P.wpre[k][j], xf, fused,
-                                                  k == k0 ? rawmask : 0u, dst, P.pay);
-                else
-                    pack_lane_group<BB, GG, false>(src, base, int(k), P.rcode[k], 0u, p.L, j, W, m,
-                                                   words + P.wpre[k][j], P.wpre[k][j + 1] - P.wpre[k][j], xf, nullptr,
-                                                   k == k0 ? rawmask : 0u, dst, P.pay);
+            if (zg) {
+                const uint32_t bm = zg_bitmap(m, GG);
+                if (fuse_bitmap) {   // only the words past the last group are zeroed here
+                    uint64_t* words = reinterpret_cast<uint64_t*>(pay + head);
+                    const uint32_t Gtot = (m + GG - 1) / GG;
+                    for (uint32_t x = (Gtot + 63) / 64 + t; x < bm / 8; x += kBlock) words[x] = 0;
+                } else {
+                    pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + head, xf);
+                }
             }
         }
+        if (cm)
+            for (uint32_t j = wv; j < NG; j += kWaves)
+                pack_lane_group<BB, GG>(src, base, cm, zm, P, p.L, j, W, m, xf, fuse_bitmap, fuse_raw ? rawmask : 0u,
+                                        dst);
         __syncthreads();
     }
 }
