@@ -47,16 +47,21 @@ struct PmWave {                 // package-merge workspace of one wave
     uint32_t leafw[256];        // leaf weights, ascending (f, symbol)
     uint16_t leafsym[256];
     uint32_t pk[256];           // package weights of the current level
-    uint32_t cur[512];          // current list weights
+    union {
+        alignas(16) uint32_t key[256];   // the sort keys, used before the lists
+        uint32_t cur[512];               // current list weights
+    };
     uint32_t leafbits[kMaxL][16];   // bit p: item p of the list of a level is a leaf
-    alignas(16) uint32_t key[256];
     uint8_t len[256];           // code length per symbol
 };
 
+// Sized by the word width B (wave k < B builds the code of byte group k), so
+// that a BF16 workgroup takes 22 KB and seven fit on a CU.
+template <int B>
 union AnalyzeLds {
     uint32_t rep[kRep][kRepStride];  // the counting pass's histogram copies
-    uint32_t hist[kWaves][4][256];   // per-wave sub-histograms (the ZG counting pass)
-    PmWave pm[kWaves];               // per-wave code construction
+    uint32_t hist[kWaves][B][256];   // per-wave sub-histograms (the ZG counting pass)
+    PmWave pm[B];                    // per-group code construction
     uint32_t lgw[2][4][64];          // words per lane group: HUF, ZG (replay)
 };
 
@@ -482,9 +487,10 @@ __device__ __attribute__((always_inline)) void count_lane_group(const uint8_t* s
     }
 }
 
+template <int B>
 struct AnalyzeTail {
-    uint8_t lens[4][256];    // HUF code lengths
-    uint8_t lens2[4][256];   // ZG code lengths
+    uint8_t lens[B][256];    // HUF code lengths
+    uint8_t lens2[B][256];   // ZG code lengths
     uint32_t z[4];           // ZG fill value: the most frequent byte (smallest on ties)
     uint32_t open;           // bit k: mode still to be decided (neither forced RAW nor RLE)
     uint32_t hc;             // bit k: HUF candidate
@@ -513,18 +519,20 @@ struct AnalyzeTail {
 //   5. the mode of each group (AUTO: the smallest of RAW, HUF, ZG, ties to
 //      RAW then HUF), its entry, its lane-group word counts and its canonical
 //      code table.
-// Four waves per SIMD (four workgroups per CU, 32 KB of LDS each): a few
-// spilled registers cost less than the lost occupancy (batched encode 5-9%
-// faster than at three).
+// Occupancy matters more than spills here: the passes are latency-bound per
+// workgroup.  Four waves per SIMD (128 VGPRs) were 5-9% faster than three;
+// for 2-byte words five (96 VGPRs, some spills in the counting loop) encode
+// the BF16 checkpoint 5% and its XOR delta 10% faster than four (six: 1%
+// slower than five on the checkpoint, 4% faster on the delta).
 template <int BB>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 ? 5 : 4, 8))) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                     EncParams p, int phase, EncEntry* __restrict__ entries,
                                                     CodeWord* __restrict__ codes, uint32_t* __restrict__ nwords)
 {
-    __shared__ AnalyzeLds S;
-    __shared__ uint32_t hist[4][256];
-    __shared__ AnalyzeTail A;
+    __shared__ AnalyzeLds<BB> S;
+    __shared__ uint32_t hist[BB][256];
+    __shared__ AnalyzeTail<BB> A;
     __shared__ uint32_t zsum[kWaves][4];
     __shared__ uint32_t zspec[kWaves][4];
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
@@ -714,11 +722,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 if ((live >> (B - 1 - b)) & 1) atomicAdd(bin(B - 1 - b, (v >> (8 * b)) & 0xFFu), 1u);
         }
         __syncthreads();
-        for (uint32_t i = t; i < 4 * 256; i += kBlock) {
+        for (uint32_t i = t; i < B * 256; i += kBlock) {
             const uint32_t k = i >> 8, s = i & 255;
             uint32_t v = 0;
-            if (k < B)
-                for (uint32_t r = 0; r < R; r++) v += S.rep[k * R + r][s + r * (32 / R)];
+            for (uint32_t r = 0; r < R; r++) v += S.rep[k * R + r][s + r * (32 / R)];
             hist[k][s] = v;
         }
         __syncthreads();
@@ -776,7 +783,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             // pass over the data
             const uint32_t need = A.zc & ~A.specok;
             if (need) {
-                for (uint32_t i = t; i < kWaves * 4 * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
+                for (uint32_t i = t; i < kWaves * B * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
                 __syncthreads();
                 uint32_t zn[4] = {0, 0, 0, 0};
                 switch (p.g) {
@@ -787,10 +794,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 if (lane == 0)
                     for (uint32_t k = 0; k < B; k++) zsum[wv][k] = zn[k];
                 __syncthreads();
-                for (uint32_t i = t; i < 4 * 256; i += kBlock) {
+                for (uint32_t i = t; i < B * 256; i += kBlock) {
                     const uint32_t k = i >> 8, s = i & 255;
                     uint32_t v = S.hist[0][k][s] + S.hist[1][k][s] + S.hist[2][k][s] + S.hist[3][k][s];
-                    if (k < B && s == A.z[k]) v += zsum[0][k] + zsum[1][k] + zsum[2][k] + zsum[3][k];
+                    if (s == A.z[k]) v += zsum[0][k] + zsum[1][k] + zsum[2][k] + zsum[3][k];
                     S.hist[0][k][s] = v;
                 }
                 __syncthreads();
