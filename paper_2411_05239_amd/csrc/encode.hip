@@ -44,9 +44,9 @@ constexpr int kRep = 16;
 constexpr int kRepStride = 288;   // 256 bins + room for the shift
 
 struct PmWave {                 // package-merge workspace of one wave
-    uint32_t leafw[256];        // leaf weights, ascending (f, symbol)
+    alignas(16) uint32_t leafw[256];   // leaf weights, ascending (f, symbol)
     uint16_t leafsym[256];
-    uint32_t pk[256];           // package weights of the current level
+    alignas(16) uint32_t pk[256];      // package weights of the current level
     union {
         alignas(16) uint32_t key[256];   // the sort keys, used before the lists
         uint32_t cur[512];               // current list weights
@@ -72,9 +72,27 @@ __device__ inline uint32_t wave_sum(uint32_t v)
     return v;
 }
 
-// number of items of a sorted u32 array a[0..n) that are < x (strict) or <= x
+// number of items of a sorted u32 array a[0..n) that are < x (strict) or <= x.
+// Up to 64 items (n uniform): a scan of 16-byte LDS reads, four in flight
+// (every lane of the wave reads the same words: a broadcast), instead of a
+// chain of dependent reads; a[] must be 16-byte aligned and hold 64 items.
+template <bool LE>
+__device__ inline uint32_t count_small(const uint32_t* a, uint32_t n, uint32_t x)
+{
+    const uint4* v = reinterpret_cast<const uint4*>(a);
+    uint32_t c = 0;
+#pragma unroll 4
+    for (uint32_t q = 0; q < 16; q++) {
+        const uint4 y = v[q];
+        const uint32_t i = 4 * q;
+        c += uint32_t(i < n && (LE ? y.x <= x : y.x < x)) + uint32_t(i + 1 < n && (LE ? y.y <= x : y.y < x)) +
+             uint32_t(i + 2 < n && (LE ? y.z <= x : y.z < x)) + uint32_t(i + 3 < n && (LE ? y.w <= x : y.w < x));
+    }
+    return c;
+}
 __device__ inline uint32_t count_lt(const uint32_t* a, uint32_t n, uint32_t x)
 {
+    if (n <= 64) return count_small<false>(a, n, x);
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
@@ -85,6 +103,7 @@ __device__ inline uint32_t count_lt(const uint32_t* a, uint32_t n, uint32_t x)
 }
 __device__ inline uint32_t count_le(const uint32_t* a, uint32_t n, uint32_t x)
 {
+    if (n <= 64) return count_small<true>(a, n, x);
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
@@ -124,15 +143,22 @@ __device__ __attribute__((always_inline)) bool build_lengths(const uint32_t* fv,
         // Any prefix code spends at least the empirical entropy, sum f log2(tot/f)
         // bits.  If even that bound gives a payload no smaller than the raw
         // bytes, AUTO cannot keep this code (the decision is the one the exact
-        // size would give), and it need not be built.
-        double h = 0.0;
+        // size would give), and it need not be built.  In single precision
+        // (v_log_f32): each log2 of a count below 2^23 is within about 2^-18
+        // of the truth, so the terms err by under 10^-5 bits per symbol in
+        // all, and rounding the products and the sum errs by under 10^-6 of
+        // the sum; the margins below (10^-4 relative, 10^-4 bits per symbol)
+        // keep the bound a lower bound.  Near the boundary the code is built
+        // and sized exactly, as without the test.
+        const float lt = __log2f(float(tot));
+        float h = 0.0f;
 #pragma unroll
         for (int r = 0; r < 4; r++)
-            if (fv[r]) h += double(fv[r]) * (log2(double(tot)) - log2(double(fv[r])));
+            if (fv[r]) h += float(fv[r]) * (lt - __log2f(float(fv[r])));
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
-        const double lb = h * (1.0 - 1e-12) - 1.0;   // margin for the rounding of the sum
-        const uint64_t words_lb = lb > 0.0 ? uint64_t(ceil(lb / 32.0)) : 0u;
+        const float lb = h * (1.0f - 1e-4f) - 1e-4f * float(tot) - 1.0f;
+        const uint64_t words_lb = lb > 0.0f ? uint64_t(lb / 32.0f) : 0u;   // floor: a lower bound too
         if (uint64_t(head) + 4 * words_lb >= raw) return false;
     }
     // sort the leaves by key = f << 8 | symbol (f < 2^24 since m <= 2^22)
