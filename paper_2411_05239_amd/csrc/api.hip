@@ -55,7 +55,9 @@ int grow_pinned(zipnn_ctx ctx, size_t n)
     return ZIPNN_OK;
 }
 
-EncParams make_params(int dtype, const zipnn_params& p)
+// delta: some tensor of the launch has an XOR base (the analysis then runs
+// its instance tuned for deltas; headers take the delta flag per tensor)
+EncParams make_params(int dtype, const zipnn_params& p, bool delta)
 {
     EncParams e;
     e.dtype = uint32_t(dtype);
@@ -64,7 +66,7 @@ EncParams make_params(int dtype, const zipnn_params& p)
     e.S = p.substream_syms;
     e.g = p.group;
     e.L = p.max_code_len;
-    e.flags = p.exponent ? kFlagExp : 0u;
+    e.flags = (p.exponent ? kFlagExp : 0u) | (delta ? kFlagDelta : 0u);
     e.skip = p.probe_skip;
     for (int k = 0; k < 4; k++) e.policy[k] = uint32_t(k) < e.B ? p.policy[k] : 0;
     return e;
@@ -269,7 +271,9 @@ static int encode_tensors(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, in
     EncDesc* d_descs = (EncDesc*)(sc + lay.descs);
     uint32_t* d_prefix = (uint32_t*)(sc + lay.prefix);
     uint64_t* d_aoff = (uint64_t*)(sc + lay.aoff);
-    EncParams ep = make_params(dtype, *p);
+    bool any_base = false;
+    for (int i = 0; i < n; i++) any_base |= t[i].base != nullptr;
+    EncParams ep = make_params(dtype, *p, any_base);
     if (hipMemcpyAsync(d_descs, hd, size_t(n) * sizeof(EncDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(d_prefix, hp, size_t(n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
         launch_encode(d_descs, n, d_prefix, uint32_t(total_chunks), ep, (uint8_t*)arena, cap,
@@ -328,7 +332,7 @@ int zipnn_compress_noalloc(zipnn_ctx ctx, const void* src, int dtype, uint64_t n
     uint32_t* d_prefix = (uint32_t*)(sc + lay.prefix);
     uint64_t* d_aoff = (uint64_t*)(sc + lay.aoff);
     uint64_t ho[2] = {0, 0};   // the arena offsets come back to the stack
-    const EncParams ep = make_params(dtype, *p);
+    const EncParams ep = make_params(dtype, *p, one.base != nullptr);
     if (launch_fill_desc(one, uint32_t(nc), d_descs, d_prefix, s) != hipSuccess ||
         launch_encode(d_descs, 1, d_prefix, uint32_t(nc), ep, (uint8_t*)dst, dst_cap, (EncEntry*)(sc + lay.entries),
                       (CodeWord*)(sc + lay.codes), (uint32_t*)(sc + lay.nwords), (uint64_t*)(sc + lay.offsets),
@@ -411,7 +415,9 @@ int zipnn_encoder_create(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, int
         return ZIPNN_E_HIP;
     }
     // capture the launches and the copy of the offsets once; every run replays them
-    const EncParams ep = make_params(dtype, *p);
+    bool any_base = false;
+    for (int i = 0; i < n; i++) any_base |= t[i].base != nullptr;
+    const EncParams ep = make_params(dtype, *p, any_base);
     if (hipStreamCreateWithFlags(&e->capst, hipStreamNonBlocking) != hipSuccess ||
         hipStreamBeginCapture(e->capst, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         zipnn_encoder_destroy(e);

@@ -548,10 +548,12 @@ struct AnalyzeTail {
 // Occupancy matters more than spills here: the passes are latency-bound per
 // workgroup.  Four waves per SIMD (128 VGPRs) were 5-9% faster than three;
 // for 2-byte words five (96 VGPRs, some spills in the counting loop) encode
-// the BF16 checkpoint 5% and its XOR delta 10% faster than four (six: 1%
-// slower than five on the checkpoint, 4% faster on the delta).
-template <int BB>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 ? 5 : 4, 8))) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
+// the BF16 checkpoint 5% and its XOR delta 10% faster than four.  XB: the
+// instance for launches with an XOR base, which reads twice the bytes per
+// element: six waves (80 VGPRs) encode the delta 8% faster than five and
+// the plain checkpoint 1% slower, so plain launches keep five.
+template <int BB, bool XB>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 ? (XB ? 6 : 5) : 4, 8))) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                     EncParams p, int phase, EncEntry* __restrict__ entries,
                                                     CodeWord* __restrict__ codes, uint32_t* __restrict__ nwords)
@@ -659,7 +661,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 
             constexpr int SK = decltype(sk_const)::value;
             constexpr bool LV = decltype(lv_const)::value;
             constexpr bool SP = decltype(sp_const)::value;
-            constexpr uint32_t HB = 8;   // vectors in flight per lane
+            constexpr uint32_t HB = 4;   // vectors in flight per lane (with the base: 8 loads)
             for (uint32_t v0 = t; v0 < nvec; v0 += HB * kBlock) {
               uint4 xs[HB];
 #pragma unroll
@@ -1493,9 +1495,11 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
     if (total_chunks) {
         // with probing, the probe chunks first: the others read their entries
         for (int phase = p.skip ? 0 : -1; phase <= (p.skip ? 1 : -1); phase++) {
-            if (p.B == 1) k_analyze<1><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
-            else if (p.B == 2) k_analyze<2><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
-            else if (p.B == 4) k_analyze<4><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
+            const bool xb = (p.flags & kFlagDelta) != 0;
+            if (p.B == 1) k_analyze<1, false><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
+            else if (p.B == 2 && xb) k_analyze<2, true><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
+            else if (p.B == 2) k_analyze<2, false><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
+            else if (p.B == 4) k_analyze<4, false><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
             else return hipErrorInvalidValue;
             if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
         }

@@ -162,7 +162,8 @@ struct EncEntry {
 using CodeWord = uint32_t;
 
 struct EncParams {
-    uint32_t dtype, B, chunk, S, g, L, flags;
+    uint32_t dtype, B, chunk, S, g, L;
+    uint32_t flags;        // kFlagExp; kFlagDelta when some tensor of the launch has an XOR base
     uint32_t skip;         // probe interval K (0: every chunk analysed)
     uint8_t policy[4];
 };
