@@ -35,7 +35,7 @@ int grow_scratch(zipnn_ctx ctx, size_t need)
     if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
     ctx->d_scratch = nullptr;
     ctx->scratch_cap = 0;
-    size_t cap = need + need / 4;
+    size_t cap = need + std::min(need / 4, size_t(256) << 20);   // room to grow, at most 256 MiB
     if (hipMalloc(&ctx->d_scratch, cap) != hipSuccess) {
         ctx->d_scratch = nullptr;
         return ZIPNN_E_NOMEM;
@@ -69,7 +69,35 @@ EncParams make_params(int dtype, const zipnn_params& p, bool delta)
     e.flags = (p.exponent ? kFlagExp : 0u) | (delta ? kFlagDelta : 0u);
     e.skip = p.probe_skip;
     for (int k = 0; k < 4; k++) e.policy[k] = uint32_t(k) < e.B ? p.policy[k] : 0;
+    e.stage = nullptr;
+    e.stage_chunk = e.stage_lg = e.stage_bm = 0;
     return e;
+}
+
+// Staged packing (the analysis skips its second pass over the data; the
+// packer writes into staging slots and a compaction places the payloads) for
+// launches with an XOR base, whose containers are small next to the bytes
+// each pass reads; its slots take about L/8 of the input.  Up to this many
+// bytes; beyond, or when the slots cannot be allocated, the exact path.
+constexpr size_t kStageMax = size_t(64) << 30;
+
+static size_t stage_bytes_of(bool any_base, uint64_t total_chunks, int dtype, const zipnn_params& p)
+{
+    if (!any_base) return 0;
+    const uint32_t B = uint32_t(dtype_bytes(dtype));
+    const StageLayout sl = stage_layout(p.chunk_bytes, B, p.substream_syms, p.group, p.max_code_len);
+    const size_t bytes = size_t(total_chunks) * B * sl.chunk;
+    return bytes <= kStageMax ? bytes : 0;
+}
+
+static void set_stage(EncParams& ep, uint8_t* stage, int dtype, const zipnn_params& p)
+{
+    const StageLayout sl = stage_layout(p.chunk_bytes, uint32_t(dtype_bytes(dtype)), p.substream_syms, p.group,
+                                        p.max_code_len);
+    ep.stage = stage;
+    ep.stage_chunk = sl.chunk;
+    ep.stage_lg = sl.lg;
+    ep.stage_bm = sl.bm;
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -240,8 +268,16 @@ static int encode_tensors(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, in
     if (map_bytes > cap) return ZIPNN_E_NOSPACE;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
-    const EncScratch lay = enc_scratch_layout(size_t(total_chunks) * B, size_t(n));
+    bool any_base = false;
+    for (int i = 0; i < n; i++) any_base |= t[i].base != nullptr;
+    size_t stage = stage_bytes_of(any_base, total_chunks, dtype, *p);
+    EncScratch lay = enc_scratch_layout(size_t(total_chunks) * B, size_t(n), stage);
     int rc = grow_scratch(ctx, lay.need);
+    if (rc && stage) {   // no room for the staging slots: the exact path
+        stage = 0;
+        lay = enc_scratch_layout(size_t(total_chunks) * B, size_t(n));
+        rc = grow_scratch(ctx, lay.need);
+    }
     if (rc) return rc;
     // host staging (pinned): descriptors, chunk prefix, then the arena offsets
     const size_t stage_bytes = size_t(n) * sizeof(EncDesc) + size_t(n + 1) * sizeof(uint32_t) +
@@ -271,9 +307,8 @@ static int encode_tensors(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, in
     EncDesc* d_descs = (EncDesc*)(sc + lay.descs);
     uint32_t* d_prefix = (uint32_t*)(sc + lay.prefix);
     uint64_t* d_aoff = (uint64_t*)(sc + lay.aoff);
-    bool any_base = false;
-    for (int i = 0; i < n; i++) any_base |= t[i].base != nullptr;
     EncParams ep = make_params(dtype, *p, any_base);
+    if (stage) set_stage(ep, sc + lay.stage, dtype, *p);
     if (hipMemcpyAsync(d_descs, hd, size_t(n) * sizeof(EncDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(d_prefix, hp, size_t(n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
         launch_encode(d_descs, n, d_prefix, uint32_t(total_chunks), ep, (uint8_t*)arena, cap,
@@ -388,7 +423,10 @@ int zipnn_encoder_create(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, int
     e->ctx = ctx;
     e->n = n;
     e->cap = cap;
-    const EncScratch lay = enc_scratch_layout(size_t(total_chunks) * B, size_t(n));
+    bool any_base = false;
+    for (int i = 0; i < n; i++) any_base |= t[i].base != nullptr;
+    size_t stage = stage_bytes_of(any_base, total_chunks, dtype, *p);
+    EncScratch lay = enc_scratch_layout(size_t(total_chunks) * B, size_t(n), stage);
     std::vector<EncDesc> hd(static_cast<size_t>(n));
     std::vector<uint32_t> hp(static_cast<size_t>(n) + 1);
     uint32_t run = 0;
@@ -400,7 +438,13 @@ int zipnn_encoder_create(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, int
         run += uint32_t(nc);
     }
     hp[size_t(n)] = run;
-    if (hipMalloc(&e->d_mem, lay.need) != hipSuccess ||
+    if (hipMalloc(&e->d_mem, lay.need) != hipSuccess && stage) {   // no room for the staging slots
+        e->d_mem = nullptr;
+        stage = 0;
+        lay = enc_scratch_layout(size_t(total_chunks) * B, size_t(n));
+        if (hipMalloc(&e->d_mem, lay.need) != hipSuccess) e->d_mem = nullptr;
+    }
+    if (!e->d_mem ||
         hipHostMalloc((void**)&e->h_offs, size_t(n + 1) * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
         zipnn_encoder_destroy(e);
         return ZIPNN_E_NOMEM;
@@ -415,9 +459,8 @@ int zipnn_encoder_create(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, int
         return ZIPNN_E_HIP;
     }
     // capture the launches and the copy of the offsets once; every run replays them
-    bool any_base = false;
-    for (int i = 0; i < n; i++) any_base |= t[i].base != nullptr;
-    const EncParams ep = make_params(dtype, *p, any_base);
+    EncParams ep = make_params(dtype, *p, any_base);
+    if (stage) set_stage(ep, sc + lay.stage, dtype, *p);
     if (hipStreamCreateWithFlags(&e->capst, hipStreamNonBlocking) != hipSuccess ||
         hipStreamBeginCapture(e->capst, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         zipnn_encoder_destroy(e);

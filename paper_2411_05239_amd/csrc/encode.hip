@@ -528,6 +528,7 @@ struct AnalyzeTail {
     uint32_t T[2][4];        // coded bits of the candidates: HUF, ZG
     int pol[4];              // policy of each group in this chunk (RAW where probing skips it)
     uint32_t specok;         // bit k: the main pass's count of zeros in marked groups holds (z = 0)
+    uint32_t amb;            // staged packing: bit k, the mode decision needs exact sizes
 };
 
 // One workgroup per chunk (phase -1: every chunk; with a probe interval K,
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 
             continue;
         }
         for (uint32_t i = t; i < kRep * kRepStride; i += kBlock) (&S.rep[0][0])[i] = 0;
-        if (t == 0) A.open = A.hc = A.zc = A.zgc = A.fin = A.coded = A.specok = 0;
+        if (t == 0) A.open = A.hc = A.zc = A.zgc = A.fin = A.coded = A.specok = A.amb = 0;
         if (t < 8) (&A.words[0][0])[t] = 0;
         if (t < 4) A.pol[t] = ((live >> t) & 1) ? int(p.policy[t]) : ZIPNN_RAW;
         __syncthreads();
@@ -880,8 +881,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 
             else if (h_hi <= z_lo) atomicAnd(&A.zgc, ~(1u << t));
         }
         __syncthreads();
+        // Staged packing: the packer counts the words, so the sizes are needed
+        // here only where the bounds of the candidates (head + coded bits, plus
+        // two words of padding per sub-stream) leave AUTO's choice open.
+        const bool staged = p.stage != nullptr;
+        if (staged && uint32_t(t) < B && ((A.open >> t) & 1) && A.pol[t] == ZIPNN_AUTO) {
+            const bool hc = (A.hc >> t) & 1, zgc = (A.zgc >> t) & 1;
+            const uint64_t h_lo = head + (A.T[0][t] + 7) / 8, h_hi = h_lo + 8 * W;
+            const uint64_t z_lo = head_z + (A.T[1][t] + 7) / 8, z_hi = z_lo + 8 * W;
+            bool amb = false;
+            uint64_t best_lo = m, best_hi = m;   // RAW
+            if (hc) {
+                if (h_hi < m) best_lo = h_lo, best_hi = h_hi;
+                else if (h_lo < m) amb = true;
+            }
+            if (zgc && z_hi >= best_lo && z_lo < best_hi) amb = true;
+            if (amb) atomicOr(&A.amb, 1u << t);
+        }
+        __syncthreads();
+        const bool exact = !staged || A.amb != 0;
         // 4. the words of every candidate, one lane group per wave
-        if (A.hc | A.zgc) {
+        if ((A.hc | A.zgc) && exact) {
             for (uint32_t j0 = 0; j0 < NG; j0 += kWaves) {
                 const uint32_t j = j0 + wv;
                 if (j < NG) {
@@ -900,11 +920,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 
             }
         }
         __syncthreads();
-        // 5. the decision, the entry and the word counts of every open group
+        // 5. the decision, the entry and the word counts of every open group.
+        // Without exact sizes (staged, no open choice) the lower bounds decide
+        // as the sizes would, and the entry's bytes are left to the packer's
+        // counts.
         if (uint32_t(t) < B && ((A.open >> t) & 1)) {
             const int policy = A.pol[t];
             const bool hc = (A.hc >> t) & 1, zgc = (A.zgc >> t) & 1;
-            const uint32_t size_h = head + 4 * A.words[0][t], size_z = head_z + 4 * A.words[1][t];
+            const uint32_t size_h = exact ? head + 4 * A.words[0][t] : head + (A.T[0][t] + 7) / 8;
+            const uint32_t size_z = exact ? head_z + 4 * A.words[1][t] : head_z + (A.T[1][t] + 7) / 8;
             int mode = kModeRaw;
             uint32_t bytes = m;
             if (policy == ZIPNN_AUTO) {
@@ -919,7 +943,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 
             e.pad = 0;
             e.mode = uint8_t(mode);
             e.rle = mode == kModeZg ? uint8_t(A.z[t]) : 0;
-            e.bytes = bytes;
+            e.bytes = (staged && mode != kModeRaw) ? 0u : bytes;
             entries[uint64_t(gc) * B + t] = e;
             if (mode != kModeRaw) atomicOr(&A.coded, 1u << t);
             if (mode == kModeZg) atomicOr(&A.fin, 1u << t);
@@ -929,7 +953,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 
             const uint64_t ei = uint64_t(gc) * B + wv;
             const int v = (A.fin >> wv) & 1;
             canonical_codes(v ? A.lens2[wv] : A.lens[wv], p.L, codes + ei * 256);
-            if (uint32_t(lane) < NG) nwords[ei * 64 + lane] = S.lgw[v][wv][lane];
+            if (!staged && uint32_t(lane) < NG) nwords[ei * 64 + lane] = S.lgw[v][wv][lane];
         }
         __syncthreads();
     }
@@ -938,8 +962,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 
 // One workgroup per tensor: offsets of its entries (128-byte aligned, in
 // chunk-major order) and the tensor's container size.
 __global__ __launch_bounds__(kBlock) void k_place(EncDesc* __restrict__ descs, EncParams p,
-                                                  const EncEntry* __restrict__ entries, uint64_t* __restrict__ offsets,
-                                                  uint64_t* __restrict__ totals)
+                                                  EncEntry* __restrict__ entries, uint64_t* __restrict__ offsets,
+                                                  uint64_t* __restrict__ totals, const uint32_t* __restrict__ nwords)
 {
     __shared__ uint64_t red[kWaves];
     __shared__ uint64_t carry;
@@ -953,8 +977,22 @@ __global__ __launch_bounds__(kBlock) void k_place(EncDesc* __restrict__ descs, E
     __syncthreads();
     for (uint64_t b0 = 0; b0 < ne; b0 += kBlock) {
         const uint64_t e = b0 + t;
-        const uint64_t sz = e < ne ? align_pay(entries[e_first + e].bytes) : 0;
-        if (e < ne && entries[e_first + e].mode == kModeZg) zg = 1;
+        uint64_t sz = 0;
+        if (e < ne) {
+            EncEntry en = entries[e_first + e];
+            if (p.stage && (en.mode == kModeHuf || en.mode == kModeZg)) {
+                // staged: the payload's size from the packer's word counts
+                const uint32_t E = p.chunk / B;
+                const uint32_t m = uint32_t(min(uint64_t(E), d.n - uint64_t(e / B) * E));
+                const uint32_t W = (m + p.S - 1) / p.S, NG = (W + 63) / 64;
+                uint32_t words = 0;
+                for (uint32_t j = 0; j < NG; j++) words += nwords[(e_first + e) * 64 + j];
+                en.bytes = huf_head(W) + (en.mode == kModeZg ? zg_bitmap(m, p.g) : 0u) + 4 * words;
+                entries[e_first + e].bytes = en.bytes;
+            }
+            sz = align_pay(en.bytes);
+            if (en.mode == kModeZg) zg = 1;
+        }
         uint64_t inc = sz;
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
@@ -1088,11 +1126,16 @@ constexpr uint32_t kNoStore = 0x80000000u;      // buffer offset past every reso
 // so a place past them (which the analysis's counts never give) is dropped.
 // Steps in which every lane has a full group run without per-lane group
 // counts; the raw byte groups of small groups are copied on the same pass.
+// Staged (stage_lg > 0): stream k's payload area is the staging slot at
+// P.pay[k], lane group j's words start at stage_bm + j * stage_lg, a ZG
+// bitmap at the slot's start; the lane group's word count goes to
+// nw_out[k * 64 + j].
 template <int B, int G>
 __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* src, const uint8_t* base, uint32_t cm,
                                                                uint32_t zm, const PackLds& P, uint32_t L, uint32_t j,
                                                                uint32_t W, uint32_t m, bool xf, bool fuse_bitmap,
-                                                               uint32_t rawmask, uint8_t* dst)
+                                                               uint32_t rawmask, uint8_t* dst, uint32_t stage_lg,
+                                                               uint32_t stage_bm, uint32_t* nw_out)
 {
     constexpr int NB = B * G;
     constexpr int NW = NB >= 4 ? NB / 4 : 1;
@@ -1136,12 +1179,14 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
         Stream& x = S(kc);
         const uint32_t zb = (zm >> k) & 1;
         const uint64_t pk = uni64(P.pay[k]);
-        const uint32_t w0 = __builtin_amdgcn_readfirstlane(P.wpre[k][j]);
-        const uint32_t nw = __builtin_amdgcn_readfirstlane(P.wpre[k][j + 1]) - w0;
-        const uint64_t wa = uni64(uint64_t(dst + pk + head + (zb ? bm : 0u)) + 4ull * w0);
+        const bool staged = stage_lg != 0;
+        const uint32_t w0 = staged ? j * (stage_lg / 4) : __builtin_amdgcn_readfirstlane(P.wpre[k][j]);
+        const uint32_t nw = staged ? stage_lg / 4 : __builtin_amdgcn_readfirstlane(P.wpre[k][j + 1]) - w0;
+        const uint32_t lead = staged ? stage_bm : head + (zb ? bm : 0u);   // bytes before the words
+        const uint64_t wa = uni64(uint64_t(dst + pk + lead) + 4ull * w0);
         x.out = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(wa), (short)0,
                                                   int(((cm >> k) & 1) ? 4 * nw : 0u), 0x00020000);
-        x.bmw = (zb && fuse_bitmap) ? reinterpret_cast<uint64_t*>(dst + pk + head) : nullptr;
+        x.bmw = (zb && fuse_bitmap) ? reinterpret_cast<uint64_t*>(dst + pk + (staged ? 0u : head)) : nullptr;
         x.cur = x.alo = x.ahi = x.nacc = x.s0 = x.s1 = 0;
         x.held = 0;
     });
@@ -1273,6 +1318,8 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
         const int pend = (x.held + int(x.nacc)) >> 5;
         __builtin_amdgcn_raw_buffer_store_b32(x.alo, x.out, pend > 0 ? x.s0 : kNoStore, 0, 0);
         __builtin_amdgcn_raw_buffer_store_b32(0u, x.out, pend > 1 ? x.s1 : kNoStore, 0, 0);
+        // staged: the words this lane group took (the cursor is uniform)
+        if (nw_out && lane == 0) nw_out[k * 64 + j] = x.cur;
     });
 }
 
@@ -1370,15 +1417,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                                                  const CodeWord* __restrict__ codes,
                                                  const uint64_t* __restrict__ offsets,
                                                  const uint64_t* __restrict__ totals,
-                                                 const uint32_t* __restrict__ nwords)
+                                                 uint32_t* __restrict__ nwords)
 {
     __shared__ PackLds P;
     const int t = threadIdx.x, wv = t >> 6;
     constexpr uint32_t B = BB;
+    // staged: the payloads go to the staging slots (their places in the
+    // container are not known yet) and the word counts come out
+    const bool staged = p.stage != nullptr;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
         const int di = find_desc(chunk_prefix, n_desc, gc);
         const EncDesc d = descs[di];
-        if (totals[di] > d.dst_cap) continue;   // too small: the host reports it
+        if (!staged && totals[di] > d.dst_cap) continue;   // too small: the host reports it
         const uint32_t c = gc - chunk_prefix[di];
         const uint32_t E = p.chunk / B;
         const uint64_t e0 = uint64_t(c) * E;
@@ -1390,7 +1440,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         for (uint32_t k = 0; k < B; k++) {
             const uint64_t ei = uint64_t(gc) * B + k;
             const EncEntry en = entries[ei];
-            if (t == 0) {
+            if (t == 0 && staged) {
+                P.mode[k] = en.mode;
+                P.bytes[k] = en.bytes;
+                P.pay[k] = ei * p.stage_chunk;
+            } else if (t == 0) {
                 P.mode[k] = en.mode;
                 P.bytes[k] = en.bytes;
                 P.pay[k] = payload_base + offsets[ei];
@@ -1407,7 +1461,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 const uint32_t cw = codes[ei * 256 + t];
                 const uint32_t l = cw >> 16;
                 P.rcode[k][t] = l ? ((__brev(cw & 0xFFFFu) >> (32 - l)) | (l << kLenShift)) : 0u;
-                if (t < 64) {
+                if (t < 64 && !staged) {
                     const uint32_t nw = uint32_t(t) < NG ? nwords[ei * 64 + t] : 0u;
                     uint32_t inc = nw;
 #pragma unroll
@@ -1423,7 +1477,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         __syncthreads();
         const uint8_t* src = d.src + e0 * B;
         const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
-        uint8_t* dst = d.dst;
+        uint8_t* dst = staged ? p.stage : d.dst;
         const bool xf = (p.flags & kFlagExp) != 0;
         // the coded groups (HUF and ZG) are packed in one pass, which also
         // copies the raw groups when groups are small (at most 4 bytes)
@@ -1442,28 +1496,113 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             const bool zg = P.mode[k] == kModeZg;
             if (P.mode[k] != kModeHuf && !zg) continue;
             uint8_t* pay = dst + P.pay[k];
-            // head: nibble table, word counts, zero pad; ZG bitmap; zero pad after words
-            if (t < 128)
-                pay[t] = uint8_t((P.rcode[k][2 * t] >> kLenShift) | ((P.rcode[k][2 * t + 1] >> kLenShift) << 4));
-            if (uint32_t(t) < NG) ((uint32_t*)(pay + 128))[t] = P.wpre[k][t + 1] - P.wpre[k][t];
-            for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
-            for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
+            // head: nibble table, word counts, zero pad; ZG bitmap; zero pad
+            // after words (staged: the compaction writes all but the bitmap)
+            if (!staged) {
+                if (t < 128)
+                    pay[t] = uint8_t((P.rcode[k][2 * t] >> kLenShift) | ((P.rcode[k][2 * t + 1] >> kLenShift) << 4));
+                if (uint32_t(t) < NG) ((uint32_t*)(pay + 128))[t] = P.wpre[k][t + 1] - P.wpre[k][t];
+                for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
+                for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
+            }
+            const uint32_t lead = staged ? 0u : head;   // where the bitmap starts
             if (zg) {
                 const uint32_t bm = zg_bitmap(m, GG);
                 if (fuse_bitmap) {   // only the words past the last group are zeroed here
-                    uint64_t* words = reinterpret_cast<uint64_t*>(pay + head);
+                    uint64_t* words = reinterpret_cast<uint64_t*>(pay + lead);
                     const uint32_t Gtot = (m + GG - 1) / GG;
                     for (uint32_t x = (Gtot + 63) / 64 + t; x < bm / 8; x += kBlock) words[x] = 0;
                 } else {
-                    pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + head, xf);
+                    pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + lead, xf);
                 }
             }
         }
         if (cm)
             for (uint32_t j = wv; j < NG; j += kWaves)
                 pack_lane_group<BB, GG>(src, base, cm, zm, P, p.L, j, W, m, xf, fuse_bitmap, fuse_raw ? rawmask : 0u,
-                                        dst);
+                                        dst, staged ? p.stage_lg : 0u, p.stage_bm,
+                                        staged ? nwords + uint64_t(gc) * B * 64 : nullptr);
         __syncthreads();
+    }
+}
+
+// Staged packing, last step: for each chunk, its map entries, and for each
+// coded stream the head (nibble table, word counts, padding), the ZG bitmap
+// and the lane groups' words copied from their staging slots to their places;
+// raw streams are copied whole; then the zero padding to the payload
+// alignment.  Tensors whose container did not fit the arena are skipped.
+template <int BB, int GG>
+__global__ __launch_bounds__(kBlock) void k_compact(const EncDesc* __restrict__ descs, int n_desc,
+                                                    const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
+                                                    EncParams p, const EncEntry* __restrict__ entries,
+                                                    const CodeWord* __restrict__ codes,
+                                                    const uint64_t* __restrict__ offsets,
+                                                    const uint64_t* __restrict__ totals,
+                                                    const uint32_t* __restrict__ nwords)
+{
+    __shared__ uint32_t wpre[65];
+    const int t = threadIdx.x;
+    constexpr uint32_t B = BB;
+    for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
+        const int di = find_desc(chunk_prefix, n_desc, gc);
+        const EncDesc d = descs[di];
+        if (totals[di] > d.dst_cap) continue;   // too small: the host reports it
+        const uint32_t c = gc - chunk_prefix[di];
+        const uint32_t E = p.chunk / B;
+        const uint32_t m = uint32_t(min(uint64_t(E), d.n - uint64_t(c) * E));
+        const uint32_t W = (m + p.S - 1) / p.S;
+        const uint32_t NG = (W + 63) / 64;
+        const uint32_t head = huf_head(W);
+        const uint64_t payload_base = payload_base_of(d.n_chunks, B);
+        for (uint32_t k = 0; k < B; k++) {
+            const uint64_t ei = uint64_t(gc) * B + k;
+            const EncEntry en = entries[ei];
+            if (t == 0) {
+                uint4 ent;
+                ent.x = uint32_t(offsets[ei]);
+                ent.y = uint32_t(offsets[ei] >> 32);
+                ent.z = en.bytes;
+                ent.w = uint32_t(en.mode) | (uint32_t(en.rle) << 8);
+                *(uint4*)(d.dst + 64 + 16 * (uint64_t(c) * B + k)) = ent;
+            }
+            uint8_t* pay = d.dst + payload_base + offsets[ei];
+            const uint8_t* slot = p.stage + ei * p.stage_chunk;
+            if (en.mode == kModeRaw) {
+                // 16-byte pieces (both ends are 16-byte aligned), then the tail
+                for (uint32_t i = t; i < m / 16; i += kBlock)
+                    reinterpret_cast<uint4*>(pay)[i] = reinterpret_cast<const uint4*>(slot)[i];
+                for (uint32_t i = m / 16 * 16 + t; i < m; i += kBlock) pay[i] = slot[i];
+            } else if (en.mode == kModeHuf || en.mode == kModeZg) {
+                const bool zg = en.mode == kModeZg;
+                const uint32_t bm = zg ? zg_bitmap(m, GG) : 0u;
+                if (t < 128)
+                    pay[t] = uint8_t((codes[ei * 256 + 2 * t] >> 16) | ((codes[ei * 256 + 2 * t + 1] >> 16) << 4));
+                if (t < 64) {
+                    const uint32_t nw = uint32_t(t) < NG ? nwords[ei * 64 + t] : 0u;
+                    if (uint32_t(t) < NG) reinterpret_cast<uint32_t*>(pay + 128)[t] = nw;
+                    uint32_t inc = nw;
+#pragma unroll
+                    for (int dd = 1; dd < 64; dd <<= 1) {
+                        uint32_t o = __shfl_up(inc, dd, 64);
+                        if (t >= dd) inc += o;
+                    }
+                    wpre[t + 1] = inc;
+                    if (t == 0) wpre[0] = 0;
+                }
+                for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
+                for (uint32_t i = t; i < bm / 16; i += kBlock)
+                    reinterpret_cast<uint4*>(pay + head)[i] = reinterpret_cast<const uint4*>(slot)[i];
+                __syncthreads();
+                uint32_t* words = reinterpret_cast<uint32_t*>(pay + head + bm);
+                for (uint32_t j = 0; j < NG; j++) {
+                    const uint32_t* from = reinterpret_cast<const uint32_t*>(slot + p.stage_bm + uint64_t(j) * p.stage_lg);
+                    const uint32_t w0 = wpre[j], nw = wpre[j + 1] - w0;
+                    for (uint32_t i = t; i < nw; i += kBlock) words[w0 + i] = from[i];
+                }
+            }
+            for (uint32_t i = en.bytes + t; i < uint32_t(align_pay(en.bytes)); i += kBlock) pay[i] = 0;
+            __syncthreads();
+        }
     }
 }
 
@@ -1504,26 +1643,39 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
             if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
         }
     }
-    k_place<<<n_desc, kBlock, 0, s>>>(d_descs, p, entries, offsets, totals);
-    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-    k_arena<<<1, kBlock, 0, s>>>(d_descs, n_desc, p, arena, cap, totals, arena_off);
-    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-    if (total_chunks) {
+    // exact: placement, arena, then packing into the containers; staged:
+    // packing into the staging slots, placement from its word counts, arena,
+    // then the compaction into the containers
+    auto pack_or_compact = [&](bool compact) -> hipError_t {
+        if (!total_chunks) return hipSuccess;
         bool launched = false;
-#define ZIPNN_PACK(B_, G_)                                                                                       \
-    if (!launched && p.B == B_ && p.g == G_) {                                                                  \
-        k_pack<B_, G_><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, \
-                                               offsets, totals, nwords);                                        \
-        launched = true;                                                                                        \
+#define ZIPNN_PACK(B_, G_)                                                                                          \
+    if (!launched && p.B == B_ && p.g == G_) {                                                                     \
+        if (compact)                                                                                               \
+            k_compact<B_, G_><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries,  \
+                                                      codes, offsets, totals, nwords);                            \
+        else                                                                                                       \
+            k_pack<B_, G_><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, entries, codes, \
+                                                   offsets, totals, nwords);                                      \
+        launched = true;                                                                                           \
     }
         ZIPNN_PACK(1, 2) ZIPNN_PACK(1, 4) ZIPNN_PACK(1, 8)
         ZIPNN_PACK(2, 2) ZIPNN_PACK(2, 4) ZIPNN_PACK(2, 8)
         ZIPNN_PACK(4, 2) ZIPNN_PACK(4, 4) ZIPNN_PACK(4, 8)
 #undef ZIPNN_PACK
         if (!launched) return hipErrorInvalidValue;
-        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+        return hipGetLastError() == hipSuccess ? hipSuccess : hipErrorLaunchFailure;
+    };
+    const bool staged = p.stage != nullptr;
+    if (staged) {
+        const hipError_t e = pack_or_compact(false);
+        if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    k_place<<<n_desc, kBlock, 0, s>>>(d_descs, p, entries, offsets, totals, nwords);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    k_arena<<<1, kBlock, 0, s>>>(d_descs, n_desc, p, arena, cap, totals, arena_off);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    return pack_or_compact(staged);
 }
 
 }  // namespace zipnn

@@ -166,7 +166,33 @@ struct EncParams {
     uint32_t flags;        // kFlagExp; kFlagDelta when some tensor of the launch has an XOR base
     uint32_t skip;         // probe interval K (0: every chunk analysed)
     uint8_t policy[4];
+    // Staged packing (nullptr: the exact-size path): every (chunk, stream)
+    // owns stage_chunk bytes of `stage` at (global chunk * B + k) *
+    // stage_chunk: a ZG bitmap or raw bytes from its start, and lane group j's
+    // words at stage_bm + j * stage_lg (StageLayout).
+    uint8_t* stage;
+    uint32_t stage_chunk, stage_lg, stage_bm;
 };
+
+// Staging slots of one launch: a lane of S symbols holds at most S * L code
+// bits and takes at most ceil((S L + 2L + 31) / 32) words (the refill rule),
+// so a lane group needs at most 64 times that; a chunk of E = chunk / B
+// elements has at most ceil(ceil(E / S) / 64) lane groups, and its raw bytes
+// (E) fit in that room since L >= 8.
+struct StageLayout {
+    uint32_t lg, bm, chunk;
+};
+__host__ __device__ inline StageLayout stage_layout(uint32_t chunk, uint32_t B, uint32_t S, uint32_t g, uint32_t L)
+{
+    const uint32_t E = chunk / B;
+    const uint32_t W = (E + S - 1) / S, NG = (W + kLanes - 1) / kLanes;
+    StageLayout st;
+    st.lg = uint32_t(align16(uint64_t(kLanes) * 4u * ((S * L + 2u * L + 31u) / 32u + 1u)));
+    st.bm = zg_bitmap(E, g);
+    const uint64_t c = uint64_t(st.bm) + uint64_t(NG) * st.lg;
+    st.chunk = uint32_t(((c > E ? c : uint64_t(E)) + 255u) & ~uint64_t(255));
+    return st;
+}
 
 // Work items of a decode descriptor: one item per (chunk, slice of kBlock
 // sub-streams) over the chunks [c_begin, min(c_end, n_chunks)); the
@@ -247,9 +273,10 @@ hipError_t launch_fill_desc(const EncDesc& one, uint32_t total_chunks, EncDesc* 
 // Offsets of the encoder's device scratch for ne = chunks * B entries of n
 // tensors (every array 256-byte aligned); `need` is the total.
 struct EncScratch {
-    size_t entries, codes, offsets, nwords, totals, aoff, descs, prefix, need;
+    size_t entries, codes, offsets, nwords, totals, aoff, descs, prefix, stage, need;
 };
-inline EncScratch enc_scratch_layout(size_t ne, size_t n)
+// stage_bytes: the staging slots of a staged launch (0: none)
+inline EncScratch enc_scratch_layout(size_t ne, size_t n, size_t stage_bytes = 0)
 {
     auto a256 = [](size_t v) { return (v + 255) & ~size_t(255); };
     EncScratch L;
@@ -261,7 +288,8 @@ inline EncScratch enc_scratch_layout(size_t ne, size_t n)
     L.aoff = a256(L.totals + n * sizeof(uint64_t));
     L.descs = a256(L.aoff + (n + 1) * sizeof(uint64_t));
     L.prefix = a256(L.descs + n * sizeof(EncDesc));
-    L.need = L.prefix + (n + 1) * sizeof(uint32_t) + 256;
+    L.stage = a256(L.prefix + (n + 1) * sizeof(uint32_t));
+    L.need = L.stage + stage_bytes + 256;
     return L;
 }
 
