@@ -1143,6 +1143,9 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
     constexpr uint32_t kPf = B == 4 ? 2 : 4;
     cm = __builtin_amdgcn_readfirstlane(cm);
     zm = __builtin_amdgcn_readfirstlane(zm);
+    // the lane group is the wave's: uniform, so every value derived from it
+    // (a buffer resource above all) stays in scalar registers
+    j = __builtin_amdgcn_readfirstlane(j);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = 64 * j + lane;
     const int twoL = int(2 * L);
