@@ -549,12 +549,15 @@ struct AnalyzeTail {
 // Occupancy matters more than spills here: the passes are latency-bound per
 // workgroup.  Four waves per SIMD (128 VGPRs) were 5-9% faster than three;
 // for 2-byte words five (96 VGPRs, some spills in the counting loop) encode
-// the BF16 checkpoint 5% and its XOR delta 10% faster than four.  XB: the
-// instance for launches with an XOR base, which reads twice the bytes per
-// element: six waves (80 VGPRs) encode the delta 8% faster than five and
-// the plain checkpoint 1% slower, so plain launches keep five.
-template <int BB, bool XB>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 ? (XB ? 6 : 5) : 4, 8))) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
+// the BF16 checkpoint 5% and its XOR delta 10% faster than four.  WV sets
+// the waves per SIMD of the instances for 2-byte words.  Launches with an
+// XOR base read twice the bytes per element: six waves (80 VGPRs) encode the
+// Huffman-only delta 8% faster than five (the plain checkpoint would lose
+// 1%); where a group may take ZG, two codes are built per group, and seven
+// waves (72 VGPRs) encode the delta 5% faster than six (the Huffman-only
+// delta would lose 2%).
+template <int BB, int WV>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WV, 8))) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                     EncParams p, int phase, EncEntry* __restrict__ entries,
                                                     CodeWord* __restrict__ codes, uint32_t* __restrict__ nwords)
@@ -1639,14 +1642,21 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
 {
     const uint32_t grid = min(max(total_chunks, 1u), 1u << 16);
     const bool xb = (p.flags & kFlagDelta) != 0;   // some tensor has an XOR base
+    bool zg_possible = false;                       // some group may take ZG
+    for (uint32_t k = 0; k < p.B && k < 4; k++) zg_possible |= p.policy[k] == ZIPNN_AUTO || p.policy[k] == ZIPNN_ZG;
     if (total_chunks) {
         // with probing, the probe chunks first: the others read their entries
         for (int phase = p.skip ? 0 : -1; phase <= (p.skip ? 1 : -1); phase++) {
-            if (p.B == 1) k_analyze<1, false><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
-            else if (p.B == 2 && xb) k_analyze<2, true><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
-            else if (p.B == 2) k_analyze<2, false><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
-            else if (p.B == 4) k_analyze<4, false><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, codes, nwords);
+#define ZIPNN_ANALYZE(B_, WV_)                                                                                   \
+    k_analyze<B_, WV_><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, \
+                                               codes, nwords)
+            if (p.B == 1) ZIPNN_ANALYZE(1, 4);
+            else if (p.B == 2 && xb && zg_possible) ZIPNN_ANALYZE(2, 7);
+            else if (p.B == 2 && xb) ZIPNN_ANALYZE(2, 6);
+            else if (p.B == 2) ZIPNN_ANALYZE(2, 5);
+            else if (p.B == 4) ZIPNN_ANALYZE(4, 4);
             else return hipErrorInvalidValue;
+#undef ZIPNN_ANALYZE
             if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
         }
     }
