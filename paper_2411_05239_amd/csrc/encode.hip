@@ -1275,13 +1275,13 @@ __device__ __attribute__((always_inline)) void pack_lane_group(const uint8_t* sr
             };
             if ((zm >> k) & 1) {
                 const bool mk = has && marked<B, G>(wd, k, ecnt, P.z[k]);
-                if (fuse_bitmap) {
-                    // ZG with W a multiple of 64: the 64 bits of this lane
-                    // group's step e are one aligned word of the bitmap
-                    const uint64_t bits = __ballot(mk);
-                    if (lane == 0) S(kc).bmw[j + e * (W / 64)] = bits;
-                }
-                pairs(mk ? ecnt : 0u);
+                const uint64_t bits = __ballot(mk);
+                // ZG with W a multiple of 64: the 64 bits of this lane
+                // group's step e are one aligned word of the bitmap
+                if (fuse_bitmap && lane == 0) S(kc).bmw[j + e * (W / 64)] = bits;
+                // where no lane of the wave holds a marked group, the pairs
+                // would take no word and add no bits: they are skipped
+                if (bits) pairs(mk ? ecnt : 0u);
             } else {
                 pairs(ecnt);   // in a fast step, G: no per-lane conditions
             }
