@@ -36,7 +36,7 @@ int grow_scratch(zipnn_ctx ctx, size_t need)
     ctx->d_scratch = nullptr;
     ctx->scratch_cap = 0;
     size_t cap = need + std::min(need / 4, size_t(256) << 20);   // room to grow, at most 256 MiB
-    if (hipMalloc(&ctx->d_scratch, cap) != hipSuccess) {
+    if (dev_malloc((void**)&ctx->d_scratch, cap) != hipSuccess) {
         ctx->d_scratch = nullptr;
         return ZIPNN_E_NOMEM;
     }
@@ -50,7 +50,7 @@ int grow_pinned(zipnn_ctx ctx, size_t n)
     if (ctx->h_total) (void)hipHostFree(ctx->h_total);
     ctx->h_total = nullptr;
     ctx->h_total_cap = 0;
-    if (hipHostMalloc((void**)&ctx->h_total, n * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) return ZIPNN_E_NOMEM;
+    if (host_malloc((void**)&ctx->h_total, n * sizeof(uint64_t)) != hipSuccess) return ZIPNN_E_NOMEM;
     ctx->h_total_cap = n;
     return ZIPNN_OK;
 }
@@ -156,8 +156,8 @@ int zipnn_ctx_create(int hip_device, zipnn_ctx* out)
     if (!ctx) return ZIPNN_E_NOMEM;
     ctx->device = hip_device;
     DeviceGuard g(hip_device);
-    if (hipMalloc((void**)&ctx->d_status, sizeof(int)) != hipSuccess ||
-        hipHostMalloc((void**)&ctx->h_status, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+    if (dev_malloc((void**)&ctx->d_status, sizeof(int)) != hipSuccess ||
+        host_malloc((void**)&ctx->h_status, sizeof(int)) != hipSuccess ||
         grow_pinned(ctx, 64) != ZIPNN_OK) {
         zipnn_ctx_destroy(ctx);
         return ZIPNN_E_NOMEM;
@@ -438,14 +438,14 @@ int zipnn_encoder_create(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* t, int
         run += uint32_t(nc);
     }
     hp[size_t(n)] = run;
-    if (hipMalloc(&e->d_mem, lay.need) != hipSuccess && stage) {   // no room for the staging slots
+    if (dev_malloc((void**)&e->d_mem, lay.need) != hipSuccess && stage) {   // no room for the staging slots
         e->d_mem = nullptr;
         stage = 0;
         lay = enc_scratch_layout(size_t(total_chunks) * B, size_t(n));
-        if (hipMalloc(&e->d_mem, lay.need) != hipSuccess) e->d_mem = nullptr;
+        if (dev_malloc((void**)&e->d_mem, lay.need) != hipSuccess) e->d_mem = nullptr;
     }
     if (!e->d_mem ||
-        hipHostMalloc((void**)&e->h_offs, size_t(n + 1) * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+        host_malloc((void**)&e->h_offs, size_t(n + 1) * sizeof(uint64_t)) != hipSuccess) {
         zipnn_encoder_destroy(e);
         return ZIPNN_E_NOMEM;
     }
@@ -644,7 +644,7 @@ int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets
     b->ctx = ctx;
     size_t bytes = 0;
     for (auto& kv : groups) bytes += align256(kv.second.size() * sizeof(DecDesc)) + align256((kv.second.size() + 1) * 8);
-    if (bytes && hipMalloc(&b->d_mem, bytes) != hipSuccess) {
+    if (bytes && dev_malloc((void**)&b->d_mem, bytes) != hipSuccess) {
         delete b;
         return ZIPNN_E_NOMEM;
     }
@@ -795,8 +795,8 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
     }
     void* arena = nullptr;
     void* outs = nullptr;
-    if (hipMalloc(&arena, cap) != hipSuccess) return ZIPNN_E_NOMEM;
-    if (hipMalloc(&outs, align256(sbytes) + 256 * smp.size()) != hipSuccess) {
+    if (dev_malloc((void**)&arena, cap) != hipSuccess) return ZIPNN_E_NOMEM;
+    if (dev_malloc((void**)&outs, align256(sbytes) + 256 * smp.size()) != hipSuccess) {
         (void)hipFree(arena);
         return ZIPNN_E_NOMEM;
     }

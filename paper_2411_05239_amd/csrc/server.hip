@@ -186,8 +186,8 @@ bool grow_iter(Iter& it, size_t need)
     if (need <= it.cap) return true;
     size_t cap = std::max<size_t>(need, 64 << 10);
     uint8_t *h = nullptr, *d = nullptr;
-    if (hipHostMalloc((void**)&h, cap, hipHostMallocDefault) != hipSuccess) return false;
-    if (hipMalloc((void**)&d, cap) != hipSuccess) {
+    if (host_malloc((void**)&h, cap) != hipSuccess) return false;
+    if (dev_malloc((void**)&d, cap) != hipSuccess) {
         (void)hipHostFree(h);
         return false;
     }
@@ -417,7 +417,7 @@ int zipnn_server_create(zipnn_ctx ctx, const zipnn_server_config* cfg, zipnn_ser
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
     int rc = ZIPNN_OK;
-    if (hipMalloc((void**)&s->pool, s->cfg.pool_bytes) != hipSuccess) rc = ZIPNN_E_NOMEM;
+    if (dev_malloc((void**)&s->pool, s->cfg.pool_bytes) != hipSuccess) rc = ZIPNN_E_NOMEM;
     if (rc == ZIPNN_OK && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) rc = ZIPNN_E_HIP;
     for (int i = 0; rc == ZIPNN_OK && i < kIterDepth; i++) {
         if (hipEventCreateWithFlags(&s->it[i].ev, hipEventDisableTiming) != hipSuccess) rc = ZIPNN_E_HIP;

@@ -29,6 +29,28 @@ constexpr int kBlock = 256;                 // threads per workgroup (4 waves)
 
 __host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15u) & ~uint64_t(15); }
 
+// Allocations that clear the thread's last HIP error when they fail: the
+// caller reports the failure, and a later kernel launch checked with
+// hipGetLastError must not read it as its own.
+inline hipError_t dev_malloc(void** p, size_t n)
+{
+    const hipError_t e = hipMalloc(p, n);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+    }
+    return e;
+}
+inline hipError_t host_malloc(void** p, size_t n)
+{
+    const hipError_t e = hipHostMalloc(p, n, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+    }
+    return e;
+}
+
 // Payloads start at multiples of kPayAlign bytes from the container start (and
 // containers at such offsets in a batch arena), so that two streams never
 // share a 128-byte memory line.
