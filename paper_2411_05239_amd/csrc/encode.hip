@@ -556,410 +556,433 @@ struct AnalyzeTail {
 // 1%); where a group may take ZG, two codes are built per group, and seven
 // waves (72 VGPRs) encode the delta 5% faster than six (the Huffman-only
 // delta would lose 2%).
+// Shared memory of the analysis of one chunk.
+template <int BB>
+struct AnalyzeShared {
+    AnalyzeLds<BB> S;
+    uint32_t hist[BB][256];
+    AnalyzeTail<BB> A;
+    uint32_t zsum[kWaves][4];
+    uint32_t zspec[kWaves][4];
+};
+
+// The analysis of chunk gc by one workgroup (steps 1-5 above).  Returns
+// false when the probing phase leaves the chunk to the other launch.
+template <int BB>
+__device__ __attribute__((always_inline)) bool analyze_chunk(uint32_t gc, const EncDesc* __restrict__ descs,
+                                                             int n_desc, const uint32_t* __restrict__ chunk_prefix,
+                                                             const EncParams& p, int phase,
+                                                             EncEntry* __restrict__ entries, CodeWord* __restrict__ codes,
+                                                             uint32_t* __restrict__ nwords, AnalyzeShared<BB>& sh)
+{
+    AnalyzeLds<BB>& S = sh.S;
+    auto& hist = sh.hist;
+    AnalyzeTail<BB>& A = sh.A;
+    auto& zsum = sh.zsum;
+    auto& zspec = sh.zspec;
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    constexpr uint32_t B = BB;
+    const int di = find_desc(chunk_prefix, n_desc, gc);
+    const EncDesc d = descs[di];
+    const uint32_t c = gc - chunk_prefix[di];
+    const uint32_t run = p.skip + 1;
+    const bool probe = c % run == 0;
+    if ((phase == 0 && !probe) || (phase == 1 && probe)) return false;
+    // the groups this chunk analyses (uniform: every thread reads the same entries)
+    uint32_t live = (1u << B) - 1;
+    if (!probe)
+        for (uint32_t k = 0; k < B; k++)
+            if (p.policy[k] == ZIPNN_AUTO && entries[uint64_t(gc - c % run) * B + k].mode == kModeRaw)
+                live &= ~(1u << k);
+    const uint32_t E = p.chunk / B;
+    const uint64_t e0 = uint64_t(c) * E;
+    const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
+    const uint32_t W = (m + p.S - 1) / p.S;
+    const uint32_t NG = (W + 63) / 64;
+    const uint32_t head = huf_head(W), head_z = head + zg_bitmap(m, p.g);
+    if (live == 0) {
+        if (uint32_t(t) < B) {
+            EncEntry e;
+            e.pad = 0;
+            e.mode = kModeRaw;
+            e.rle = 0;
+            e.bytes = m;
+            entries[uint64_t(gc) * B + t] = e;
+        }
+        return true;
+    }
+    for (uint32_t i = t; i < kRep * kRepStride; i += kBlock) (&S.rep[0][0])[i] = 0;
+    if (t == 0) A.open = A.hc = A.zc = A.zgc = A.fin = A.coded = A.specok = A.amb = 0;
+    if (t < 8) (&A.words[0][0])[t] = 0;
+    if (t < 4) A.pol[t] = ((live >> t) & 1) ? int(p.policy[t]) : ZIPNN_RAW;
+    __syncthreads();
+    const uint8_t* src = d.src + e0 * B;
+    const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
+    const uint32_t nbytes = m * B;
+    const bool xf = (p.flags & kFlagExp) != 0;
+    // this lane's copy of every byte group's histogram
+    constexpr uint32_t R = kRep / B;
+    const uint32_t rc = uint32_t(lane) / (64 / R);
+    const uint32_t rshift = rc * (32 / R);
+    auto bin = [&](uint32_t k, uint32_t v) { return &S.rep[k * R + rc][v + rshift]; };
+    // 16-byte vectors; the element boundary is aligned since 16 % B == 0
+    const uint32_t nvec = nbytes / 16;
+    // a stream whose bytes agree across an eighth of the wave's lanes in
+    // the first vector is taken as skewed: there, the lanes holding the
+    // first active lane's value add together, since LDS atomics on one
+    // bin serialise (the rule only changes how the counts are summed)
+    uint32_t skew = 0;
+    if (uint32_t(t) < nvec) {
+        uint4 x = ((const uint4*)src)[t];
+        if (base) {
+            const uint4 y = ((const uint4*)base)[t];
+            x.x ^= y.x;
+        }
+        if (xf) x.x = exp_fwd<B>(x.x);
+        for (uint32_t k = 0; k < B; k++) {
+            const uint32_t byte = (x.x >> (8 * (B - 1 - k))) & 0xFFu;
+            const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
+            if (__popcll(__ballot(byte == hot)) >= 8) skew |= 1u << k;
+        }
+    }
+    skew = __builtin_amdgcn_readfirstlane(skew);
+    // Delta-like groups (zero bytes in at least half of the first 64
+    // vectors; the same vectors in every wave, so the choice is uniform)
+    // also count, in this pass, the zero bytes that lie in groups of g
+    // holding a nonzero byte.  Every nonzero byte lies in such a group, so
+    // if 0 turns out to be the most frequent value, the ZG histogram is
+    // this pass's histogram with that count in place of the count of 0,
+    // and the ZG pass over the data is not needed.
+    uint32_t spec = 0;
+    if (nbytes % 16 == 0 && p.g * B <= 16) {
+        uint32_t x0 = 0;
+        if (uint32_t(lane) < nvec) {
+            x0 = ((const uint32_t*)src)[4 * lane];
+            if (base) x0 ^= ((const uint32_t*)base)[4 * lane];
+            if (xf) x0 = exp_fwd<B>(x0);
+        }
+        for (uint32_t k = 0; k < B; k++) {
+            const uint32_t byte = (x0 >> (8 * (B - 1 - k))) & 0xFFu;
+            const bool zg_policy = A.pol[k] == ZIPNN_AUTO || A.pol[k] == ZIPNN_ZG;
+            if (zg_policy && __popcll(__ballot(uint32_t(lane) < nvec && byte == 0)) >= 32) spec |= 1u << k;
+        }
+    }
+    spec = __builtin_amdgcn_readfirstlane(spec);
+    uint32_t zin[4] = {0, 0, 0, 0};   // zero bytes in marked groups, per group of bytes
+    const uint32_t G = p.g;
+    // SK: the skewed streams, known here (or -1: tested per byte)
+    // LV: every group is live (no per-byte test)
+    // SP: count the zeros in marked groups of the streams in `spec`
+    auto count = [&](auto sk_const, auto lv_const, auto sp_const) {
+        constexpr int SK = decltype(sk_const)::value;
+        constexpr bool LV = decltype(lv_const)::value;
+        constexpr bool SP = decltype(sp_const)::value;
+        constexpr uint32_t HB = 4;   // vectors in flight per lane (with the base: 8 loads)
+        for (uint32_t v0 = t; v0 < nvec; v0 += HB * kBlock) {
+          uint4 xs[HB];
+#pragma unroll
+          for (uint32_t i = 0; i < HB; i++) {
+              const uint32_t v = v0 + i * kBlock;
+              if (v < nvec) {
+                  xs[i] = ((const uint4*)src)[v];
+                  if (base) {
+                      const uint4 y = ((const uint4*)base)[v];
+                      xs[i].x ^= y.x;
+                      xs[i].y ^= y.y;
+                      xs[i].z ^= y.z;
+                      xs[i].w ^= y.w;
+                  }
+                  if (xf) {
+                      xs[i].x = exp_fwd<B>(xs[i].x);
+                      xs[i].y = exp_fwd<B>(xs[i].y);
+                      xs[i].z = exp_fwd<B>(xs[i].z);
+                      xs[i].w = exp_fwd<B>(xs[i].w);
+                  }
+              }
+          }
+#pragma unroll
+          for (uint32_t i = 0; i < HB; i++) {
+            if (v0 + i * kBlock < nvec) {
+            const uint32_t wds[4] = {xs[i].x, xs[i].y, xs[i].z, xs[i].w};
+#pragma unroll
+            for (int jb = 0; jb < 16; jb++) {
+                const uint32_t byte = (wds[jb >> 2] >> (8 * (jb & 3))) & 0xFF;
+                const int k = int(B) - 1 - (jb % int(B));   // byte jb%B of a word -> stream B-1-jb%B
+                if (!LV && !((live >> k) & 1)) continue;
+                const bool sk = SK >= 0 ? ((SK >> k) & 1) != 0 : ((skew >> k) & 1) != 0;
+                if (sk) {
+                    const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
+                    const uint64_t msk = __ballot(byte == hot);
+                    if (byte != hot) atomicAdd(bin(k, byte), 1u);
+                    else if (__builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo(uint32_t(msk), 0u)) == 0)
+                        atomicAdd(bin(k, hot), uint32_t(__popcll(msk)));
+                } else {
+                    atomicAdd(bin(k, byte), 1u);
+                }
+            }
+            if constexpr (SP) {
+#pragma unroll
+                for (int k = 0; k < int(B); k++) {
+                    if (!((spec >> k) & 1)) continue;
+                    uint32_t nz = 0;   // bit e: element e's byte of group k is nonzero
+#pragma unroll
+                    for (int e = 0; e < 16 / int(B); e++) {
+                        const int jb = e * int(B) + (int(B) - 1 - k);
+                        nz |= uint32_t(((wds[jb >> 2] >> (8 * (jb & 3))) & 0xFFu) != 0) << e;
+                    }
+                    uint32_t mk = 0;   // bit e: element e's group of g holds a nonzero byte
+                    for (uint32_t g0 = 0; g0 < 16 / B; g0 += G) {
+                        const uint32_t gm = ((1u << G) - 1) << g0;
+                        if (nz & gm) mk |= gm;
+                    }
+                    zin[k] += __popc(mk & ~nz);
+                }
+            }
+            }
+          }
+        }
+    };
+    {
+        using std::integral_constant;
+        using T = integral_constant<bool, true>;
+        using F = integral_constant<bool, false>;
+        if (live != (1u << B) - 1) count(integral_constant<int, -1>{}, F{}, F{});
+        else if (spec) count(integral_constant<int, -1>{}, T{}, T{});
+        else if (skew == 0) count(integral_constant<int, 0>{}, T{}, F{});
+        else if (skew == 1) count(integral_constant<int, 1>{}, T{}, F{});
+        else if (B >= 2 && skew == 3) count(integral_constant<int, B >= 2 ? 3 : -1>{}, T{}, F{});
+        else count(integral_constant<int, -1>{}, T{}, F{});
+    }
+    if (spec)
+        for (uint32_t k = 0; k < B; k++) {
+            const uint32_t zs = wave_sum(zin[k]);
+            if (lane == 0) zspec[wv][k] = zs;
+        }
+    // the elements after the last whole vector
+    for (uint32_t e = nvec * 16 / B + t; e < m; e += kBlock) {
+        const uint32_t v = element_word<B>(src, base, e, xf);
+        for (uint32_t b = 0; b < B; b++)
+            if ((live >> (B - 1 - b)) & 1) atomicAdd(bin(B - 1 - b, (v >> (8 * b)) & 0xFFu), 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < B * 256; i += kBlock) {
+        const uint32_t k = i >> 8, s = i & 255;
+        uint32_t v = 0;
+        for (uint32_t r = 0; r < R; r++) v += S.rep[k * R + r][s + r * (32 / R)];
+        hist[k][s] = v;
+    }
+    __syncthreads();
+    // 2. classification and HUF lengths, wave k for group k
+    if (uint32_t(wv) < B) {
+        const int k = wv;
+        const int policy = A.pol[k];
+        uint32_t fv[4], d = 0, best = 0, arg = 0;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            fv[r] = hist[k][lane + 64 * r];
+            d += __popcll(__ballot(fv[r] > 0));
+            // most frequent value, smallest on ties: key f << 8 | (255 - s)
+            const uint32_t key = (fv[r] << 8) | uint32_t(255 - (lane + 64 * r));
+            if (key > best) best = key;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) best = max(best, uint32_t(__shfl_xor(best, o, 64)));
+        arg = 255 - (best & 0xFFu);
+        const uint64_t ei = uint64_t(gc) * B + k;
+        if (policy == ZIPNN_RAW || d <= 1) {
+            if (lane == 0) {
+                EncEntry e;
+                e.pad = 0;
+                const bool rle = policy != ZIPNN_RAW && d == 1;
+                e.mode = rle ? kModeRle : kModeRaw;
+                e.rle = rle ? uint8_t(arg) : 0;
+                e.bytes = rle ? 0 : m;
+                entries[ei] = e;
+            }
+        } else {
+            bool hc = false;
+            if (policy != ZIPNN_ZG) {
+                uint32_t T;
+                hc = build_lengths(fv, m, m, head, p.L, policy == ZIPNN_AUTO, S.pm[k], T);
+                if (lane == 0) A.T[0][k] = T;
+                if (hc)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) A.lens[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
+            }
+            const bool zc = policy == ZIPNN_ZG || (policy == ZIPNN_AUTO && 2 * (best >> 8) >= m);
+            if (lane == 0) {
+                atomicOr(&A.open, 1u << k);
+                if (hc) atomicOr(&A.hc, 1u << k);
+                if (zc) atomicOr(&A.zc, 1u << k);
+                if (zc && ((spec >> k) & 1) && arg == 0) atomicOr(&A.specok, 1u << k);
+                A.z[k] = arg;
+            }
+        }
+    }
+    __syncthreads();
+    // 3. ZG: histogram over the marked groups, then lengths
+    if (A.zc) {
+        // groups whose ZG histogram the main pass could not give: one more
+        // pass over the data
+        const uint32_t need = A.zc & ~A.specok;
+        if (need) {
+            for (uint32_t i = t; i < kWaves * B * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
+            __syncthreads();
+            uint32_t zn[4] = {0, 0, 0, 0};
+            switch (p.g) {
+            case 2: zg_count<BB, 2>(src, base, need, A.z, m, S.hist[wv], zn, xf); break;
+            case 4: zg_count<BB, 4>(src, base, need, A.z, m, S.hist[wv], zn, xf); break;
+            default: zg_count<BB, 8>(src, base, need, A.z, m, S.hist[wv], zn, xf); break;
+            }
+            if (lane == 0)
+                for (uint32_t k = 0; k < B; k++) zsum[wv][k] = zn[k];
+            __syncthreads();
+            for (uint32_t i = t; i < B * 256; i += kBlock) {
+                const uint32_t k = i >> 8, s = i & 255;
+                uint32_t v = S.hist[0][k][s] + S.hist[1][k][s] + S.hist[2][k][s] + S.hist[3][k][s];
+                if (s == A.z[k]) v += zsum[0][k] + zsum[1][k] + zsum[2][k] + zsum[3][k];
+                S.hist[0][k][s] = v;
+            }
+            __syncthreads();
+        }
+        uint32_t fv[4] = {0, 0, 0, 0}, tot = 0, d2 = 0;
+        if (uint32_t(wv) < B) {
+            const bool fromspec = (A.specok >> wv) & 1;
+            const uint32_t z0 = zspec[0][wv] + zspec[1][wv] + zspec[2][wv] + zspec[3][wv];
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const uint32_t sym = lane + 64 * r;
+                fv[r] = fromspec ? (sym == 0 ? z0 : hist[wv][sym]) : S.hist[0][wv][sym];
+                tot += fv[r];
+                d2 += __popcll(__ballot(fv[r] > 0));
+            }
+            tot = wave_sum(tot);
+        }
+        __syncthreads();   // the sums are read before the workspace is reused
+        if (uint32_t(wv) < B && ((A.zc >> wv) & 1)) {
+            const int k = wv;
+            const int policy = A.pol[k];
+            if (d2 >= 2) {
+                uint32_t T;
+                const bool zgc = build_lengths(fv, tot, m, head_z, p.L, policy == ZIPNN_AUTO, S.pm[k], T);
+                if (lane == 0) A.T[1][k] = T;
+                if (zgc) {
+#pragma unroll
+                    for (int r = 0; r < 4; r++) A.lens2[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
+                    if (lane == 0) atomicOr(&A.zgc, 1u << k);
+                }
+            } else if (policy == ZIPNN_ZG) {
+                // the marked groups hold a single value: forced ZG falls back to HUF
+                uint32_t f[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) f[r] = hist[k][lane + 64 * r];
+                uint32_t T;
+                build_lengths(f, m, m, head, p.L, false, S.pm[k], T);
+#pragma unroll
+                for (int r = 0; r < 4; r++) A.lens[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
+                if (lane == 0) atomicOr(&A.hc, 1u << k);
+            }
+        }
+        __syncthreads();
+    }
+    // AUTO with both candidates: a candidate that loses even at its best
+    // (head + coded bits) against the other at its worst (plus two words
+    // of padding per sub-stream) needs no replay; ties go to HUF
+    if (uint32_t(t) < B && A.pol[t] == ZIPNN_AUTO && ((A.hc & A.zgc) >> t & 1)) {
+        const uint64_t h_lo = head + (A.T[0][t] + 7) / 8, h_hi = h_lo + 8 * W;
+        const uint64_t z_lo = head_z + (A.T[1][t] + 7) / 8, z_hi = z_lo + 8 * W;
+        if (z_hi < h_lo) atomicAnd(&A.hc, ~(1u << t));
+        else if (h_hi <= z_lo) atomicAnd(&A.zgc, ~(1u << t));
+    }
+    __syncthreads();
+    // Staged packing: the packer counts the words, so the sizes are needed
+    // here only where the bounds of the candidates (head + coded bits, plus
+    // two words of padding per sub-stream) leave AUTO's choice open.
+    const bool staged = p.stage != nullptr;
+    if (staged && uint32_t(t) < B && ((A.open >> t) & 1) && A.pol[t] == ZIPNN_AUTO) {
+        const bool hc = (A.hc >> t) & 1, zgc = (A.zgc >> t) & 1;
+        const uint64_t h_lo = head + (A.T[0][t] + 7) / 8, h_hi = h_lo + 8 * W;
+        const uint64_t z_lo = head_z + (A.T[1][t] + 7) / 8, z_hi = z_lo + 8 * W;
+        bool amb = false;
+        uint64_t best_lo = m, best_hi = m;   // RAW
+        if (hc) {
+            if (h_hi < m) best_lo = h_lo, best_hi = h_hi;
+            else if (h_lo < m) amb = true;
+        }
+        if (zgc && z_hi >= best_lo && z_lo < best_hi) amb = true;
+        if (amb) atomicOr(&A.amb, 1u << t);
+    }
+    __syncthreads();
+    const bool exact = !staged || A.amb != 0;
+    // 4. the words of every candidate, one lane group per wave
+    if ((A.hc | A.zgc) && exact) {
+        for (uint32_t j0 = 0; j0 < NG; j0 += kWaves) {
+            const uint32_t j = j0 + wv;
+            if (j < NG) {
+                switch (p.g) {
+                case 2: count_lane_group<BB, 2>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw, xf); break;
+                case 4: count_lane_group<BB, 4>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw, xf); break;
+                default: count_lane_group<BB, 8>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw, xf); break;
+                }
+                if (lane == 0) {
+                    for (uint32_t k = 0; k < B; k++) {
+                        if ((A.hc >> k) & 1) atomicAdd(&A.words[0][k], S.lgw[0][k][j]);
+                        if ((A.zgc >> k) & 1) atomicAdd(&A.words[1][k], S.lgw[1][k][j]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // 5. the decision, the entry and the word counts of every open group.
+    // Without exact sizes (staged, no open choice) the lower bounds decide
+    // as the sizes would, and the entry's bytes are left to the packer's
+    // counts.
+    if (uint32_t(t) < B && ((A.open >> t) & 1)) {
+        const int policy = A.pol[t];
+        const bool hc = (A.hc >> t) & 1, zgc = (A.zgc >> t) & 1;
+        const uint32_t size_h = exact ? head + 4 * A.words[0][t] : head + (A.T[0][t] + 7) / 8;
+        const uint32_t size_z = exact ? head_z + 4 * A.words[1][t] : head_z + (A.T[1][t] + 7) / 8;
+        int mode = kModeRaw;
+        uint32_t bytes = m;
+        if (policy == ZIPNN_AUTO) {
+            if (hc && size_h < bytes) mode = kModeHuf, bytes = size_h;
+            if (zgc && size_z < bytes) mode = kModeZg, bytes = size_z;
+        } else if (zgc) {
+            mode = kModeZg, bytes = size_z;
+        } else {
+            mode = kModeHuf, bytes = size_h;
+        }
+        EncEntry e;
+        e.pad = 0;
+        e.mode = uint8_t(mode);
+        e.rle = mode == kModeZg ? uint8_t(A.z[t]) : 0;
+        e.bytes = (staged && mode != kModeRaw) ? 0u : bytes;
+        entries[uint64_t(gc) * B + t] = e;
+        if (mode != kModeRaw) atomicOr(&A.coded, 1u << t);
+        if (mode == kModeZg) atomicOr(&A.fin, 1u << t);
+    }
+    __syncthreads();
+    if (uint32_t(wv) < B && ((A.coded >> wv) & 1)) {
+        const uint64_t ei = uint64_t(gc) * B + wv;
+        const int v = (A.fin >> wv) & 1;
+        canonical_codes(v ? A.lens2[wv] : A.lens[wv], p.L, codes + ei * 256);
+        if (!staged && uint32_t(lane) < NG) nwords[ei * 64 + lane] = S.lgw[v][wv][lane];
+    }
+    __syncthreads();
+    return true;
+}
+
 template <int BB, int WV>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WV, 8))) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
                                                     EncParams p, int phase, EncEntry* __restrict__ entries,
                                                     CodeWord* __restrict__ codes, uint32_t* __restrict__ nwords)
 {
-    __shared__ AnalyzeLds<BB> S;
-    __shared__ uint32_t hist[BB][256];
-    __shared__ AnalyzeTail<BB> A;
-    __shared__ uint32_t zsum[kWaves][4];
-    __shared__ uint32_t zspec[kWaves][4];
-    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
-    constexpr uint32_t B = BB;
-    for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
-        const int di = find_desc(chunk_prefix, n_desc, gc);
-        const EncDesc d = descs[di];
-        const uint32_t c = gc - chunk_prefix[di];
-        const uint32_t run = p.skip + 1;
-        const bool probe = c % run == 0;
-        if ((phase == 0 && !probe) || (phase == 1 && probe)) continue;
-        // the groups this chunk analyses (uniform: every thread reads the same entries)
-        uint32_t live = (1u << B) - 1;
-        if (!probe)
-            for (uint32_t k = 0; k < B; k++)
-                if (p.policy[k] == ZIPNN_AUTO && entries[uint64_t(gc - c % run) * B + k].mode == kModeRaw)
-                    live &= ~(1u << k);
-        const uint32_t E = p.chunk / B;
-        const uint64_t e0 = uint64_t(c) * E;
-        const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
-        const uint32_t W = (m + p.S - 1) / p.S;
-        const uint32_t NG = (W + 63) / 64;
-        const uint32_t head = huf_head(W), head_z = head + zg_bitmap(m, p.g);
-        if (live == 0) {
-            if (uint32_t(t) < B) {
-                EncEntry e;
-                e.pad = 0;
-                e.mode = kModeRaw;
-                e.rle = 0;
-                e.bytes = m;
-                entries[uint64_t(gc) * B + t] = e;
-            }
-            continue;
-        }
-        for (uint32_t i = t; i < kRep * kRepStride; i += kBlock) (&S.rep[0][0])[i] = 0;
-        if (t == 0) A.open = A.hc = A.zc = A.zgc = A.fin = A.coded = A.specok = A.amb = 0;
-        if (t < 8) (&A.words[0][0])[t] = 0;
-        if (t < 4) A.pol[t] = ((live >> t) & 1) ? int(p.policy[t]) : ZIPNN_RAW;
-        __syncthreads();
-        const uint8_t* src = d.src + e0 * B;
-        const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
-        const uint32_t nbytes = m * B;
-        const bool xf = (p.flags & kFlagExp) != 0;
-        // this lane's copy of every byte group's histogram
-        constexpr uint32_t R = kRep / B;
-        const uint32_t rc = uint32_t(lane) / (64 / R);
-        const uint32_t rshift = rc * (32 / R);
-        auto bin = [&](uint32_t k, uint32_t v) { return &S.rep[k * R + rc][v + rshift]; };
-        // 16-byte vectors; the element boundary is aligned since 16 % B == 0
-        const uint32_t nvec = nbytes / 16;
-        // a stream whose bytes agree across an eighth of the wave's lanes in
-        // the first vector is taken as skewed: there, the lanes holding the
-        // first active lane's value add together, since LDS atomics on one
-        // bin serialise (the rule only changes how the counts are summed)
-        uint32_t skew = 0;
-        if (uint32_t(t) < nvec) {
-            uint4 x = ((const uint4*)src)[t];
-            if (base) {
-                const uint4 y = ((const uint4*)base)[t];
-                x.x ^= y.x;
-            }
-            if (xf) x.x = exp_fwd<B>(x.x);
-            for (uint32_t k = 0; k < B; k++) {
-                const uint32_t byte = (x.x >> (8 * (B - 1 - k))) & 0xFFu;
-                const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
-                if (__popcll(__ballot(byte == hot)) >= 8) skew |= 1u << k;
-            }
-        }
-        skew = __builtin_amdgcn_readfirstlane(skew);
-        // Delta-like groups (zero bytes in at least half of the first 64
-        // vectors; the same vectors in every wave, so the choice is uniform)
-        // also count, in this pass, the zero bytes that lie in groups of g
-        // holding a nonzero byte.  Every nonzero byte lies in such a group, so
-        // if 0 turns out to be the most frequent value, the ZG histogram is
-        // this pass's histogram with that count in place of the count of 0,
-        // and the ZG pass over the data is not needed.
-        uint32_t spec = 0;
-        if (nbytes % 16 == 0 && p.g * B <= 16) {
-            uint32_t x0 = 0;
-            if (uint32_t(lane) < nvec) {
-                x0 = ((const uint32_t*)src)[4 * lane];
-                if (base) x0 ^= ((const uint32_t*)base)[4 * lane];
-                if (xf) x0 = exp_fwd<B>(x0);
-            }
-            for (uint32_t k = 0; k < B; k++) {
-                const uint32_t byte = (x0 >> (8 * (B - 1 - k))) & 0xFFu;
-                const bool zg_policy = A.pol[k] == ZIPNN_AUTO || A.pol[k] == ZIPNN_ZG;
-                if (zg_policy && __popcll(__ballot(uint32_t(lane) < nvec && byte == 0)) >= 32) spec |= 1u << k;
-            }
-        }
-        spec = __builtin_amdgcn_readfirstlane(spec);
-        uint32_t zin[4] = {0, 0, 0, 0};   // zero bytes in marked groups, per group of bytes
-        const uint32_t G = p.g;
-        // SK: the skewed streams, known here (or -1: tested per byte)
-        // LV: every group is live (no per-byte test)
-        // SP: count the zeros in marked groups of the streams in `spec`
-        auto count = [&](auto sk_const, auto lv_const, auto sp_const) {
-            constexpr int SK = decltype(sk_const)::value;
-            constexpr bool LV = decltype(lv_const)::value;
-            constexpr bool SP = decltype(sp_const)::value;
-            constexpr uint32_t HB = 4;   // vectors in flight per lane (with the base: 8 loads)
-            for (uint32_t v0 = t; v0 < nvec; v0 += HB * kBlock) {
-              uint4 xs[HB];
-#pragma unroll
-              for (uint32_t i = 0; i < HB; i++) {
-                  const uint32_t v = v0 + i * kBlock;
-                  if (v < nvec) {
-                      xs[i] = ((const uint4*)src)[v];
-                      if (base) {
-                          const uint4 y = ((const uint4*)base)[v];
-                          xs[i].x ^= y.x;
-                          xs[i].y ^= y.y;
-                          xs[i].z ^= y.z;
-                          xs[i].w ^= y.w;
-                      }
-                      if (xf) {
-                          xs[i].x = exp_fwd<B>(xs[i].x);
-                          xs[i].y = exp_fwd<B>(xs[i].y);
-                          xs[i].z = exp_fwd<B>(xs[i].z);
-                          xs[i].w = exp_fwd<B>(xs[i].w);
-                      }
-                  }
-              }
-#pragma unroll
-              for (uint32_t i = 0; i < HB; i++) {
-                if (v0 + i * kBlock < nvec) {
-                const uint32_t wds[4] = {xs[i].x, xs[i].y, xs[i].z, xs[i].w};
-#pragma unroll
-                for (int jb = 0; jb < 16; jb++) {
-                    const uint32_t byte = (wds[jb >> 2] >> (8 * (jb & 3))) & 0xFF;
-                    const int k = int(B) - 1 - (jb % int(B));   // byte jb%B of a word -> stream B-1-jb%B
-                    if (!LV && !((live >> k) & 1)) continue;
-                    const bool sk = SK >= 0 ? ((SK >> k) & 1) != 0 : ((skew >> k) & 1) != 0;
-                    if (sk) {
-                        const uint32_t hot = __builtin_amdgcn_readfirstlane(byte);
-                        const uint64_t msk = __ballot(byte == hot);
-                        if (byte != hot) atomicAdd(bin(k, byte), 1u);
-                        else if (__builtin_amdgcn_mbcnt_hi(uint32_t(msk >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo(uint32_t(msk), 0u)) == 0)
-                            atomicAdd(bin(k, hot), uint32_t(__popcll(msk)));
-                    } else {
-                        atomicAdd(bin(k, byte), 1u);
-                    }
-                }
-                if constexpr (SP) {
-#pragma unroll
-                    for (int k = 0; k < int(B); k++) {
-                        if (!((spec >> k) & 1)) continue;
-                        uint32_t nz = 0;   // bit e: element e's byte of group k is nonzero
-#pragma unroll
-                        for (int e = 0; e < 16 / int(B); e++) {
-                            const int jb = e * int(B) + (int(B) - 1 - k);
-                            nz |= uint32_t(((wds[jb >> 2] >> (8 * (jb & 3))) & 0xFFu) != 0) << e;
-                        }
-                        uint32_t mk = 0;   // bit e: element e's group of g holds a nonzero byte
-                        for (uint32_t g0 = 0; g0 < 16 / B; g0 += G) {
-                            const uint32_t gm = ((1u << G) - 1) << g0;
-                            if (nz & gm) mk |= gm;
-                        }
-                        zin[k] += __popc(mk & ~nz);
-                    }
-                }
-                }
-              }
-            }
-        };
-        {
-            using std::integral_constant;
-            using T = integral_constant<bool, true>;
-            using F = integral_constant<bool, false>;
-            if (live != (1u << B) - 1) count(integral_constant<int, -1>{}, F{}, F{});
-            else if (spec) count(integral_constant<int, -1>{}, T{}, T{});
-            else if (skew == 0) count(integral_constant<int, 0>{}, T{}, F{});
-            else if (skew == 1) count(integral_constant<int, 1>{}, T{}, F{});
-            else if (B >= 2 && skew == 3) count(integral_constant<int, B >= 2 ? 3 : -1>{}, T{}, F{});
-            else count(integral_constant<int, -1>{}, T{}, F{});
-        }
-        if (spec)
-            for (uint32_t k = 0; k < B; k++) {
-                const uint32_t zs = wave_sum(zin[k]);
-                if (lane == 0) zspec[wv][k] = zs;
-            }
-        // the elements after the last whole vector
-        for (uint32_t e = nvec * 16 / B + t; e < m; e += kBlock) {
-            const uint32_t v = element_word<B>(src, base, e, xf);
-            for (uint32_t b = 0; b < B; b++)
-                if ((live >> (B - 1 - b)) & 1) atomicAdd(bin(B - 1 - b, (v >> (8 * b)) & 0xFFu), 1u);
-        }
-        __syncthreads();
-        for (uint32_t i = t; i < B * 256; i += kBlock) {
-            const uint32_t k = i >> 8, s = i & 255;
-            uint32_t v = 0;
-            for (uint32_t r = 0; r < R; r++) v += S.rep[k * R + r][s + r * (32 / R)];
-            hist[k][s] = v;
-        }
-        __syncthreads();
-        // 2. classification and HUF lengths, wave k for group k
-        if (uint32_t(wv) < B) {
-            const int k = wv;
-            const int policy = A.pol[k];
-            uint32_t fv[4], d = 0, best = 0, arg = 0;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                fv[r] = hist[k][lane + 64 * r];
-                d += __popcll(__ballot(fv[r] > 0));
-                // most frequent value, smallest on ties: key f << 8 | (255 - s)
-                const uint32_t key = (fv[r] << 8) | uint32_t(255 - (lane + 64 * r));
-                if (key > best) best = key;
-            }
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) best = max(best, uint32_t(__shfl_xor(best, o, 64)));
-            arg = 255 - (best & 0xFFu);
-            const uint64_t ei = uint64_t(gc) * B + k;
-            if (policy == ZIPNN_RAW || d <= 1) {
-                if (lane == 0) {
-                    EncEntry e;
-                    e.pad = 0;
-                    const bool rle = policy != ZIPNN_RAW && d == 1;
-                    e.mode = rle ? kModeRle : kModeRaw;
-                    e.rle = rle ? uint8_t(arg) : 0;
-                    e.bytes = rle ? 0 : m;
-                    entries[ei] = e;
-                }
-            } else {
-                bool hc = false;
-                if (policy != ZIPNN_ZG) {
-                    uint32_t T;
-                    hc = build_lengths(fv, m, m, head, p.L, policy == ZIPNN_AUTO, S.pm[k], T);
-                    if (lane == 0) A.T[0][k] = T;
-                    if (hc)
-#pragma unroll
-                        for (int r = 0; r < 4; r++) A.lens[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
-                }
-                const bool zc = policy == ZIPNN_ZG || (policy == ZIPNN_AUTO && 2 * (best >> 8) >= m);
-                if (lane == 0) {
-                    atomicOr(&A.open, 1u << k);
-                    if (hc) atomicOr(&A.hc, 1u << k);
-                    if (zc) atomicOr(&A.zc, 1u << k);
-                    if (zc && ((spec >> k) & 1) && arg == 0) atomicOr(&A.specok, 1u << k);
-                    A.z[k] = arg;
-                }
-            }
-        }
-        __syncthreads();
-        // 3. ZG: histogram over the marked groups, then lengths
-        if (A.zc) {
-            // groups whose ZG histogram the main pass could not give: one more
-            // pass over the data
-            const uint32_t need = A.zc & ~A.specok;
-            if (need) {
-                for (uint32_t i = t; i < kWaves * B * 256; i += kBlock) (&S.hist[0][0][0])[i] = 0;
-                __syncthreads();
-                uint32_t zn[4] = {0, 0, 0, 0};
-                switch (p.g) {
-                case 2: zg_count<BB, 2>(src, base, need, A.z, m, S.hist[wv], zn, xf); break;
-                case 4: zg_count<BB, 4>(src, base, need, A.z, m, S.hist[wv], zn, xf); break;
-                default: zg_count<BB, 8>(src, base, need, A.z, m, S.hist[wv], zn, xf); break;
-                }
-                if (lane == 0)
-                    for (uint32_t k = 0; k < B; k++) zsum[wv][k] = zn[k];
-                __syncthreads();
-                for (uint32_t i = t; i < B * 256; i += kBlock) {
-                    const uint32_t k = i >> 8, s = i & 255;
-                    uint32_t v = S.hist[0][k][s] + S.hist[1][k][s] + S.hist[2][k][s] + S.hist[3][k][s];
-                    if (s == A.z[k]) v += zsum[0][k] + zsum[1][k] + zsum[2][k] + zsum[3][k];
-                    S.hist[0][k][s] = v;
-                }
-                __syncthreads();
-            }
-            uint32_t fv[4] = {0, 0, 0, 0}, tot = 0, d2 = 0;
-            if (uint32_t(wv) < B) {
-                const bool fromspec = (A.specok >> wv) & 1;
-                const uint32_t z0 = zspec[0][wv] + zspec[1][wv] + zspec[2][wv] + zspec[3][wv];
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const uint32_t sym = lane + 64 * r;
-                    fv[r] = fromspec ? (sym == 0 ? z0 : hist[wv][sym]) : S.hist[0][wv][sym];
-                    tot += fv[r];
-                    d2 += __popcll(__ballot(fv[r] > 0));
-                }
-                tot = wave_sum(tot);
-            }
-            __syncthreads();   // the sums are read before the workspace is reused
-            if (uint32_t(wv) < B && ((A.zc >> wv) & 1)) {
-                const int k = wv;
-                const int policy = A.pol[k];
-                if (d2 >= 2) {
-                    uint32_t T;
-                    const bool zgc = build_lengths(fv, tot, m, head_z, p.L, policy == ZIPNN_AUTO, S.pm[k], T);
-                    if (lane == 0) A.T[1][k] = T;
-                    if (zgc) {
-#pragma unroll
-                        for (int r = 0; r < 4; r++) A.lens2[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
-                        if (lane == 0) atomicOr(&A.zgc, 1u << k);
-                    }
-                } else if (policy == ZIPNN_ZG) {
-                    // the marked groups hold a single value: forced ZG falls back to HUF
-                    uint32_t f[4];
-#pragma unroll
-                    for (int r = 0; r < 4; r++) f[r] = hist[k][lane + 64 * r];
-                    uint32_t T;
-                    build_lengths(f, m, m, head, p.L, false, S.pm[k], T);
-#pragma unroll
-                    for (int r = 0; r < 4; r++) A.lens[k][lane + 64 * r] = S.pm[k].len[lane + 64 * r];
-                    if (lane == 0) atomicOr(&A.hc, 1u << k);
-                }
-            }
-            __syncthreads();
-        }
-        // AUTO with both candidates: a candidate that loses even at its best
-        // (head + coded bits) against the other at its worst (plus two words
-        // of padding per sub-stream) needs no replay; ties go to HUF
-        if (uint32_t(t) < B && A.pol[t] == ZIPNN_AUTO && ((A.hc & A.zgc) >> t & 1)) {
-            const uint64_t h_lo = head + (A.T[0][t] + 7) / 8, h_hi = h_lo + 8 * W;
-            const uint64_t z_lo = head_z + (A.T[1][t] + 7) / 8, z_hi = z_lo + 8 * W;
-            if (z_hi < h_lo) atomicAnd(&A.hc, ~(1u << t));
-            else if (h_hi <= z_lo) atomicAnd(&A.zgc, ~(1u << t));
-        }
-        __syncthreads();
-        // Staged packing: the packer counts the words, so the sizes are needed
-        // here only where the bounds of the candidates (head + coded bits, plus
-        // two words of padding per sub-stream) leave AUTO's choice open.
-        const bool staged = p.stage != nullptr;
-        if (staged && uint32_t(t) < B && ((A.open >> t) & 1) && A.pol[t] == ZIPNN_AUTO) {
-            const bool hc = (A.hc >> t) & 1, zgc = (A.zgc >> t) & 1;
-            const uint64_t h_lo = head + (A.T[0][t] + 7) / 8, h_hi = h_lo + 8 * W;
-            const uint64_t z_lo = head_z + (A.T[1][t] + 7) / 8, z_hi = z_lo + 8 * W;
-            bool amb = false;
-            uint64_t best_lo = m, best_hi = m;   // RAW
-            if (hc) {
-                if (h_hi < m) best_lo = h_lo, best_hi = h_hi;
-                else if (h_lo < m) amb = true;
-            }
-            if (zgc && z_hi >= best_lo && z_lo < best_hi) amb = true;
-            if (amb) atomicOr(&A.amb, 1u << t);
-        }
-        __syncthreads();
-        const bool exact = !staged || A.amb != 0;
-        // 4. the words of every candidate, one lane group per wave
-        if ((A.hc | A.zgc) && exact) {
-            for (uint32_t j0 = 0; j0 < NG; j0 += kWaves) {
-                const uint32_t j = j0 + wv;
-                if (j < NG) {
-                    switch (p.g) {
-                    case 2: count_lane_group<BB, 2>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw, xf); break;
-                    case 4: count_lane_group<BB, 4>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw, xf); break;
-                    default: count_lane_group<BB, 8>(src, base, A.hc, A.zgc, A.lens, A.lens2, A.z, p.L, j, W, m, S.lgw, xf); break;
-                    }
-                    if (lane == 0) {
-                        for (uint32_t k = 0; k < B; k++) {
-                            if ((A.hc >> k) & 1) atomicAdd(&A.words[0][k], S.lgw[0][k][j]);
-                            if ((A.zgc >> k) & 1) atomicAdd(&A.words[1][k], S.lgw[1][k][j]);
-                        }
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // 5. the decision, the entry and the word counts of every open group.
-        // Without exact sizes (staged, no open choice) the lower bounds decide
-        // as the sizes would, and the entry's bytes are left to the packer's
-        // counts.
-        if (uint32_t(t) < B && ((A.open >> t) & 1)) {
-            const int policy = A.pol[t];
-            const bool hc = (A.hc >> t) & 1, zgc = (A.zgc >> t) & 1;
-            const uint32_t size_h = exact ? head + 4 * A.words[0][t] : head + (A.T[0][t] + 7) / 8;
-            const uint32_t size_z = exact ? head_z + 4 * A.words[1][t] : head_z + (A.T[1][t] + 7) / 8;
-            int mode = kModeRaw;
-            uint32_t bytes = m;
-            if (policy == ZIPNN_AUTO) {
-                if (hc && size_h < bytes) mode = kModeHuf, bytes = size_h;
-                if (zgc && size_z < bytes) mode = kModeZg, bytes = size_z;
-            } else if (zgc) {
-                mode = kModeZg, bytes = size_z;
-            } else {
-                mode = kModeHuf, bytes = size_h;
-            }
-            EncEntry e;
-            e.pad = 0;
-            e.mode = uint8_t(mode);
-            e.rle = mode == kModeZg ? uint8_t(A.z[t]) : 0;
-            e.bytes = (staged && mode != kModeRaw) ? 0u : bytes;
-            entries[uint64_t(gc) * B + t] = e;
-            if (mode != kModeRaw) atomicOr(&A.coded, 1u << t);
-            if (mode == kModeZg) atomicOr(&A.fin, 1u << t);
-        }
-        __syncthreads();
-        if (uint32_t(wv) < B && ((A.coded >> wv) & 1)) {
-            const uint64_t ei = uint64_t(gc) * B + wv;
-            const int v = (A.fin >> wv) & 1;
-            canonical_codes(v ? A.lens2[wv] : A.lens[wv], p.L, codes + ei * 256);
-            if (!staged && uint32_t(lane) < NG) nwords[ei * 64 + lane] = S.lgw[v][wv][lane];
-        }
-        __syncthreads();
-    }
+    __shared__ AnalyzeShared<BB> sh;
+    for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x)
+        analyze_chunk<BB>(gc, descs, n_desc, chunk_prefix, p, phase, entries, codes, nwords, sh);
 }
 
 // One workgroup per tensor: offsets of its entries (128-byte aligned, in
@@ -1420,6 +1443,121 @@ __device__ void pack_raw(const uint8_t* src, const uint8_t* base, uint8_t* dst, 
 // spills).  XB: the instance for launches with an XOR base, six waves for
 // 2-byte words (80 VGPRs): the deltas 4% faster again, where the plain
 // checkpoint would lose 2%.
+// The packing of chunk gc by one workgroup (into its container, or staged
+// into its staging slots with the word counts).
+template <int BB, int GG>
+__device__ __attribute__((always_inline)) void pack_chunk(uint32_t gc, const EncDesc* __restrict__ descs, int n_desc,
+                                                          const uint32_t* __restrict__ chunk_prefix, const EncParams& p,
+                                                          const EncEntry* __restrict__ entries,
+                                                          const CodeWord* __restrict__ codes,
+                                                          const uint64_t* __restrict__ offsets,
+                                                          const uint64_t* __restrict__ totals,
+                                                          uint32_t* __restrict__ nwords, PackLds& P)
+{
+    const int t = threadIdx.x, wv = t >> 6;
+    constexpr uint32_t B = BB;
+    // staged: the payloads go to the staging slots (their places in the
+    // container are not known yet) and the word counts come out
+    const bool staged = p.stage != nullptr;
+    const int di = find_desc(chunk_prefix, n_desc, gc);
+    const EncDesc d = descs[di];
+    if (!staged && totals[di] > d.dst_cap) return;   // too small: the host reports it
+    const uint32_t c = gc - chunk_prefix[di];
+    const uint32_t E = p.chunk / B;
+    const uint64_t e0 = uint64_t(c) * E;
+    const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
+    const uint32_t W = (m + p.S - 1) / p.S;
+    const uint32_t NG = (W + 63) / 64;
+    const uint32_t head = huf_head(W);
+    const uint64_t payload_base = payload_base_of(d.n_chunks, B);
+    for (uint32_t k = 0; k < B; k++) {
+        const uint64_t ei = uint64_t(gc) * B + k;
+        const EncEntry en = entries[ei];
+        if (t == 0 && staged) {
+            P.mode[k] = en.mode;
+            P.bytes[k] = en.bytes;
+            P.pay[k] = ei * p.stage_chunk;
+        } else if (t == 0) {
+            P.mode[k] = en.mode;
+            P.bytes[k] = en.bytes;
+            P.pay[k] = payload_base + offsets[ei];
+            // this chunk's map entry
+            uint4 ent;
+            ent.x = uint32_t(offsets[ei]);
+            ent.y = uint32_t(offsets[ei] >> 32);
+            ent.z = en.bytes;
+            ent.w = uint32_t(en.mode) | (uint32_t(en.rle) << 8);
+            *(uint4*)(d.dst + 64 + 16 * (uint64_t(c) * B + k)) = ent;
+        }
+        if (t == 0) P.z[k] = en.rle;
+        if (en.mode == kModeHuf || en.mode == kModeZg) {
+            const uint32_t cw = codes[ei * 256 + t];
+            const uint32_t l = cw >> 16;
+            P.rcode[k][t] = l ? ((__brev(cw & 0xFFFFu) >> (32 - l)) | (l << kLenShift)) : 0u;
+            if (t < 64 && !staged) {
+                const uint32_t nw = uint32_t(t) < NG ? nwords[ei * 64 + t] : 0u;
+                uint32_t inc = nw;
+#pragma unroll
+                for (int dd = 1; dd < 64; dd <<= 1) {
+                    uint32_t o = __shfl_up(inc, dd, 64);
+                    if (t >= dd) inc += o;
+                }
+                P.wpre[k][t + 1] = inc;
+                if (t == 0) P.wpre[k][0] = 0;
+            }
+        }
+    }
+    __syncthreads();
+    const uint8_t* src = d.src + e0 * B;
+    const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
+    uint8_t* dst = staged ? p.stage : d.dst;
+    const bool xf = (p.flags & kFlagExp) != 0;
+    // the coded groups (HUF and ZG) are packed in one pass, which also
+    // copies the raw groups when groups are small (at most 4 bytes)
+    uint32_t rawmask = 0, cm = 0, zm = 0;
+    for (uint32_t k = 0; k < B; k++) {
+        if (P.mode[k] == kModeRaw) rawmask |= 1u << k;
+        if (P.mode[k] == kModeHuf || P.mode[k] == kModeZg) cm |= 1u << k;
+        if (P.mode[k] == kModeZg) zm |= 1u << k;
+    }
+    const bool fuse_raw = GG <= 4 && BB * GG <= 16 && cm != 0;
+    pack_raw<BB>(src, base, dst, P, m, xf, fuse_raw);
+    // with W a multiple of 64 the packer writes a ZG bitmap's words as it
+    // marks the groups
+    const bool fuse_bitmap = W % 64 == 0;
+    for (uint32_t k = 0; k < B; k++) {
+        const bool zg = P.mode[k] == kModeZg;
+        if (P.mode[k] != kModeHuf && !zg) continue;
+        uint8_t* pay = dst + P.pay[k];
+        // head: nibble table, word counts, zero pad; ZG bitmap; zero pad
+        // after words (staged: the compaction writes all but the bitmap)
+        if (!staged) {
+            if (t < 128)
+                pay[t] = uint8_t((P.rcode[k][2 * t] >> kLenShift) | ((P.rcode[k][2 * t + 1] >> kLenShift) << 4));
+            if (uint32_t(t) < NG) ((uint32_t*)(pay + 128))[t] = P.wpre[k][t + 1] - P.wpre[k][t];
+            for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
+            for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
+        }
+        const uint32_t lead = staged ? 0u : head;   // where the bitmap starts
+        if (zg) {
+            const uint32_t bm = zg_bitmap(m, GG);
+            if (fuse_bitmap) {   // only the words past the last group are zeroed here
+                uint64_t* words = reinterpret_cast<uint64_t*>(pay + lead);
+                const uint32_t Gtot = (m + GG - 1) / GG;
+                for (uint32_t x = (Gtot + 63) / 64 + t; x < bm / 8; x += kBlock) words[x] = 0;
+            } else {
+                pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + lead, xf);
+            }
+        }
+    }
+    if (cm)
+        for (uint32_t j = wv; j < NG; j += kWaves)
+            pack_lane_group<BB, GG>(src, base, cm, zm, P, p.L, j, W, m, xf, fuse_bitmap, fuse_raw ? rawmask : 0u,
+                                    dst, staged ? p.stage_lg : 0u, p.stage_bm,
+                                    staged ? nwords + uint64_t(gc) * B * 64 : nullptr);
+    __syncthreads();
+}
+
 template <int BB, int GG, bool XB>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 ? (XB ? 6 : 5) : 4, 8))) void k_pack(const EncDesc* __restrict__ descs, int n_desc,
                                                  const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
@@ -1430,108 +1568,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BB == 2 
                                                  uint32_t* __restrict__ nwords)
 {
     __shared__ PackLds P;
-    const int t = threadIdx.x, wv = t >> 6;
-    constexpr uint32_t B = BB;
-    // staged: the payloads go to the staging slots (their places in the
-    // container are not known yet) and the word counts come out
-    const bool staged = p.stage != nullptr;
+    for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x)
+        pack_chunk<BB, GG>(gc, descs, n_desc, chunk_prefix, p, entries, codes, offsets, totals, nwords, P);
+}
+
+template <int BB>
+union FusedLds {
+    AnalyzeShared<BB> a;
+    PackLds pk;
+};
+
+// Staged launches: a workgroup analyses a chunk and packs it at once into its
+// staging slots, which need no placement first; a chunk's analysis and
+// packing thus share a launch, and the workgroups on a CU mix the two (the
+// checkpoint's XOR delta: Huffman-only encode 16.9 -> 16.0 ms, zero-aware
+// 18.4 -> 17.5 ms).  For 2-byte words seven waves per SIMD (72 VGPRs):
+// faster than six by 5% on the Huffman-only delta, and by about 10% than
+// five.
+template <int BB, int GG, int WV>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WV, 8))) void k_analyze_pack(
+    const EncDesc* __restrict__ descs, int n_desc, const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
+    EncParams p, int phase, EncEntry* entries, CodeWord* codes, uint32_t* nwords)
+{
+    __shared__ FusedLds<BB> u;
     for (uint32_t gc = blockIdx.x; gc < total_chunks; gc += gridDim.x) {
-        const int di = find_desc(chunk_prefix, n_desc, gc);
-        const EncDesc d = descs[di];
-        if (!staged && totals[di] > d.dst_cap) continue;   // too small: the host reports it
-        const uint32_t c = gc - chunk_prefix[di];
-        const uint32_t E = p.chunk / B;
-        const uint64_t e0 = uint64_t(c) * E;
-        const uint32_t m = uint32_t(min(uint64_t(E), d.n - e0));
-        const uint32_t W = (m + p.S - 1) / p.S;
-        const uint32_t NG = (W + 63) / 64;
-        const uint32_t head = huf_head(W);
-        const uint64_t payload_base = payload_base_of(d.n_chunks, B);
-        for (uint32_t k = 0; k < B; k++) {
-            const uint64_t ei = uint64_t(gc) * B + k;
-            const EncEntry en = entries[ei];
-            if (t == 0 && staged) {
-                P.mode[k] = en.mode;
-                P.bytes[k] = en.bytes;
-                P.pay[k] = ei * p.stage_chunk;
-            } else if (t == 0) {
-                P.mode[k] = en.mode;
-                P.bytes[k] = en.bytes;
-                P.pay[k] = payload_base + offsets[ei];
-                // this chunk's map entry
-                uint4 ent;
-                ent.x = uint32_t(offsets[ei]);
-                ent.y = uint32_t(offsets[ei] >> 32);
-                ent.z = en.bytes;
-                ent.w = uint32_t(en.mode) | (uint32_t(en.rle) << 8);
-                *(uint4*)(d.dst + 64 + 16 * (uint64_t(c) * B + k)) = ent;
-            }
-            if (t == 0) P.z[k] = en.rle;
-            if (en.mode == kModeHuf || en.mode == kModeZg) {
-                const uint32_t cw = codes[ei * 256 + t];
-                const uint32_t l = cw >> 16;
-                P.rcode[k][t] = l ? ((__brev(cw & 0xFFFFu) >> (32 - l)) | (l << kLenShift)) : 0u;
-                if (t < 64 && !staged) {
-                    const uint32_t nw = uint32_t(t) < NG ? nwords[ei * 64 + t] : 0u;
-                    uint32_t inc = nw;
-#pragma unroll
-                    for (int dd = 1; dd < 64; dd <<= 1) {
-                        uint32_t o = __shfl_up(inc, dd, 64);
-                        if (t >= dd) inc += o;
-                    }
-                    P.wpre[k][t + 1] = inc;
-                    if (t == 0) P.wpre[k][0] = 0;
-                }
-            }
-        }
-        __syncthreads();
-        const uint8_t* src = d.src + e0 * B;
-        const uint8_t* base = d.base ? d.base + e0 * B : nullptr;
-        uint8_t* dst = staged ? p.stage : d.dst;
-        const bool xf = (p.flags & kFlagExp) != 0;
-        // the coded groups (HUF and ZG) are packed in one pass, which also
-        // copies the raw groups when groups are small (at most 4 bytes)
-        uint32_t rawmask = 0, cm = 0, zm = 0;
-        for (uint32_t k = 0; k < B; k++) {
-            if (P.mode[k] == kModeRaw) rawmask |= 1u << k;
-            if (P.mode[k] == kModeHuf || P.mode[k] == kModeZg) cm |= 1u << k;
-            if (P.mode[k] == kModeZg) zm |= 1u << k;
-        }
-        const bool fuse_raw = GG <= 4 && BB * GG <= 16 && cm != 0;
-        pack_raw<BB>(src, base, dst, P, m, xf, fuse_raw);
-        // with W a multiple of 64 the packer writes a ZG bitmap's words as it
-        // marks the groups
-        const bool fuse_bitmap = W % 64 == 0;
-        for (uint32_t k = 0; k < B; k++) {
-            const bool zg = P.mode[k] == kModeZg;
-            if (P.mode[k] != kModeHuf && !zg) continue;
-            uint8_t* pay = dst + P.pay[k];
-            // head: nibble table, word counts, zero pad; ZG bitmap; zero pad
-            // after words (staged: the compaction writes all but the bitmap)
-            if (!staged) {
-                if (t < 128)
-                    pay[t] = uint8_t((P.rcode[k][2 * t] >> kLenShift) | ((P.rcode[k][2 * t + 1] >> kLenShift) << 4));
-                if (uint32_t(t) < NG) ((uint32_t*)(pay + 128))[t] = P.wpre[k][t + 1] - P.wpre[k][t];
-                for (uint32_t i = 128 + 4 * NG + t; i < head; i += kBlock) pay[i] = 0;
-                for (uint32_t i = P.bytes[k] + t; i < uint32_t(align_pay(P.bytes[k])); i += kBlock) pay[i] = 0;
-            }
-            const uint32_t lead = staged ? 0u : head;   // where the bitmap starts
-            if (zg) {
-                const uint32_t bm = zg_bitmap(m, GG);
-                if (fuse_bitmap) {   // only the words past the last group are zeroed here
-                    uint64_t* words = reinterpret_cast<uint64_t*>(pay + lead);
-                    const uint32_t Gtot = (m + GG - 1) / GG;
-                    for (uint32_t x = (Gtot + 63) / 64 + t; x < bm / 8; x += kBlock) words[x] = 0;
-                } else {
-                    pack_bitmap<BB, GG>(src, base, int(k), P.z[k], m, bm, pay + lead, xf);
-                }
-            }
-        }
-        if (cm)
-            for (uint32_t j = wv; j < NG; j += kWaves)
-                pack_lane_group<BB, GG>(src, base, cm, zm, P, p.L, j, W, m, xf, fuse_bitmap, fuse_raw ? rawmask : 0u,
-                                        dst, staged ? p.stage_lg : 0u, p.stage_bm,
-                                        staged ? nwords + uint64_t(gc) * B * 64 : nullptr);
+        if (!analyze_chunk<BB>(gc, descs, n_desc, chunk_prefix, p, phase, entries, codes, nwords, u.a)) continue;
+        __syncthreads();   // the chunk's entries and code tables, written above, are read below
+        pack_chunk<BB, GG>(gc, descs, n_desc, chunk_prefix, p, entries, codes, nullptr, nullptr, nwords, u.pk);
         __syncthreads();
     }
 }
@@ -1644,25 +1707,42 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
     const bool xb = (p.flags & kFlagDelta) != 0;   // some tensor has an XOR base
     bool zg_possible = false;                       // some group may take ZG
     for (uint32_t k = 0; k < p.B && k < 4; k++) zg_possible |= p.policy[k] == ZIPNN_AUTO || p.policy[k] == ZIPNN_ZG;
+    const bool staged = p.stage != nullptr;
     if (total_chunks) {
         // with probing, the probe chunks first: the others read their entries
         for (int phase = p.skip ? 0 : -1; phase <= (p.skip ? 1 : -1); phase++) {
+            bool launched = false;
+            if (staged) {
+#define ZIPNN_FUSED(B_, G_, WV_)                                                                                 \
+    if (!launched && p.B == B_ && p.g == G_) {                                                                  \
+        k_analyze_pack<B_, G_, WV_><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p,   \
+                                                            phase, entries, codes, nwords);                      \
+        launched = true;                                                                                        \
+    }
+                ZIPNN_FUSED(1, 2, 4) ZIPNN_FUSED(1, 4, 4) ZIPNN_FUSED(1, 8, 4)
+                ZIPNN_FUSED(2, 2, 7) ZIPNN_FUSED(2, 4, 7) ZIPNN_FUSED(2, 8, 7)
+                ZIPNN_FUSED(4, 2, 4) ZIPNN_FUSED(4, 4, 4) ZIPNN_FUSED(4, 8, 4)
+#undef ZIPNN_FUSED
+            } else {
 #define ZIPNN_ANALYZE(B_, WV_)                                                                                   \
     k_analyze<B_, WV_><<<grid, kBlock, 0, s>>>(d_descs, n_desc, d_chunk_prefix, total_chunks, p, phase, entries, \
                                                codes, nwords)
-            if (p.B == 1) ZIPNN_ANALYZE(1, 4);
-            else if (p.B == 2 && xb && zg_possible) ZIPNN_ANALYZE(2, 7);
-            else if (p.B == 2 && xb) ZIPNN_ANALYZE(2, 6);
-            else if (p.B == 2) ZIPNN_ANALYZE(2, 5);
-            else if (p.B == 4) ZIPNN_ANALYZE(4, 4);
-            else return hipErrorInvalidValue;
+                launched = true;
+                if (p.B == 1) ZIPNN_ANALYZE(1, 4);
+                else if (p.B == 2 && xb && zg_possible) ZIPNN_ANALYZE(2, 7);
+                else if (p.B == 2 && xb) ZIPNN_ANALYZE(2, 6);
+                else if (p.B == 2) ZIPNN_ANALYZE(2, 5);
+                else if (p.B == 4) ZIPNN_ANALYZE(4, 4);
+                else launched = false;
 #undef ZIPNN_ANALYZE
+            }
+            if (!launched) return hipErrorInvalidValue;
             if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
         }
     }
-    // exact: placement, arena, then packing into the containers; staged:
-    // packing into the staging slots, placement from its word counts, arena,
-    // then the compaction into the containers
+    // exact: analysis, placement, arena, then packing into the containers;
+    // staged: analysis with packing into the staging slots, placement from
+    // the word counts, arena, then the compaction into the containers
     auto pack_or_compact = [&](bool compact) -> hipError_t {
         if (!total_chunks) return hipSuccess;
         bool launched = false;
@@ -1686,11 +1766,6 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
         if (!launched) return hipErrorInvalidValue;
         return hipGetLastError() == hipSuccess ? hipSuccess : hipErrorLaunchFailure;
     };
-    const bool staged = p.stage != nullptr;
-    if (staged) {
-        const hipError_t e = pack_or_compact(false);
-        if (e != hipSuccess) return e;
-    }
     k_place<<<n_desc, kBlock, 0, s>>>(d_descs, p, entries, offsets, totals, nwords);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     k_arena<<<1, kBlock, 0, s>>>(d_descs, n_desc, p, arena, cap, totals, arena_off);
