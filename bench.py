@@ -468,6 +468,7 @@ def _serve_pass(Z, srv, handles, sizes, rate, count, seed):
     from paper_2411_05239_amd import workloads
 
     arr = workloads.poisson_arrivals(rate, count, seed)
+    it0 = Z.zipnn_server_stats(srv.h).iterations
     g = torch.Generator().manual_seed(seed)
     pick = torch.randint(0, len(handles), (count,), generator=g).tolist()
     t0 = Z.zipnn_clock() + 0.05
@@ -509,10 +510,21 @@ def _serve_pass(Z, srv, handles, sizes, rate, count, seed):
         t_last = max(t_last, tm.t_done)
         n_done += 1
     th.join()
-    span = t_last - t0
-    return {"rate": rate, "requests": n_done, "p50_ms": round(_pct(lat, 0.5) * 1e3, 3),
+    return {"lat": lat, "ph": ph, "bytes": nbytes, "span": t_last - t0,
+            "iters": Z.zipnn_server_stats(srv.h).iterations - it0}
+
+
+def _serve_stats(rate, parts, sizes):
+    """Latency and rate statistics over the passes `parts` of one mode."""
+    lat = [v for q in parts for v in q["lat"]]
+    ph = {k: [v for q in parts for v in q["ph"][k]] for k in parts[0]["ph"]}
+    span = sum(q["span"] for q in parts)
+    iters = sum(q["iters"] for q in parts)
+    return {"rate": rate, "requests": len(lat), "requests_per_iteration": round(len(lat) / max(iters, 1), 3),
+            "p50_ms": round(_pct(lat, 0.5) * 1e3, 3),
             "p99_ms": round(_pct(lat, 0.99) * 1e3, 3), "mean_ms": round(statistics.mean(lat) * 1e3, 3),
-            "GBps": round(nbytes / span / 1e9, 2), "offered_GBps": round(rate * statistics.mean(sizes) / 1e9, 2),
+            "GBps": round(sum(q["bytes"] for q in parts) / span / 1e9, 2),
+            "offered_GBps": round(rate * statistics.mean(sizes) / 1e9, 2),
             "p50_phase_ms": {k: round(_pct(v, 0.5) * 1e3, 4) for k, v in ph.items()},
             "p99_phase_ms": {k: round(_pct(v, 0.99) * 1e3, 4) for k, v in ph.items()}}
 
@@ -597,10 +609,11 @@ def serve_block(args, rates) -> dict:
     torch.cuda.synchronize()
     sizes = [x.numel() * x.element_size() for x in xs]
     U, C = sum(sizes), sum(c.numel() for c in cs)
-    res, closed = {}, {}
+    res, closed, servers = {}, {}, {}
     for mode, name in [(Z.ZIPNN_SERVE_CONTINUOUS, "continuous"), (Z.ZIPNN_SERVE_PER_REQUEST, "per_request")]:
         srv = Z.Server(codec, pool_bytes=16 << 30, max_inflight=256, mode=mode)
         handles = [srv.register(c) for c in cs]
+        servers[name] = (srv, handles)
         # closed loop: all items at t=0, every result checked
         t0 = Z.zipnn_clock()
         tks = {srv.submit(h, t0): i for i, h in enumerate(handles)}
@@ -622,19 +635,33 @@ def serve_block(args, rates) -> dict:
         closed[name] = {"requests": len(tks), "seconds": round(t_last - t0, 4),
                         "GBps": round(U / (t_last - t0) / 1e9, 2), "p50_ms": round(_pct(lat, 0.5) * 1e3, 3),
                         "p99_ms": round(_pct(lat, 0.99) * 1e3, 3), "all_equal_original": ok}
-        res[name] = []
-        for ri, rate in enumerate(rates):
-            count = int(min(4000, max(200, rate * args.serve_seconds)))
-            res[name].append(_serve_pass(Z, srv, handles, sizes, rate, count, 4000 + ri))
+        closed[name]["iterations"] = Z.zipnn_server_stats(srv.h).iterations
+    # open loop: per rate two halves of the same two request streams, run
+    # continuous, per-request, per-request, continuous, so that neither mode
+    # gains from going second (clocks, warm pools); at least 1000 requests
+    # per rate and mode, so that p99 is the 10th slowest, not the 2nd
+    res = {"continuous": [], "per_request": []}
+    for ri, rate in enumerate(rates):
+        half = int(min(2000, max(500, rate * args.serve_seconds / 2)))
+        parts = {"continuous": [], "per_request": []}
+        for name, h in (("continuous", 0), ("per_request", 0), ("per_request", 1), ("continuous", 1)):
+            srv, handles = servers[name]
+            parts[name].append(_serve_pass(Z, srv, handles, sizes, rate, half, 4000 + 2 * ri + h))
+        for name in res:
+            res[name].append(_serve_stats(rate, parts[name], sizes))
             print(json.dumps({"progress": name, **res[name][-1]}), file=sys.stderr, flush=True)
-        st = Z.zipnn_server_stats(srv.h)
-        closed[name]["iterations"] = st.iterations
+    for srv, _ in servers.values():
         srv.close()
     codec.close()
     del xs, cs
     torch.cuda.empty_cache()
+    # where continuous batching finds no second request to join an iteration
+    # (requests_per_iteration near 1), both modes launch the same
+    # iterations, one request each, and their p99s differ by run-to-run noise
     cmp = [{"rate": a["rate"], "p99_continuous_ms": a["p99_ms"], "p99_per_request_ms": b["p99_ms"],
             "continuous_p99_le_per_request": a["p99_ms"] <= b["p99_ms"],
+            "p99_ratio": round(a["p99_ms"] / b["p99_ms"], 4) if b["p99_ms"] else None,
+            "requests_per_iteration_continuous": a["requests_per_iteration"],
             "GBps_continuous": a["GBps"], "GBps_per_request": b["GBps"]}
            for a, b in zip(res["continuous"], res["per_request"])]
     return {"workload": "serving_corpus_128_tensors_64KiB_1GiB_bf16_fp32_fp8", "bytes": U, "compressed_bytes": C,

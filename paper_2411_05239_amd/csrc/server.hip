@@ -33,10 +33,6 @@ constexpr uint32_t kDefaultChunksPerIter = 2048;
 // each arrival a thread wake-up (tens of microseconds); at 100 requests/s
 // only gaps longer than this (e^-5 of them) pay it.
 constexpr double kIdleSpinSeconds = 50e-3;
-// A request admitted this long ago goes before the others (oldest first), so
-// that a large one is not held back by a steady stream of smaller ones.
-constexpr double kAgeSeconds = 2e-3;
-
 double now_s()
 {
     timespec ts;
@@ -213,28 +209,28 @@ bool launch_iteration(zipnn_server s)
         const Req& r = s->reqs[ticket];
         take.push_back({ticket, r.n_chunks - r.next});
     } else {
-        // order: requests waiting longer than kAgeSeconds first (oldest
-        // first), then the others with the fewest chunks left first
-        const double now = now_s();
-        std::vector<std::tuple<int, double, uint64_t>> order;   // aged?, key, ticket
-        for (uint64_t ticket : s->active) {
-            const Req& r = s->reqs[ticket];
-            const bool aged = now - r.t.t_admit > kAgeSeconds;
-            order.push_back({aged ? 0 : 1, aged ? r.t.t_admit : double(r.n_chunks - r.next), ticket});
+        // whole requests: the oldest first (the largest requests set the
+        // tail latency, and so they never wait behind later small ones),
+        // then the others fewest chunks first while they fit under the
+        // chunk cap.  At 5000 requests/s the p99 was 1.50 ms in this order,
+        // 1.54 ms in arrival order and 1.81 ms with every request fewest
+        // chunks first (older than 2 ms first); a burst of 128 requests had
+        // its p50 at 1.6, 3.8 and 2.0 ms.  A request is never split: a split
+        // only adds a launch to the largest requests, while those batched
+        // with it would wait for the whole iteration anyway.
+        std::vector<std::pair<uint32_t, uint64_t>> rest;   // chunks, ticket
+        for (size_t i = 1; i < s->active.size(); i++) {
+            const Req& r = s->reqs[s->active[i]];
+            rest.push_back({r.n_chunks - r.next, s->active[i]});
         }
-        std::sort(order.begin(), order.end());
-        // whole requests, in that order, while they fit under the chunk cap
-        // (the first one always): a request is never split, since the
-        // largest requests set the tail latency and a split only adds a
-        // launch to theirs, while the requests batched with it would wait
-        // for the whole iteration anyway
-        uint64_t used = 0;
-        for (auto& o : order) {
-            const Req& r = s->reqs[std::get<2>(o)];
-            const uint32_t n = r.n_chunks - r.next;
-            if (!take.empty() && used + n > s->cfg.chunks_per_iter) continue;
-            take.push_back({std::get<2>(o), n});
-            used += n;
+        std::sort(rest.begin(), rest.end());
+        const Req& r0 = s->reqs[s->active.front()];
+        uint64_t used = r0.n_chunks - r0.next;
+        take.push_back({s->active.front(), uint32_t(used)});
+        for (auto& o : rest) {
+            if (used + o.first > s->cfg.chunks_per_iter) continue;
+            take.push_back({o.second, o.first});
+            used += o.first;
         }
     }
     // descriptors by kernel class, in the order taken
