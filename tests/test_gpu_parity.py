@@ -143,10 +143,12 @@ def test_code_length_limits(codec):
 
 @pytest.mark.parametrize("dtype,g", [(torch.uint8, 2), (torch.uint8, 4), (torch.uint8, 8), (torch.bfloat16, 8),
                                      (torch.float32, 4)])
-def test_longest_codes_fill_the_packer_queue(codec, dtype, g):
+def test_longest_codes_at_the_length_limit(codec, dtype, g, base=False):
     """A few sub-streams hold only rare bytes among zeros: with Huffman forced
-    their codes all reach the L = 11 limit, so the packer's per-lane queue of
-    finished words reaches its largest fill, (LG + 1) g L / 32 words."""
+    their codes all reach the L = 11 limit, so those lanes add the most bits a
+    pair can (2L) at every pair and take the most words the layout allows.
+    With `base` the same bytes are the XOR delta against a random base (the
+    staged path, whose slots are sized for such lanes)."""
     gen = torch.Generator().manual_seed(40 + g)
     bsz = torch.tensor([], dtype=dtype).element_size()
     chunk, S = 65536, 512
@@ -160,9 +162,10 @@ def test_longest_codes_fill_the_packer_queue(codec, dtype, g):
     idx = e[hot]
     for b in range(bsz):
         x[idx * bsz + b] = torch.randint(1, 256, (idx.numel(),), generator=gen, dtype=torch.uint8)
-    xt = x.view(dtype)
+    b = torch.randint(0, 256, (n * bsz,), generator=gen, dtype=torch.uint8) if base else None
+    xt = (x ^ b).view(dtype) if base else x.view(dtype)
     p = Z.make_params(Z.torch_dtype_code(dtype), chunk_bytes=chunk, S=S, g=g, policy=[Z.ZIPNN_HUF] * bsz)
-    c = roundtrip(codec, xt, p).cpu().numpy()
+    c = roundtrip(codec, xt, p, base_cpu=b.view(dtype) if base else None).cpu().numpy()
     # every entry is Huffman-coded and the rare bytes' codes are at the limit
     for ch in range(4):
         for k in range(bsz):

@@ -17,6 +17,7 @@ import pytest
 import torch
 
 import oracle
+import test_gpu_parity
 from paper_2411_05239_amd import workloads
 from paper_2411_05239_amd import zipnn as Z
 
@@ -185,3 +186,10 @@ def test_output_too_small_leaves_the_rest_untouched(codec):
     assert ei.value.code == Z.ZIPNN_E_NOSPACE
     torch.cuda.synchronize()
     assert bool((dst[cap:] == 0xA5).all())
+
+
+@pytest.mark.parametrize("dtype,g", [(torch.uint8, 2), (torch.uint8, 8), (torch.bfloat16, 8), (torch.float32, 4)])
+def test_longest_codes_through_the_slots(codec, dtype, g):
+    """Lanes whose every code is at the length limit take the most words a
+    staging slot is sized for."""
+    test_gpu_parity.test_longest_codes_at_the_length_limit(codec, dtype, g, base=True)
