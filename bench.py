@@ -609,11 +609,16 @@ def serve_block(args, rates) -> dict:
     torch.cuda.synchronize()
     sizes = [x.numel() * x.element_size() for x in xs]
     U, C = sum(sizes), sum(c.numel() for c in cs)
-    res, closed, servers = {}, {}, {}
-    for mode, name in [(Z.ZIPNN_SERVE_CONTINUOUS, "continuous"), (Z.ZIPNN_SERVE_PER_REQUEST, "per_request")]:
-        srv = Z.Server(codec, pool_bytes=16 << 30, max_inflight=256, mode=mode)
-        handles = [srv.register(c) for c in cs]
-        servers[name] = (srv, handles)
+    # one server, switched between the two modes: both use the same output
+    # pool, stream and registrations (two servers, one per mode, measured up
+    # to 4% apart at low rates, either one ahead, in either creation order)
+    res, closed = {}, {}
+    modes = {"continuous": Z.ZIPNN_SERVE_CONTINUOUS, "per_request": Z.ZIPNN_SERVE_PER_REQUEST}
+    srv = Z.Server(codec, pool_bytes=16 << 30, max_inflight=256, mode=modes["continuous"])
+    handles = [srv.register(c) for c in cs]
+    for name, mode in modes.items():
+        srv.set_mode(mode)
+        it0 = Z.zipnn_server_stats(srv.h).iterations
         # closed loop: all items at t=0, every result checked
         t0 = Z.zipnn_clock()
         tks = {srv.submit(h, t0): i for i, h in enumerate(handles)}
@@ -635,23 +640,22 @@ def serve_block(args, rates) -> dict:
         closed[name] = {"requests": len(tks), "seconds": round(t_last - t0, 4),
                         "GBps": round(U / (t_last - t0) / 1e9, 2), "p50_ms": round(_pct(lat, 0.5) * 1e3, 3),
                         "p99_ms": round(_pct(lat, 0.99) * 1e3, 3), "all_equal_original": ok}
-        closed[name]["iterations"] = Z.zipnn_server_stats(srv.h).iterations
+        closed[name]["iterations"] = Z.zipnn_server_stats(srv.h).iterations - it0
     # open loop: per rate two halves of the same two request streams, run
     # continuous, per-request, per-request, continuous, so that neither mode
-    # gains from going second (clocks, warm pools); at least 1000 requests
-    # per rate and mode, so that p99 is the 10th slowest, not the 2nd
+    # gains from going second; at least 1000 requests per rate and mode, so
+    # that p99 is the 10th slowest, not the 2nd
     res = {"continuous": [], "per_request": []}
     for ri, rate in enumerate(rates):
         half = int(min(2000, max(500, rate * args.serve_seconds / 2)))
         parts = {"continuous": [], "per_request": []}
         for name, h in (("continuous", 0), ("per_request", 0), ("per_request", 1), ("continuous", 1)):
-            srv, handles = servers[name]
+            srv.set_mode(modes[name])
             parts[name].append(_serve_pass(Z, srv, handles, sizes, rate, half, 4000 + 2 * ri + h))
         for name in res:
             res[name].append(_serve_stats(rate, parts[name], sizes))
             print(json.dumps({"progress": name, **res[name][-1]}), file=sys.stderr, flush=True)
-    for srv, _ in servers.values():
-        srv.close()
+    srv.close()
     codec.close()
     del xs, cs
     torch.cuda.empty_cache()

@@ -417,6 +417,12 @@ int zipnn_server_release(zipnn_server srv, uint64_t ticket);
 /* Counters since create. */
 int zipnn_server_stats(zipnn_server srv, zipnn_server_counters* out);
 
+/* Switch the batching mode (zipnn_serve_mode); iterations launched from then
+ * on follow it, those in flight are unaffected.  Lets one server, with one
+ * output pool and one stream, compare continuous batching with the plain
+ * per-request launch on the same memory.  ZIPNN_E_INVAL for another mode. */
+int zipnn_server_set_mode(zipnn_server srv, int mode);
+
 /* Validate a container's header and map from HOST memory (len bytes: at
  * least the header and the map) and summarise it in *out. */
 int zipnn_inspect(const void* host_buf, uint64_t len, zipnn_info* out);

@@ -567,4 +567,12 @@ int zipnn_server_stats(zipnn_server s, zipnn_server_counters* out)
     return ZIPNN_OK;
 }
 
+int zipnn_server_set_mode(zipnn_server s, int mode)
+{
+    if (!s || (mode != ZIPNN_SERVE_CONTINUOUS && mode != ZIPNN_SERVE_PER_REQUEST)) return ZIPNN_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);   // launch_iteration reads the mode under this lock
+    s->cfg.mode = mode;
+    return ZIPNN_OK;
+}
+
 }  // extern "C"

@@ -31,7 +31,7 @@ EXPORTS = [
     "zipnn_batch_create", "zipnn_batch_decompress", "zipnn_batch_destroy",
     "zipnn_decompress_batch", "zipnn_autotune", "zipnn_clock", "zipnn_server_create", "zipnn_server_destroy",
     "zipnn_server_register", "zipnn_server_submit", "zipnn_server_poll", "zipnn_server_next_done",
-    "zipnn_server_release", "zipnn_server_stats",
+    "zipnn_server_release", "zipnn_server_stats", "zipnn_server_set_mode",
 ]
 ZIPNN_SERVE_CONTINUOUS, ZIPNN_SERVE_PER_REQUEST = 0, 1
 
@@ -147,6 +147,8 @@ def lib():
         L.zipnn_server_release.argtypes, L.zipnn_server_release.restype = [vp, u64], i32
         L.zipnn_server_stats.argtypes = [vp, P(zipnn_server_counters)]
         L.zipnn_server_stats.restype = i32
+        L.zipnn_server_set_mode.argtypes = [vp, i32]
+        L.zipnn_server_set_mode.restype = i32
         _lib = L
     return _lib
 
@@ -369,6 +371,10 @@ def zipnn_server_next_done(srv, timeout_s: float):
 
 def zipnn_server_release(srv, ticket: int) -> None:
     _check(lib().zipnn_server_release(srv, ticket), "zipnn_server_release")
+
+
+def zipnn_server_set_mode(srv, mode: int) -> None:
+    _check(lib().zipnn_server_set_mode(srv, mode), "zipnn_server_set_mode")
 
 
 def zipnn_server_stats(srv) -> zipnn_server_counters:
@@ -645,6 +651,9 @@ class Server:
 
     def stats(self) -> zipnn_server_counters:
         return zipnn_server_stats(self.h)
+
+    def set_mode(self, mode: int) -> None:
+        zipnn_server_set_mode(self.h, mode)
 
     def close(self):
         if self.h:

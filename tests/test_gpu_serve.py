@@ -123,6 +123,29 @@ def test_mix_equals_solo(codec, corpus, mode, cap):
     srv.close()
 
 
+def test_mode_switch_on_a_live_server(codec, corpus):
+    """zipnn_server_set_mode switches a running server between continuous
+    batching and one iteration per request: bursts in each mode give the solo
+    bytes, and the iteration counts follow the mode of each burst."""
+    srv = Z.Server(codec, pool_bytes=256 << 20, max_inflight=64)
+    handles = [srv.register(d["c"], d["base"]) for d in corpus]
+    with_chunks = sum(1 for d in corpus if d["x"].numel() > 0)
+    for mode in (Z.ZIPNN_SERVE_PER_REQUEST, Z.ZIPNN_SERVE_CONTINUOUS, Z.ZIPNN_SERVE_PER_REQUEST):
+        srv.set_mode(mode)
+        it0 = srv.stats().iterations
+        tickets = [(srv.submit(handles[i]), i) for rep in range(3) for i in range(len(corpus))]
+        _drain(srv, tickets, corpus, handles)
+        iters = srv.stats().iterations - it0
+        if mode == Z.ZIPNN_SERVE_PER_REQUEST:
+            assert iters == 3 * with_chunks
+        else:
+            assert iters < 3 * with_chunks   # the burst was batched
+    with pytest.raises(Z.ZipnnError) as ei:
+        srv.set_mode(7)
+    assert ei.value.code == Z.ZIPNN_E_INVAL
+    srv.close()
+
+
 def test_admission_by_pool_bytes(codec, corpus):
     # pool for about two of the largest outputs: requests wait for releases
     big = max(d["x"].numel() * d["x"].element_size() for d in corpus)
