@@ -218,8 +218,14 @@ bool launch_iteration(zipnn_server s)
         // its p50 at 1.6, 3.8 and 2.0 ms.  A request is never split: a split
         // only adds a launch to the largest requests, while those batched
         // with it would wait for the whole iteration anyway.
+        // Batching only when requests would otherwise wait: while every
+        // admitted request can have an iteration of its own in flight now,
+        // each goes alone, as in per-request mode (a batch would hold its
+        // oldest request until the others are decoded too).
+        const size_t free_slots = size_t(kIterDepth - s->it_busy);
+        const bool fill = s->active.size() > free_slots;
         std::vector<std::pair<uint32_t, uint64_t>> rest;   // chunks, ticket
-        for (size_t i = 1; i < s->active.size(); i++) {
+        for (size_t i = 1; fill && i < s->active.size(); i++) {
             const Req& r = s->reqs[s->active[i]];
             rest.push_back({r.n_chunks - r.next, s->active[i]});
         }
