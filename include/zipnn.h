@@ -343,10 +343,12 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
  * Requests are admitted in arrival order while the pool has room for the
  * output (and fewer than max_inflight are admitted).  A scheduler thread
  * runs decode iterations on a private stream, keeping two in flight: in
- * ZIPNN_SERVE_CONTINUOUS mode an iteration takes admitted requests whole:
- * the oldest, then the others with the fewest chunks first while they fit
- * under chunks_per_iter, so requests that arrive while others decode join
- * the next iteration, many to a launch; ZIPNN_SERVE_PER_REQUEST runs one
+ * ZIPNN_SERVE_CONTINUOUS mode, when more requests are admitted than can
+ * each have an iteration in flight, an iteration takes them whole: the
+ * oldest, then the others with the fewest chunks first while they fit under
+ * chunks_per_iter, so requests that arrive while others decode join the next
+ * iteration, many to a launch (otherwise each goes alone);
+ * ZIPNN_SERVE_PER_REQUEST runs one
  * iteration per request holding all of its chunks (the plain per-request
  * launch).  Chunks
  * decode independently given the map (paper §V-A), so the bytes of a result
