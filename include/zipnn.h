@@ -348,12 +348,11 @@ int zipnn_autotune(zipnn_ctx ctx, int dtype, const zipnn_tensor_in* tensors, int
  * oldest, then the others with the fewest chunks first while they fit under
  * chunks_per_iter, so requests that arrive while others decode join the next
  * iteration, many to a launch (otherwise each goes alone);
- * ZIPNN_SERVE_PER_REQUEST runs one
- * iteration per request holding all of its chunks (the plain per-request
- * launch).  Chunks
- * decode independently given the map (paper §V-A), so the bytes of a result
- * do not depend on what else was in its iterations.  Every call is
- * thread-safe.  Times are seconds on the host monotonic clock (zipnn_clock). */
+ * ZIPNN_SERVE_PER_REQUEST runs one iteration per request holding all of its
+ * chunks (the plain per-request launch).  Chunks decode independently given
+ * the map (paper §V-A), so the bytes of a result do not depend on what else
+ * was in its iterations.  Every call is thread-safe.  Times are seconds on
+ * the host monotonic clock (zipnn_clock). */
 
 typedef struct zipnn_server_s* zipnn_server;
 
