@@ -643,7 +643,7 @@ int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets
     if (!b) return ZIPNN_E_NOMEM;
     b->ctx = ctx;
     size_t bytes = 0;
-    for (auto& kv : groups) bytes += align256(kv.second.size() * sizeof(DecDesc)) + align256((kv.second.size() + 1) * 8);
+    for (auto& kv : groups) bytes += align256(kv.second.size() * sizeof(DecDesc)) + align256((kv.second.size() + 2) * 8);
     if (bytes && dev_malloc((void**)&b->d_mem, bytes) != hipSuccess) {
         delete b;
         return ZIPNN_E_NOMEM;
@@ -656,7 +656,7 @@ int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets
         c.d_descs = (DecDesc*)((uint8_t*)b->d_mem + off);
         off += align256(kv.second.size() * sizeof(DecDesc));
         c.d_prefix = (uint64_t*)((uint8_t*)b->d_mem + off);
-        off += align256((kv.second.size() + 1) * 8);
+        off += align256((kv.second.size() + 2) * 8);
         if (hipMemcpy(c.d_descs, kv.second.data(), kv.second.size() * sizeof(DecDesc), hipMemcpyHostToDevice) !=
             hipSuccess) {
             zipnn_batch_destroy(b);

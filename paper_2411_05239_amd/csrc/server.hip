@@ -270,14 +270,15 @@ bool launch_iteration(zipnn_server s)
         }
         s->st.chunks += tk.second;
     }
-    // buffer layout: per class descriptors then prefixes, then the status words
+    // buffer layout: per class descriptors, then the item prefix and the
+    // decode's item counter (zero), then the status words
     size_t off = 0;
     std::vector<std::pair<size_t, size_t>> at;   // per class: descs, prefix
     for (auto& kv : classes) {
         const size_t dd = off;
         off = round_up(off + kv.second.descs.size() * sizeof(DecDesc), 256);
         const size_t pp = off;
-        off = round_up(off + kv.second.prefix.size() * sizeof(uint64_t), 256);
+        off = round_up(off + (kv.second.prefix.size() + 1) * sizeof(uint64_t), 256);
         at.push_back({dd, pp});
     }
     it.status_off = off;
@@ -291,6 +292,7 @@ bool launch_iteration(zipnn_server s)
             for (size_t i = 0; i < c.descs.size(); i++) c.descs[i].status = d_status + c.member[i];
             memcpy(it.h_buf + at[ci].first, c.descs.data(), c.descs.size() * sizeof(DecDesc));
             memcpy(it.h_buf + at[ci].second, c.prefix.data(), c.prefix.size() * sizeof(uint64_t));
+            memset(it.h_buf + at[ci].second + c.prefix.size() * sizeof(uint64_t), 0, sizeof(uint64_t));
             ci++;
         }
         memset(it.h_buf + it.status_off, 0, it.members.size() * sizeof(int));
@@ -305,7 +307,7 @@ bool launch_iteration(zipnn_server s)
             const int grid = int(std::min<uint64_t>(uint64_t(s->ctx->dec_grid[dec_class_index(k)]),
                                                     std::max<uint64_t>(items, 1)));
             e = launch_decode_planned(k, (const DecDesc*)(it.d_buf + at[ci].first), int(c.descs.size()),
-                                      (const uint64_t*)(it.d_buf + at[ci].second), d_status, grid, s->stream);
+                                      (uint64_t*)(it.d_buf + at[ci].second), d_status, grid, s->stream);
             ci++;
         }
         if (e == hipSuccess)

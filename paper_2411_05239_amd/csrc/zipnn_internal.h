@@ -264,12 +264,16 @@ __host__ __device__ inline DecClass dec_class(const Header& h)
     return DecClass{h.B, h.g, (h.flags & kFlagDelta) != 0, (h.flags & kFlagZg) != 0};
 }
 hipError_t launch_decode_one(const Header& h, const DecDesc& one, int* d_status, int grid, hipStream_t s);
+// Batched decode: k_plan writes the item prefix (n_desc + 1 entries) and
+// zeroes the item counter after it, from which the workgroups take their
+// items; d_item_prefix has room for n_desc + 2 entries.
 hipError_t launch_decode_batch(const DecClass& k, const DecDesc* d_descs, int n_desc, uint64_t* d_item_prefix,
                                int* d_status, int grid, hipStream_t s);
 // Batched decode whose item prefix (plan_items per descriptor) was computed
-// on the host and copied beside the descriptors.
-hipError_t launch_decode_planned(const DecClass& k, const DecDesc* d_descs, int n_desc,
-                                 const uint64_t* d_item_prefix, int* d_status, int grid, hipStream_t s);
+// on the host and copied beside the descriptors, followed by the item
+// counter, zero at launch (n_desc + 2 entries).
+hipError_t launch_decode_planned(const DecClass& k, const DecDesc* d_descs, int n_desc, uint64_t* d_item_prefix,
+                                 int* d_status, int grid, hipStream_t s);
 hipError_t launch_clear_status(int* d_status, hipStream_t s);
 hipError_t launch_gather_headers(const uint8_t* arena, const uint64_t* d_offs, int n, void* d_out, hipStream_t s);
 int decode_grid_size(int device, const DecClass& k);
