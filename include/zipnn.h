@@ -282,7 +282,10 @@ int zipnn_batch_create(zipnn_ctx ctx, const void* arena, const uint64_t* offsets
                        const uint64_t* dst_cap, const void* const* base, zipnn_batch* out);
 
 /* Queue the prepared decompression on `stream` (graph replay; asynchronous).
- * Device-side checks report through the context status. */
+ * Device-side checks report through the context status.  A replay must not
+ * overlap another replay of the same batch (they share the outputs and the
+ * counters the workgroups take their items from); replays on one stream
+ * never do. */
 int zipnn_batch_decompress(zipnn_batch b, void* stream);
 
 /* Wait for the device, then release the batch. NULL is ignored. */
