@@ -43,18 +43,23 @@ def _src_hash(path: str) -> str:
 
 
 def _traffic(workload: str, alg_bytes: int):
-    """HBM bytes per decode launch from the committed rocprofv3 counter
-    summary, or None if it is missing or the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", f"k_decode_{workload}_traffic.json")
-    if not os.path.exists(path):
-        return None
-    try:
-        rec = json.load(open(path))
-        if rec.get("decode_src_sha") != _src_hash(os.path.join(ROOT, "paper_2411_05239_amd", "csrc", "decode.hip")):
-            return None
-        return rec.get("hbm_bytes_per_launch")
-    except Exception:
-        return None
+    """HBM bytes per decode launch from a committed rocprofv3 counter summary
+    of this workload (profiles/k_decode_<workload>[_<shape>]_traffic.json)
+    taken on the same decoder source and the same containers (equal
+    algorithmic bytes, so the same chunk size and S), or None."""
+    import glob
+
+    sha = _src_hash(os.path.join(ROOT, "paper_2411_05239_amd", "csrc", "decode.hip"))
+    paths = [os.path.join(ROOT, "profiles", f"k_decode_{workload}_traffic.json")]
+    paths += sorted(glob.glob(os.path.join(ROOT, "profiles", f"k_decode_{workload}_*_traffic.json")))
+    for path in paths:
+        try:
+            rec = json.load(open(path))
+        except Exception:
+            continue
+        if rec.get("decode_src_sha") == sha and rec.get("algorithmic_bytes_per_launch") == alg_bytes:
+            return rec.get("hbm_bytes_per_launch")
+    return None
 
 
 def make_workload(name: str, probe_skip: int = 0, exponent: bool = False):
