@@ -546,16 +546,9 @@ struct AnalyzeTail {
 //   5. the mode of each group (AUTO: the smallest of RAW, HUF, ZG, ties to
 //      RAW then HUF), its entry, its lane-group word counts and its canonical
 //      code table.
-// Occupancy matters more than spills here: the passes are latency-bound per
-// workgroup.  Four waves per SIMD (128 VGPRs) were 5-9% faster than three;
-// for 2-byte words five (96 VGPRs, some spills in the counting loop) encode
-// the BF16 checkpoint 5% and its XOR delta 10% faster than four.  WV sets
-// the waves per SIMD of the instances for 2-byte words.  Launches with an
-// XOR base read twice the bytes per element: six waves (80 VGPRs) encode the
-// Huffman-only delta 8% faster than five (the plain checkpoint would lose
-// 1%); where a group may take ZG, two codes are built per group, and seven
-// waves (72 VGPRs) encode the delta 5% faster than six (the Huffman-only
-// delta would lose 2%).
+// (analyze_chunk below; k_analyze runs it over the chunks, k_analyze_pack
+// packs each chunk after it.)
+
 // Shared memory of the analysis of one chunk.
 template <int BB>
 struct AnalyzeShared {
@@ -974,6 +967,17 @@ __device__ __attribute__((always_inline)) bool analyze_chunk(uint32_t gc, const 
     return true;
 }
 
+// Occupancy matters more than spills here: the passes are latency-bound per
+// workgroup.  Four waves per SIMD (128 VGPRs) were 5-9% faster than three;
+// for 2-byte words five (96 VGPRs, some spills in the counting loop) encoded
+// the BF16 checkpoint 5% and its XOR delta 10% faster than four, and six (80
+// VGPRs) are faster again: the checkpoint 1-3% at 256 and 512 KiB chunks, the
+// Huffman-only delta 8%.  WV sets the waves per SIMD of the instances for
+// 2-byte words.  Where a group of a launch with an XOR base may take ZG, two
+// codes are built per group, and seven waves (72 VGPRs) encode the delta 5%
+// faster than six (the Huffman-only delta would lose 2%).  Launches with a
+// base use these instances only when they take the exact path; staged ones
+// run k_analyze_pack.
 template <int BB, int WV>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WV, 8))) void k_analyze(const EncDesc* __restrict__ descs, int n_desc,
                                                     const uint32_t* __restrict__ chunk_prefix, uint32_t total_chunks,
@@ -1730,8 +1734,7 @@ hipError_t launch_encode(EncDesc* d_descs, int n_desc, const uint32_t* d_chunk_p
                 launched = true;
                 if (p.B == 1) ZIPNN_ANALYZE(1, 4);
                 else if (p.B == 2 && xb && zg_possible) ZIPNN_ANALYZE(2, 7);
-                else if (p.B == 2 && xb) ZIPNN_ANALYZE(2, 6);
-                else if (p.B == 2) ZIPNN_ANALYZE(2, 5);
+                else if (p.B == 2) ZIPNN_ANALYZE(2, 6);
                 else if (p.B == 4) ZIPNN_ANALYZE(4, 4);
                 else launched = false;
 #undef ZIPNN_ANALYZE
