@@ -528,6 +528,7 @@ def _serve_stats(rate, parts, sizes):
     return {"rate": rate, "requests": len(lat), "requests_per_iteration": round(len(lat) / max(iters, 1), 3),
             "p50_ms": round(_pct(lat, 0.5) * 1e3, 3),
             "p99_ms": round(_pct(lat, 0.99) * 1e3, 3), "mean_ms": round(statistics.mean(lat) * 1e3, 3),
+            "p99_halves_ms": [round(_pct(q["lat"], 0.99) * 1e3, 3) for q in parts],
             "GBps": round(sum(q["bytes"] for q in parts) / span / 1e9, 2),
             "offered_GBps": round(rate * statistics.mean(sizes) / 1e9, 2),
             "p50_phase_ms": {k: round(_pct(v, 0.5) * 1e3, 4) for k, v in ph.items()},
@@ -666,10 +667,16 @@ def serve_block(args, rates) -> dict:
     torch.cuda.empty_cache()
     # where continuous batching finds no second request to join an iteration
     # (requests_per_iteration near 1), both modes launch the same
-    # iterations, one request each, and their p99s differ by run-to-run noise
+    # iterations, one request each, and their p99s differ by run-to-run noise:
+    # the gap is set beside the spread of one mode's p99 between its two halves
+    def spread(r):
+        return max(r["p99_halves_ms"]) - min(r["p99_halves_ms"])
+
     cmp = [{"rate": a["rate"], "p99_continuous_ms": a["p99_ms"], "p99_per_request_ms": b["p99_ms"],
             "continuous_p99_le_per_request": a["p99_ms"] <= b["p99_ms"],
             "p99_ratio": round(a["p99_ms"] / b["p99_ms"], 4) if b["p99_ms"] else None,
+            "p99_gap_ms": round(a["p99_ms"] - b["p99_ms"], 3),
+            "p99_half_to_half_spread_ms": round(max(spread(a), spread(b)), 3),
             "requests_per_iteration_continuous": a["requests_per_iteration"],
             "GBps_continuous": a["GBps"], "GBps_per_request": b["GBps"]}
            for a, b in zip(res["continuous"], res["per_request"])]
