@@ -14,11 +14,11 @@ headline `value` is decode throughput in GB/s of uncompressed bytes (the
 paper's convention), from HIP events around every decode launch of the timed
 steps (on the stream the graph runs on); `encode_GBps` is the same for
 compress.  The same line carries the plain per-tensor decode, the roofline of
-the decode kernel, the oracle timed on the host cores (1 thread and the
-box's 16), and a serving block: the continuous-batching server against plain
+the decode kernel, the oracle timed on the host cores (1 thread and up to
+16), and a serving block: the continuous-batching server against plain
 per-request launches at 100, 1000 and 5000 requests/s plus a closed loop.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+Prints ONE JSON line.  `--gpus N` with N > 1 is refused: the codec runs on
 one GPU.
 """
 from __future__ import annotations
@@ -85,7 +85,7 @@ def make_workload(name: str, probe_skip: int = 0, exponent: bool = False):
     return x, p, desc
 
 
-BOX_THREADS = 16   # host threads the benchmark boxes give one GPU
+HOST_THREADS = 16   # at most this many host threads: the CPU share of one GPU on a shared node
 
 
 def host_info() -> dict:
@@ -103,7 +103,7 @@ def host_info() -> dict:
 
 def oracle_legs(tensors, bases, p, gpu_containers, budget_s: float, sample: str) -> dict:
     """The oracle (plain C, test infrastructure) on the host cores, at 1
-    thread and at the box's share of threads: every sample tensor is
+    thread and at one GPU's share of the host threads: every sample tensor is
     compressed once (its container compared with the GPU's) and the sample is
     decompressed repeatedly until `budget_s` seconds of decode have passed."""
     import numpy as np
@@ -112,7 +112,7 @@ def oracle_legs(tensors, bases, p, gpu_containers, budget_s: float, sample: str)
 
     from paper_2411_05239_amd import zipnn as Z
 
-    many = max(1, min(BOX_THREADS, os.cpu_count() or 1))
+    many = max(1, min(HOST_THREADS, os.cpu_count() or 1))
     kw = dict(chunk_bytes=p.chunk_bytes, S=p.substream_syms, g=p.group, L=p.max_code_len, policy=list(p.policy),
               skip=p.probe_skip, exp=bool(p.exponent))
     U = sum(x.numel() * x.element_size() for x in tensors)
@@ -142,7 +142,7 @@ def oracle_legs(tensors, bases, p, gpu_containers, budget_s: float, sample: str)
                       f"{many} threads; 1 compress + {legs[1]['decode_passes']} decompress passes at 1 thread",
             "encode_GBps": legs[many]["encode_GBps"], "single_thread": legs[1],
             "host": {**host_info(), "threads_used": many,
-                     "note": f"the all-cores leg uses the {BOX_THREADS} host threads a one-GPU box is given"},
+                     "note": f"the all-cores leg uses at most {HOST_THREADS} host threads, one GPU's share"},
             "roundtrip_ok": ok, "containers_match_gpu": matches}
 
 
@@ -729,7 +729,7 @@ def main():
                     help="compressibility probing interval K (0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this codec build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the codec runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "serve":
         run_serve(args)
